@@ -1,0 +1,188 @@
+"""FP64 CPU oracle of the explicit MLS-MPM substep (CRESSim-MPM, Sec. III-B,
+Algorithm 1, with the contact law of Sec. IV-A).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the GPU library. It shares no code with
+the HIP path. The arithmetic lives in ``mpm_oracle.cpp`` (plain FP64 loops);
+this module only marshals arguments through ctypes.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpm_oracle.so")
+
+TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE = 0, 1, 2, 3
+ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDOMAIN, ST_ENONFINITE, ST_EINVERTED = 0, -1, -2, -4, -5, -6
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.c_void_p
+        L.oracle_create.restype = ctypes.c_void_p
+        L.oracle_create.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double]
+        L.oracle_destroy.argtypes = [ctypes.c_void_p]
+        L.oracle_set_particles.argtypes = [ctypes.c_void_p, ctypes.c_longlong, fp, fp, fp, fp, fp,
+                                           ctypes.c_double, ctypes.c_double]
+        L.oracle_set_tool.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp,
+                                      dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.oracle_read.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
+        L.oracle_last_grid.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.oracle_impulses.argtypes = [ctypes.c_void_p, dp]
+        L.oracle_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)]
+        L.oracle_weights.argtypes = [ctypes.c_double, dp]
+        L.oracle_polar.restype = ctypes.c_double
+        L.oracle_polar.argtypes = [dp, dp]
+        L.oracle_kirchhoff.restype = ctypes.c_double
+        L.oracle_kirchhoff.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_energy.restype = ctypes.c_double
+        L.oracle_energy.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        L.oracle_sdf.restype = ctypes.c_double
+        L.oracle_sdf.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
+        L.oracle_contact.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f32(a):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- unit calls
+def weights(f):
+    o, p = _d(np.zeros(3))
+    lib().oracle_weights(float(f), p)
+    return o
+
+
+def polar(F):
+    F, pF = _d(np.asarray(F).reshape(9))
+    R, pR = _d(np.zeros(9))
+    J = lib().oracle_polar(pF, pR)
+    return R.reshape(3, 3), J
+
+
+def kirchhoff(F, E, nu):
+    F, pF = _d(np.asarray(F).reshape(9))
+    t, pt = _d(np.zeros(9))
+    J = lib().oracle_kirchhoff(pF, float(E), float(nu), pt)
+    return t.reshape(3, 3), J
+
+
+def energy(F, E, nu):
+    F, pF = _d(np.asarray(F).reshape(9))
+    return lib().oracle_energy(pF, float(E), float(nu))
+
+
+def sdf(tool_type, center, quat, size, p):
+    c, pc = _d(center)
+    q, pq = _d(quat)
+    s, ps = _d(size)
+    x, px = _d(p)
+    g, pg = _d(np.zeros(3))
+    phi = lib().oracle_sdf(int(tool_type), pc, pq, ps, px, pg)
+    return phi, g.copy()
+
+
+def contact(n, u, mu, drag):
+    n, pn = _d(n)
+    u, pu = _d(u)
+    o, po = _d(np.zeros(3))
+    lib().oracle_contact(pn, pu, float(mu), float(drag), po)
+    return o.copy()
+
+
+# ---------------------------------------------------------------- scene object
+class Oracle:
+    """One scene on the FP64 oracle. Inputs are the FP32 arrays the GPU
+    library receives; they are widened to FP64 inside."""
+
+    def __init__(self, n_grid, dt, gravity=(0.0, -9.8, 0.0), wall_band=3, nu=0.3, E_default=5e3):
+        g, pg = _d(gravity)
+        self.n = int(n_grid)
+        self.h = lib().oracle_create(self.n, float(dt), pg, int(wall_band), float(nu), float(E_default))
+        if not self.h:
+            raise ValueError("oracle_create rejected its arguments")
+        self.N = 0
+
+    def close(self):
+        if self.h:
+            lib().oracle_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_particles(self, x, v=None, C=None, F=None, E=None, mass=1.0, vol0=1.0):
+        x, px = _f32(x)
+        keep = [x]
+        ptrs = []
+        for a in (v, C, F, E):
+            arr, p = _f32(a)
+            keep.append(arr)
+            ptrs.append(p)
+        self.N = x.shape[0]
+        st = lib().oracle_set_particles(self.h, self.N, px, *ptrs, float(mass), float(vol0))
+        if st != 0:
+            raise ValueError(f"oracle_set_particles: status {st}")
+
+    def set_tool(self, tool_id, tool_type, center=(0, 0, 0), quat=(1, 0, 0, 0), size=(0, 0, 0),
+                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0):
+        arrs = [_d(a) for a in (center, quat, size, lin_vel, ang_vel)]
+        st = lib().oracle_set_tool(self.h, int(tool_id), int(tool_type), *[p for _, p in arrs],
+                                   float(mu), float(drag), float(margin))
+        if st != 0:
+            raise ValueError(f"oracle_set_tool: status {st}")
+
+    def step(self, n):
+        return lib().oracle_step(self.h, int(n))
+
+    def read(self):
+        N = self.N
+        x, px = _d(np.zeros((N, 3)))
+        v, pv = _d(np.zeros((N, 3)))
+        C, pC = _d(np.zeros((N, 3, 3)))
+        F, pF = _d(np.zeros((N, 3, 3)))
+        st = lib().oracle_read(self.h, px, pv, pC, pF)
+        return {"x": x, "v": v, "C": C, "F": F, "status": st}
+
+    def last_grid(self):
+        n = self.n
+        m, pm = _d(np.zeros((n, n, n)))
+        p, pp = _d(np.zeros((n, n, n, 3)))
+        v, pv = _d(np.zeros((n, n, n, 3)))
+        lib().oracle_last_grid(self.h, pm, pp, pv)
+        return m, p, v
+
+    def impulses(self):
+        o, po = _d(np.zeros((9, 3)))
+        lib().oracle_impulses(self.h, po)
+        return o
+
+    def counters(self):
+        o = np.zeros(3, dtype=np.int64)
+        lib().oracle_counters(self.h, o.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+        return {"inverted": int(o[0]), "domain": int(o[1]), "nonfinite": int(o[2])}

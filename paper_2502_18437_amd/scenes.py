@@ -1,0 +1,262 @@
+"""Seeded synthetic scenes shaped like the paper's workloads.
+
+This module only generates inputs (particle lattices, materials, tool
+poses); it holds none of the method's arithmetic and imports neither the GPU
+library nor the oracle, so both can be fed from it.
+
+The paper's tissue scenes are Unity assets without stated sizes (Sec. V);
+its one measured workload is a falling cube on a fixed 56^3 grid
+(Sec. III-D). The scenes below are synthetic stand-ins:
+
+* ``c1``   8,000 particles, 20^3 lattice at dx/2 spacing in a cube at the
+  centre of a 32^3 grid, free fall, uniform E = 5e3 Pa, nu = 0.3.
+* ``c1s``  c1 spinning about z at 2 rad/s with F0 = diag(1.05, 1, 1).
+* ``c2``   1,048,576 particles filling a 0.8 x 0.2 x 0.8 slab on a 128^3
+  grid, E ~ U(2e3, 8e3), nu = 0.4, a capsule (r = 3 dx) pressing down at
+  0.05 m/s, dt = 5e-5, 1,000 substeps.
+* ``c2s``  c2 on a 32^3 grid (16,384 particles), 100 substeps.
+* ``c3``   4,194,304 particles in the slab on a 256^3 grid, a thin oriented
+  box blade (thickness 0.5 dx, length 0.3) sweeping along x at 1 m/s through
+  the slab plus a capsule grasper, friction 0.3, dt = 5e-5, 500 substeps.
+* ``c3s``  c3 on a 32^3 grid (8,192 particles), 100 substeps.
+* ``c5``   65,536 particles on a 64^3 grid, per-particle E = exp(theta),
+  capsule tool, dt = 1e-4, 200 substeps (differentiable-rollout shape).
+* ``cube`` the paper's performance scene: falling cube, 56^3 grid,
+  dt = 2e-3, 10 substeps per frame, ``n_particles`` chosen by the caller.
+
+Every scene: domain [0, 1)^3, dx = 1/n, rho = 1e3, gravity (0, -9.8, 0),
+sticky walls 3 nodes thick, v0 = 0, C0 = 0, F0 = I unless stated,
+lattice points cell-centred and jittered per component by U[0, 0.1 dx)
+drawn from numpy's PCG64 seeded with the scene seed; positions are drawn
+before E.
+"""
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE = 0, 1, 2, 3
+RHO = 1e3
+GRAVITY = (0.0, -9.8, 0.0)
+WALL_BAND = 3
+SQRT_HALF = math.sqrt(0.5)
+
+
+@dataclass
+class Tool:
+    type: int
+    center: tuple
+    quat: tuple = (1.0, 0.0, 0.0, 0.0)
+    size: tuple = (0.0, 0.0, 0.0)
+    lin_vel: tuple = (0.0, 0.0, 0.0)
+    ang_vel: tuple = (0.0, 0.0, 0.0)
+    mu: float = 0.3
+    drag: float = 1.0
+    margin: float = 0.0
+
+    def kwargs(self):
+        return dict(center=self.center, quat=self.quat, size=self.size, lin_vel=self.lin_vel,
+                    ang_vel=self.ang_vel, mu=self.mu, drag=self.drag, margin=self.margin)
+
+
+@dataclass
+class Scene:
+    name: str
+    n_grid: int
+    dt: float
+    n_substeps: int
+    nu: float
+    E_default: float
+    mass: float
+    vol0: float
+    x: np.ndarray                      # (N, 3) float32
+    v: np.ndarray = None               # (N, 3) float32 or None (zero)
+    C: np.ndarray = None               # (N, 3, 3) float32 or None (zero)
+    F: np.ndarray = None               # (N, 3, 3) float32 or None (identity)
+    E: np.ndarray = None               # (N,) float32 or None (E_default)
+    tools: list = field(default_factory=list)
+    gravity: tuple = GRAVITY
+    wall_band: int = WALL_BAND
+
+    @property
+    def N(self):
+        return int(self.x.shape[0])
+
+    @property
+    def dx(self):
+        return 1.0 / self.n_grid
+
+    def particle_arrays(self):
+        return dict(x=self.x, v=self.v, C=self.C, F=self.F, E=self.E)
+
+
+def lattice(lo, counts, spacing):
+    """Cell-centred lattice points lo + (i + 1/2) * spacing, x fastest."""
+    axes = [lo[a] + (np.arange(counts[a], dtype=np.float64) + 0.5) * spacing[a] for a in range(3)]
+    X, Y, Z = np.meshgrid(axes[0], axes[1], axes[2], indexing="ij")
+    pts = np.stack([X.ravel(order="F"), Y.ravel(order="F"), Z.ravel(order="F")], axis=1)
+    return pts
+
+
+def jitter(rng, n, dx):
+    return rng.uniform(0.0, 0.1 * dx, size=(n, 3))
+
+
+def _cube(n_grid, per_axis, spacing, seed):
+    dx = 1.0 / n_grid
+    side = per_axis * spacing
+    lo = 0.5 - 0.5 * side
+    rng = np.random.default_rng(seed)
+    pts = lattice((lo, lo, lo), (per_axis,) * 3, (spacing,) * 3)
+    pts = pts + jitter(rng, pts.shape[0], dx)
+    return pts.astype(np.float32), rng
+
+
+def scene_c1(seed=1):
+    n = 32
+    dx = 1.0 / n
+    x, _ = _cube(n, 20, dx / 2, seed)
+    vol0 = (dx / 2) ** 3
+    return Scene("c1", n, 1e-4, 100, 0.3, 5e3, RHO * vol0, vol0, x)
+
+
+def scene_c1s(seed=1, omega=(0.0, 0.0, 2.0), stretch=1.05, gravity=GRAVITY):
+    s = scene_c1(seed)
+    w = np.asarray(omega, dtype=np.float64)
+    r = s.x.astype(np.float64) - 0.5
+    v = np.cross(np.broadcast_to(w, r.shape), r)
+    W = np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+    s.name = "c1s"
+    s.v = v.astype(np.float32)
+    s.C = np.broadcast_to(W, (s.N, 3, 3)).astype(np.float32).copy()
+    F = np.zeros((s.N, 3, 3), dtype=np.float32)
+    F[:, 0, 0], F[:, 1, 1], F[:, 2, 2] = stretch, 1.0, 1.0
+    s.F = F
+    s.gravity = tuple(gravity)
+    return s
+
+
+def _slab(n_grid, counts, seed, E_range=(2e3, 8e3)):
+    """Slab x, z in [0.1, 0.9], y in [3 dx, 3 dx + 0.2], resting on the floor band."""
+    dx = 1.0 / n_grid
+    lo = (0.1, 3 * dx, 0.1)
+    ext = (0.8, 0.2, 0.8)
+    spacing = tuple(ext[a] / counts[a] for a in range(3))
+    rng = np.random.default_rng(seed)
+    pts = lattice(lo, counts, spacing)
+    pts = pts + jitter(rng, pts.shape[0], dx)
+    E = rng.uniform(E_range[0], E_range[1], size=pts.shape[0]).astype(np.float32)
+    N = pts.shape[0]
+    vol0 = 0.128 / N
+    top = 3 * dx + 0.2
+    return pts.astype(np.float32), E, vol0, top
+
+
+def _press_capsule(n_grid, top, center_xz=(0.5, 0.5), axis="z", half_length=0.15, speed=0.05):
+    dx = 1.0 / n_grid
+    r = 3 * dx
+    quat = (SQRT_HALF, 0.0, -SQRT_HALF, 0.0) if axis == "z" else (1.0, 0.0, 0.0, 0.0)
+    return Tool(TOOL_CAPSULE, (center_xz[0], top + r, center_xz[1]), quat, (half_length, r, 0.0),
+                (0.0, -speed, 0.0), mu=0.3)
+
+
+def scene_c2(seed=2, n_grid=128, counts=(128, 64, 128), n_substeps=1000):
+    x, E, vol0, top = _slab(n_grid, counts, seed)
+    tool = _press_capsule(n_grid, top)
+    return Scene("c2", n_grid, 5e-5, n_substeps, 0.4, 5e3, RHO * vol0, vol0, x, E=E, tools=[tool])
+
+
+def scene_c2s(seed=2):
+    s = scene_c2(seed, n_grid=32, counts=(32, 16, 32), n_substeps=100)
+    s.name = "c2s"
+    return s
+
+
+def _blade_and_grasper(n_grid, top):
+    dx = 1.0 / n_grid
+    blade = Tool(TOOL_BOX, (0.1, top, 0.5), (1.0, 0.0, 0.0, 0.0), (0.15, 0.15, 0.25 * dx),
+                 (1.0, 0.0, 0.0), mu=0.3)
+    r = 3 * dx
+    grasper = Tool(TOOL_CAPSULE, (0.7, top + r, 0.3), (1.0, 0.0, 0.0, 0.0), (0.1, r, 0.0),
+                   (0.0, -0.05, 0.0), mu=0.3)
+    return [blade, grasper]
+
+
+def scene_c3(seed=3, n_grid=256, counts=(256, 64, 256), n_substeps=500):
+    x, E, vol0, top = _slab(n_grid, counts, seed)
+    return Scene("c3", n_grid, 5e-5, n_substeps, 0.4, 5e3, RHO * vol0, vol0, x, E=E,
+                 tools=_blade_and_grasper(n_grid, top))
+
+
+def scene_c3s(seed=3):
+    s = scene_c3(seed, n_grid=32, counts=(32, 8, 32), n_substeps=100)
+    s.name = "c3s"
+    return s
+
+
+def scene_c3m(seed=3):
+    """c3 on a 64^3 grid (65,536 particles): several blocks per axis."""
+    s = scene_c3(seed, n_grid=64, counts=(64, 16, 64), n_substeps=100)
+    s.name = "c3m"
+    return s
+
+
+def scene_c5(seed=5, n_substeps=200):
+    n = 64
+    dx = 1.0 / n
+    x, _, vol0, top = _slab(n, (64, 16, 64), seed)
+    rng = np.random.default_rng(seed + 1000)
+    theta = math.log(5e3) + rng.uniform(-0.2, 0.2, size=x.shape[0])
+    E = np.exp(theta).astype(np.float32)
+    tool = _press_capsule(n, top)
+    tool.lin_vel = (0.0, -0.05, 0.0)
+    s = Scene("c5", n, 1e-4, n_substeps, 0.3, 5e3, RHO * vol0, vol0, x, E=E, tools=[tool])
+    s.theta = theta.astype(np.float32)
+    return s
+
+
+def scene_cube(n_particles=1 << 16, seed=7, n_grid=56):
+    """The paper's performance scene: a cube falling under gravity on a fixed
+    56^3 grid, 10 substeps of dt = 2e-3 per 0.02 s frame."""
+    per_axis = max(2, int(round(n_particles ** (1.0 / 3.0))))
+    dx = 1.0 / n_grid
+    side = 0.4
+    spacing = side / per_axis
+    rng = np.random.default_rng(seed)
+    lo = 0.5 - side / 2
+    pts = lattice((lo, lo, lo), (per_axis,) * 3, (spacing,) * 3)
+    pts = (pts + jitter(rng, pts.shape[0], dx)).astype(np.float32)
+    vol0 = side ** 3 / pts.shape[0]
+    return Scene("cube", n_grid, 2e-3, 10, 0.3, 5e3, RHO * vol0, vol0, pts)
+
+
+def tiny_block(n_grid=16, per_axis=6, seed=11, spacing_dx=0.5, center=(0.5, 0.5, 0.5),
+               gravity=GRAVITY, with_state=True, E_range=None):
+    """A small random block of particles for unit tests (<= a few hundred)."""
+    dx = 1.0 / n_grid
+    spacing = spacing_dx * dx
+    side = per_axis * spacing
+    rng = np.random.default_rng(seed)
+    lo = tuple(center[a] - side / 2 for a in range(3))
+    pts = lattice(lo, (per_axis,) * 3, (spacing,) * 3)
+    pts = (pts + jitter(rng, pts.shape[0], dx)).astype(np.float32)
+    N = pts.shape[0]
+    vol0 = spacing ** 3
+    s = Scene("tiny", n_grid, 1e-4, 10, 0.3, 5e3, RHO * vol0, vol0, pts, gravity=tuple(gravity))
+    if with_state:
+        s.v = rng.normal(0.0, 0.05, size=(N, 3)).astype(np.float32)
+        s.C = rng.normal(0.0, 0.5, size=(N, 3, 3)).astype(np.float32)
+        s.F = (np.eye(3) + rng.normal(0.0, 0.03, size=(N, 3, 3))).astype(np.float32)
+    if E_range is not None:
+        s.E = rng.uniform(E_range[0], E_range[1], size=N).astype(np.float32)
+    return s
+
+
+SCENES = {
+    "c1": scene_c1, "c1s": scene_c1s, "c2": scene_c2, "c2s": scene_c2s, "c3": scene_c3,
+    "c3s": scene_c3s, "c3m": scene_c3m, "c5": scene_c5, "cube": scene_cube,
+}
+
+
+def make(name, **kw):
+    return SCENES[name](**kw)
