@@ -1,0 +1,211 @@
+/*
+ * mpm.h -- C ABI of the MI355X explicit MLS-MPM substep library.
+ *
+ * The library advances one scene of the material point method of
+ * CRESSim-MPM (arXiv 2502.18437): per substep, P2G scatter of mass, APIC
+ * affine momentum and MLS stress (Sec. III-B, eq. mls_mpm_p2g_momentum_force),
+ * a grid update with gravity, rigid-tool SDF contact with friction and drag
+ * (Sec. IV-A, eq. v_correction) and sticky box walls (Sec. III-A, boundary
+ * conditions), then a G2P gather of velocity, affine matrix C, deformation
+ * gradient F and position (eqs. mls_mpm_g2p_momentum, mls_mpm_g2p_f,
+ * mls_mpm_g2p_integration) -- Algorithm 1 of the paper.
+ *
+ * The call sequence mirrors the paper's object model (Sec. V-A): a scene is
+ * created (SimulationFactory / Scene), particles and tools are set
+ * (ParticleObject / Shape), mpm_step enqueues work and returns at once like
+ * Scene::advance, and mpm_read_state blocks like Scene::fetchResults.
+ *
+ * Conventions for every call:
+ *  - Return value: MPM_OK (0) or a negative MPM_E* code. mpm_last_error()
+ *    gives a per-handle message for the most recent failure.
+ *  - Units: SI (m, s, kg, Pa). The domain is [0, 1)^3 with n_grid^3 nodes at
+ *    i * dx, dx = 1 / n_grid; y is up.
+ *  - Arrays at the API are row-major per particle: x and v are (n, 3), C and
+ *    F are (n, 3, 3) with element [a][b] at 9p + 3a + b, E is (n,).
+ *  - `where` = MPM_HOST (0): the pointer is host memory; MPM_DEVICE (1): it is
+ *    device memory on the handle's GPU. Device pointers must stay valid until
+ *    the handle's stream has passed the call.
+ *  - Ownership: the library owns every device buffer it allocates until
+ *    mpm_destroy; the caller owns all arrays it passes; inputs are copied.
+ *  - Asynchrony: mpm_set_particles, mpm_set_tool_sdf and mpm_step enqueue
+ *    on the handle's stream and return without waiting. mpm_read_state,
+ *    mpm_get_info and mpm_destroy synchronise the stream.
+ *  - Deferred errors: errors detected on the device (MPM_EDOMAIN,
+ *    MPM_ENONFINITE, MPM_EINVERTED) are sticky; they are returned by the next
+ *    blocking call and stay set until the next mpm_set_particles.
+ *  - Threading: one host thread per handle at a time.
+ */
+#ifndef MPM_H_
+#define MPM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define MPM_OK 0
+#define MPM_EINVAL (-1)     /* bad argument, NULL handle, size out of range */
+#define MPM_ENOMEM (-2)     /* a device or host allocation failed */
+#define MPM_EHIP (-3)       /* a HIP runtime call failed */
+#define MPM_EDOMAIN (-4)    /* a particle's 3x3x3 stencil left the grid; that
+                               particle is left unchanged */
+#define MPM_ENONFINITE (-5) /* a particle's state is not finite; it is left
+                               unchanged */
+#define MPM_EINVERTED (-6)  /* det F <= 0 was seen in the stress evaluation */
+
+/* Precedence when several device errors are pending:
+ * MPM_ENONFINITE, then MPM_EDOMAIN, then MPM_EINVERTED. */
+
+#define MPM_HOST 0
+#define MPM_DEVICE 1
+
+#define MPM_MAX_TOOLS 8
+
+/* Grid accumulation mode of the P2G scatter. */
+#define MPM_ACCUM_F32 0   /* FP32 atomics: fast, summation order varies */
+#define MPM_ACCUM_FIXED 1 /* 64-bit fixed-point atomics: results are
+                             bit-identical run to run and independent of
+                             particle order and re-sort schedule */
+
+/* Tool geometries (Sec. IV-A: one SDF per rigid shape). */
+#define MPM_TOOL_NONE 0    /* removes the tool */
+#define MPM_TOOL_CAPSULE 1 /* segment along the body x axis;
+                              size = {half_length, radius, unused} */
+#define MPM_TOOL_BOX 2     /* oriented box; size = half extents in body axes */
+#define MPM_TOOL_PLANE 3   /* half space; body +y is the outward normal
+                              through center; size unused */
+
+typedef struct mpm_handle mpm_handle;
+
+/* Scene constants. */
+typedef struct mpm_params {
+  int32_t n_grid;          /* nodes per axis, 8 <= n_grid <= 1024; dx = 1/n_grid */
+  float dt;                /* substep length in s, > 0 */
+  float gravity[3];        /* m/s^2, e.g. {0, -9.8, 0} */
+  int32_t wall_band;       /* nodes with an index < band or > n_grid-1-band
+                              get v = 0 (sticky walls); 0 disables */
+  float nu;                /* Poisson ratio, 0 <= nu < 0.5 */
+  float E_default;         /* Young's modulus used when no per-particle E */
+  int32_t accum_mode;      /* MPM_ACCUM_F32 or MPM_ACCUM_FIXED */
+  int32_t tile;            /* 0 = default (8); grid block edge in nodes: 8 */
+  int32_t resort_interval; /* substeps between particle re-binning; 0 = default */
+  int64_t max_particles;   /* capacity reserved at create, >= 0 */
+} mpm_params;
+
+/* One rigid tool. The pose is kinematic: during the k-th substep after the
+ * mpm_set_tool_sdf call the centre is center + k * dt * lin_vel (the pose at
+ * the start of that substep); the orientation stays fixed, and ang_vel only
+ * enters the rigid velocity v_r = lin_vel + ang_vel x (x_I - centre) used by
+ * the contact law. */
+typedef struct mpm_tool {
+  int32_t type;        /* MPM_TOOL_* */
+  double center[3];    /* m */
+  double quat[4];      /* body-to-world rotation (w, x, y, z); normalised */
+  double size[3];      /* see MPM_TOOL_* */
+  double lin_vel[3];   /* m/s */
+  double ang_vel[3];   /* rad/s */
+  float mu;            /* kinetic friction coefficient mu_k >= 0 */
+  float drag;          /* drag factor c_d in [0, 1]: 1 = no drag, 0 = sticky */
+  float margin;        /* contact when phi(x_I) < margin (fattened region) */
+} mpm_tool;
+
+/* Counters, valid after a blocking call. */
+typedef struct mpm_info {
+  int64_t n_particles;
+  int64_t substeps;          /* substeps enqueued since mpm_create */
+  int64_t resorts;           /* particle re-binnings since mpm_create */
+  int64_t occupied_blocks;   /* grid blocks holding particles, last binning */
+  int64_t active_blocks;     /* blocks the grid update visits, last binning */
+  int64_t active_nodes;      /* nodes with mass > 0 in the last substep */
+  int64_t n_inverted;        /* particle-substeps with det F <= 0 */
+  int64_t n_domain;          /* particles found outside the grid */
+  int64_t n_nonfinite;       /* particles with non-finite state */
+  int64_t n_fallback;        /* particle-substeps that left their block's
+                                tile and took the global-memory path */
+  int32_t tile;
+  int32_t resort_interval;
+  int32_t accum_mode;
+  int32_t n_tools;
+} mpm_info;
+
+/* Create a scene on the current HIP device. `hip_stream` is a hipStream_t
+ * cast to uint64_t (e.g. torch.cuda.current_stream().cuda_stream); 0 makes
+ * the library create and own a stream. Allocates the dense n_grid^3 grid
+ * (two float4 arrays) and room for max_particles particles.
+ * Errors: MPM_EINVAL (NULL pointers, out-of-range field), MPM_ENOMEM,
+ * MPM_EHIP. On error *out is NULL. */
+int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out);
+
+/* Destroy the scene: synchronises its stream, frees every device buffer
+ * and returns the pending device error, if any. NULL is a no-op (MPM_OK). */
+int mpm_destroy(mpm_handle* h);
+
+/* Replace the particle set (ParticleObject, Sec. V-A) with n particles.
+ * x is required when n > 0; v = NULL means 0, C = NULL means 0, F = NULL
+ * means I, E = NULL means E_default for every particle. mass and vol0 are the
+ * per-particle mass and initial volume (> 0). Particles are identified by
+ * their index 0..n-1 in these arrays; mpm_read_state returns them in this
+ * order. Clears the deferred errors. The scene clock (substep counter) and
+ * the tools are left as they are.
+ * Errors: MPM_EINVAL (n < 0, n > max_particles, NULL x with n > 0,
+ * mass or vol0 <= 0, bad where), MPM_EHIP. */
+int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v,
+                      const float* C, const float* F, const float* E,
+                      float mass, float vol0, int32_t where);
+
+/* Set, replace (or with type MPM_TOOL_NONE remove) tool `tool_id`
+ * (0 <= tool_id < MPM_MAX_TOOLS). Tools are applied to each grid node in id
+ * order, then the walls. Errors: MPM_EINVAL (bad id, type, size <= 0 for
+ * the used fields, non-finite values, mu < 0, drag outside [0, 1]). */
+int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t);
+
+/* Enqueue n_substeps substeps of Algorithm 1 and return without waiting
+ * (Scene::advance). n_substeps = 0 is a no-op. Errors: MPM_EINVAL
+ * (n_substeps < 0), MPM_EHIP (launch failure). */
+int mpm_step(mpm_handle* h, int32_t n_substeps);
+
+/* Block until the stream drains (Scene::fetchResults) and write the state
+ * in the caller's original particle order. NULL outputs are skipped.
+ * Returns the pending device error, if any (the state is still written).
+ * Errors: MPM_EINVAL (bad where), MPM_EHIP. */
+int mpm_read_state(mpm_handle* h, float* x, float* v, float* C, float* F, int32_t where);
+
+/* Synchronise and fill *info. Errors: MPM_EINVAL, MPM_EHIP. */
+int mpm_get_info(mpm_handle* h, mpm_info* info);
+
+/* Message of the most recent failure on this handle ("" if none). The
+ * string is owned by the handle and valid until its next call. A NULL
+ * handle gives the message of the last failed mpm_create. */
+const char* mpm_last_error(const mpm_handle* h);
+
+/* Fixed-corotated Kirchhoff stress (Stomakhin et al. 2012) of n deformation
+ * gradients with the GPU's own polar decomposition:
+ * tau = 2 mu (F - R) F^T + lambda (J - 1) J I, mu and lambda from E[i] and nu.
+ * F and tau are (n, 3, 3) row-major, E is (n,); all host (where = MPM_HOST)
+ * or all device memory. Synchronous. Diagnostic entry point for tests of the
+ * constitutive step; the substep computes the same quantity in registers.
+ * Errors: MPM_EINVAL, MPM_ENOMEM, MPM_EHIP. */
+int mpm_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,
+                    int32_t where);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch while enabled. Kinds, in order: 0 sort (binning pipeline),
+ * 1 p2g, 2 g2p2g (fused), 3 g2p, 4 grid update. */
+#define MPM_KERNEL_KINDS 5
+typedef struct mpm_kernel_times {
+  double total_ms[MPM_KERNEL_KINDS];
+  int64_t launches[MPM_KERNEL_KINDS];
+} mpm_kernel_times;
+
+/* Enable (1) or disable (0) event timing; enabling clears the totals. */
+int mpm_profile(mpm_handle* h, int32_t enable);
+/* Synchronise and return the totals accumulated since timing was enabled. */
+int mpm_profile_read(mpm_handle* h, mpm_kernel_times* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM_H_ */

@@ -1,0 +1,636 @@
+// Host runtime and C ABI of the MLS-MPM substep library (declared in
+// include/mpm.h). One handle = one scene: device buffers, the stream, the
+// tool table, the binning schedule and the substep driver.
+//
+// mpm_step(n) enqueues, for substeps k = 0..n-1 (Algorithm 1 of the paper):
+//   k == 0 or re-binning due:  [G2P(k-1)] -> binning -> P2G(k)
+//   otherwise:                 fused G2P(k-1) + P2G(k)
+//   then the grid update of substep k (tools at their substep-k pose),
+// and a final G2P, so that x, v, C, F are materialised when the call's work
+// completes. Nothing here waits on the device except mpm_read_state,
+// mpm_get_info, mpm_profile_read, mpm_eval_stress and mpm_destroy.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mpm.h"
+#include "mpm_internal.h"
+
+using namespace mpm;
+
+namespace {
+
+constexpr int kDefaultResort = 32;
+
+struct HostTool {
+  mpm_tool t;
+  int64_t set_at = 0;
+  double R[9];
+  bool active = false;
+};
+
+struct ProfEvent {
+  int kind;
+  hipEvent_t a, b;
+};
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct mpm_handle {
+  mpm_params p{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int cus = 256;
+  Buffers b;
+  int nb = 0;
+  uint32_t n_blocks = 0;
+  int key_bits = 0;
+  int64_t N = 0;
+  bool has_E = false;
+  float mass = 0.0f, vol0 = 0.0f;
+  SimK sim{};
+  HostTool tools[kMaxTools];
+  int64_t substep = 0;
+  int64_t since_sort = 0;
+  bool dirty = true;
+  int resort_interval = kDefaultResort;
+  int64_t resorts = 0;
+  int transfer_wgs = 512;
+  std::string err;
+  bool prof = false;
+  std::vector<ProfEvent> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[MPM_KERNEL_KINDS] = {0, 0, 0, 0, 0};
+  int64_t prof_n[MPM_KERNEL_KINDS] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(mpm_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_fail(mpm_handle* h, hipError_t e, const char* what) {
+  return fail(h, MPM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_RETURN(h, expr)                       \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(h, e_, #expr); \
+  } while (0)
+
+hipError_t select_device(const mpm_handle* h) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != h->device) return hipSetDevice(h->device);
+  return hipSuccess;
+}
+
+void quat_to_R(const double* q, double* R) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  const double n = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= n, x /= n, y /= n, z /= n;
+  R[0] = 1 - 2 * (y * y + z * z);
+  R[1] = 2 * (x * y - w * z);
+  R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);
+  R[4] = 1 - 2 * (x * x + z * z);
+  R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);
+  R[7] = 2 * (y * z + w * x);
+  R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Tools at the pose of global substep `k` (centre + elapsed * lin_vel in FP64,
+// then rounded to FP32).
+ToolSetK tools_at(const mpm_handle* h, int64_t k) {
+  ToolSetK ts;
+  std::memset(&ts, 0, sizeof(ts));
+  ts.n = 0;
+  for (int i = 0; i < kMaxTools; ++i) {
+    const HostTool& ht = h->tools[i];
+    ToolK& t = ts.t[i];
+    if (!ht.active) {
+      t.type = TOOL_NONE;
+      continue;
+    }
+    ts.n = i + 1;
+    t.type = ht.t.type;
+    const double el = (double)(k - ht.set_at) * (double)h->p.dt;
+    for (int a = 0; a < 3; ++a) {
+      t.c[a] = (float)(ht.t.center[a] + el * ht.t.lin_vel[a]);
+      t.size[a] = (float)ht.t.size[a];
+      t.lv[a] = (float)ht.t.lin_vel[a];
+      t.av[a] = (float)ht.t.ang_vel[a];
+    }
+    for (int i2 = 0; i2 < 9; ++i2) t.R[i2] = (float)ht.R[i2];
+    t.mu = ht.t.mu;
+    t.drag = ht.t.drag;
+    t.margin = ht.t.margin;
+  }
+  return ts;
+}
+
+hipEvent_t prof_event(mpm_handle* h) {
+  if (!h->prof_pool.empty()) {
+    hipEvent_t e = h->prof_pool.back();
+    h->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  mpm_handle* h;
+  int kind;
+  hipEvent_t a = nullptr;
+  ProfScope(mpm_handle* hh, int k) : h(hh), kind(k) {
+    if (h->prof) {
+      a = prof_event(h);
+      if (a) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (h->prof && a) {
+      hipEvent_t b = prof_event(h);
+      if (b) {
+        (void)hipEventRecord(b, h->stream);
+        h->prof_pending.push_back({kind, a, b});
+      } else {
+        h->prof_pool.push_back(a);
+      }
+    }
+  }
+};
+
+void prof_collect(mpm_handle* h) {
+  for (auto& pe : h->prof_pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+      h->prof_ms[pe.kind] += ms;
+      h->prof_n[pe.kind] += 1;
+    }
+    h->prof_pool.push_back(pe.a);
+    h->prof_pool.push_back(pe.b);
+  }
+  h->prof_pending.clear();
+}
+
+void free_buffers(Buffers& b) {
+  void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
+                  b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.act_list, b.mark,
+                  b.ovf_list[0], b.ovf_list[1], b.acc, b.vel, b.status};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  b = Buffers();
+}
+
+__global__ void k_reset_status(Status* st) {
+  st->n_inverted = 0ull;
+  st->n_domain = 0ull;
+  st->n_nonfinite = 0ull;
+  st->n_fallback = 0ull;
+  st->active_nodes[0] = 0ull;
+  st->active_nodes[1] = 0ull;
+  st->n_occ = 0u;
+  st->n_act = 0u;
+  st->ovf_count[0] = 0u;
+  st->ovf_count[1] = 0u;
+}
+
+__global__ void k_zero_f4(float4* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+int pending_status(mpm_handle* h, Status* out) {
+  Status st;
+  HIP_OR_RETURN(h, hipMemcpy(&st, h->b.status, sizeof(Status), hipMemcpyDeviceToHost));
+  if (out) *out = st;
+  if (st.n_nonfinite) return fail(h, MPM_ENONFINITE, "non-finite particle state");
+  if (st.n_domain) return fail(h, MPM_EDOMAIN, "a particle stencil left the grid");
+  if (st.n_inverted) return fail(h, MPM_EINVERTED, "det F <= 0 in the stress evaluation");
+  return MPM_OK;
+}
+
+int sync(mpm_handle* h) {
+  HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));
+  HIP_OR_RETURN(h, hipGetLastError());
+  return MPM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
+  g_create_error.clear();
+  if (!out) {
+    g_create_error = "out is NULL";
+    return MPM_EINVAL;
+  }
+  *out = nullptr;
+  if (!p) {
+    g_create_error = "params is NULL";
+    return MPM_EINVAL;
+  }
+  if (p->n_grid < 8 || p->n_grid > 1024 || !(p->dt > 0.0f) || !std::isfinite(p->dt) ||
+      !(p->nu >= 0.0f && p->nu < 0.5f) || !(p->E_default >= 0.0f) || !std::isfinite(p->E_default) ||
+      p->wall_band < 0 || p->wall_band > p->n_grid / 2 ||
+      !(p->accum_mode == MPM_ACCUM_F32) || !(p->tile == 0 || p->tile == kTile) ||
+      p->resort_interval < 0 || p->max_particles < 0 || p->max_particles > 0x7fffffffLL ||
+      !std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2])) {
+    g_create_error = "parameter out of range";
+    return MPM_EINVAL;
+  }
+  mpm_handle* h = new (std::nothrow) mpm_handle();
+  if (!h) {
+    g_create_error = "host allocation failed";
+    return MPM_ENOMEM;
+  }
+  h->p = *p;
+  if (h->p.tile == 0) h->p.tile = kTile;
+  h->resort_interval = p->resort_interval > 0 ? p->resort_interval : kDefaultResort;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    delete h;
+    return MPM_EHIP;
+  }
+  if (hip_stream) {
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    e = hipStreamCreate(&h->stream);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+      delete h;
+      return MPM_EHIP;
+    }
+    h->own_stream = true;
+  }
+  const int n = p->n_grid;
+  h->nb = (n + kTile - 1) / kTile;
+  h->n_blocks = (uint32_t)h->nb * h->nb * h->nb;
+  int bits = 1;
+  while ((1u << bits) < h->n_blocks + 1u) ++bits;
+  h->key_bits = bits;
+  // Persistent transfer grid: two workgroups per CU (LDS bound), a multiple of 8.
+  int wgs = 2 * h->cus;
+  wgs = (wgs + 7) / 8 * 8;
+  h->transfer_wgs = wgs;
+
+  const int64_t cap = p->max_particles > 0 ? p->max_particles : 1;
+  Buffers& b = h->b;
+  b.cap = cap;
+  const int64_t n_tiles = (cap + 4095) / 4096;
+  const int64_t hist_n = 256 * n_tiles;
+  const int64_t scan_part = (std::max<int64_t>(hist_n, h->n_blocks) + 2047) / 2048 + 1;
+  const size_t grid_nodes = (size_t)h->n_blocks * kBlockNodes;
+  bool ok = true;
+  auto alloc = [&](void** ptr, size_t bytes) {
+    if (!ok) return;
+    if (hipMalloc(ptr, bytes) != hipSuccess) ok = false;
+  };
+  for (int i = 0; i < 2; ++i) {
+    alloc((void**)&b.part[i], sizeof(float) * kFields * cap);
+    alloc((void**)&b.id[i], sizeof(uint32_t) * cap);
+    alloc((void**)&b.keys[i], sizeof(uint32_t) * cap);
+    alloc((void**)&b.vals[i], sizeof(uint32_t) * cap);
+    alloc((void**)&b.ovf_list[i], sizeof(uint32_t) * h->n_blocks);
+  }
+  alloc((void**)&b.hist, sizeof(uint32_t) * hist_n);
+  alloc((void**)&b.scan_tmp, sizeof(uint32_t) * scan_part);
+  alloc((void**)&b.blk_begin, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.blk_end, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.flags, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.occ_list, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.acc, sizeof(float4) * grid_nodes);
+  alloc((void**)&b.vel, sizeof(float4) * grid_nodes);
+  alloc((void**)&b.status, sizeof(Status));
+  if (!ok) {
+    free_buffers(b);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    g_create_error = "device allocation failed";
+    return MPM_ENOMEM;
+  }
+  // The accumulator must start (and stay, outside a substep) at zero.
+  hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.acc, (int64_t)grid_nodes);
+  hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
+  e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_create_error = std::string("initialisation: ") + hipGetErrorString(e);
+    free_buffers(b);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return MPM_EHIP;
+  }
+  // Scene constants.
+  SimK& s = h->sim;
+  s.n = n;
+  s.nb = h->nb;
+  s.dx = (float)(1.0 / n);
+  s.inv_dx = (float)n;
+  s.dt = p->dt;
+  s.band = p->wall_band;
+  s.E_default = p->E_default;
+  const double nu = p->nu;
+  s.c_mu = (float)(1.0 / (2.0 * (1.0 + nu)));
+  s.c_la = (float)(nu / ((1.0 + nu) * (1.0 - 2.0 * nu)));
+  for (int a = 0; a < 3; ++a) s.g[a] = p->gravity[a];
+  *out = h;
+  return MPM_OK;
+}
+
+int mpm_destroy(mpm_handle* h) {
+  if (!h) return MPM_OK;
+  int rc = MPM_OK;
+  if (select_device(h) == hipSuccess && hipStreamSynchronize(h->stream) == hipSuccess) {
+    rc = pending_status(h, nullptr);
+  } else {
+    rc = MPM_EHIP;
+  }
+  for (auto& pe : h->prof_pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  for (auto e : h->prof_pool) (void)hipEventDestroy(e);
+  free_buffers(h->b);
+  if (h->own_stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return rc;
+}
+
+int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v, const float* C,
+                      const float* F, const float* E, float mass, float vol0, int32_t where) {
+  if (!h) return MPM_EINVAL;
+  if (n < 0 || n > h->b.cap || (n > 0 && !x) || !(mass > 0.0f) || !(vol0 > 0.0f) ||
+      !std::isfinite(mass) || !std::isfinite(vol0) || (where != MPM_HOST && where != MPM_DEVICE))
+    return fail(h, MPM_EINVAL, "mpm_set_particles: argument out of range");
+  HIP_OR_RETURN(h, select_device(h));
+  Buffers& b = h->b;
+  const float* dx = x;
+  const float* dv = v;
+  const float* dC = C;
+  const float* dF = F;
+  const float* dE = E;
+  if (where == MPM_HOST && n > 0) {
+    // Stage the AoS inputs in the idle half of the particle ping-pong.
+    float* stg = b.part[b.cur ^ 1];
+    float* sx = stg;
+    float* sv = stg + 3 * n;
+    float* sC = stg + 6 * n;
+    float* sF = stg + 15 * n;
+    float* sE = stg + 24 * n;
+    HIP_OR_RETURN(h, hipMemcpyAsync(sx, x, sizeof(float) * 3 * n, hipMemcpyHostToDevice, h->stream));
+    if (v) HIP_OR_RETURN(h, hipMemcpyAsync(sv, v, sizeof(float) * 3 * n, hipMemcpyHostToDevice, h->stream));
+    if (C) HIP_OR_RETURN(h, hipMemcpyAsync(sC, C, sizeof(float) * 9 * n, hipMemcpyHostToDevice, h->stream));
+    if (F) HIP_OR_RETURN(h, hipMemcpyAsync(sF, F, sizeof(float) * 9 * n, hipMemcpyHostToDevice, h->stream));
+    if (E) HIP_OR_RETURN(h, hipMemcpyAsync(sE, E, sizeof(float) * n, hipMemcpyHostToDevice, h->stream));
+    dx = sx;
+    dv = v ? sv : nullptr;
+    dC = C ? sC : nullptr;
+    dF = F ? sF : nullptr;
+    dE = E ? sE : nullptr;
+  }
+  launch_load_particles(b, n, dx, dv, dC, dF, dE, h->stream);
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
+  HIP_OR_RETURN(h, hipGetLastError());
+  if (where == MPM_HOST && n > 0) HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));
+  h->N = n;
+  h->has_E = (E != nullptr);
+  h->mass = mass;
+  h->vol0 = vol0;
+  h->sim.mass = mass;
+  h->sim.has_E = h->has_E ? 1 : 0;
+  h->sim.p2g_stress = (float)((double)h->p.dt * (double)vol0 * 4.0 * (double)h->p.n_grid * (double)h->p.n_grid);
+  h->since_sort = 0;
+  h->dirty = true;
+  h->err.clear();
+  return MPM_OK;
+}
+
+int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t) {
+  if (!h) return MPM_EINVAL;
+  if (tool_id < 0 || tool_id >= kMaxTools || !t) return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: bad id");
+  HostTool& ht = h->tools[tool_id];
+  if (t->type == MPM_TOOL_NONE) {
+    ht.active = false;
+    return MPM_OK;
+  }
+  if (t->type < MPM_TOOL_CAPSULE || t->type > MPM_TOOL_PLANE)
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: bad type");
+  bool fin = std::isfinite(t->mu) && std::isfinite(t->drag) && std::isfinite(t->margin);
+  for (int a = 0; a < 3; ++a)
+    fin = fin && std::isfinite(t->center[a]) && std::isfinite(t->size[a]) && std::isfinite(t->lin_vel[a]) &&
+          std::isfinite(t->ang_vel[a]);
+  double qn = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    fin = fin && std::isfinite(t->quat[a]);
+    qn += t->quat[a] * t->quat[a];
+  }
+  if (!fin || !(qn > 0.0) || t->mu < 0.0f || t->drag < 0.0f || t->drag > 1.0f)
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: value out of range");
+  if (t->type == MPM_TOOL_CAPSULE && (!(t->size[0] >= 0.0) || !(t->size[1] > 0.0)))
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: capsule needs half_length >= 0, radius > 0");
+  if (t->type == MPM_TOOL_BOX && (!(t->size[0] > 0.0) || !(t->size[1] > 0.0) || !(t->size[2] > 0.0)))
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: box needs positive half extents");
+  ht.t = *t;
+  ht.set_at = h->substep;
+  quat_to_R(t->quat, ht.R);
+  ht.active = true;
+  return MPM_OK;
+}
+
+int mpm_step(mpm_handle* h, int32_t n_substeps) {
+  if (!h) return MPM_EINVAL;
+  if (n_substeps < 0) return fail(h, MPM_EINVAL, "mpm_step: n_substeps < 0");
+  if (n_substeps == 0) return MPM_OK;
+  if (h->N == 0) {
+    h->substep += n_substeps;
+    return MPM_OK;
+  }
+  HIP_OR_RETURN(h, select_device(h));
+  Buffers& b = h->b;
+  const int64_t N = h->N;
+  const int wgs = h->transfer_wgs;
+  for (int k = 0; k < n_substeps; ++k) {
+    const int parity = (int)(h->substep & 1);
+    const bool rebin = h->dirty || h->since_sort >= h->resort_interval;
+    if (k == 0 || rebin) {
+      if (k > 0) {
+        ProfScope ps(h, 3);
+        launch_g2p(b, N, h->sim, wgs, h->stream);
+      }
+      if (rebin) {
+        ProfScope ps(h, 0);
+        launch_binning(b, N, h->sim, h->key_bits, h->stream);
+        h->dirty = false;
+        h->since_sort = 0;
+        h->resorts++;
+      }
+      ProfScope ps(h, 1);
+      launch_p2g(b, N, h->sim, parity, wgs, h->stream);
+    } else {
+      ProfScope ps(h, 2);
+      launch_g2p2g(b, N, h->sim, parity, wgs, h->stream);
+    }
+    {
+      ProfScope ps(h, 4);
+      launch_grid(b, h->sim, tools_at(h, h->substep), parity, (int)h->n_blocks, h->stream);
+    }
+    h->substep++;
+    h->since_sort++;
+  }
+  {
+    ProfScope ps(h, 3);
+    launch_g2p(b, N, h->sim, wgs, h->stream);
+  }
+  HIP_OR_RETURN(h, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_read_state(mpm_handle* h, float* x, float* v, float* C, float* F, int32_t where) {
+  if (!h) return MPM_EINVAL;
+  if (where != MPM_HOST && where != MPM_DEVICE) return fail(h, MPM_EINVAL, "mpm_read_state: bad where");
+  HIP_OR_RETURN(h, select_device(h));
+  const int64_t N = h->N;
+  Buffers& b = h->b;
+  if (N > 0 && (x || v || C || F)) {
+    if (where == MPM_DEVICE) {
+      launch_unpermute(b, N, x, v, C, F, h->stream);
+    } else {
+      float* stg = b.part[b.cur ^ 1];
+      float* sx = stg;
+      float* sv = stg + 3 * N;
+      float* sC = stg + 6 * N;
+      float* sF = stg + 15 * N;
+      launch_unpermute(b, N, x ? sx : nullptr, v ? sv : nullptr, C ? sC : nullptr, F ? sF : nullptr,
+                       h->stream);
+      if (x) HIP_OR_RETURN(h, hipMemcpyAsync(x, sx, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, h->stream));
+      if (v) HIP_OR_RETURN(h, hipMemcpyAsync(v, sv, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, h->stream));
+      if (C) HIP_OR_RETURN(h, hipMemcpyAsync(C, sC, sizeof(float) * 9 * N, hipMemcpyDeviceToHost, h->stream));
+      if (F) HIP_OR_RETURN(h, hipMemcpyAsync(F, sF, sizeof(float) * 9 * N, hipMemcpyDeviceToHost, h->stream));
+    }
+  }
+  int rc = sync(h);
+  if (rc != MPM_OK) return rc;
+  return pending_status(h, nullptr);
+}
+
+int mpm_get_info(mpm_handle* h, mpm_info* info) {
+  if (!h || !info) return fail(h, MPM_EINVAL, "mpm_get_info: NULL");
+  HIP_OR_RETURN(h, select_device(h));
+  int rc = sync(h);
+  if (rc != MPM_OK) return rc;
+  Status st;
+  HIP_OR_RETURN(h, hipMemcpy(&st, h->b.status, sizeof(Status), hipMemcpyDeviceToHost));
+  std::memset(info, 0, sizeof(*info));
+  info->n_particles = h->N;
+  info->substeps = h->substep;
+  info->resorts = h->resorts;
+  info->occupied_blocks = st.n_occ;
+  info->active_blocks = st.n_act;
+  info->active_nodes = h->substep > 0 ? (int64_t)st.active_nodes[(h->substep - 1) & 1] : 0;
+  info->n_inverted = (int64_t)st.n_inverted;
+  info->n_domain = (int64_t)st.n_domain;
+  info->n_nonfinite = (int64_t)st.n_nonfinite;
+  info->n_fallback = (int64_t)st.n_fallback;
+  info->tile = kTile;
+  info->resort_interval = h->resort_interval;
+  info->accum_mode = h->p.accum_mode;
+  int nt = 0;
+  for (int i = 0; i < kMaxTools; ++i)
+    if (h->tools[i].active) nt++;
+  info->n_tools = nt;
+  return MPM_OK;
+}
+
+const char* mpm_last_error(const mpm_handle* h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+int mpm_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau, int32_t where) {
+  if (n < 0 || (n > 0 && (!F || !E || !tau)) || !(nu >= 0.0f && nu < 0.5f) ||
+      (where != MPM_HOST && where != MPM_DEVICE))
+    return MPM_EINVAL;
+  if (n == 0) return MPM_OK;
+  if (where == MPM_DEVICE) {
+    launch_eval_stress(n, F, E, nu, tau, nullptr);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? MPM_OK : MPM_EHIP;
+  }
+  float *dF = nullptr, *dE = nullptr, *dT = nullptr;
+  if (hipMalloc((void**)&dF, sizeof(float) * 9 * n) != hipSuccess ||
+      hipMalloc((void**)&dE, sizeof(float) * n) != hipSuccess ||
+      hipMalloc((void**)&dT, sizeof(float) * 9 * n) != hipSuccess) {
+    (void)hipFree(dF);
+    (void)hipFree(dE);
+    (void)hipFree(dT);
+    return MPM_ENOMEM;
+  }
+  hipError_t e = hipMemcpy(dF, F, sizeof(float) * 9 * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dE, E, sizeof(float) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_eval_stress(n, dF, dE, nu, dT, nullptr);
+    e = hipDeviceSynchronize();
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(tau, dT, sizeof(float) * 9 * n, hipMemcpyDeviceToHost);
+  (void)hipFree(dF);
+  (void)hipFree(dE);
+  (void)hipFree(dT);
+  return e == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
+int mpm_profile(mpm_handle* h, int32_t enable) {
+  if (!h) return MPM_EINVAL;
+  if (enable) {
+    HIP_OR_RETURN(h, select_device(h));
+    int rc = sync(h);
+    if (rc != MPM_OK) return rc;
+    prof_collect(h);
+    for (int k = 0; k < MPM_KERNEL_KINDS; ++k) {
+      h->prof_ms[k] = 0.0;
+      h->prof_n[k] = 0;
+    }
+  }
+  h->prof = enable != 0;
+  return MPM_OK;
+}
+
+int mpm_profile_read(mpm_handle* h, mpm_kernel_times* out) {
+  if (!h || !out) return fail(h, MPM_EINVAL, "mpm_profile_read: NULL");
+  HIP_OR_RETURN(h, select_device(h));
+  int rc = sync(h);
+  if (rc != MPM_OK) return rc;
+  prof_collect(h);
+  for (int k = 0; k < MPM_KERNEL_KINDS; ++k) {
+    out->total_ms[k] = h->prof_ms[k];
+    out->launches[k] = h->prof_n[k];
+  }
+  return MPM_OK;
+}
+
+}  // extern "C"

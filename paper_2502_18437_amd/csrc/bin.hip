@@ -1,0 +1,413 @@
+// Particle binning for the block-tiled transfers (not a step of the paper's
+// method; it orders the work so that each grid block's particles are
+// contiguous): key = grid block of the particle's base cell, a stable LSD
+// radix sort of (key, index) with 8-bit digits, a gather of the particle SoA
+// into key order, per-block [begin, end) ranges, the list of occupied blocks
+// and the list of active blocks (occupied blocks dilated by one block in every
+// direction: the blocks a tile can touch). Also the host<->SoA marshalling
+// kernels and the diagnostic stress kernel.
+//
+// Every buffer is cleared with fill kernels (no memset nodes), so the whole
+// pipeline can be captured in a HIP graph.
+#include "mpm_device.h"
+#include "mpm_internal.h"
+
+namespace mpm {
+
+constexpr int kSortWG = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortWG * kSortItems;  // keys per workgroup
+constexpr int kRadix = 256;
+constexpr int kScanWG = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanWG * kScanItems;
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return;
+  int64_t wgs = (n + 255) / 256;
+  if (wgs > 4096) wgs = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)wgs), dim3(256), 0, st, p, n, v);
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive prefix sum of a u32 array, three passes: per-tile sums, a scan of
+// the tile sums in one workgroup, then per-tile scans offset by it.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  // Hillis-Steele over kScanWG thread values in LDS.
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanWG; off <<= 1) {
+    const uint32_t add = (t >= off) ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const uint32_t incl = sh[t];
+  *total = sh[kScanWG - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kScanWG) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                         uint32_t* __restrict__ partial) {
+  __shared__ uint32_t sh[kScanWG];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t s = 0;
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) s += in[base + k];
+  uint32_t total;
+  block_exclusive_scan(s, sh, &total);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanWG) void k_scan_partials(uint32_t* partial, int n_part,
+                                                           uint32_t* total_out) {
+  __shared__ uint32_t sh[kScanWG];
+  const int per = (n_part + kScanWG - 1) / kScanWG;
+  const int lo = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int k = 0; k < per; ++k)
+    if (lo + k < n_part) s += partial[lo + k];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, sh, &total);
+  for (int k = 0; k < per; ++k)
+    if (lo + k < n_part) {
+      const uint32_t x = partial[lo + k];
+      partial[lo + k] = run;
+      run += x;
+    }
+  if (threadIdx.x == 0 && total_out) *total_out = total;
+}
+
+__global__ __launch_bounds__(kScanWG) void k_scan_down(const uint32_t* __restrict__ in, int64_t n,
+                                                       const uint32_t* __restrict__ partial,
+                                                       uint32_t* __restrict__ out) {
+  __shared__ uint32_t sh[kScanWG];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t vals[kScanItems];
+  uint32_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    vals[k] = (base + k < n) ? in[base + k] : 0u;
+    s += vals[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, sh, &total) + partial[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) {
+      out[base + k] = run;
+      run += vals[k];
+    }
+}
+
+// out may alias in. partial needs ceil(n / kScanTile) entries.
+static void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partial,
+                           uint32_t* total_out, hipStream_t st) {
+  const int n_part = (int)((n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(n_part), dim3(kScanWG), 0, st, in, n, partial);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanWG), 0, st, partial, n_part, total_out);
+  hipLaunchKernelGGL(k_scan_down, dim3(n_part), dim3(kScanWG), 0, st, in, n, partial, out);
+}
+
+// ------------------------------------------------------------------ keys
+__global__ void k_keygen(const float* __restrict__ part, int64_t cap, int64_t N, SimK s,
+                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t sentinel,
+                         Status* st) {
+  unsigned dom = 0, nf = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t key = sentinel;
+    int cell[3];
+    bool ok = true, fin = true;
+    for (int a = 0; a < 3; ++a) {
+      const float r = part[(FX + a) * cap + i] * s.inv_dx;
+      fin = fin && isfinite(r);
+      const float b = floorf(r - 0.5f);
+      ok = ok && (b >= 0.0f) && (b + 2.0f <= (float)(s.n - 1));
+      cell[a] = ok ? (int)b : 0;
+    }
+    if (ok && fin) {
+      key = (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb + (cell[0] >> kTileLog2));
+    } else if (!fin) {
+      nf++;
+    } else {
+      dom++;
+    }
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+  }
+  if (dom) atomicAdd(&st->n_domain, (unsigned long long)dom);
+  if (nf) atomicAdd(&st->n_nonfinite, (unsigned long long)nf);
+}
+
+// ------------------------------------------------------------------ radix sort
+// Lanes of one wave whose digit equals this lane's (a match over 8 ballots).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const unsigned lane = threadIdx.x & 63u;
+  return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Per tile digit counts; hist is digit-major: hist[d * n_tiles + tile].
+__global__ __launch_bounds__(kSortWG) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t N,
+                                                        int shift, uint32_t* __restrict__ hist,
+                                                        int n_tiles) {
+  __shared__ uint32_t cnt[kSortWG / 64][kRadix];
+  const int wave = threadIdx.x >> 6;
+  for (int w = 0; w < kSortWG / 64; ++w) cnt[w][threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = tile0 + (int64_t)r * kSortWG + threadIdx.x;
+    const bool valid = i < N;
+    const uint32_t d = valid ? ((keys[i] >> shift) & (kRadix - 1)) : 0u;
+    const uint64_t peers = match_digit(d, valid);
+    if (valid && (peers & lanemask_lt()) == 0ull) cnt[wave][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  uint32_t s = 0;
+  for (int w = 0; w < kSortWG / 64; ++w) s += cnt[w][threadIdx.x];
+  hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = s;
+}
+
+// Stable scatter of a tile: keys keep their order within a digit.
+__global__ __launch_bounds__(kSortWG) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin,
+                                                           uint32_t* __restrict__ kout,
+                                                           uint32_t* __restrict__ vout, int64_t N,
+                                                           int shift, const uint32_t* __restrict__ offs,
+                                                           int n_tiles) {
+  __shared__ uint32_t run[kRadix];
+  __shared__ uint32_t wcnt[kSortWG / 64][kRadix];
+  const int wave = threadIdx.x >> 6;
+  run[threadIdx.x] = offs[(int64_t)threadIdx.x * n_tiles + blockIdx.x];
+  for (int w = 0; w < kSortWG / 64; ++w) wcnt[w][threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = tile0 + (int64_t)r * kSortWG + threadIdx.x;
+    const bool valid = i < N;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t v = valid ? vin[i] : 0u;
+    const uint32_t d = (k >> shift) & (kRadix - 1);
+    const uint64_t peers = match_digit(d, valid);
+    const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+    if (valid && rank == 0u) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kSortWG / 64; ++w) {
+      add += wcnt[w][threadIdx.x];
+      wcnt[w][threadIdx.x] = 0u;
+    }
+    run[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ permutation, ranges
+__global__ void k_permute(const float* __restrict__ src, float* __restrict__ dst,
+                          const uint32_t* __restrict__ id_src, uint32_t* __restrict__ id_dst,
+                          const uint32_t* __restrict__ perm, int64_t cap, int64_t N, int n_fields) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = perm[i];
+    for (int f = 0; f < n_fields; ++f) dst[f * cap + i] = src[f * cap + j];
+    id_dst[i] = id_src[j];
+  }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t N, uint32_t n_blocks,
+                         uint32_t* __restrict__ begin, uint32_t* __restrict__ end) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (k >= n_blocks) continue;
+    if (i == 0 || keys[i - 1] != k) begin[k] = (uint32_t)i;
+    if (i == N - 1 || keys[i + 1] != k) end[k] = (uint32_t)(i + 1);
+  }
+}
+
+__global__ void k_flag_occupied(const uint32_t* __restrict__ begin, const uint32_t* __restrict__ end,
+                                uint32_t n_blocks, uint32_t* __restrict__ flags) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x)
+    flags[b] = end[b] > begin[b] ? 1u : 0u;
+}
+
+__global__ void k_mark_dilated(const uint32_t* __restrict__ begin, const uint32_t* __restrict__ end,
+                               int nb, uint32_t* __restrict__ mark) {
+  const uint32_t n_blocks = (uint32_t)nb * nb * nb;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x) {
+    if (!(end[b] > begin[b])) continue;
+    const int bi = b % nb, bj = (b / nb) % nb, bk = b / (nb * nb);
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const int i = bi + di, j = bj + dj, k = bk + dk;
+          if (i < 0 || j < 0 || k < 0 || i >= nb || j >= nb || k >= nb) continue;
+          mark[(k * nb + j) * nb + i] = 1u;
+        }
+  }
+}
+
+__global__ void k_flag_marked(const uint32_t* __restrict__ mark, uint32_t n_blocks,
+                              uint32_t* __restrict__ flags) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x)
+    flags[b] = mark[b] == 1u ? 1u : 0u;
+}
+
+// list[pos[b]] = b for flagged blocks; flags and pos may not alias.
+__global__ void k_compact(const uint32_t* __restrict__ mark_or_range_b,
+                          const uint32_t* __restrict__ range_e, const uint32_t* __restrict__ pos,
+                          uint32_t n_blocks, int mode, uint32_t* __restrict__ list) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x) {
+    const bool take = (mode == 0) ? (range_e[b] > mark_or_range_b[b]) : (mark_or_range_b[b] == 1u);
+    if (take) list[pos[b]] = b;
+  }
+}
+
+__global__ void k_reset_epoch(Status* st) {
+  st->ovf_count[0] = 0u;
+  st->ovf_count[1] = 0u;
+}
+
+static unsigned grid_for(int64_t n, int wg) {
+  int64_t g = (n + wg - 1) / wg;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st) {
+  const uint32_t n_blocks = (uint32_t)s.nb * s.nb * s.nb;
+  const uint32_t sentinel = n_blocks;
+  // 1. keys
+  hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.cap, N, s,
+                     b.keys[0], b.vals[0], sentinel, b.status);
+  // 2. stable LSD radix sort, 8 bits per pass
+  int src = 0;
+  if (N > 0) {
+    const int n_tiles = (int)((N + kSortTile - 1) / kSortTile);
+    for (int shift = 0; shift < key_bits; shift += 8) {
+      hipLaunchKernelGGL(k_radix_hist, dim3(n_tiles), dim3(kSortWG), 0, st, b.keys[src], N, shift,
+                         b.hist, n_tiles);
+      exclusive_scan(b.hist, b.hist, (int64_t)kRadix * n_tiles, b.scan_tmp, nullptr, st);
+      hipLaunchKernelGGL(k_radix_scatter, dim3(n_tiles), dim3(kSortWG), 0, st, b.keys[src], b.vals[src],
+                         b.keys[src ^ 1], b.vals[src ^ 1], N, shift, b.hist, n_tiles);
+      src ^= 1;
+    }
+  }
+  // 3. gather the particle state into key order
+  const int n_fields = s.has_E ? kFields : kFields - 1;
+  hipLaunchKernelGGL(k_permute, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.part[b.cur ^ 1],
+                     b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N, n_fields);
+  b.cur ^= 1;
+  // 4. per-block ranges
+  fill_u32(b.blk_begin, n_blocks, 0u, st);
+  fill_u32(b.blk_end, n_blocks, 0u, st);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks,
+                     b.blk_begin, b.blk_end);
+  // 5. occupied list (ascending block id: spatially ordered, x fastest)
+  hipLaunchKernelGGL(k_flag_occupied, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,
+                     b.blk_end, n_blocks, b.flags);
+  exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_occ, st);
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     b.flags, n_blocks, 0, b.occ_list);
+  // 6. active list: occupied blocks dilated by one block
+  fill_u32(b.mark, n_blocks, 0u, st);
+  hipLaunchKernelGGL(k_mark_dilated, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,
+                     b.blk_end, s.nb, b.mark);
+  hipLaunchKernelGGL(k_flag_marked, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.mark, n_blocks,
+                     b.flags);
+  exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_act, st);
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.mark, nullptr,
+                     b.flags, n_blocks, 1, b.act_list);
+  hipLaunchKernelGGL(k_reset_epoch, dim3(1), dim3(1), 0, st, b.status);
+}
+
+// ------------------------------------------------------------------ marshalling
+__global__ void k_load(float* __restrict__ part, uint32_t* __restrict__ id, int64_t cap, int64_t N,
+                       const float* __restrict__ x, const float* __restrict__ v,
+                       const float* __restrict__ C, const float* __restrict__ F,
+                       const float* __restrict__ E) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int a = 0; a < 3; ++a) {
+      part[(FX + a) * cap + i] = x[3 * i + a];
+      part[(FV + a) * cap + i] = v ? v[3 * i + a] : 0.0f;
+    }
+    for (int k = 0; k < 9; ++k) {
+      part[(FC + k) * cap + i] = C ? C[9 * i + k] : 0.0f;
+      part[(FF + k) * cap + i] = F ? F[9 * i + k] : ((k % 4 == 0) ? 1.0f : 0.0f);
+    }
+    if (E) part[FE * cap + i] = E[i];
+    id[i] = (uint32_t)i;
+  }
+}
+
+void launch_load_particles(Buffers& b, int64_t N, const float* x, const float* v, const float* C,
+                           const float* F, const float* E, hipStream_t st) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_load, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur], b.cap, N,
+                     x, v, C, F, E);
+}
+
+__global__ void k_unpermute(const float* __restrict__ part, const uint32_t* __restrict__ id, int64_t cap,
+                            int64_t N, float* __restrict__ x, float* __restrict__ v,
+                            float* __restrict__ C, float* __restrict__ F) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = id[i];
+    for (int a = 0; a < 3; ++a) {
+      if (x) x[3 * o + a] = part[(FX + a) * cap + i];
+      if (v) v[3 * o + a] = part[(FV + a) * cap + i];
+    }
+    for (int k = 0; k < 9; ++k) {
+      if (C) C[9 * o + k] = part[(FC + k) * cap + i];
+      if (F) F[9 * o + k] = part[(FF + k) * cap + i];
+    }
+  }
+}
+
+void launch_unpermute(const Buffers& b, int64_t N, float* x, float* v, float* C, float* F, hipStream_t st) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_unpermute, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur], b.cap,
+                     N, x, v, C, F);
+}
+
+__global__ void k_eval_stress(int64_t n, const float* __restrict__ F, const float* __restrict__ E,
+                              float c_mu, float c_la, float* __restrict__ tau) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float f[9], t[9];
+    for (int k = 0; k < 9; ++k) f[k] = F[9 * i + k];
+    bool inv;
+    kirchhoff(f, c_mu * E[i], c_la * E[i], t, &inv);
+    for (int k = 0; k < 9; ++k) tau[9 * i + k] = t[k];
+  }
+}
+
+void launch_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau, hipStream_t st) {
+  if (n <= 0) return;
+  const double dnu = nu;
+  const float c_mu = (float)(1.0 / (2.0 * (1.0 + dnu)));
+  const float c_la = (float)(dnu / ((1.0 + dnu) * (1.0 - 2.0 * dnu)));
+  hipLaunchKernelGGL(k_eval_stress, dim3(grid_for(n, 256)), dim3(256), 0, st, n, F, E, c_mu, c_la, tau);
+}
+
+}  // namespace mpm

@@ -1,0 +1,78 @@
+// Grid update of the explicit MLS-MPM substep (CRESSim-MPM Algorithm 1, second
+// loop): for every node with mass, v = (m v)/m + dt g (Sec. III-A, eq.
+// mls_mpm_grid), then the SDF contact of each tool in id order (Sec. IV-A,
+// eq. v_correction), then sticky walls (Sec. III-A, boundary conditions by
+// altering the momentum). Empty nodes get v = 0. The kernel also clears the
+// accumulator it has read, which is the grid reset of Algorithm 1 for the next
+// substep.
+//
+// Work list: the active blocks of the current binning, then the overflow
+// blocks claimed by particles that drifted out of their tile in this substep.
+// The tool poses arrive as kernel arguments (they live in SGPRs).
+#include "mpm_device.h"
+#include "mpm_internal.h"
+
+namespace mpm {
+
+constexpr int kGridWG = 256;
+
+__global__ __launch_bounds__(kGridWG) void k_grid(float4* __restrict__ acc, float4* __restrict__ vel,
+                                                  const uint32_t* __restrict__ act_list,
+                                                  const uint32_t* __restrict__ ovf_list,
+                                                  uint32_t* mark, Status* st, int parity, SimK s,
+                                                  ToolSetK tools) {
+  const unsigned n_act = st->n_act;
+  const unsigned total = n_act + st->ovf_count[parity];
+  unsigned cnt = 0;
+  const int lo = s.band, hi = s.n - 1 - s.band;
+  for (unsigned li = blockIdx.x; li < total; li += gridDim.x) {
+    const bool overflow = li >= n_act;
+    const unsigned b = overflow ? ovf_list[li - n_act] : act_list[li];
+    const int bi = (int)(b % (unsigned)s.nb);
+    const int bj = (int)((b / (unsigned)s.nb) % (unsigned)s.nb);
+    const int bk = (int)(b / ((unsigned)s.nb * (unsigned)s.nb));
+    for (int l = threadIdx.x; l < kBlockNodes; l += kGridWG) {
+      const size_t g = ((size_t)b << (3 * kTileLog2)) + (size_t)l;
+      const float4 a = acc[g];
+      float v[3] = {0.0f, 0.0f, 0.0f};
+      if (a.x > 0.0f) {
+        cnt++;
+        const float im = 1.0f / a.x;
+        v[0] = a.y * im + s.dt * s.g[0];
+        v[1] = a.z * im + s.dt * s.g[1];
+        v[2] = a.w * im + s.dt * s.g[2];
+        const int i = bi * kTile + (l & (kTile - 1));
+        const int j = bj * kTile + ((l >> kTileLog2) & (kTile - 1));
+        const int k = bk * kTile + (l >> (2 * kTileLog2));
+        const float xI[3] = {(float)i * s.dx, (float)j * s.dx, (float)k * s.dx};
+        for (int q = 0; q < tools.n; ++q)
+          if (tools.t[q].type != TOOL_NONE) tool_contact(tools.t[q], xI, v);
+        if (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi) v[0] = v[1] = v[2] = 0.0f;
+      }
+      vel[g] = make_float4(v[0], v[1], v[2], 0.0f);
+      acc[g] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    if (overflow && threadIdx.x == 0) mark[b] = 0u;
+  }
+  // Clear the other parity's overflow list for the next substep; count nodes.
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->ovf_count[parity ^ 1] = 0u;
+    st->active_nodes[parity ^ 1] = 0ull;
+  }
+  __shared__ unsigned wg_cnt;
+  if (threadIdx.x == 0) wg_cnt = 0u;
+  __syncthreads();
+  if (cnt) atomicAdd(&wg_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0 && wg_cnt) atomicAdd(&st->active_nodes[parity], (unsigned long long)wg_cnt);
+}
+
+void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
+                 hipStream_t st) {
+  int wgs = max_act < 4096 ? max_act : 4096;
+  if (wgs < 1) wgs = 1;
+  hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc, b.vel, b.act_list,
+                     b.ovf_list[parity], b.mark, b.status, parity, s, tools);
+}
+
+}  // namespace mpm

@@ -1,0 +1,256 @@
+// Device-side per-particle and per-node arithmetic of the MLS-MPM substep
+// (FP32): quadratic B-spline weights, polar decomposition, fixed-corotated
+// Kirchhoff stress, tool SDFs and the contact law.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mpm_internal.h"
+
+namespace mpm {
+
+// Quadratic B-spline weights of the nodes base, base+1, base+2 along one
+// axis, f = x/dx - base in [0.5, 1.5) (Sec. III-A: 3 nodes per dimension).
+__device__ __forceinline__ void bspline_w(float f, float w[3]) {
+  const float a = 1.5f - f, b = f - 1.0f, c = f - 0.5f;
+  w[0] = 0.5f * a * a;
+  w[1] = 0.75f - b * b;
+  w[2] = 0.5f * c * c;
+}
+
+__device__ __forceinline__ float det3(const float* X) {
+  return X[0] * (X[4] * X[8] - X[5] * X[7]) - X[1] * (X[3] * X[8] - X[5] * X[6]) +
+         X[2] * (X[3] * X[7] - X[4] * X[6]);
+}
+
+// Rotation factor of F (det F > 0) by Newton's iteration for the polar
+// decomposition, X <- (z X + X^-T / z) / 2, with the determinant scaling
+// z = |det X|^(-1/3) on the first two iterations (Higham 1986, "Computing
+// the polar decomposition -- with applications"; Byers & Xu 2008). The
+// iteration squares the distance of the stretch from I each step, so it
+// stops once an update is below 1e-4: the next error is then below FP32
+// round-off. Returns false if it did not converge.
+__device__ inline bool polar_newton(const float* F, float* R) {
+  float X[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) X[i] = F[i];
+  for (int it = 0; it < 16; ++it) {
+    float c[9];
+    c[0] = X[4] * X[8] - X[5] * X[7];
+    c[1] = X[5] * X[6] - X[3] * X[8];
+    c[2] = X[3] * X[7] - X[4] * X[6];
+    c[3] = X[2] * X[7] - X[1] * X[8];
+    c[4] = X[0] * X[8] - X[2] * X[6];
+    c[5] = X[1] * X[6] - X[0] * X[7];
+    c[6] = X[1] * X[5] - X[2] * X[4];
+    c[7] = X[2] * X[3] - X[0] * X[5];
+    c[8] = X[0] * X[4] - X[1] * X[3];
+    const float det = X[0] * c[0] + X[1] * c[1] + X[2] * c[2];
+    if (!(det > 0.0f)) return false;
+    const float z = (it < 2) ? rcbrtf(det) : 1.0f;
+    const float a = 0.5f * z;
+    const float b = 0.5f / (z * det);
+    float delta = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float xn = a * X[i] + b * c[i];
+      delta = fmaxf(delta, fabsf(xn - X[i]));
+      X[i] = xn;
+    }
+    if (delta < 1e-4f) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R[i] = X[i];
+      return true;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = X[i];
+  return false;
+}
+
+// Rotation of the sign-fixed SVD F = U diag(s0, s1, +-s2) V^T (U, V
+// rotations; Irving et al. 2004), from a cyclic Jacobi eigen-decomposition
+// of F^T F (Golub & Van Loan, Sec. 8.5). Used only when det F <= 0, where
+// Newton's iteration does not give a rotation.
+__device__ __noinline__ void polar_svd_signfix(const float* F, float* R) {
+  float A[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      A[3 * r + c] = F[r] * F[c] + F[3 + r] * F[3 + c] + F[6 + r] * F[6 + c];
+  for (int sweep = 0; sweep < 10; ++sweep) {
+    for (int pi = 0; pi < 3; ++pi) {
+      const int p = (pi == 2) ? 1 : 0;
+      const int q = (pi == 0) ? 1 : 2;
+      const float apq = A[3 * p + q];
+      if (fabsf(apq) < 1e-30f) continue;
+      const float th = (A[3 * q + q] - A[3 * p + p]) / (2.0f * apq);
+      const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(th * th + 1.0f));
+      const float c = rsqrtf(t * t + 1.0f), s = t * c;
+      for (int k = 0; k < 3; ++k) {  // columns p, q of A and V
+        const float akp = A[3 * k + p], akq = A[3 * k + q];
+        A[3 * k + p] = c * akp - s * akq;
+        A[3 * k + q] = s * akp + c * akq;
+        const float vkp = V[3 * k + p], vkq = V[3 * k + q];
+        V[3 * k + p] = c * vkp - s * vkq;
+        V[3 * k + q] = s * vkp + c * vkq;
+      }
+      for (int k = 0; k < 3; ++k) {  // rows p, q of A
+        const float apk = A[3 * p + k], aqk = A[3 * q + k];
+        A[3 * p + k] = c * apk - s * aqk;
+        A[3 * q + k] = s * apk + c * aqk;
+      }
+    }
+  }
+  float lam[3] = {A[0], A[4], A[8]};
+  int o[3] = {0, 1, 2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (lam[o[j]] > lam[o[i]]) {
+        const int t = o[i];
+        o[i] = o[j];
+        o[j] = t;
+      }
+  float v[3][3], u[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) v[i][k] = V[3 * k + o[i]];
+  const float dv = v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) -
+                   v[0][1] * (v[1][0] * v[2][2] - v[1][2] * v[2][0]) +
+                   v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
+  if (dv < 0.0f)
+    for (int k = 0; k < 3; ++k) v[2][k] = -v[2][k];
+  for (int i = 0; i < 2; ++i)
+    for (int r = 0; r < 3; ++r)
+      u[i][r] = F[3 * r] * v[i][0] + F[3 * r + 1] * v[i][1] + F[3 * r + 2] * v[i][2];
+  float n0 = sqrtf(u[0][0] * u[0][0] + u[0][1] * u[0][1] + u[0][2] * u[0][2]);
+  if (n0 > 0.0f) {
+    for (int r = 0; r < 3; ++r) u[0][r] /= n0;
+  } else {
+    u[0][0] = 1.0f, u[0][1] = 0.0f, u[0][2] = 0.0f;
+  }
+  const float d01 = u[0][0] * u[1][0] + u[0][1] * u[1][1] + u[0][2] * u[1][2];
+  for (int r = 0; r < 3; ++r) u[1][r] -= d01 * u[0][r];
+  float n1 = sqrtf(u[1][0] * u[1][0] + u[1][1] * u[1][1] + u[1][2] * u[1][2]);
+  if (n1 > 1e-30f) {
+    for (int r = 0; r < 3; ++r) u[1][r] /= n1;
+  } else {
+    float a[3] = {0.0f, 0.0f, 0.0f};
+    a[fabsf(u[0][0]) < 0.9f ? 0 : 1] = 1.0f;
+    const float d = a[0] * u[0][0] + a[1] * u[0][1] + a[2] * u[0][2];
+    for (int r = 0; r < 3; ++r) a[r] -= d * u[0][r];
+    const float na = sqrtf(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (int r = 0; r < 3; ++r) u[1][r] = a[r] / na;
+  }
+  u[2][0] = u[0][1] * u[1][2] - u[0][2] * u[1][1];
+  u[2][1] = u[0][2] * u[1][0] - u[0][0] * u[1][2];
+  u[2][2] = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) R[3 * r + c] = u[0][r] * v[0][c] + u[1][r] * v[1][c] + u[2][r] * v[2][c];
+}
+
+// Fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + la (J - 1) J I
+// (Stomakhin et al. 2012; the paper leaves the MLS-MPM constitutive law
+// open, Algorithm 1). Returns J = det F; *inverted is set when J <= 0.
+__device__ __forceinline__ float kirchhoff(const float* F, float mu, float la, float* tau,
+                                           bool* inverted) {
+  float R[9];
+  const float J = det3(F);
+  bool ok = (J > 0.0f) && polar_newton(F, R);
+  if (!ok) polar_svd_signfix(F, R);
+  *inverted = !(J > 0.0f);
+  float D[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) D[i] = 2.0f * mu * (F[i] - R[i]);
+  const float vol = la * (J - 1.0f) * J;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      tau[3 * r + c] = D[3 * r] * F[3 * c] + D[3 * r + 1] * F[3 * c + 1] + D[3 * r + 2] * F[3 * c + 2] +
+                       (r == c ? vol : 0.0f);
+  return J;
+}
+
+// Signed distance of a tool at world point p and its unit outward normal.
+// Capsule: segment along body x, size {half_length, radius}. Box: half
+// extents; inside, the normal of the nearest face (lowest axis on ties,
+// sign(0) = +1). Plane: body +y through the centre.
+__device__ __forceinline__ float tool_sdf(const ToolK& t, const float* p, float* n) {
+  const float d0 = p[0] - t.c[0], d1 = p[1] - t.c[1], d2 = p[2] - t.c[2];
+  float pl[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pl[i] = t.R[i] * d0 + t.R[3 + i] * d1 + t.R[6 + i] * d2;
+  float g[3] = {0.0f, 1.0f, 0.0f};
+  float phi = 0.0f;
+  if (t.type == TOOL_CAPSULE) {
+    const float h = t.size[0], r = t.size[1];
+    const float e0 = pl[0] - fminf(fmaxf(pl[0], -h), h);
+    const float L = sqrtf(e0 * e0 + pl[1] * pl[1] + pl[2] * pl[2]);
+    phi = L - r;
+    if (L > 0.0f) {
+      const float il = 1.0f / L;
+      g[0] = e0 * il, g[1] = pl[1] * il, g[2] = pl[2] * il;
+    }
+  } else if (t.type == TOOL_BOX) {
+    float q[3], o[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      q[i] = fabsf(pl[i]) - t.size[i];
+      o[i] = fmaxf(q[i], 0.0f);
+    }
+    const float L = sqrtf(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+    int k = 0;
+    float qm = q[0];
+    if (q[1] > qm) qm = q[1], k = 1;
+    if (q[2] > qm) qm = q[2], k = 2;
+    phi = L + fminf(qm, 0.0f);
+    if (L > 0.0f) {
+      const float il = 1.0f / L;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) g[i] = copysignf(o[i], pl[i]) * il;
+    } else {
+      g[0] = g[1] = g[2] = 0.0f;
+      g[k] = (pl[k] < 0.0f) ? -1.0f : 1.0f;
+    }
+  } else {  // plane
+    phi = pl[1];
+  }
+  float nw[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) nw[i] = t.R[3 * i] * g[0] + t.R[3 * i + 1] * g[1] + t.R[3 * i + 2] * g[2];
+  const float inv = rsqrtf(nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2]);
+  n[0] = nw[0] * inv, n[1] = nw[1] * inv, n[2] = nw[2] * inv;
+  return phi;
+}
+
+// Contact of one node with one tool (Sec. IV-A, eq. v_correction): the
+// relative velocity u = v - v_r is left alone when separating (u.n >= 0);
+// otherwise its normal part is removed and its tangential part t is scaled
+// by c_d max(1 + mu u.n / |t|, 0).
+__device__ __forceinline__ void tool_contact(const ToolK& t, const float* xI, float* v) {
+  float n[3];
+  const float phi = tool_sdf(t, xI, n);
+  if (!(phi < t.margin)) return;
+  const float r0 = xI[0] - t.c[0], r1 = xI[1] - t.c[1], r2 = xI[2] - t.c[2];
+  const float vr0 = t.lv[0] + t.av[1] * r2 - t.av[2] * r1;
+  const float vr1 = t.lv[1] + t.av[2] * r0 - t.av[0] * r2;
+  const float vr2 = t.lv[2] + t.av[0] * r1 - t.av[1] * r0;
+  const float u0 = v[0] - vr0, u1 = v[1] - vr1, u2 = v[2] - vr2;
+  const float un = n[0] * u0 + n[1] * u1 + n[2] * u2;
+  if (!(un < 0.0f)) return;
+  const float t0 = u0 - un * n[0], t1 = u1 - un * n[1], t2 = u2 - un * n[2];
+  const float s = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
+  float k = 0.0f;
+  if (s > 0.0f) k = t.drag * fmaxf(1.0f + t.mu * un / s, 0.0f);
+  v[0] = vr0 + k * t0;
+  v[1] = vr1 + k * t1;
+  v[2] = vr2 + k * t2;
+}
+
+// Node (i, j, k) -> index in the blocked grid layout.
+__device__ __forceinline__ int grid_index(int i, int j, int k, int nb) {
+  const int b = ((k >> kTileLog2) * nb + (j >> kTileLog2)) * nb + (i >> kTileLog2);
+  const int l = (((k & (kTile - 1)) * kTile) + (j & (kTile - 1))) * kTile + (i & (kTile - 1));
+  return (b << (3 * kTileLog2)) + l;
+}
+
+}  // namespace mpm

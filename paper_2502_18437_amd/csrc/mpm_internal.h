@@ -1,0 +1,117 @@
+// Internal declarations shared by the translation units of the library:
+// kernel-argument structs, the device status word and host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpm {
+
+// Grid blocks are kTile^3 nodes, stored contiguously (x fastest inside a
+// block, blocks x fastest). A block's particles work on a tile of
+// (kTile + 2 + 2 * kSlack)^3 nodes in LDS: the 3-node stencils of the
+// block's cells plus kSlack cells of drift on each side since binning.
+constexpr int kTile = 8;
+constexpr int kTileLog2 = 3;
+constexpr int kSlack = 1;
+constexpr int kSpan = kTile + 2 + 2 * kSlack;  // 12
+constexpr int kSpanNodes = kSpan * kSpan * kSpan;  // 1728
+constexpr int kBlockNodes = kTile * kTile * kTile;  // 512
+constexpr int kMaxTools = 8;
+constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA
+
+// Field offsets in the particle SoA (each field is `cap` floats).
+enum Field { FX = 0, FV = 3, FC = 6, FF = 15, FE = 24 };
+
+enum ToolType { TOOL_NONE = 0, TOOL_CAPSULE = 1, TOOL_BOX = 2, TOOL_PLANE = 3 };
+
+// One tool as the grid kernel sees it (FP32, pose of the current substep).
+struct ToolK {
+  int type;
+  float c[3];      // centre at the start of the substep
+  float R[9];      // body-to-world rotation, row-major
+  float size[3];
+  float lv[3];
+  float av[3];
+  float mu, drag, margin;
+};
+
+struct ToolSetK {
+  int n;           // tools 0..n-1 are scanned; NONE entries are skipped
+  ToolK t[kMaxTools];
+};
+
+// Scene constants for the transfer kernels.
+struct SimK {
+  int n;           // nodes per axis
+  int nb;          // blocks per axis
+  float dx, inv_dx, dt;
+  float mass;      // per particle
+  float p2g_stress;  // dt * vol0 * 4 / dx^2
+  float c_mu, c_la;  // mu = c_mu E, lambda = c_la E
+  float E_default;
+  int has_E;         // per-particle E stored in field FE
+  int band;          // wall band
+  float g[3];
+};
+
+// Device status word (one per handle).
+struct Status {
+  unsigned long long n_inverted;
+  unsigned long long n_domain;
+  unsigned long long n_nonfinite;
+  unsigned long long n_fallback;
+  unsigned long long active_nodes[2];  // nodes with mass, per substep parity
+  unsigned int n_occ;               // occupied blocks (this binning)
+  unsigned int n_act;               // active blocks (this binning)
+  unsigned int ovf_count[2];        // overflow blocks claimed, per parity
+};
+
+// Device buffers of one handle.
+struct Buffers {
+  float* part[2] = {nullptr, nullptr};      // particle SoA ping-pong, kFields * cap
+  uint32_t* id[2] = {nullptr, nullptr};     // original particle index
+  int cur = 0;                              // which ping-pong half is live
+  int64_t cap = 0;
+  uint32_t* keys[2] = {nullptr, nullptr};   // sort keys ping-pong
+  uint32_t* vals[2] = {nullptr, nullptr};   // sort values ping-pong
+  uint32_t* hist = nullptr;                 // radix histograms
+  uint32_t* scan_tmp = nullptr;             // scan partials
+  uint32_t* blk_begin = nullptr;            // per block [begin, end)
+  uint32_t* blk_end = nullptr;
+  uint32_t* flags = nullptr;                // per block scratch for compaction
+  uint32_t* occ_list = nullptr;             // occupied blocks
+  uint32_t* act_list = nullptr;             // active (dilated) blocks
+  uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
+  uint32_t* ovf_list[2] = {nullptr, nullptr};
+  float4* acc = nullptr;                    // grid accumulator (m, p)
+  float4* vel = nullptr;                    // grid velocity
+  Status* status = nullptr;
+};
+
+// ---------------------------------------------------------------- launchers
+// Binning pipeline: keys from positions, radix sort, permutation, block
+// ranges, occupied and active block lists. Resets the overflow lists.
+void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st);
+
+// Transfers. `first_substep`: parity of the overflow list used by P2G.
+void launch_p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st);
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st);
+void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
+
+// Grid update over active blocks and this parity's overflow blocks.
+void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
+                 hipStream_t st);
+
+// Stress evaluation (diagnostic entry point).
+void launch_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,
+                        hipStream_t st);
+
+// Gather particles back into the caller's order (AoS outputs).
+void launch_unpermute(const Buffers& b, int64_t N, float* x, float* v, float* C, float* F,
+                      hipStream_t st);
+// Scatter caller AoS inputs into the SoA (identity order, id = index).
+void launch_load_particles(Buffers& b, int64_t N, const float* x, const float* v, const float* C,
+                           const float* F, const float* E, hipStream_t st);
+
+}  // namespace mpm

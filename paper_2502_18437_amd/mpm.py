@@ -1,0 +1,256 @@
+"""Thin ctypes binding of the C ABI in include/mpm.h (argument marshalling
+only: every step of the substep runs in the HIP library).
+
+Importing this module loads ``libmpm.so`` from the package directory and
+raises ImportError if it has not been built (``__graft_entry__.build()`` or
+``python paper_2502_18437_amd/build.py``); there is no CPU fallback.
+
+Module-level functions carry the C names (``mpm_create``, ``mpm_step``, ...);
+``Simulation`` wraps one handle for Python callers. Arrays may be NumPy
+arrays (host memory) or torch CUDA tensors (device memory, ``where`` =
+MPM_DEVICE); they must be float32 and C-contiguous.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpm.so")
+
+MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EHIP, MPM_EDOMAIN, MPM_ENONFINITE, MPM_EINVERTED = 0, -1, -2, -3, -4, -5, -6
+MPM_HOST, MPM_DEVICE = 0, 1
+MPM_ACCUM_F32, MPM_ACCUM_FIXED = 0, 1
+MPM_TOOL_NONE, MPM_TOOL_CAPSULE, MPM_TOOL_BOX, MPM_TOOL_PLANE = 0, 1, 2, 3
+MPM_MAX_TOOLS = 8
+MPM_KERNEL_KINDS = 5
+KERNEL_NAMES = ("binning", "p2g", "g2p2g", "g2p", "grid")
+
+STATUS_NAMES = {0: "MPM_OK", -1: "MPM_EINVAL", -2: "MPM_ENOMEM", -3: "MPM_EHIP", -4: "MPM_EDOMAIN",
+                -5: "MPM_ENONFINITE", -6: "MPM_EINVERTED"}
+
+EXPORTED = ("mpm_create", "mpm_destroy", "mpm_set_particles", "mpm_set_tool_sdf", "mpm_step",
+            "mpm_read_state", "mpm_get_info", "mpm_last_error", "mpm_eval_stress", "mpm_profile",
+            "mpm_profile_read")
+
+
+class mpm_params(ctypes.Structure):
+    _fields_ = [("n_grid", ctypes.c_int32), ("dt", ctypes.c_float), ("gravity", ctypes.c_float * 3),
+                ("wall_band", ctypes.c_int32), ("nu", ctypes.c_float), ("E_default", ctypes.c_float),
+                ("accum_mode", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("resort_interval", ctypes.c_int32), ("max_particles", ctypes.c_int64)]
+
+
+class mpm_tool(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("center", ctypes.c_double * 3), ("quat", ctypes.c_double * 4),
+                ("size", ctypes.c_double * 3), ("lin_vel", ctypes.c_double * 3),
+                ("ang_vel", ctypes.c_double * 3), ("mu", ctypes.c_float), ("drag", ctypes.c_float),
+                ("margin", ctypes.c_float)]
+
+
+class mpm_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "n_particles", "substeps", "resorts", "occupied_blocks", "active_blocks", "active_nodes",
+        "n_inverted", "n_domain", "n_nonfinite", "n_fallback")] + \
+        [(n, ctypes.c_int32) for n in ("tile", "resort_interval", "accum_mode", "n_tools")]
+
+
+class mpm_kernel_times(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double * MPM_KERNEL_KINDS),
+                ("launches", ctypes.c_int64 * MPM_KERNEL_KINDS)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                      "(run __graft_entry__.build() or python paper_2502_18437_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_h = ctypes.c_void_p
+_lib.mpm_create.argtypes = [ctypes.POINTER(mpm_params), ctypes.c_uint64, ctypes.POINTER(_h)]
+_lib.mpm_destroy.argtypes = [_h]
+_lib.mpm_set_particles.argtypes = [_h, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_int32]
+_lib.mpm_set_tool_sdf.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(mpm_tool)]
+_lib.mpm_step.argtypes = [_h, ctypes.c_int32]
+_lib.mpm_read_state.argtypes = [_h, _vp, _vp, _vp, _vp, ctypes.c_int32]
+_lib.mpm_get_info.argtypes = [_h, ctypes.POINTER(mpm_info)]
+_lib.mpm_last_error.argtypes = [_h]
+_lib.mpm_last_error.restype = ctypes.c_char_p
+_lib.mpm_eval_stress.argtypes = [ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32]
+_lib.mpm_profile.argtypes = [_h, ctypes.c_int32]
+_lib.mpm_profile_read.argtypes = [_h, ctypes.POINTER(mpm_kernel_times)]
+
+# C names, re-exported
+mpm_create = _lib.mpm_create
+mpm_destroy = _lib.mpm_destroy
+mpm_set_particles = _lib.mpm_set_particles
+mpm_set_tool_sdf = _lib.mpm_set_tool_sdf
+mpm_step = _lib.mpm_step
+mpm_read_state = _lib.mpm_read_state
+mpm_get_info = _lib.mpm_get_info
+mpm_last_error = _lib.mpm_last_error
+mpm_eval_stress = _lib.mpm_eval_stress
+mpm_profile = _lib.mpm_profile
+mpm_profile_read = _lib.mpm_profile_read
+
+
+class MPMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _arg(a, shape_tail, n):
+    """(pointer, where, keepalive) of one float32 array argument."""
+    if a is None:
+        return None, None, None
+    if _is_torch(a):
+        if not a.is_cuda:
+            a = a.numpy()
+        else:
+            if a.dtype != __import__("torch").float32 or not a.is_contiguous():
+                raise ValueError("device arrays must be contiguous float32 tensors")
+            if a.numel() != n * int(np.prod(shape_tail)):
+                raise ValueError(f"expected {n} x {shape_tail}, got {tuple(a.shape)}")
+            return a.data_ptr(), MPM_DEVICE, a
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != n * int(np.prod(shape_tail)):
+        raise ValueError(f"expected {n} x {shape_tail}, got {a.shape}")
+    return a.ctypes.data, MPM_HOST, a
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return 0
+
+
+class Simulation:
+    """One scene (mpm_handle)."""
+
+    def __init__(self, n_grid, dt, gravity=(0.0, -9.8, 0.0), wall_band=3, nu=0.3, E_default=5e3,
+                 accum_mode=MPM_ACCUM_F32, tile=0, resort_interval=0, max_particles=0, stream=None):
+        p = mpm_params(int(n_grid), float(dt), (ctypes.c_float * 3)(*gravity), int(wall_band), float(nu),
+                       float(E_default), int(accum_mode), int(tile), int(resort_interval), int(max_particles))
+        h = _h()
+        s = _current_stream() if stream is None else int(stream)
+        rc = _lib.mpm_create(ctypes.byref(p), ctypes.c_uint64(s), ctypes.byref(h))
+        if rc != MPM_OK:
+            raise MPMError(rc, _lib.mpm_last_error(None).decode())
+        self.h = h
+        self.n_grid = int(n_grid)
+        self.N = 0
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "h", None):
+            rc = _lib.mpm_destroy(self.h)
+            self.h = None
+            return rc
+        return MPM_OK
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != MPM_OK and rc not in allow:
+            raise MPMError(rc, _lib.mpm_last_error(self.h).decode())
+        return rc
+
+    # -- calls
+    def set_particles(self, x, v=None, C=None, F=None, E=None, mass=1.0, vol0=1.0):
+        n = int(x.shape[0])
+        args = [_arg(x, (3,), n), _arg(v, (3,), n), _arg(C, (3, 3), n), _arg(F, (3, 3), n), _arg(E, (), n)]
+        wheres = {w for _, w, _ in args if w is not None}
+        if len(wheres) > 1:
+            raise ValueError("all arrays must be host or all device")
+        where = wheres.pop() if wheres else MPM_HOST
+        ptrs = [p for p, _, _ in args]
+        self._keep = [k for _, _, k in args]
+        rc = _lib.mpm_set_particles(self.h, n, *ptrs, float(mass), float(vol0), where)
+        self._check(rc)
+        self.N = n
+
+    def set_tool(self, tool_id, tool_type, center=(0, 0, 0), quat=(1, 0, 0, 0), size=(0, 0, 0),
+                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0):
+        t = mpm_tool(int(tool_type), (ctypes.c_double * 3)(*center), (ctypes.c_double * 4)(*quat),
+                     (ctypes.c_double * 3)(*size), (ctypes.c_double * 3)(*lin_vel),
+                     (ctypes.c_double * 3)(*ang_vel), float(mu), float(drag), float(margin))
+        self._check(_lib.mpm_set_tool_sdf(self.h, int(tool_id), ctypes.byref(t)))
+
+    def step(self, n):
+        self._check(_lib.mpm_step(self.h, int(n)))
+
+    def read_state(self, out=None, allow_errors=False):
+        """Blocking read. Returns (dict of arrays, status). Without `out`,
+        host NumPy arrays are returned; `out` may hold torch CUDA tensors
+        (keys x, v, C, F) to read into device memory."""
+        n = self.N
+        if out is None:
+            out = {"x": np.empty((n, 3), np.float32), "v": np.empty((n, 3), np.float32),
+                   "C": np.empty((n, 3, 3), np.float32), "F": np.empty((n, 3, 3), np.float32)}
+        args = {k: _arg(out.get(k), (3,) if k in "xv" else (3, 3), n) for k in ("x", "v", "C", "F")}
+        wheres = {w for _, w, _ in args.values() if w is not None}
+        where = wheres.pop() if wheres else MPM_HOST
+        rc = _lib.mpm_read_state(self.h, *[args[k][0] for k in ("x", "v", "C", "F")], where)
+        if rc in (MPM_EDOMAIN, MPM_ENONFINITE, MPM_EINVERTED) and allow_errors:
+            return out, rc
+        self._check(rc)
+        return out, rc
+
+    def info(self):
+        i = mpm_info()
+        self._check(_lib.mpm_get_info(self.h, ctypes.byref(i)))
+        return {name: getattr(i, name) for name, _ in mpm_info._fields_}
+
+    def profile(self, enable=True):
+        self._check(_lib.mpm_profile(self.h, int(bool(enable))))
+
+    def profile_read(self):
+        t = mpm_kernel_times()
+        self._check(_lib.mpm_profile_read(self.h, ctypes.byref(t)))
+        return {KERNEL_NAMES[k]: (t.total_ms[k], t.launches[k]) for k in range(MPM_KERNEL_KINDS)}
+
+
+def eval_stress(F, E, nu):
+    """Kirchhoff stress of (n, 3, 3) deformation gradients on the GPU."""
+    n = int(F.shape[0])
+    pF, w1, kF = _arg(F, (3, 3), n)
+    pE, w2, kE = _arg(E, (), n)
+    if w1 != w2:
+        raise ValueError("F and E must both be host or both be device arrays")
+    if w1 == MPM_DEVICE:
+        import torch
+        tau = torch.empty((n, 3, 3), dtype=torch.float32, device=F.device)
+        ptr = tau.data_ptr()
+    else:
+        tau = np.empty((n, 3, 3), np.float32)
+        ptr = tau.ctypes.data
+    rc = _lib.mpm_eval_stress(n, pF, pE, float(nu), ptr, w1)
+    if rc != MPM_OK:
+        raise MPMError(rc, "mpm_eval_stress")
+    return tau
+
+
+def simulation_from_scene(scene, **kw):
+    """Create a Simulation holding a scenes.Scene (particles and tools)."""
+    params = dict(n_grid=scene.n_grid, dt=scene.dt, gravity=scene.gravity, wall_band=scene.wall_band,
+                  nu=scene.nu, E_default=scene.E_default, max_particles=max(1, scene.N))
+    params.update(kw)
+    sim = Simulation(**params)
+    sim.set_particles(scene.x, scene.v, scene.C, scene.F, scene.E, scene.mass, scene.vol0)
+    for k, t in enumerate(scene.tools):
+        sim.set_tool(k, t.type, **t.kwargs())
+    return sim

@@ -1,0 +1,98 @@
+"""C-ABI checks that need no GPU: the library loads, it exports every function
+include/mpm.h declares, and the ctypes structs of the Python binding have the
+layout the C compiler gives the header's structs."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s*(mpm_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for core in ("mpm_create", "mpm_set_particles", "mpm_set_tool_sdf", "mpm_step", "mpm_read_state"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2502_18437_amd import mpm
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(mpm._lib, n)]
+    assert not missing, missing
+    assert set(names) == set(mpm.EXPORTED)
+    nm = subprocess.run(["nm", "-D", "--defined-only", mpm.LIB_PATH], capture_output=True, text=True)
+    exported = set(re.findall(r" T (mpm_\w+)$", nm.stdout, flags=re.M))
+    assert set(names) <= exported
+
+
+LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "mpm.h"
+#define F(T, m) printf(#T " " #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("mpm_params SIZEOF %zu\n", sizeof(mpm_params));
+  F(mpm_params, n_grid) F(mpm_params, dt) F(mpm_params, gravity) F(mpm_params, wall_band)
+  F(mpm_params, nu) F(mpm_params, E_default) F(mpm_params, accum_mode) F(mpm_params, tile)
+  F(mpm_params, resort_interval) F(mpm_params, max_particles)
+  printf("mpm_tool SIZEOF %zu\n", sizeof(mpm_tool));
+  F(mpm_tool, type) F(mpm_tool, center) F(mpm_tool, quat) F(mpm_tool, size) F(mpm_tool, lin_vel)
+  F(mpm_tool, ang_vel) F(mpm_tool, mu) F(mpm_tool, drag) F(mpm_tool, margin)
+  printf("mpm_info SIZEOF %zu\n", sizeof(mpm_info));
+  F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, tile) F(mpm_info, n_tools)
+  printf("mpm_kernel_times SIZEOF %zu\n", sizeof(mpm_kernel_times));
+  F(mpm_kernel_times, total_ms) F(mpm_kernel_times, launches)
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_ctypes(tmp_path):
+    from paper_2502_18437_amd import mpm
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    structs = {"mpm_params": mpm.mpm_params, "mpm_tool": mpm.mpm_tool, "mpm_info": mpm.mpm_info,
+               "mpm_kernel_times": mpm.mpm_kernel_times}
+    for line in out:
+        if not line:
+            continue
+        sname, field, val = line.split()
+        cls = structs[sname]
+        if field == "SIZEOF":
+            assert mpm.ctypes.sizeof(cls) == int(val), sname
+        else:
+            assert getattr(cls, field).offset == int(val), (sname, field)
+
+
+def test_status_codes_match_header():
+    from paper_2502_18437_amd import mpm
+    text = open(HEADER).read()
+    for name in ("MPM_OK", "MPM_EINVAL", "MPM_ENOMEM", "MPM_EHIP", "MPM_EDOMAIN", "MPM_ENONFINITE",
+                 "MPM_EINVERTED", "MPM_HOST", "MPM_DEVICE", "MPM_TOOL_CAPSULE", "MPM_TOOL_BOX",
+                 "MPM_TOOL_PLANE", "MPM_ACCUM_FIXED", "MPM_KERNEL_KINDS", "MPM_MAX_TOOLS"):
+        m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, text)
+        assert m, name
+        assert getattr(mpm, name) == int(m.group(1)), name
+
+
+def test_null_handle_calls_are_rejected_without_a_gpu():
+    """Argument validation happens before any device work."""
+    from paper_2502_18437_amd import mpm
+    assert mpm._lib.mpm_step(None, 1) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_destroy(None) == mpm.MPM_OK
+    assert mpm._lib.mpm_set_tool_sdf(None, 0, None) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_create(None, 0, None) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_eval_stress(-1, None, None, 0.3, None, 0) == mpm.MPM_EINVAL
