@@ -1,0 +1,148 @@
+"""Benchmark of the explicit MLS-MPM substep on one MI355X.
+
+Workload (default): the cutting-style contact scene -- 4,194,304 particles
+in a 0.8 x 0.2 x 0.8 slab on a 256^3 grid, an oriented-box blade sweeping
+through it and a capsule grasper pressing on it, 500 substeps of dt = 5e-5.
+One benchmark step = the whole 500-substep job from the initial state:
+mpm_set_particles from device-resident inputs, the tools reset to their
+initial pose, mpm_step(500) (binning, P2G, grid update, G2P of every
+substep, all in the HIP library). `value` = particles x substeps / second.
+
+Also reported on the same JSON line:
+* roofline: the dominant kernel (the fused G2P2G) against the HBM peak,
+  from its algorithmic bytes per launch and its mean duration measured with
+  HIP events on the library's stream during the timed steps;
+* substep_roofline: the whole substep against the HBM byte model
+  N x 100 B + N_act x 72 B;
+* cpu_baseline: the FP64 oracle timed on the host for a bounded sample of
+  the same workload (a few substeps of the full scene).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-substeps/s (P2G+grid+G2P) fwd & fwd+bwd; % HBM roofline at 4M particles"
+HBM_PEAK_GBS = 8000.0
+B_PARTICLE = 100.0      # x, F, E read + x, F written per particle-substep (fused path)
+B_NODE_SUBSTEP = 72.0   # P2G result write+read, reset, velocity write+read per active node
+B_NODE_G2P2G = 28.0     # the fused kernel's share: velocity read 12 B + P2G result write 16 B
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, n_sub):
+    """The FP64 oracle (single-threaded) on the full scene for n_sub substeps."""
+    from tests.parity import run_oracle
+    t0 = time.perf_counter()
+    run_oracle(scene, n_sub)
+    dt = time.perf_counter() - t0
+    return {"value": scene.N * n_sub / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sub} substeps of the full {scene.name} scene ({scene.N} particles, "
+                      f"{scene.n_grid}^3 grid), FP64, one host thread; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scene", default="c3")
+    ap.add_argument("--substeps", type=int, default=0, help="substeps per step (default: the scene's)")
+    ap.add_argument("--resort", type=int, default=0)
+    ap.add_argument("--cpu-substeps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_18437_amd import mpm, scenes
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = scenes.make(args.scene)
+    n_sub = args.substeps or s.n_substeps
+    log(f"[bench] scene {s.name}: {s.N} particles, {s.n_grid}^3 grid, {n_sub} substeps/step")
+
+    # Inputs resident in HBM before timing.
+    x_d = torch.from_numpy(s.x).to(dev)
+    E_d = torch.from_numpy(s.E).to(dev) if s.E is not None else None
+    sim = mpm.Simulation(s.n_grid, s.dt, gravity=s.gravity, wall_band=s.wall_band, nu=s.nu,
+                         E_default=s.E_default, resort_interval=args.resort, max_particles=s.N)
+
+    def step():
+        sim.set_particles(x_d, None, None, None, E_d, s.mass, s.vol0)
+        for k, t in enumerate(s.tools):
+            sim.set_tool(k, t.type, **t.kwargs())
+        sim.step(n_sub)
+
+    for _ in range(args.warmup):
+        step()
+    sim.read_state(out={})  # synchronise and surface deferred errors
+    torch.cuda.synchronize()
+
+    if not args.no_profile:
+        sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    _, st = sim.read_state(out={})
+    info = sim.info()
+    prof = sim.profile_read() if not args.no_profile else None
+    sim.close()
+    assert st == 0, st
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = s.N * n_sub * args.steps / elapsed
+    n_act = int(info["active_nodes"])
+    per_substep_s = elapsed / (args.steps * n_sub)
+    model_bytes = s.N * B_PARTICLE + n_act * B_NODE_SUBSTEP
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-substeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name}: {s.N} particles, {s.n_grid}^3 grid, {len(s.tools)} tools, "
+                               f"{n_sub} substeps of dt={s.dt}", "particles": s.N, "grid": s.n_grid,
+                   "substeps_per_step": n_sub, "resort_interval": info["resort_interval"],
+                   "active_nodes": n_act, "occupied_blocks": info["occupied_blocks"],
+                   "active_blocks": info["active_blocks"]},
+        "substep_roofline": {"bound": "hbm", "model_bytes": model_bytes, "us_per_substep": 1e6 * per_substep_s,
+                             "achieved": model_bytes / per_substep_s / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": model_bytes / per_substep_s / 1e9 / HBM_PEAK_GBS},
+    }
+    if prof is not None:
+        ms, n = prof["g2p2g"]
+        avg_s = ms / max(n, 1) / 1e3
+        bytes_launch = s.N * B_PARTICLE + n_act * B_NODE_G2P2G
+        achieved = bytes_launch / avg_s / 1e9
+        out["roofline"] = {"kernel": "k_g2p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n}
+        out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
+                                "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
+    if not args.no_cpu:
+        log(f"[bench] oracle CPU baseline: {args.cpu_substeps} substeps of the full scene ...")
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_substeps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

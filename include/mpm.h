@@ -54,20 +54,28 @@ extern "C" {
 #define MPM_ENONFINITE (-5) /* a particle's state is not finite; it is left
                                unchanged */
 #define MPM_EINVERTED (-6)  /* det F <= 0 was seen in the stress evaluation */
+#define MPM_ERANGE (-7)     /* a particle's P2G contribution exceeded the
+                               fixed-point range of the grid accumulator
+                               (|m v| beyond about 1000 m_p m/s); that particle
+                               is left out of the P2G of that substep */
 
 /* Precedence when several device errors are pending:
- * MPM_ENONFINITE, then MPM_EDOMAIN, then MPM_EINVERTED. */
+ * MPM_ENONFINITE, then MPM_EDOMAIN, then MPM_ERANGE, then MPM_EINVERTED. */
 
 #define MPM_HOST 0
 #define MPM_DEVICE 1
 
 #define MPM_MAX_TOOLS 8
 
-/* Grid accumulation mode of the P2G scatter. */
-#define MPM_ACCUM_F32 0   /* FP32 atomics: fast, summation order varies */
-#define MPM_ACCUM_FIXED 1 /* 64-bit fixed-point atomics: results are
-                             bit-identical run to run and independent of
-                             particle order and re-sort schedule */
+/* Grid accumulation mode of the P2G scatter. Each particle's contributions
+ * are rounded to fixed point (weights in units of 2^-24, momentum in units
+ * of 2^-40 of the particle mass times 1 m/s) and summed exactly per block in
+ * LDS; the modes differ in the global sum over blocks. */
+#define MPM_ACCUM_F32 0   /* block sums added with FP32 atomics: fastest; the
+                             summation order of the FP32 adds varies */
+#define MPM_ACCUM_FIXED 1 /* block sums added with integer atomics: results
+                             are bit-identical run to run, for any particle
+                             order and re-binning schedule */
 
 /* Tool geometries (Sec. IV-A: one SDF per rigid shape). */
 #define MPM_TOOL_NONE 0    /* removes the tool */
@@ -124,6 +132,7 @@ typedef struct mpm_info {
   int64_t n_nonfinite;       /* particles with non-finite state */
   int64_t n_fallback;        /* particle-substeps that left their block's
                                 tile and took the global-memory path */
+  int64_t n_range;           /* particle-substeps refused by the range check */
   int32_t tile;
   int32_t resort_interval;
   int32_t accum_mode;

@@ -192,7 +192,8 @@ void prof_collect(mpm_handle* h) {
 void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
                   b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.act_list, b.mark,
-                  b.ovf_list[0], b.ovf_list[1], b.acc, b.vel, b.status};
+                  b.ovf_list[0], b.ovf_list[1], b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
+                  b.status};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   b = Buffers();
@@ -203,12 +204,18 @@ __global__ void k_reset_status(Status* st) {
   st->n_domain = 0ull;
   st->n_nonfinite = 0ull;
   st->n_fallback = 0ull;
+  st->n_range = 0ull;
   st->active_nodes[0] = 0ull;
   st->active_nodes[1] = 0ull;
   st->n_occ = 0u;
   st->n_act = 0u;
   st->ovf_count[0] = 0u;
   st->ovf_count[1] = 0u;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 __global__ void k_zero_f4(float4* p, int64_t n) {
@@ -222,6 +229,7 @@ int pending_status(mpm_handle* h, Status* out) {
   if (out) *out = st;
   if (st.n_nonfinite) return fail(h, MPM_ENONFINITE, "non-finite particle state");
   if (st.n_domain) return fail(h, MPM_EDOMAIN, "a particle stencil left the grid");
+  if (st.n_range) return fail(h, MPM_ERANGE, "a P2G contribution exceeded the fixed-point range");
   if (st.n_inverted) return fail(h, MPM_EINVERTED, "det F <= 0 in the stress evaluation");
   return MPM_OK;
 }
@@ -251,7 +259,8 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   if (p->n_grid < 8 || p->n_grid > 1024 || !(p->dt > 0.0f) || !std::isfinite(p->dt) ||
       !(p->nu >= 0.0f && p->nu < 0.5f) || !(p->E_default >= 0.0f) || !std::isfinite(p->E_default) ||
       p->wall_band < 0 || p->wall_band > p->n_grid / 2 ||
-      !(p->accum_mode == MPM_ACCUM_F32) || !(p->tile == 0 || p->tile == kTile) ||
+      !(p->accum_mode == MPM_ACCUM_F32 || p->accum_mode == MPM_ACCUM_FIXED) ||
+      !(p->tile == 0 || p->tile == kTile) ||
       p->resort_interval < 0 || p->max_particles < 0 || p->max_particles > 0x7fffffffLL ||
       !std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2])) {
     g_create_error = "parameter out of range";
@@ -321,7 +330,9 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   alloc((void**)&b.occ_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
-  alloc((void**)&b.acc, sizeof(float4) * grid_nodes);
+  const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
+  alloc(&b.acc_m, sizeof(float) * grid_nodes);
+  for (int a = 0; a < 3; ++a) alloc(&b.acc_p[a], mom_bytes * grid_nodes);
   alloc((void**)&b.vel, sizeof(float4) * grid_nodes);
   alloc((void**)&b.status, sizeof(Status));
   if (!ok) {
@@ -332,7 +343,10 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
     return MPM_ENOMEM;
   }
   // The accumulator must start (and stay, outside a substep) at zero.
-  hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.acc, (int64_t)grid_nodes);
+  hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(256), 0, h->stream, (uint32_t*)b.acc_m, (int64_t)grid_nodes);
+  for (int a = 0; a < 3; ++a)
+    hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(256), 0, h->stream, (uint32_t*)b.acc_p[a],
+                       (int64_t)(grid_nodes * mom_bytes / 4));
   hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
   e = hipStreamSynchronize(h->stream);
@@ -357,6 +371,7 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   s.c_mu = (float)(1.0 / (2.0 * (1.0 + nu)));
   s.c_la = (float)(nu / ((1.0 + nu) * (1.0 - 2.0 * nu)));
   for (int a = 0; a < 3; ++a) s.g[a] = p->gravity[a];
+  s.fixed = p->accum_mode == MPM_ACCUM_FIXED ? 1 : 0;
   *out = h;
   return MPM_OK;
 }
@@ -423,6 +438,13 @@ int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v, 
   h->sim.mass = mass;
   h->sim.has_E = h->has_E ? 1 : 0;
   h->sim.p2g_stress = (float)((double)h->p.dt * (double)vol0 * 4.0 * (double)h->p.n_grid * (double)h->p.n_grid);
+  // Fixed-point units: a weight is 2^-24; momentum units are chosen so that
+  // one particle at 1 m/s is 2^40 units (exact powers of two).
+  h->sim.m_unit = std::ldexp(mass, -24);
+  const int shift = 40 - std::ilogb(mass);
+  h->sim.fx_p = std::ldexp(1.0, shift);
+  h->sim.fx_p_inv = std::ldexp(1.0, -shift);
+  h->sim.p_limit = (float)std::ldexp(1.0, 50 - shift);
   h->since_sort = 0;
   h->dirty = true;
   h->err.clear();
@@ -555,6 +577,7 @@ int mpm_get_info(mpm_handle* h, mpm_info* info) {
   info->n_domain = (int64_t)st.n_domain;
   info->n_nonfinite = (int64_t)st.n_nonfinite;
   info->n_fallback = (int64_t)st.n_fallback;
+  info->n_range = (int64_t)st.n_range;
   info->tile = kTile;
   info->resort_interval = h->resort_interval;
   info->accum_mode = h->p.accum_mode;

@@ -16,7 +16,9 @@ namespace mpm {
 
 constexpr int kGridWG = 256;
 
-__global__ __launch_bounds__(kGridWG) void k_grid(float4* __restrict__ acc, float4* __restrict__ vel,
+__global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void* __restrict__ acc_p0,
+                                                  void* __restrict__ acc_p1, void* __restrict__ acc_p2,
+                                                  float4* __restrict__ vel,
                                                   const uint32_t* __restrict__ act_list,
                                                   const uint32_t* __restrict__ ovf_list,
                                                   uint32_t* mark, Status* st, int parity, SimK s,
@@ -33,14 +35,34 @@ __global__ __launch_bounds__(kGridWG) void k_grid(float4* __restrict__ acc, floa
     const int bk = (int)(b / ((unsigned)s.nb * (unsigned)s.nb));
     for (int l = threadIdx.x; l < kBlockNodes; l += kGridWG) {
       const size_t g = ((size_t)b << (3 * kTileLog2)) + (size_t)l;
-      const float4 a = acc[g];
+      // Mass and momentum of the node (P2G result), then the reset.
+      float m, p0, p1, p2;
+      if (s.fixed) {
+        m = (float)((uint32_t*)acc_m)[g] * s.m_unit;
+        p0 = (float)((double)((long long*)acc_p0)[g] * s.fx_p_inv);
+        p1 = (float)((double)((long long*)acc_p1)[g] * s.fx_p_inv);
+        p2 = (float)((double)((long long*)acc_p2)[g] * s.fx_p_inv);
+        ((uint32_t*)acc_m)[g] = 0u;
+        ((long long*)acc_p0)[g] = 0ll;
+        ((long long*)acc_p1)[g] = 0ll;
+        ((long long*)acc_p2)[g] = 0ll;
+      } else {
+        m = ((float*)acc_m)[g];
+        p0 = ((float*)acc_p0)[g];
+        p1 = ((float*)acc_p1)[g];
+        p2 = ((float*)acc_p2)[g];
+        ((float*)acc_m)[g] = 0.0f;
+        ((float*)acc_p0)[g] = 0.0f;
+        ((float*)acc_p1)[g] = 0.0f;
+        ((float*)acc_p2)[g] = 0.0f;
+      }
       float v[3] = {0.0f, 0.0f, 0.0f};
-      if (a.x > 0.0f) {
+      if (m > 0.0f) {
         cnt++;
-        const float im = 1.0f / a.x;
-        v[0] = a.y * im + s.dt * s.g[0];
-        v[1] = a.z * im + s.dt * s.g[1];
-        v[2] = a.w * im + s.dt * s.g[2];
+        const float im = 1.0f / m;
+        v[0] = p0 * im + s.dt * s.g[0];
+        v[1] = p1 * im + s.dt * s.g[1];
+        v[2] = p2 * im + s.dt * s.g[2];
         const int i = bi * kTile + (l & (kTile - 1));
         const int j = bj * kTile + ((l >> kTileLog2) & (kTile - 1));
         const int k = bk * kTile + (l >> (2 * kTileLog2));
@@ -50,7 +72,6 @@ __global__ __launch_bounds__(kGridWG) void k_grid(float4* __restrict__ acc, floa
         if (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi) v[0] = v[1] = v[2] = 0.0f;
       }
       vel[g] = make_float4(v[0], v[1], v[2], 0.0f);
-      acc[g] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     if (overflow && threadIdx.x == 0) mark[b] = 0u;
   }
@@ -71,7 +92,8 @@ void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, i
                  hipStream_t st) {
   int wgs = max_act < 4096 ? max_act : 4096;
   if (wgs < 1) wgs = 1;
-  hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc, b.vel, b.act_list,
+  hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
+                     b.acc_p[2], b.vel, b.act_list,
                      b.ovf_list[parity], b.mark, b.status, parity, s, tools);
 }
 

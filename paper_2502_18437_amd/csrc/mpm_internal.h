@@ -42,6 +42,14 @@ struct ToolSetK {
 };
 
 // Scene constants for the transfer kernels.
+//
+// P2G accumulates in integers (LDS float atomics are slow on gfx950, and
+// integer sums are exact and order independent): the mass channel as the sum
+// of the B-spline weights in units of 2^-24 (u32), the momentum channels as
+// int64 in units of 2^-fx_shift kg m/s, where fx_shift is chosen per scene
+// so that one particle moving at 1 m/s is about 2^40 units. The conversion
+// of a value to int64 is the round-to-nearest of an FP64 sum with 1.5 * 2^52,
+// exact for magnitudes below 2^51 units.
 struct SimK {
   int n;           // nodes per axis
   int nb;          // blocks per axis
@@ -53,6 +61,11 @@ struct SimK {
   int has_E;         // per-particle E stored in field FE
   int band;          // wall band
   float g[3];
+  int fixed;         // global accumulator: 0 FP32, 1 integer (bit-reproducible)
+  float m_unit;      // kg per weight unit: mass * 2^-24
+  double fx_p;       // 2^fx_shift (momentum units per kg m/s)
+  double fx_p_inv;   // 2^-fx_shift
+  float p_limit;     // largest |contribution| (kg m/s) kept in range
 };
 
 // Device status word (one per handle).
@@ -61,6 +74,7 @@ struct Status {
   unsigned long long n_domain;
   unsigned long long n_nonfinite;
   unsigned long long n_fallback;
+  unsigned long long n_range;      // P2G contributions outside the fixed-point range
   unsigned long long active_nodes[2];  // nodes with mass, per substep parity
   unsigned int n_occ;               // occupied blocks (this binning)
   unsigned int n_act;               // active blocks (this binning)
@@ -84,7 +98,8 @@ struct Buffers {
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
   uint32_t* ovf_list[2] = {nullptr, nullptr};
-  float4* acc = nullptr;                    // grid accumulator (m, p)
+  void* acc_m = nullptr;                    // grid accumulator, mass channel (float or u32)
+  void* acc_p[3] = {nullptr, nullptr, nullptr};  // momentum channels (float or int64)
   float4* vel = nullptr;                    // grid velocity
   Status* status = nullptr;
 };

@@ -5,11 +5,15 @@
 // One workgroup owns one block at a time: it stages the grid velocities of the
 // block's tile (kSpan^3 nodes: the block's stencils plus kSlack cells of
 // drift) in LDS, gathers (G2P) from LDS, scatters (P2G) into an LDS
-// accumulator tile with LDS float atomics, then flushes the non-empty tile
-// nodes into the global accumulator with one float atomic per value. A
-// particle whose stencil has drifted out of the tile since binning takes a
-// correct global-memory path and claims the blocks it touches for the grid
-// update (overflow list).
+// accumulator tile with integer LDS atomics, then flushes the non-empty tile
+// nodes into the global accumulator (FP32 or integer atomics, one per value).
+// A particle whose stencil has drifted out of the tile since binning takes a
+// global-memory path with the same integer contributions and claims the
+// blocks it touches for the grid update (overflow list).
+//
+// P2G accumulates integers because LDS float atomics are slow on gfx950 while
+// ds_add_u32 / ds_add_u64 run near LDS bandwidth; integer sums are also exact,
+// so the result does not depend on the order of the atomics.
 //
 // k_g2p2g fuses the G2P of substep k-1 with the P2G of substep k: v and C never
 // leave registers between the two, so a fused substep streams x, F, E in and
@@ -21,6 +25,9 @@ namespace mpm {
 
 constexpr int kXcds = 8;
 constexpr int kWG = 256;
+constexpr double kMagic = 6755399441055744.0;           // 1.5 * 2^52
+constexpr long long kMagicBits = 0x4338000000000000LL;  // its bit pattern
+constexpr float kWeightUnits = 16777216.0f;            // 2^24
 
 // Walk of a block list by a persistent grid whose size is a multiple of 8.
 // Workgroups are dealt round-robin to the 8 XCDs, so workgroup w runs on XCD
@@ -38,7 +45,7 @@ __device__ __forceinline__ void xcd_walk(unsigned n_items, unsigned* pos, unsign
 }
 
 struct Counters {
-  unsigned inv = 0, dom = 0, nf = 0, fb = 0;
+  unsigned inv = 0, dom = 0, nf = 0, fb = 0, rng = 0;
 };
 
 __device__ __forceinline__ void flush_counters(Status* st, const Counters& c) {
@@ -46,6 +53,7 @@ __device__ __forceinline__ void flush_counters(Status* st, const Counters& c) {
   if (c.dom) atomicAdd(&st->n_domain, (unsigned long long)c.dom);
   if (c.nf) atomicAdd(&st->n_nonfinite, (unsigned long long)c.nf);
   if (c.fb) atomicAdd(&st->n_fallback, (unsigned long long)c.fb);
+  if (c.rng) atomicAdd(&st->n_range, (unsigned long long)c.rng);
 }
 
 // Base node and fractional offsets of a particle; false if the 3x3x3
@@ -63,31 +71,101 @@ __device__ __forceinline__ bool particle_stencil(const SimK& s, const float* x, 
   return ok;
 }
 
-// ------------------------------------------------------------------ fallbacks
-// P2G of one particle straight into the global accumulator; claims every
-// block its stencil touches that the current binning did not activate.
-__device__ __forceinline__ void p2g_global(const SimK& s, const int* base, const float (*w)[3],
-                                        const float* q, const float* Adx, float4* acc,
-                                        uint32_t* mark, uint32_t* ovf, Status* st, int parity) {
+// ------------------------------------------------------------------ P2G values
+// Per-particle inputs of the P2G scatter: weights and the affine momentum
+// field m v + A (x_I - x_p) = q + A o dx in fixed-point units (q = m v - A f dx,
+// A = m C - dt V0 (4/dx^2) tau).
+struct P2GIn {
+  int base[3];
+  float w[3][3];
+  double q[3];
+  double Adx[9];
+};
+
+// o in {0, 1, 2}: base, base + slope, base + 2 slope (o is a constant after
+// unrolling, so only the needed operation remains).
+__device__ __forceinline__ double affine_step(double base, double slope, int o) {
+  return o == 0 ? base : (o == 1 ? base + slope : fma(slope, 2.0, base));
+}
+
+__device__ __forceinline__ long long fx_mul(double n, double v) {
+  return __double_as_longlong(fma(n, v, kMagic)) - kMagicBits;
+}
+
+// The 27 contributions (weight units, 3 momentum values) of one particle, in
+// a fixed order and with one fixed sequence of operations, handed to `sink`.
+template <class Sink>
+__device__ __forceinline__ void p2g_emit(const P2GIn& P, Sink&& sink) {
 #pragma unroll
-  for (int ox = 0; ox < 3; ++ox)
+  for (int ox = 0; ox < 3; ++ox) {
+    double qx[3];
 #pragma unroll
-    for (int oy = 0; oy < 3; ++oy)
+    for (int a = 0; a < 3; ++a) qx[a] = affine_step(P.q[a], P.Adx[3 * a], ox);
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) {
+      double qy[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) qy[a] = affine_step(qx[a], P.Adx[3 * a + 1], oy);
+      const float wxy = P.w[0][ox] * P.w[1][oy];
 #pragma unroll
       for (int oz = 0; oz < 3; ++oz) {
-        const float N = w[0][ox] * w[1][oy] * w[2][oz];
-        const float fo[3] = {(float)ox, (float)oy, (float)oz};
-        float val[3];
-        for (int a = 0; a < 3; ++a)
-          val[a] = q[a] + Adx[3 * a] * fo[0] + Adx[3 * a + 1] * fo[1] + Adx[3 * a + 2] * fo[2];
-        const int g = grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb);
-        unsafeAtomicAdd(&acc[g].x, N * s.mass);
-        unsafeAtomicAdd(&acc[g].y, N * val[0]);
-        unsafeAtomicAdd(&acc[g].z, N * val[1]);
-        unsafeAtomicAdd(&acc[g].w, N * val[2]);
+        const float N = wxy * P.w[2][oz];
+        const double Nd = (double)N;
+        const uint32_t wq = (uint32_t)fmaf(N, kWeightUnits, 0.5f);
+        const long long p0 = fx_mul(Nd, affine_step(qy[0], P.Adx[2], oz));
+        const long long p1 = fx_mul(Nd, affine_step(qy[1], P.Adx[5], oz));
+        const long long p2 = fx_mul(Nd, affine_step(qy[2], P.Adx[8], oz));
+        sink(ox, oy, oz, wq, p0, p1, p2);
       }
-  const int b0[3] = {base[0] >> kTileLog2, base[1] >> kTileLog2, base[2] >> kTileLog2};
-  const int b1[3] = {(base[0] + 2) >> kTileLog2, (base[1] + 2) >> kTileLog2, (base[2] + 2) >> kTileLog2};
+    }
+  }
+}
+
+// ------------------------------------------------------------------ global accumulator
+// Channel types of the global accumulator: FP32 sums, or exact integer sums
+// (weights in 2^-24 units, momentum in 2^-fx_shift units).
+template <bool FIXED> struct AccT;
+template <> struct AccT<false> {
+  using M = float;
+  using P = float;
+};
+template <> struct AccT<true> {
+  using M = uint32_t;
+  using P = long long;
+};
+
+template <bool FIXED>
+__device__ __forceinline__ void acc_add(const SimK& s, typename AccT<FIXED>::M* am, typename AccT<FIXED>::P* ap0,
+                                        typename AccT<FIXED>::P* ap1, typename AccT<FIXED>::P* ap2, int g,
+                                        uint32_t wq, long long p0, long long p1, long long p2) {
+  if constexpr (FIXED) {
+    atomicAdd(am + g, wq);
+    atomicAdd((unsigned long long*)ap0 + g, (unsigned long long)p0);
+    atomicAdd((unsigned long long*)ap1 + g, (unsigned long long)p1);
+    atomicAdd((unsigned long long*)ap2 + g, (unsigned long long)p2);
+  } else {
+    unsafeAtomicAdd(am + g, (float)wq * s.m_unit);
+    unsafeAtomicAdd(ap0 + g, (float)((double)p0 * s.fx_p_inv));
+    unsafeAtomicAdd(ap1 + g, (float)((double)p1 * s.fx_p_inv));
+    unsafeAtomicAdd(ap2 + g, (float)((double)p2 * s.fx_p_inv));
+  }
+}
+
+#define ACC_PARAMS typename AccT<FIXED>::M *__restrict__ am, typename AccT<FIXED>::P *__restrict__ ap0, \
+                   typename AccT<FIXED>::P *__restrict__ ap1, typename AccT<FIXED>::P *__restrict__ ap2
+#define ACC_ARGS am, ap0, ap1, ap2
+
+// P2G of one particle straight into the global accumulator; claims every
+// block its stencil touches that the current binning did not activate.
+template <bool FIXED>
+__device__ __noinline__ void p2g_global(const SimK& s, const P2GIn& P, ACC_PARAMS, uint32_t* mark,
+                                        uint32_t* ovf, Status* st, int parity) {
+  p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
+    const int g = grid_index(P.base[0] + ox, P.base[1] + oy, P.base[2] + oz, s.nb);
+    acc_add<FIXED>(s, ACC_ARGS, g, wq, p0, p1, p2);
+  });
+  const int b0[3] = {P.base[0] >> kTileLog2, P.base[1] >> kTileLog2, P.base[2] >> kTileLog2};
+  const int b1[3] = {(P.base[0] + 2) >> kTileLog2, (P.base[1] + 2) >> kTileLog2, (P.base[2] + 2) >> kTileLog2};
   for (int bz = b0[2]; bz <= b1[2]; ++bz)
     for (int by = b0[1]; by <= b1[1]; ++by)
       for (int bx = b0[0]; bx <= b1[0]; ++bx) {
@@ -101,7 +179,7 @@ __device__ __forceinline__ void p2g_global(const SimK& s, const int* base, const
 }
 
 // G2P of one particle from the global velocity grid.
-__device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const float (*w)[3],
+__device__ __noinline__ void g2p_global(const SimK& s, const int* base, const float (*w)[3],
                                         const float4* vel, float* S, float* T) {
   for (int i = 0; i < 3; ++i) S[i] = 0.0f;
   for (int i = 0; i < 9; ++i) T[i] = 0.0f;
@@ -114,97 +192,95 @@ __device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const
         const float N = w[0][ox] * w[1][oy] * w[2][oz];
         const float4 vv = vel[grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
         const float nv[3] = {N * vv.x, N * vv.y, N * vv.z};
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
           S[a] += nv[a];
-          T[3 * a + 0] += nv[a] * (float)ox;
-          T[3 * a + 1] += nv[a] * (float)oy;
-          T[3 * a + 2] += nv[a] * (float)oz;
+          if (ox) T[3 * a + 0] += nv[a] * (float)ox;
+          if (oy) T[3 * a + 1] += nv[a] * (float)oy;
+          if (oz) T[3 * a + 2] += nv[a] * (float)oz;
         }
       }
 }
 
 // ------------------------------------------------------------------ per particle
 struct Lds {
-  float4 v[kSpanNodes];     // staged grid velocity
-  float m[kSpanNodes];      // accumulated mass
-  float p0[kSpanNodes], p1[kSpanNodes], p2[kSpanNodes];  // accumulated momentum
+  float4 v[kSpanNodes];                                     // staged grid velocity
+  uint32_t m[kSpanNodes];                                   // weight sums (2^-24 units)
+  long long p0[kSpanNodes], p1[kSpanNodes], p2[kSpanNodes];  // momentum (fixed point)
 };
 
 __device__ __forceinline__ int lds_index(int lx, int ly, int lz) {
   return (lz * kSpan + ly) * kSpan + lx;
 }
 
-// P2G of one particle (Algorithm 1, first loop): mass N m and momentum
+// P2G of one particle (Algorithm 1, first loop): weight N and momentum
 // N [m v + (m C - dt V0 (4/dx^2) tau)(x_I - x_p)] to each of the 27 nodes.
+template <bool FIXED>
 __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, const float* v,
                                              const float* C, const float* F, float E,
-                                             const int* to, Lds& L, float4* acc, uint32_t* mark,
+                                             const int* to, Lds& L, ACC_PARAMS, uint32_t* mark,
                                              uint32_t* ovf, Status* st, int parity, Counters& cnt) {
-  int base[3];
+  P2GIn P;
   float f[3];
-  if (!particle_stencil(s, x, base, f)) {
+  if (!particle_stencil(s, x, P.base, f)) {
     if (isfinite(x[0] + x[1] + x[2]))
       cnt.dom++;
     else
       cnt.nf++;
     return;
   }
-  float w[3][3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]);
+  for (int a = 0; a < 3; ++a) bspline_w(f[a], P.w[a]);
   float tau[9];
   bool inv;
   kirchhoff(F, s.c_mu * E, s.c_la * E, tau, &inv);
-  float A[9];
+  float Af[9];
   float chk = v[0] + v[1] + v[2];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    A[i] = s.mass * C[i] - s.p2g_stress * tau[i];
-    chk += A[i];
+    Af[i] = s.mass * C[i] - s.p2g_stress * tau[i];
+    chk += Af[i];
   }
   if (!isfinite(chk)) {
     cnt.nf++;
     return;
   }
   if (inv) cnt.inv++;
-  // m v + A (x_I - x_p) = q + A o dx with q = m v - A f dx.
-  float q[3], Adx[9];
+  // Bound of |m v + A (x_I - x_p)| over the stencil (|x_I - x_p| <= 1.5 dx
+  // per axis): contributions beyond the fixed-point range are refused.
+  float bound = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    q[a] = s.mass * v[a] - (A[3 * a] * f[0] + A[3 * a + 1] * f[1] + A[3 * a + 2] * f[2]) * s.dx;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) Adx[3 * a + b] = A[3 * a + b] * s.dx;
+    const float row = fabsf(Af[3 * a]) + fabsf(Af[3 * a + 1]) + fabsf(Af[3 * a + 2]);
+    bound = fmaxf(bound, fabsf(s.mass * v[a]) + 1.5f * s.dx * row);
   }
-  const int l0 = base[0] - to[0], l1 = base[1] - to[1], l2 = base[2] - to[2];
+  if (!(bound < s.p_limit)) {
+    cnt.rng++;
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float qa = s.mass * v[a] - (Af[3 * a] * f[0] + Af[3 * a + 1] * f[1] + Af[3 * a + 2] * f[2]) * s.dx;
+    P.q[a] = (double)qa * s.fx_p;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) P.Adx[3 * a + b] = (double)(Af[3 * a + b] * s.dx) * s.fx_p;
+  }
+  const int l0 = P.base[0] - to[0], l1 = P.base[1] - to[1], l2 = P.base[2] - to[2];
   const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
                        ((unsigned)l2 <= (unsigned)(kSpan - 3));
   if (!in_tile) {
     cnt.fb++;
-    p2g_global(s, base, w, q, Adx, acc, mark, ovf, st, parity);
+    p2g_global<FIXED>(s, P, ACC_ARGS, mark, ovf, st, parity);
     return;
   }
-#pragma unroll
-  for (int ox = 0; ox < 3; ++ox) {
-    float qx[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) qx[a] = q[a] + Adx[3 * a] * (float)ox;
-#pragma unroll
-    for (int oy = 0; oy < 3; ++oy) {
-      float qy[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) qy[a] = qx[a] + Adx[3 * a + 1] * (float)oy;
-      const float wxy = w[0][ox] * w[1][oy];
-#pragma unroll
-      for (int oz = 0; oz < 3; ++oz) {
-        const float N = wxy * w[2][oz];
-        const int idx = lds_index(l0 + ox, l1 + oy, l2 + oz);
-        atomicAdd(&L.m[idx], N * s.mass);
-        atomicAdd(&L.p0[idx], N * (qy[0] + Adx[2] * (float)oz));
-        atomicAdd(&L.p1[idx], N * (qy[1] + Adx[5] * (float)oz));
-        atomicAdd(&L.p2[idx], N * (qy[2] + Adx[8] * (float)oz));
-      }
-    }
-  }
+  const int l = lds_index(l0, l1, l2);
+  p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
+    const int idx = l + lds_index(ox, oy, oz);
+    atomicAdd(&L.m[idx], wq);
+    atomicAdd((unsigned long long*)&L.p0[idx], (unsigned long long)p0);
+    atomicAdd((unsigned long long*)&L.p1[idx], (unsigned long long)p1);
+    atomicAdd((unsigned long long*)&L.p2[idx], (unsigned long long)p2);
+  });
 }
 
 // G2P of one particle (Algorithm 1, third loop): v' = sum N v_I,
@@ -225,6 +301,7 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
   const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
                        ((unsigned)l2 <= (unsigned)(kSpan - 3));
   if (in_tile) {
+    const int l = lds_index(l0, l1, l2);
 #pragma unroll
     for (int ox = 0; ox < 3; ++ox)
 #pragma unroll
@@ -233,7 +310,7 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
 #pragma unroll
         for (int oz = 0; oz < 3; ++oz) {
           const float N = wxy * w[2][oz];
-          const float4 vv = L.v[lds_index(l0 + ox, l1 + oy, l2 + oz)];
+          const float4 vv = L.v[l + lds_index(ox, oy, oz)];
           const float nv[3] = {N * vv.x, N * vv.y, N * vv.z};
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -270,10 +347,10 @@ __device__ __forceinline__ void block_origin(const SimK& s, unsigned b, int* to)
 
 __device__ __forceinline__ void tile_clear(Lds& L) {
   for (int i = threadIdx.x; i < kSpanNodes; i += blockDim.x) {
-    L.m[i] = 0.0f;
-    L.p0[i] = 0.0f;
-    L.p1[i] = 0.0f;
-    L.p2[i] = 0.0f;
+    L.m[i] = 0u;
+    L.p0[i] = 0ll;
+    L.p1[i] = 0ll;
+    L.p2[i] = 0ll;
   }
 }
 
@@ -290,20 +367,18 @@ __device__ __forceinline__ void tile_stage_velocity(const SimK& s, const int* to
 }
 
 // Non-empty tile nodes -> global accumulator.
-__device__ __forceinline__ void tile_flush(const SimK& s, const int* to, const Lds& L, float4* acc) {
+template <bool FIXED>
+__device__ __forceinline__ void tile_flush(const SimK& s, const int* to, const Lds& L, ACC_PARAMS) {
   for (int i = threadIdx.x; i < kSpanNodes; i += blockDim.x) {
-    const float m = L.m[i];
-    if (m == 0.0f) continue;
+    const uint32_t wq = L.m[i];
+    const long long p0 = L.p0[i], p1 = L.p1[i], p2 = L.p2[i];
+    if ((wq | p0 | p1 | p2) == 0) continue;
     const int lx = i % kSpan, ly = (i / kSpan) % kSpan, lz = i / (kSpan * kSpan);
     const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
-    // Only in-grid nodes can carry mass (stencils are checked against the
-    // grid); the test keeps the index in range regardless.
+    // Only in-grid nodes can receive contributions (stencils are checked
+    // against the grid); the test keeps the index in range regardless.
     if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
-    const int g = grid_index(gx, gy, gz, s.nb);
-    unsafeAtomicAdd(&acc[g].x, m);
-    unsafeAtomicAdd(&acc[g].y, L.p0[i]);
-    unsafeAtomicAdd(&acc[g].z, L.p1[i]);
-    unsafeAtomicAdd(&acc[g].w, L.p2[i]);
+    acc_add<FIXED>(s, ACC_ARGS, grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2);
   }
 }
 
@@ -314,12 +389,12 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 
 // ------------------------------------------------------------------ kernels
 // P2G from the materialised particle state (first substep after binning).
+template <bool FIXED>
 __global__ __launch_bounds__(kWG) void k_p2g(const float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint32_t* __restrict__ occ_list, Status* st,
-                                             float4* acc, uint32_t* mark, uint32_t* ovf, int parity,
-                                             SimK s) {
+                                             ACC_PARAMS, uint32_t* mark, uint32_t* ovf, int parity, SimK s) {
   __shared__ Lds L;
   Counters cnt;
   unsigned pos, end, stride;
@@ -343,21 +418,23 @@ __global__ __launch_bounds__(kWG) void k_p2g(const float* __restrict__ part, int
         C[i] = part[(FC + i) * cap + p];
         F[i] = part[(FF + i) * cap + p];
       }
-      p2g_particle(s, x, v, C, F, particle_E(s, part, cap, p), to, L, acc, mark, ovf, st, parity, cnt);
+      p2g_particle<FIXED>(s, x, v, C, F, particle_E(s, part, cap, p), to, L, ACC_ARGS, mark, ovf, st, parity,
+                          cnt);
     }
     __syncthreads();
-    tile_flush(s, to, L, acc);
+    tile_flush<FIXED>(s, to, L, ACC_ARGS);
     __syncthreads();
   }
   flush_counters(st, cnt);
 }
 
 // Fused G2P (substep k-1) -> F, x update -> stress -> P2G (substep k).
+template <bool FIXED>
 __global__ __launch_bounds__(kWG) void k_g2p2g(float* __restrict__ part, int64_t cap,
                                                const uint32_t* __restrict__ blk_begin,
                                                const uint32_t* __restrict__ blk_end,
                                                const uint32_t* __restrict__ occ_list, Status* st,
-                                               float4* acc, const float4* __restrict__ vel,
+                                               ACC_PARAMS, const float4* __restrict__ vel,
                                                uint32_t* mark, uint32_t* ovf, int parity, SimK s) {
   __shared__ Lds L;
   Counters cnt;
@@ -393,11 +470,11 @@ __global__ __launch_bounds__(kWG) void k_g2p2g(float* __restrict__ part, int64_t
       }
 #pragma unroll
       for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
-      p2g_particle(s, x, vn, Cn, Fn, particle_E(s, part, cap, p), to, L, acc, mark, ovf, st, parity,
-                   cnt);
+      p2g_particle<FIXED>(s, x, vn, Cn, Fn, particle_E(s, part, cap, p), to, L, ACC_ARGS, mark, ovf, st,
+                          parity, cnt);
     }
     __syncthreads();
-    tile_flush(s, to, L, acc);
+    tile_flush<FIXED>(s, to, L, ACC_ARGS);
     __syncthreads();
   }
   flush_counters(st, cnt);
@@ -449,17 +526,38 @@ __global__ __launch_bounds__(kWG) void k_g2p(float* __restrict__ part, int64_t c
 }
 
 // ------------------------------------------------------------------ launchers
+template <bool FIXED>
+static void launch_p2g_t(Buffers& b, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
+  using M = typename AccT<FIXED>::M;
+  using P = typename AccT<FIXED>::P;
+  hipLaunchKernelGGL(k_p2g<FIXED>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
+                     b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
+                     (P*)b.acc_p[2], b.mark, b.ovf_list[parity], parity, s);
+}
+
+template <bool FIXED>
+static void launch_g2p2g_t(Buffers& b, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
+  using M = typename AccT<FIXED>::M;
+  using P = typename AccT<FIXED>::P;
+  hipLaunchKernelGGL(k_g2p2g<FIXED>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
+                     b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
+                     (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[parity], parity, s);
+}
+
 void launch_p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
   (void)N;
-  hipLaunchKernelGGL(k_p2g, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
-                     b.blk_end, b.occ_list, b.status, b.acc, b.mark, b.ovf_list[parity], parity, s);
+  if (s.fixed)
+    launch_p2g_t<true>(b, s, parity, grid_wgs, st);
+  else
+    launch_p2g_t<false>(b, s, parity, grid_wgs, st);
 }
 
 void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
   (void)N;
-  hipLaunchKernelGGL(k_g2p2g, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
-                     b.blk_end, b.occ_list, b.status, b.acc, b.vel, b.mark, b.ovf_list[parity],
-                     parity, s);
+  if (s.fixed)
+    launch_g2p2g_t<true>(b, s, parity, grid_wgs, st);
+  else
+    launch_g2p2g_t<false>(b, s, parity, grid_wgs, st);
 }
 
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpm.so")
 
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EHIP, MPM_EDOMAIN, MPM_ENONFINITE, MPM_EINVERTED = 0, -1, -2, -3, -4, -5, -6
+MPM_ERANGE = -7
 MPM_HOST, MPM_DEVICE = 0, 1
 MPM_ACCUM_F32, MPM_ACCUM_FIXED = 0, 1
 MPM_TOOL_NONE, MPM_TOOL_CAPSULE, MPM_TOOL_BOX, MPM_TOOL_PLANE = 0, 1, 2, 3
@@ -27,7 +28,7 @@ MPM_KERNEL_KINDS = 5
 KERNEL_NAMES = ("binning", "p2g", "g2p2g", "g2p", "grid")
 
 STATUS_NAMES = {0: "MPM_OK", -1: "MPM_EINVAL", -2: "MPM_ENOMEM", -3: "MPM_EHIP", -4: "MPM_EDOMAIN",
-                -5: "MPM_ENONFINITE", -6: "MPM_EINVERTED"}
+                -5: "MPM_ENONFINITE", -6: "MPM_EINVERTED", -7: "MPM_ERANGE"}
 
 EXPORTED = ("mpm_create", "mpm_destroy", "mpm_set_particles", "mpm_set_tool_sdf", "mpm_step",
             "mpm_read_state", "mpm_get_info", "mpm_last_error", "mpm_eval_stress", "mpm_profile",
@@ -51,7 +52,7 @@ class mpm_tool(ctypes.Structure):
 class mpm_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_particles", "substeps", "resorts", "occupied_blocks", "active_blocks", "active_nodes",
-        "n_inverted", "n_domain", "n_nonfinite", "n_fallback")] + \
+        "n_inverted", "n_domain", "n_nonfinite", "n_fallback", "n_range")] + \
         [(n, ctypes.c_int32) for n in ("tile", "resort_interval", "accum_mode", "n_tools")]
 
 
@@ -205,7 +206,7 @@ class Simulation:
         wheres = {w for _, w, _ in args.values() if w is not None}
         where = wheres.pop() if wheres else MPM_HOST
         rc = _lib.mpm_read_state(self.h, *[args[k][0] for k in ("x", "v", "C", "F")], where)
-        if rc in (MPM_EDOMAIN, MPM_ENONFINITE, MPM_EINVERTED) and allow_errors:
+        if rc in (MPM_EDOMAIN, MPM_ENONFINITE, MPM_EINVERTED, MPM_ERANGE) and allow_errors:
             return out, rc
         self._check(rc)
         return out, rc

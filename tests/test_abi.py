@@ -48,7 +48,7 @@ int main(void) {
   F(mpm_tool, type) F(mpm_tool, center) F(mpm_tool, quat) F(mpm_tool, size) F(mpm_tool, lin_vel)
   F(mpm_tool, ang_vel) F(mpm_tool, mu) F(mpm_tool, drag) F(mpm_tool, margin)
   printf("mpm_info SIZEOF %zu\n", sizeof(mpm_info));
-  F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, tile) F(mpm_info, n_tools)
+  F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, n_range) F(mpm_info, tile) F(mpm_info, n_tools)
   printf("mpm_kernel_times SIZEOF %zu\n", sizeof(mpm_kernel_times));
   F(mpm_kernel_times, total_ms) F(mpm_kernel_times, launches)
   return 0;
@@ -81,7 +81,7 @@ def test_status_codes_match_header():
     from paper_2502_18437_amd import mpm
     text = open(HEADER).read()
     for name in ("MPM_OK", "MPM_EINVAL", "MPM_ENOMEM", "MPM_EHIP", "MPM_EDOMAIN", "MPM_ENONFINITE",
-                 "MPM_EINVERTED", "MPM_HOST", "MPM_DEVICE", "MPM_TOOL_CAPSULE", "MPM_TOOL_BOX",
+                 "MPM_EINVERTED", "MPM_ERANGE", "MPM_HOST", "MPM_DEVICE", "MPM_TOOL_CAPSULE", "MPM_TOOL_BOX",
                  "MPM_TOOL_PLANE", "MPM_ACCUM_FIXED", "MPM_KERNEL_KINDS", "MPM_MAX_TOOLS"):
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, text)
         assert m, name
