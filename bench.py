@@ -123,7 +123,7 @@ def main():
                                f"{n_sub} substeps of dt={s.dt}", "particles": s.N, "grid": s.n_grid,
                    "substeps_per_step": n_sub, "resort_interval": info["resort_interval"],
                    "active_nodes": n_act, "occupied_blocks": info["occupied_blocks"],
-                   "active_blocks": info["active_blocks"]},
+                   "active_blocks": info["active_blocks"], "fallback_particle_substeps": info["n_fallback"]},
         "substep_roofline": {"bound": "hbm", "model_bytes": model_bytes, "us_per_substep": 1e6 * per_substep_s,
                              "achieved": model_bytes / per_substep_s / 1e9, "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": model_bytes / per_substep_s / 1e9 / HBM_PEAK_GBS},

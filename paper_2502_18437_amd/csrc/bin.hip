@@ -3,8 +3,8 @@
 // contiguous): key = grid block of the particle's base cell, a stable LSD
 // radix sort of (key, index) with 8-bit digits, a gather of the particle SoA
 // into key order, per-block [begin, end) ranges, the list of occupied blocks
-// and the list of active blocks (occupied blocks dilated by one block in every
-// direction: the blocks a tile can touch). Also the host<->SoA marshalling
+// and the list of active blocks (each occupied block with the neighbours its
+// tile reaches). Also the host<->SoA marshalling
 // kernels and the diagnostic stress kernel.
 //
 // Every buffer is cleared with fill kernels (no memset nodes), so the whole
@@ -258,9 +258,9 @@ __global__ void k_mark_dilated(const uint32_t* __restrict__ begin, const uint32_
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x) {
     if (!(end[b] > begin[b])) continue;
     const int bi = b % nb, bj = (b / nb) % nb, bk = b / (nb * nb);
-    for (int dk = -1; dk <= 1; ++dk)
-      for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
+    for (int dk = kTileLo; dk <= kTileHi; ++dk)
+      for (int dj = kTileLo; dj <= kTileHi; ++dj)
+        for (int di = kTileLo; di <= kTileHi; ++di) {
           const int i = bi + di, j = bj + dj, k = bk + dk;
           if (i < 0 || j < 0 || k < 0 || i >= nb || j >= nb || k >= nb) continue;
           mark[(k * nb + j) * nb + i] = 1u;

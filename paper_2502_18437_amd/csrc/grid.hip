@@ -14,7 +14,7 @@
 
 namespace mpm {
 
-constexpr int kGridWG = 256;
+constexpr int kGridWG = kBlockNodes;  // one thread per node of a block
 
 __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void* __restrict__ acc_p0,
                                                   void* __restrict__ acc_p1, void* __restrict__ acc_p2,
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
 
 void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
                  hipStream_t st) {
-  int wgs = max_act < 4096 ? max_act : 4096;
+  int wgs = max_act < 8192 ? max_act : 8192;
   if (wgs < 1) wgs = 1;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
                      b.acc_p[2], b.vel, b.act_list,

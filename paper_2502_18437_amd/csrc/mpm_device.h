@@ -24,12 +24,14 @@ __device__ __forceinline__ float det3(const float* X) {
 }
 
 // Rotation factor of F (det F > 0) by Newton's iteration for the polar
-// decomposition, X <- (z X + X^-T / z) / 2, with the determinant scaling
-// z = |det X|^(-1/3) on the first two iterations (Higham 1986, "Computing
-// the polar decomposition -- with applications"; Byers & Xu 2008). The
-// iteration squares the distance of the stretch from I each step, so it
-// stops once an update is below 1e-4: the next error is then below FP32
-// round-off. Returns false if it did not converge.
+// decomposition, X <- (z X + X^-T / z) / 2 (Higham 1986, "Computing the polar
+// decomposition -- with applications"), with the determinant scaling
+// z = |det X|^(-1/3) (Byers & Xu 2008) on the first two iterations when det X
+// is far from 1. Near convergence the distance of the stretch from I is
+// squared every step, so the loop stops once an update is below 1e-4: the
+// next error is then below FP32 round-off. X^-T = cof(X) / det X uses the
+// hardware reciprocal; the fixed point is still orthogonal to within its
+// rounding. Returns false if it did not converge.
 __device__ inline bool polar_newton(const float* F, float* R) {
   float X[9];
 #pragma unroll
@@ -47,9 +49,10 @@ __device__ inline bool polar_newton(const float* F, float* R) {
     c[8] = X[0] * X[4] - X[1] * X[3];
     const float det = X[0] * c[0] + X[1] * c[1] + X[2] * c[2];
     if (!(det > 0.0f)) return false;
-    const float z = (it < 2) ? rcbrtf(det) : 1.0f;
+    float z = 1.0f;
+    if (it < 2 && fabsf(det - 1.0f) > 0.05f) z = rcbrtf(det);
     const float a = 0.5f * z;
-    const float b = 0.5f / (z * det);
+    const float b = 0.5f * __builtin_amdgcn_rcpf(z * det);
     float delta = 0.0f;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -72,7 +75,7 @@ __device__ inline bool polar_newton(const float* F, float* R) {
 // rotations; Irving et al. 2004), from a cyclic Jacobi eigen-decomposition
 // of F^T F (Golub & Van Loan, Sec. 8.5). Used only when det F <= 0, where
 // Newton's iteration does not give a rotation.
-__device__ __noinline__ void polar_svd_signfix(const float* F, float* R) {
+__device__ __forceinline__ void polar_svd_signfix(const float* F, float* R) {
   float A[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)

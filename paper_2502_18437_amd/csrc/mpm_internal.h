@@ -11,11 +11,15 @@ namespace mpm {
 // block, blocks x fastest). A block's particles work on a tile of
 // (kTile + 2 + 2 * kSlack)^3 nodes in LDS: the 3-node stencils of the
 // block's cells plus kSlack cells of drift on each side since binning.
+// Particles that drift further take the global-memory path.
 constexpr int kTile = 8;
 constexpr int kTileLog2 = 3;
-constexpr int kSlack = 1;
-constexpr int kSpan = kTile + 2 + 2 * kSlack;  // 12
-constexpr int kSpanNodes = kSpan * kSpan * kSpan;  // 1728
+constexpr int kSlack = 0;
+constexpr int kSpan = kTile + 2 + 2 * kSlack;  // 10
+constexpr int kSpanNodes = kSpan * kSpan * kSpan;  // 1000
+// Blocks a tile touches, relative to its own block: [kTileLo, kTileHi].
+constexpr int kTileLo = -((kSlack + kTile - 1) / kTile);
+constexpr int kTileHi = (kTile + 1 + kSlack) / kTile;
 constexpr int kBlockNodes = kTile * kTile * kTile;  // 512
 constexpr int kMaxTools = 8;
 constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA

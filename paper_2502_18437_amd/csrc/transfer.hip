@@ -96,17 +96,19 @@ __device__ __forceinline__ long long fx_mul(double n, double v) {
 // a fixed order and with one fixed sequence of operations, handed to `sink`.
 template <class Sink>
 __device__ __forceinline__ void p2g_emit(const P2GIn& P, Sink&& sink) {
-#pragma unroll
+  // The x offset is a loop variable (not unrolled) to bound register use.
+#pragma unroll 1
   for (int ox = 0; ox < 3; ++ox) {
+    const float wx = ox == 0 ? P.w[0][0] : (ox == 1 ? P.w[0][1] : P.w[0][2]);
     double qx[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) qx[a] = affine_step(P.q[a], P.Adx[3 * a], ox);
+    for (int a = 0; a < 3; ++a) qx[a] = fma(P.Adx[3 * a], (double)ox, P.q[a]);
 #pragma unroll
     for (int oy = 0; oy < 3; ++oy) {
       double qy[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) qy[a] = affine_step(qx[a], P.Adx[3 * a + 1], oy);
-      const float wxy = P.w[0][ox] * P.w[1][oy];
+      const float wxy = wx * P.w[1][oy];
 #pragma unroll
       for (int oz = 0; oz < 3; ++oz) {
         const float N = wxy * P.w[2][oz];
@@ -158,7 +160,7 @@ __device__ __forceinline__ void acc_add(const SimK& s, typename AccT<FIXED>::M* 
 // P2G of one particle straight into the global accumulator; claims every
 // block its stencil touches that the current binning did not activate.
 template <bool FIXED>
-__device__ __noinline__ void p2g_global(const SimK& s, const P2GIn& P, ACC_PARAMS, uint32_t* mark,
+__device__ __forceinline__ void p2g_global(const SimK& s, const P2GIn& P, ACC_PARAMS, uint32_t* mark,
                                         uint32_t* ovf, Status* st, int parity) {
   p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
     const int g = grid_index(P.base[0] + ox, P.base[1] + oy, P.base[2] + oz, s.nb);
@@ -178,28 +180,51 @@ __device__ __noinline__ void p2g_global(const SimK& s, const P2GIn& P, ACC_PARAM
       }
 }
 
-// G2P of one particle from the global velocity grid.
-__device__ __noinline__ void g2p_global(const SimK& s, const int* base, const float (*w)[3],
-                                        const float4* vel, float* S, float* T) {
+// G2P sums of one particle, S = sum N v_I and T[a][b] = sum N v_I[a] o_b, with
+// the sum over oz done first for each (ox, oy) (separable weights). `node`
+// returns the velocity of stencil node (ox, oy, oz); the LDS and the global
+// path share this arithmetic, so both give the same bits.
+template <class Node>
+__device__ __forceinline__ void g2p_sums(const float (*w)[3], Node&& node, float* S, float* T) {
+#pragma unroll
   for (int i = 0; i < 3; ++i) S[i] = 0.0f;
+#pragma unroll
   for (int i = 0; i < 9; ++i) T[i] = 0.0f;
+  const float wz1 = w[2][1], wz2 = 2.0f * w[2][2];
+  // The x offset is a loop variable (not unrolled) to bound the LDS loads in
+  // flight and the register use.
+#pragma unroll 1
+  for (int ox = 0; ox < 3; ++ox) {
+    const float wx = ox == 0 ? w[0][0] : (ox == 1 ? w[0][1] : w[0][2]);
+    const float fox = (float)ox;
 #pragma unroll
-  for (int ox = 0; ox < 3; ++ox)
+    for (int oy = 0; oy < 3; ++oy) {
+      const float4 v0 = node(ox, oy, 0), v1 = node(ox, oy, 1), v2 = node(ox, oy, 2);
+      float Z0[3], Z1[3];
+      Z0[0] = w[2][0] * v0.x + w[2][1] * v1.x + w[2][2] * v2.x;
+      Z0[1] = w[2][0] * v0.y + w[2][1] * v1.y + w[2][2] * v2.y;
+      Z0[2] = w[2][0] * v0.z + w[2][1] * v1.z + w[2][2] * v2.z;
+      Z1[0] = wz1 * v1.x + wz2 * v2.x;
+      Z1[1] = wz1 * v1.y + wz2 * v2.y;
+      Z1[2] = wz1 * v1.z + wz2 * v2.z;
+      const float wxy = wx * w[1][oy];
 #pragma unroll
-    for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-      for (int oz = 0; oz < 3; ++oz) {
-        const float N = w[0][ox] * w[1][oy] * w[2][oz];
-        const float4 vv = vel[grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
-        const float nv[3] = {N * vv.x, N * vv.y, N * vv.z};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          S[a] += nv[a];
-          if (ox) T[3 * a + 0] += nv[a] * (float)ox;
-          if (oy) T[3 * a + 1] += nv[a] * (float)oy;
-          if (oz) T[3 * a + 2] += nv[a] * (float)oz;
-        }
+      for (int a = 0; a < 3; ++a) {
+        S[a] += wxy * Z0[a];
+        T[3 * a + 2] += wxy * Z1[a];
+        T[3 * a + 0] += (fox * wxy) * Z0[a];
+        if (oy) T[3 * a + 1] += ((float)oy * wxy) * Z0[a];
       }
+    }
+  }
+}
+
+// G2P of one particle from the global velocity grid.
+__device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const float (*w)[3],
+                                        const float4* vel, float* S, float* T) {
+  g2p_sums(w, [&](int ox, int oy, int oz) {
+    return vel[grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
+  }, S, T);
 }
 
 // ------------------------------------------------------------------ per particle
@@ -295,32 +320,13 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
   float w[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]);
-  float S[3] = {0.0f, 0.0f, 0.0f};
-  float T[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // T[a][b] = sum N v_a o_b
+  float S[3], T[9];  // T[a][b] = sum N v_a o_b
   const int l0 = base[0] - to[0], l1 = base[1] - to[1], l2 = base[2] - to[2];
   const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
                        ((unsigned)l2 <= (unsigned)(kSpan - 3));
   if (in_tile) {
     const int l = lds_index(l0, l1, l2);
-#pragma unroll
-    for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
-      for (int oy = 0; oy < 3; ++oy) {
-        const float wxy = w[0][ox] * w[1][oy];
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-          const float N = wxy * w[2][oz];
-          const float4 vv = L.v[l + lds_index(ox, oy, oz)];
-          const float nv[3] = {N * vv.x, N * vv.y, N * vv.z};
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            S[a] += nv[a];
-            if (ox) T[3 * a + 0] += nv[a] * (float)ox;
-            if (oy) T[3 * a + 1] += nv[a] * (float)oy;
-            if (oz) T[3 * a + 2] += nv[a] * (float)oz;
-          }
-        }
-      }
+    g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
   } else {
     cnt.fb++;
     g2p_global(s, base, w, vel, S, T);
@@ -390,7 +396,7 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 // ------------------------------------------------------------------ kernels
 // P2G from the materialised particle state (first substep after binning).
 template <bool FIXED>
-__global__ __launch_bounds__(kWG) void k_p2g(const float* __restrict__ part, int64_t cap,
+__global__ __launch_bounds__(kWG, 3) void k_p2g(const float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint32_t* __restrict__ occ_list, Status* st,
@@ -430,7 +436,7 @@ __global__ __launch_bounds__(kWG) void k_p2g(const float* __restrict__ part, int
 
 // Fused G2P (substep k-1) -> F, x update -> stress -> P2G (substep k).
 template <bool FIXED>
-__global__ __launch_bounds__(kWG) void k_g2p2g(float* __restrict__ part, int64_t cap,
+__global__ __launch_bounds__(kWG, 3) void k_g2p2g(float* __restrict__ part, int64_t cap,
                                                const uint32_t* __restrict__ blk_begin,
                                                const uint32_t* __restrict__ blk_end,
                                                const uint32_t* __restrict__ occ_list, Status* st,
@@ -481,7 +487,7 @@ __global__ __launch_bounds__(kWG) void k_g2p2g(float* __restrict__ part, int64_t
 }
 
 // G2P that materialises the full state (x, v, C, F) in memory.
-__global__ __launch_bounds__(kWG) void k_g2p(float* __restrict__ part, int64_t cap,
+__global__ __launch_bounds__(kWG, 3) void k_g2p(float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint32_t* __restrict__ occ_list, Status* st,
