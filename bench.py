@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--cpu-substeps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device-to-device copy of MIB MiB (a kernel of known "
+                         "traffic that scales hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -108,6 +111,15 @@ def main():
     prof = sim.profile_read() if not args.no_profile else None
     sim.close()
     assert st == 0, st
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = s.N * n_sub * args.steps / elapsed

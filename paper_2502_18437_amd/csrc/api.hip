@@ -70,6 +70,7 @@ struct mpm_handle {
   std::vector<hipEvent_t> prof_pool;
   double prof_ms[MPM_KERNEL_KINDS] = {0, 0, 0, 0, 0};
   int64_t prof_n[MPM_KERNEL_KINDS] = {0, 0, 0, 0, 0};
+  unsigned long long* scratch_u64 = nullptr;  // device word for on-demand reductions
 };
 
 namespace {
@@ -192,7 +193,7 @@ void prof_collect(mpm_handle* h) {
 void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
                   b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.act_list, b.mark,
-                  b.ovf_list[0], b.ovf_list[1], b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
+                  b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
                   b.status};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -205,8 +206,6 @@ __global__ void k_reset_status(Status* st) {
   st->n_nonfinite = 0ull;
   st->n_fallback = 0ull;
   st->n_range = 0ull;
-  st->active_nodes[0] = 0ull;
-  st->active_nodes[1] = 0ull;
   st->n_occ = 0u;
   st->n_act = 0u;
   st->ovf_count[0] = 0u;
@@ -330,6 +329,8 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   alloc((void**)&b.occ_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.node_cnt, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&h->scratch_u64, sizeof(unsigned long long));
   const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
   alloc(&b.acc_m, sizeof(float) * grid_nodes);
   for (int a = 0; a < 3; ++a) alloc(&b.acc_p[a], mom_bytes * grid_nodes);
@@ -337,6 +338,7 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   alloc((void**)&b.status, sizeof(Status));
   if (!ok) {
     free_buffers(b);
+    if (h->scratch_u64) (void)hipFree(h->scratch_u64);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
     g_create_error = "device allocation failed";
@@ -390,6 +392,7 @@ int mpm_destroy(mpm_handle* h) {
   }
   for (auto e : h->prof_pool) (void)hipEventDestroy(e);
   free_buffers(h->b);
+  if (h->scratch_u64) (void)hipFree(h->scratch_u64);
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return rc;
@@ -572,7 +575,14 @@ int mpm_get_info(mpm_handle* h, mpm_info* info) {
   info->resorts = h->resorts;
   info->occupied_blocks = st.n_occ;
   info->active_blocks = st.n_act;
-  info->active_nodes = h->substep > 0 ? (int64_t)st.active_nodes[(h->substep - 1) & 1] : 0;
+  info->active_nodes = 0;
+  if (h->N > 0 && h->substep > 0 && !h->dirty) {
+    launch_count_active_nodes(h->b, (int)((h->substep - 1) & 1), h->scratch_u64, h->stream);
+    unsigned long long cnt = 0;
+    HIP_OR_RETURN(h, hipMemcpyAsync(&cnt, h->scratch_u64, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));
+    info->active_nodes = (int64_t)cnt;
+  }
   info->n_inverted = (int64_t)st.n_inverted;
   info->n_domain = (int64_t)st.n_domain;
   info->n_nonfinite = (int64_t)st.n_nonfinite;

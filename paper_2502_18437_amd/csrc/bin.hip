@@ -343,6 +343,29 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStrea
   hipLaunchKernelGGL(k_reset_epoch, dim3(1), dim3(1), 0, st, b.status);
 }
 
+// ------------------------------------------------------------------ diagnostics
+__global__ void k_count_active_nodes(const uint32_t* __restrict__ node_cnt, const uint32_t* __restrict__ act_list,
+                                     const uint32_t* __restrict__ ovf_list, const Status* st, int parity,
+                                     unsigned long long* out) {
+  __shared__ unsigned long long sh[256];
+  const unsigned n_act = st->n_act, total = n_act + st->ovf_count[parity];
+  unsigned long long s = 0;
+  for (unsigned i = threadIdx.x; i < total; i += blockDim.x)
+    s += node_cnt[i < n_act ? act_list[i] : ovf_list[i - n_act]];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+void launch_count_active_nodes(Buffers& b, int parity, unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_active_nodes, dim3(1), dim3(256), 0, st, b.node_cnt, b.act_list,
+                     b.ovf_list[parity], b.status, parity, out);
+}
+
 // ------------------------------------------------------------------ marshalling
 __global__ void k_load(float* __restrict__ part, uint32_t* __restrict__ id, int64_t cap, int64_t N,
                        const float* __restrict__ x, const float* __restrict__ v,

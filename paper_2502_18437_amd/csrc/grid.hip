@@ -14,18 +14,19 @@
 
 namespace mpm {
 
-constexpr int kGridWG = kBlockNodes;  // one thread per node of a block
+constexpr int kGridWG = 256;
 
 __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void* __restrict__ acc_p0,
                                                   void* __restrict__ acc_p1, void* __restrict__ acc_p2,
                                                   float4* __restrict__ vel,
                                                   const uint32_t* __restrict__ act_list,
                                                   const uint32_t* __restrict__ ovf_list,
-                                                  uint32_t* mark, Status* st, int parity, SimK s,
+                                                  uint32_t* mark, uint32_t* __restrict__ node_cnt,
+                                                  Status* st, int parity, SimK s,
                                                   ToolSetK tools) {
   const unsigned n_act = st->n_act;
   const unsigned total = n_act + st->ovf_count[parity];
-  unsigned cnt = 0;
+  __shared__ unsigned blk_cnt;
   const int lo = s.band, hi = s.n - 1 - s.band;
   for (unsigned li = blockIdx.x; li < total; li += gridDim.x) {
     const bool overflow = li >= n_act;
@@ -33,6 +34,9 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
     const int bi = (int)(b % (unsigned)s.nb);
     const int bj = (int)((b / (unsigned)s.nb) % (unsigned)s.nb);
     const int bk = (int)(b / ((unsigned)s.nb * (unsigned)s.nb));
+    if (threadIdx.x == 0) blk_cnt = 0u;
+    __syncthreads();
+    unsigned cnt = 0;
     for (int l = threadIdx.x; l < kBlockNodes; l += kGridWG) {
       const size_t g = ((size_t)b << (3 * kTileLog2)) + (size_t)l;
       // Mass and momentum of the node (P2G result), then the reset.
@@ -73,19 +77,17 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
       }
       vel[g] = make_float4(v[0], v[1], v[2], 0.0f);
     }
-    if (overflow && threadIdx.x == 0) mark[b] = 0u;
+    // Nodes with mass in this block (plain store, summed on demand by the host
+    // call that reports it; a shared counter would serialise every workgroup).
+    if (cnt) atomicAdd(&blk_cnt, cnt);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      node_cnt[b] = blk_cnt;
+      if (overflow) mark[b] = 0u;
+    }
   }
-  // Clear the other parity's overflow list for the next substep; count nodes.
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->ovf_count[parity ^ 1] = 0u;
-    st->active_nodes[parity ^ 1] = 0ull;
-  }
-  __shared__ unsigned wg_cnt;
-  if (threadIdx.x == 0) wg_cnt = 0u;
-  __syncthreads();
-  if (cnt) atomicAdd(&wg_cnt, cnt);
-  __syncthreads();
-  if (threadIdx.x == 0 && wg_cnt) atomicAdd(&st->active_nodes[parity], (unsigned long long)wg_cnt);
+  // Clear the other parity's overflow list for the next substep.
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->ovf_count[parity ^ 1] = 0u;
 }
 
 void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
@@ -94,7 +96,7 @@ void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, i
   if (wgs < 1) wgs = 1;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
                      b.acc_p[2], b.vel, b.act_list,
-                     b.ovf_list[parity], b.mark, b.status, parity, s, tools);
+                     b.ovf_list[parity], b.mark, b.node_cnt, b.status, parity, s, tools);
 }
 
 }  // namespace mpm

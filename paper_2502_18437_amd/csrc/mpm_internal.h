@@ -79,7 +79,6 @@ struct Status {
   unsigned long long n_nonfinite;
   unsigned long long n_fallback;
   unsigned long long n_range;      // P2G contributions outside the fixed-point range
-  unsigned long long active_nodes[2];  // nodes with mass, per substep parity
   unsigned int n_occ;               // occupied blocks (this binning)
   unsigned int n_act;               // active blocks (this binning)
   unsigned int ovf_count[2];        // overflow blocks claimed, per parity
@@ -101,6 +100,7 @@ struct Buffers {
   uint32_t* occ_list = nullptr;             // occupied blocks
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
+  uint32_t* node_cnt = nullptr;             // per block: nodes with mass, last grid update
   uint32_t* ovf_list[2] = {nullptr, nullptr};
   void* acc_m = nullptr;                    // grid accumulator, mass channel (float or u32)
   void* acc_p[3] = {nullptr, nullptr, nullptr};  // momentum channels (float or int64)
@@ -121,6 +121,10 @@ void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t 
 // Grid update over active blocks and this parity's overflow blocks.
 void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
                  hipStream_t st);
+
+// Nodes with mass in the last grid update (sum of node_cnt over the active
+// and overflow blocks of `parity`), written to *out (device memory).
+void launch_count_active_nodes(Buffers& b, int parity, unsigned long long* out, hipStream_t st);
 
 // Stress evaluation (diagnostic entry point).
 void launch_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,

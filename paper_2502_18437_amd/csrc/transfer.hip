@@ -24,7 +24,7 @@
 namespace mpm {
 
 constexpr int kXcds = 8;
-constexpr int kWG = 256;
+constexpr int kWG = 512;
 constexpr double kMagic = 6755399441055744.0;           // 1.5 * 2^52
 constexpr long long kMagicBits = 0x4338000000000000LL;  // its bit pattern
 constexpr float kWeightUnits = 16777216.0f;            // 2^24
@@ -396,7 +396,7 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 // ------------------------------------------------------------------ kernels
 // P2G from the materialised particle state (first substep after binning).
 template <bool FIXED>
-__global__ __launch_bounds__(kWG, 3) void k_p2g(const float* __restrict__ part, int64_t cap,
+__global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint32_t* __restrict__ occ_list, Status* st,
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kWG, 3) void k_p2g(const float* __restrict__ part, 
 
 // Fused G2P (substep k-1) -> F, x update -> stress -> P2G (substep k).
 template <bool FIXED>
-__global__ __launch_bounds__(kWG, 3) void k_g2p2g(float* __restrict__ part, int64_t cap,
+__global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int64_t cap,
                                                const uint32_t* __restrict__ blk_begin,
                                                const uint32_t* __restrict__ blk_end,
                                                const uint32_t* __restrict__ occ_list, Status* st,
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(kWG, 3) void k_g2p2g(float* __restrict__ part, int6
 }
 
 // G2P that materialises the full state (x, v, C, F) in memory.
-__global__ __launch_bounds__(kWG, 3) void k_g2p(float* __restrict__ part, int64_t cap,
+__global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint32_t* __restrict__ occ_list, Status* st,
