@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpm_oracle.so")
 
-TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE = 0, 1, 2, 3
+TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE, TOOL_SLICER, TOOL_SEGMENT, TOOL_ARC = 0, 1, 2, 3, 4, 5, 6
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDOMAIN, ST_ENONFINITE, ST_EINVERTED = 0, -1, -2, -4, -5, -6
 
 _lib = None
@@ -52,6 +52,9 @@ def lib():
         L.oracle_sdf.restype = ctypes.c_double
         L.oracle_sdf.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
         L.oracle_contact.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_node_contact.restype = ctypes.c_int
+        L.oracle_node_contact.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, dp, dp]
         _lib = L
     return _lib
 
@@ -110,6 +113,16 @@ def contact(n, u, mu, drag):
     o, po = _d(np.zeros(3))
     lib().oracle_contact(pn, pu, float(mu), float(drag), po)
     return o.copy()
+
+
+def node_contact(tool_type, center, quat, size, lin_vel, ang_vel, mu, drag, margin, xI, vI):
+    """(velocity after contact, in_contact) of one node and one tool."""
+    args = [_d(a) for a in (center, quat, size, lin_vel, ang_vel)]
+    x, px = _d(xI)
+    v, pv = _d(np.array(vI, dtype=np.float64))
+    hit = lib().oracle_node_contact(int(tool_type), *[p for _, p in args], float(mu), float(drag),
+                                    float(margin), px, pv)
+    return v.copy(), bool(hit)
 
 
 # ---------------------------------------------------------------- scene object

@@ -16,7 +16,7 @@ Readings of the paper are the ones the C++ oracle states in its header.
 """
 import numpy as np
 
-TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE = 0, 1, 2, 3
+TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE, TOOL_SLICER, TOOL_SEGMENT, TOOL_ARC = 0, 1, 2, 3, 4, 5, 6
 
 
 def kernel(r):
@@ -97,6 +97,78 @@ def sdf_nodes(tool, pts):
     return phi, g
 
 
+def _friction(u, un, tg_vec, tg_len, mu, drag):
+    """Corrected relative velocity for approaching nodes: the kept tangential
+    vector scaled by c_d max(1 + mu u_n / |t|, 0) (0 where |t| = 0)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        k = np.where(tg_len > 0, np.maximum(1.0 + mu * un / np.where(tg_len > 0, tg_len, 1.0), 0.0), 0.0)
+    return drag * k[:, None] * tg_vec
+
+
+def thin_tool_contact(tool, pts, vel):
+    """Slicer, line segment and arc contact (Sec. IV-B/IV-C) on nodes
+    (M, 3) with velocities (M, 3); returns (new velocities, hit mask)."""
+    R = quat_matrix(tool["quat"])
+    c = np.asarray(tool["center"], dtype=np.float64)
+    size = np.asarray(tool["size"], dtype=np.float64)
+    r = pts - c
+    pl = r @ R
+    M = pts.shape[0]
+    vr = np.asarray(tool["lv"]) + np.cross(np.asarray(tool["av"]), r)
+    u = vel - vr
+    t = tool["type"]
+    out = vel.copy()
+    if t == TOOL_SLICER:
+        hx, hy = size[0], size[1]
+        qx = np.maximum(np.abs(pl[:, 0]) - hx, 0.0)
+        qy = np.maximum(np.abs(pl[:, 1]) - hy, 0.0)
+        d = np.sqrt(qx * qx + qy * qy + pl[:, 2] ** 2)
+        hit = d < tool["margin"]
+        spine = hit & (pl[:, 1] > hy)
+        face = hit & ~spine
+        nl = np.zeros((M, 3))
+        nl[:, 2] = np.where(pl[:, 2] < 0, -1.0, 1.0)
+        n = nl @ R.T
+        un = np.einsum("ia,ia->i", n, u)
+        tv = u - un[:, None] * n
+        unew = _friction(u, un, tv, np.linalg.norm(tv, axis=1), tool["mu"], tool["drag"])
+        app = face & (un < 0)
+        out[app] = vr[app] + unew[app]
+        out[spine] = vr[spine]
+        return out, hit
+    if t == TOOL_SEGMENT:
+        h, thick = size[0], size[1]
+        proj = np.zeros((M, 3))
+        proj[:, 0] = np.clip(pl[:, 0], -h, h)
+        tl = np.tile([1.0, 0.0, 0.0], (M, 1))
+    elif t == TOOL_ARC:
+        ra, ha, thick = size[0], size[1], size[2]
+        ang = np.arctan2(pl[:, 1], pl[:, 0])
+        outside = (ang > ha) | (ang < -ha)
+        e0 = np.array([ra * np.cos(ha), ra * np.sin(ha)])
+        e1 = np.array([ra * np.cos(-ha), ra * np.sin(-ha)])
+        d0 = ((pl[:, :2] - e0) ** 2).sum(axis=1)
+        d1 = ((pl[:, :2] - e1) ** 2).sum(axis=1)
+        ang = np.where(outside, np.where(d1 < d0, -ha, ha), ang)
+        proj = np.stack([ra * np.cos(ang), ra * np.sin(ang), np.zeros(M)], axis=1)
+        tl = np.stack([-np.sin(ang), np.cos(ang), np.zeros(M)], axis=1)
+    else:
+        raise ValueError(t)
+    e = pl - proj
+    L = np.linalg.norm(e, axis=1)
+    hit = L < thick
+    nl = np.where(L[:, None] > 0, e / np.where(L > 0, L, 1.0)[:, None],
+                  np.stack([-tl[:, 1], tl[:, 0], np.zeros(M)], axis=1))
+    n = nl @ R.T
+    tg = tl @ R.T
+    un = np.einsum("ia,ia->i", n, u)
+    ut = np.einsum("ia,ia->i", tg, u)
+    unew = _friction(u, un, ut[:, None] * tg, np.abs(ut), tool["mu"], tool["drag"])
+    app = hit & (un < 0)
+    out[app] = vr[app] + unew[app]
+    return out, hit
+
+
 class Brute:
     def __init__(self, n_grid, dt, gravity=(0.0, -9.8, 0.0), wall_band=3, nu=0.3, E_default=5e3):
         self.n = int(n_grid)
@@ -167,6 +239,11 @@ class Brute:
             t = self.tools[tid]
             c = t["center0"] + (self.substep - t["set_at"]) * dt * t["lv"]
             tt = dict(t, center=c)
+            if t["type"] in (TOOL_SLICER, TOOL_SEGMENT, TOOL_ARC):
+                vnew, hit = thin_tool_contact(tt, self.xI, vI)
+                hit = hit & has
+                vI[hit] = vnew[hit]
+                continue
             phi, nrm = sdf_nodes(tt, self.xI)
             hit = has & (phi < t["margin"])
             r = self.xI - c

@@ -37,6 +37,16 @@
 //     tangential part (u' = 0 if |t| = 0); otherwise unchanged. Tools are
 //     applied in id order at their pose at the start of the substep, then
 //     sticky walls (band of B nodes per face). Empty nodes get v = 0.
+//   * Cutting and suturing geometries (Sec. IV-B, IV-C): a slicer is a
+//     rectangle in its body x-y plane whose side is the sign of body z; a node
+//     within the fattened distance `margin` of it gets the contact law with
+//     normal +-body z on its own side, except beyond the spine edge (body
+//     y > half height), where the field is the distance to the spine and the
+//     contact is sticky (relative velocity 0). A line segment (body x axis)
+//     and an arc (body x-y plane, centred on the tool) have the unsigned
+//     distance to the curve; a node within the thickness keeps only the
+//     part of its relative velocity along the curve tangent, corrected by
+//     friction and drag, unless it separates.
 //   * Errors: a particle whose stencil leaves the grid (EDOMAIN) or whose
 //     state is not finite (ENONFINITE) is left unchanged for that substep;
 //     det F <= 0 is counted (EINVERTED). Status precedence:
@@ -58,7 +68,7 @@ enum {
   ST_EINVERTED = -6,
 };
 
-enum { TOOL_NONE = 0, TOOL_CAPSULE = 1, TOOL_BOX = 2, TOOL_PLANE = 3 };
+enum { TOOL_NONE = 0, TOOL_CAPSULE = 1, TOOL_BOX = 2, TOOL_PLANE = 3, TOOL_SLICER = 4, TOOL_SEGMENT = 5, TOOL_ARC = 6 };
 constexpr int kMaxTools = 8;
 
 // ---------------------------------------------------------------- 3x3 algebra
@@ -337,6 +347,110 @@ void contact_correct(const double* n, const double* u, double mu, double drag, d
   out[0] = k * t[0], out[1] = k * t[1], out[2] = k * t[2];
 }
 
+// Contact law of the 1D geometries (Sec. IV-C): the tangential part of eq.
+// v_correction is replaced by the part along the curve tangent tg; the
+// cross-section and normal parts are dropped unless the node separates.
+void contact_tangent(const double* n, const double* tg, const double* u, double mu, double drag,
+                     double* out) {
+  const double un = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+  if (!(un < 0.0)) {
+    out[0] = u[0], out[1] = u[1], out[2] = u[2];
+    return;
+  }
+  const double ut = tg[0] * u[0] + tg[1] * u[1] + tg[2] * u[2];
+  const double s = std::fabs(ut);
+  if (!(s > 0.0)) {
+    out[0] = out[1] = out[2] = 0.0;
+    return;
+  }
+  double k = 1.0 + mu * un / s;
+  if (k < 0.0) k = 0.0;
+  k *= drag * ut;
+  out[0] = k * tg[0], out[1] = k * tg[1], out[2] = k * tg[2];
+}
+
+void rotate(const double* R, const double* a, double* out) {
+  for (int i = 0; i < 3; ++i) out[i] = R[3 * i] * a[0] + R[3 * i + 1] * a[1] + R[3 * i + 2] * a[2];
+}
+
+// Contact of one node (position xI, velocity vI) with one tool centred at c.
+// Returns true when the tool changed the velocity field (node in contact).
+bool tool_node_contact(int type, const double* c, const double* R, const double* size, const double* lv,
+                       const double* av, double mu, double drag, double margin, const double* xI,
+                       double* vI) {
+  const double r[3] = {xI[0] - c[0], xI[1] - c[1], xI[2] - c[2]};
+  double pl[3];
+  for (int i = 0; i < 3; ++i) pl[i] = R[0 * 3 + i] * r[0] + R[1 * 3 + i] * r[1] + R[2 * 3 + i] * r[2];
+  const double vr[3] = {lv[0] + av[1] * r[2] - av[2] * r[1], lv[1] + av[2] * r[0] - av[0] * r[2],
+                        lv[2] + av[0] * r[1] - av[1] * r[0]};
+  const double u[3] = {vI[0] - vr[0], vI[1] - vr[1], vI[2] - vr[2]};
+  double un[3];
+  if (type == TOOL_CAPSULE || type == TOOL_BOX || type == TOOL_PLANE) {
+    double grad[3];
+    const double phi = tool_sdf(type, c, R, size, xI, grad);
+    if (!(phi < margin)) return false;
+    const double gn = std::sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
+    const double nrm[3] = {grad[0] / gn, grad[1] / gn, grad[2] / gn};
+    contact_correct(nrm, u, mu, drag, un);
+  } else if (type == TOOL_SLICER) {
+    const double hx = size[0], hy = size[1];
+    const double qx = std::fabs(pl[0]) - hx > 0.0 ? std::fabs(pl[0]) - hx : 0.0;
+    const double qy = std::fabs(pl[1]) - hy > 0.0 ? std::fabs(pl[1]) - hy : 0.0;
+    const double d = std::sqrt(qx * qx + qy * qy + pl[2] * pl[2]);
+    if (!(d < margin)) return false;
+    if (pl[1] > hy) {
+      un[0] = un[1] = un[2] = 0.0;  // spine side: sticky
+    } else {
+      const double nl[3] = {0.0, 0.0, pl[2] < 0.0 ? -1.0 : 1.0};
+      double nrm[3];
+      rotate(R, nl, nrm);
+      contact_correct(nrm, u, mu, drag, un);
+    }
+  } else if (type == TOOL_SEGMENT || type == TOOL_ARC) {
+    double proj[3], tl[3];
+    double thick;
+    if (type == TOOL_SEGMENT) {
+      const double h = size[0];
+      thick = size[1];
+      double t = pl[0];
+      if (t < -h) t = -h;
+      if (t > h) t = h;
+      proj[0] = t, proj[1] = 0.0, proj[2] = 0.0;
+      tl[0] = 1.0, tl[1] = 0.0, tl[2] = 0.0;
+    } else {
+      const double ra = size[0], ha = size[1];
+      thick = size[2];
+      double ang = std::atan2(pl[1], pl[0]);
+      if (ang > ha || ang < -ha) {  // nearest end point
+        const double e0[2] = {ra * std::cos(ha), ra * std::sin(ha)};
+        const double e1[2] = {ra * std::cos(-ha), ra * std::sin(-ha)};
+        const double d0 = (pl[0] - e0[0]) * (pl[0] - e0[0]) + (pl[1] - e0[1]) * (pl[1] - e0[1]);
+        const double d1 = (pl[0] - e1[0]) * (pl[0] - e1[0]) + (pl[1] - e1[1]) * (pl[1] - e1[1]);
+        ang = (d1 < d0) ? -ha : ha;
+      }
+      proj[0] = ra * std::cos(ang), proj[1] = ra * std::sin(ang), proj[2] = 0.0;
+      tl[0] = -std::sin(ang), tl[1] = std::cos(ang), tl[2] = 0.0;
+    }
+    double e[3] = {pl[0] - proj[0], pl[1] - proj[1], pl[2] - proj[2]};
+    const double L = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (!(L < thick)) return false;
+    double nl[3];
+    if (L > 0.0) {
+      nl[0] = e[0] / L, nl[1] = e[1] / L, nl[2] = e[2] / L;
+    } else {  // on the curve: the body direction orthogonal to the tangent in the x-y plane
+      nl[0] = -tl[1], nl[1] = tl[0], nl[2] = 0.0;
+    }
+    double nrm[3], tg[3];
+    rotate(R, nl, nrm);
+    rotate(R, tl, tg);
+    contact_tangent(nrm, tg, u, mu, drag, un);
+  } else {
+    return false;
+  }
+  for (int a = 0; a < 3; ++a) vI[a] = vr[a] + un[a];
+  return true;
+}
+
 // -------------------------------------------------------------------- scene
 struct Scene {
   int n = 0;
@@ -447,22 +561,13 @@ void substep(Scene& s) {
         for (int q = 0; q < kMaxTools; ++q) {
           const Tool& t = s.tools[q];
           if (t.type == TOOL_NONE) continue;
-          double grad[3];
-          const double phi = tool_sdf(t.type, poses[q], t.R, t.size, xI, grad);
-          if (!(phi < t.margin)) continue;
-          const double gn = std::sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
-          const double nrm[3] = {grad[0] / gn, grad[1] / gn, grad[2] / gn};
-          const double r[3] = {xI[0] - poses[q][0], xI[1] - poses[q][1], xI[2] - poses[q][2]};
-          const double vr[3] = {t.lv[0] + t.av[1] * r[2] - t.av[2] * r[1],
-                                t.lv[1] + t.av[2] * r[0] - t.av[0] * r[2],
-                                t.lv[2] + t.av[0] * r[1] - t.av[1] * r[0]};
-          const double u[3] = {vI[0] - vr[0], vI[1] - vr[1], vI[2] - vr[2]};
-          double un[3];
-          contact_correct(nrm, u, t.mu, t.drag, un);
+          double vnew[3] = {vI[0], vI[1], vI[2]};
+          if (!tool_node_contact(t.type, poses[q], t.R, t.size, t.lv, t.av, t.mu, t.drag, t.margin, xI,
+                                 vnew))
+            continue;
           for (int a = 0; a < 3; ++a) {
-            const double vnew = vr[a] + un[a];
-            s.impulse[q][a] += m * (vnew - vI[a]);
-            vI[a] = vnew;
+            s.impulse[q][a] += m * (vnew[a] - vI[a]);
+            vI[a] = vnew[a];
           }
         }
         const int lo = s.band, hi = s.n - 1 - s.band;
@@ -587,7 +692,7 @@ int oracle_set_tool(void* h, int id, int type, const double* center, const doubl
                     const double* size, const double* lin_vel, const double* ang_vel,
                     double mu, double drag, double margin) {
   Scene* s = static_cast<Scene*>(h);
-  if (!s || id < 0 || id >= kMaxTools || type < TOOL_NONE || type > TOOL_PLANE) return ST_EINVAL;
+  if (!s || id < 0 || id >= kMaxTools || type < TOOL_NONE || type > TOOL_ARC) return ST_EINVAL;
   Tool& t = s->tools[id];
   t = Tool();
   t.type = type;
@@ -673,6 +778,15 @@ double oracle_sdf(int type, const double* center, const double* quat, const doub
 }
 void oracle_contact(const double* n, const double* u, double mu, double drag, double* out) {
   contact_correct(n, u, mu, drag, out);
+}
+// Velocity of a node at xI after contact with one tool (all geometries);
+// returns 1 if the node was in contact.
+int oracle_node_contact(int type, const double* center, const double* quat, const double* size,
+                        const double* lin_vel, const double* ang_vel, double mu, double drag, double margin,
+                        const double* xI, double* vI) {
+  double R[9];
+  quat_to_matrix(quat, R);
+  return tool_node_contact(type, center, R, size, lin_vel, ang_vel, mu, drag, margin, xI, vI) ? 1 : 0;
 }
 
 }  // extern "C"
