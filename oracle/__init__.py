@@ -55,6 +55,19 @@ def lib():
         L.oracle_node_contact.restype = ctypes.c_int
         L.oracle_node_contact.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, dp, dp]
+        L.oracle_set_state_f64.argtypes = [ctypes.c_void_p, ctypes.c_longlong, dp, dp, dp, dp, dp,
+                                           ctypes.c_double, ctypes.c_double]
+        L.oracle_set_velocity_table.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, dp]
+        L.oracle_rollout_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp,
+                                             dp, dp]
+        L.oracle_polar_adjoint.argtypes = [dp, dp, dp]
+        L.oracle_kirchhoff_adjoint.restype = ctypes.c_double
+        L.oracle_kirchhoff_adjoint.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_frame_contact.restype = ctypes.c_int
+        L.oracle_frame_contact.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, dp, dp]
+        L.oracle_contact_adjoint.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -125,6 +138,48 @@ def node_contact(tool_type, center, quat, size, lin_vel, ang_vel, mu, drag, marg
     return v.copy(), bool(hit)
 
 
+def polar_adjoint(F, Rb):
+    """Cotangent of F for a cotangent Rb of its rotation factor."""
+    F, pF = _d(np.asarray(F).reshape(9))
+    Rb, pRb = _d(np.asarray(Rb).reshape(9))
+    o, po = _d(np.zeros(9))
+    lib().oracle_polar_adjoint(pF, pRb, po)
+    return o.reshape(3, 3)
+
+
+def kirchhoff_adjoint(F, E, nu, taub):
+    """(cotangent of F, d/d log E) for a cotangent taub of the Kirchhoff stress."""
+    F, pF = _d(np.asarray(F).reshape(9))
+    t, pt = _d(np.asarray(taub).reshape(9))
+    o, po = _d(np.zeros(9))
+    th = lib().oracle_kirchhoff_adjoint(pF, float(E), float(nu), pt, po)
+    return o.reshape(3, 3), th
+
+
+def frame_contact(tool_type, center, quat, size, lin_vel, ang_vel, mu, drag, margin, xI, vI):
+    """(velocity after contact, law code) through the differentiable contact frame."""
+    args = [_d(a) for a in (center, quat, size, lin_vel, ang_vel)]
+    x, px = _d(xI)
+    v, pv = _d(np.array(vI, dtype=np.float64))
+    law = lib().oracle_frame_contact(int(tool_type), *[p for _, p in args], float(mu), float(drag),
+                                     float(margin), px, pv)
+    return v.copy(), int(law)
+
+
+def contact_adjoint(tool_type, center, quat, size, lin_vel, ang_vel, mu, drag, margin, xI, vin, vbar):
+    """Cotangents (of the input velocity, of the tool centre, of its linear
+    velocity) of one node's contact map for a cotangent vbar of its output."""
+    args = [_d(a) for a in (center, quat, size, lin_vel, ang_vel)]
+    x, px = _d(xI)
+    vi, pvi = _d(vin)
+    vb, pvb = _d(np.array(vbar, dtype=np.float64))
+    cb, pcb = _d(np.zeros(3))
+    lb, plb = _d(np.zeros(3))
+    lib().oracle_contact_adjoint(int(tool_type), *[p for _, p in args], float(mu), float(drag), float(margin),
+                                 px, pvi, pvb, pcb, plb)
+    return vb.copy(), cb.copy(), lb.copy()
+
+
 # ---------------------------------------------------------------- scene object
 class Oracle:
     """One scene on the FP64 oracle. Inputs are the FP32 arrays the GPU
@@ -161,6 +216,54 @@ class Oracle:
         st = lib().oracle_set_particles(self.h, self.N, px, *ptrs, float(mass), float(vol0))
         if st != 0:
             raise ValueError(f"oracle_set_particles: status {st}")
+
+    def set_state_f64(self, x, v=None, C=None, F=None, E=None, mass=1.0, vol0=1.0):
+        """FP64 state, for finite-difference checks."""
+        x, px = _d(np.asarray(x).reshape(-1, 3))
+        keep, ptrs = [x], []
+        for a in (v, C, F, E):
+            if a is None:
+                ptrs.append(None)
+            else:
+                arr, p = _d(np.asarray(a).reshape(-1))
+                keep.append(arr)
+                ptrs.append(p)
+        self.N = x.shape[0]
+        st = lib().oracle_set_state_f64(self.h, self.N, px, *ptrs, float(mass), float(vol0))
+        if st != 0:
+            raise ValueError(f"oracle_set_state_f64: status {st}")
+
+    def set_velocity_table(self, tool_id, table):
+        """Per-substep linear velocities (T x 3) of a tool from now on."""
+        t, pt = _d(np.asarray(table, dtype=np.float64).reshape(-1, 3))
+        st = lib().oracle_set_velocity_table(self.h, int(tool_id), t.shape[0], pt)
+        if st != 0:
+            raise ValueError(f"oracle_set_velocity_table: status {st}")
+
+    def rollout_adjoint(self, T, xb=None, vb=None, Cb=None, Fb=None):
+        """Advance T substeps and return the reverse-mode gradient for the
+        seeds (cotangents of the final x, v, C, F): a dict with theta
+        (d/d log E per particle), vel (8 x T x 3, per tool and substep
+        linear velocity), x0, v0, C0, F0 (cotangent of the starting state)
+        and status."""
+        N = self.N
+        seeds = []
+        keep = []
+        for a in (xb, vb, Cb, Fb):
+            if a is None:
+                seeds.append(None)
+            else:
+                arr, p = _d(np.asarray(a).reshape(-1))
+                keep.append(arr)
+                seeds.append(p)
+        th, pth = _d(np.zeros(N))
+        vel, pvel = _d(np.zeros((8, int(T), 3)))
+        outs = [_d(np.zeros(shape)) for shape in ((N, 3), (N, 3), (N, 3, 3), (N, 3, 3))]
+        st = lib().oracle_rollout_adjoint(self.h, int(T), *seeds, pth, pvel, *[p for _, p in outs])
+        r = {"theta": th, "vel": vel, "status": st}
+        for k, (arr, _) in zip(("x0", "v0", "C0", "F0"), outs):
+            r[k] = arr
+        return r
 
     def set_tool(self, tool_id, tool_type, center=(0, 0, 0), quat=(1, 0, 0, 0), size=(0, 0, 0),
                  lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0):

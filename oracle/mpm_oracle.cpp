@@ -263,6 +263,7 @@ struct Tool {
   double av[3] = {0, 0, 0};   // angular velocity (enters v_r only)
   double mu = 0.0, drag = 1.0, margin = 0.0;
   long long set_at = 0;       // substep counter when the tool was set
+  std::vector<double> vtab;   // optional per-substep linear velocities (T x 3) from set_at on
 };
 
 void quat_to_matrix(const double* q, double* R) {
@@ -490,17 +491,41 @@ bool stencil(const Scene& s, const double* xp, int* base, double* f) {
   return true;
 }
 
-void substep(Scene& s) {
+// Pose (centre) and linear velocity of tool q during substep k (Sec. V,
+// a shape's velocity is set per step; the pose follows kinematically). With
+// no velocity table the pose is the closed form c0 + (k - set_at) dt v; with
+// a table of T rows, substep set_at + j uses row j and the pose is c0 plus dt
+// times the sum of the rows before it; past the table the constant velocity
+// resumes from the pose at its end.
+void tool_kinematics(const Scene& s, int q, long long k, double* pose, double* vel) {
+  const Tool& t = s.tools[q];
+  const long long rel = k - t.set_at;
+  const long long T = static_cast<long long>(t.vtab.size() / 3);
+  if (T == 0) {
+    const double el = static_cast<double>(rel) * s.dt;
+    for (int a = 0; a < 3; ++a) pose[a] = t.c0[a] + el * t.lv[a], vel[a] = t.lv[a];
+    return;
+  }
+  const long long m = rel < T ? rel : T;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long long j = 0; j < m; ++j)
+    for (int a = 0; a < 3; ++a) acc[a] += t.vtab[3 * j + a];
+  for (int a = 0; a < 3; ++a) {
+    pose[a] = t.c0[a] + s.dt * acc[a] + static_cast<double>(rel - m) * s.dt * t.lv[a];
+    vel[a] = rel < T ? t.vtab[3 * rel + a] : t.lv[a];
+  }
+}
+
+// Stage 4 of the previous step, done first (Algorithm 1, reset grid), then
+// P2G: mass and fused momentum/force transfer (Algorithm 1, first loop).
+// Marks the particles that are skipped this substep.
+void p2g(Scene& s, std::vector<char>& skip) {
   const double dx = s.dx, dt = s.dt;
   const double Minv = 4.0 / (dx * dx);
-  const size_t nn = static_cast<size_t>(s.n) * s.n * s.n;
-  // Stage 4 of the previous step, done first (Algorithm 1, reset grid).
   std::fill(s.gm.begin(), s.gm.end(), 0.0);
   std::fill(s.gp.begin(), s.gp.end(), 0.0);
   std::fill(s.gv.begin(), s.gv.end(), 0.0);
-  std::vector<char> skip(static_cast<size_t>(s.N), 0);
-
-  // ---- P2G: mass and fused momentum/force transfer (Algorithm 1, first loop)
+  skip.assign(static_cast<size_t>(s.N), 0);
   for (long long p = 0; p < s.N; ++p) {
     const double* xp = &s.x[3 * p];
     const double* vp = &s.v[3 * p];
@@ -541,14 +566,18 @@ void substep(Scene& s) {
           }
         }
   }
+}
 
-  // ---- Grid update: velocity, gravity, contact, walls (Algorithm 1, second loop)
-  double poses[kMaxTools][3];
-  for (int k = 0; k < kMaxTools; ++k) {
-    const Tool& t = s.tools[k];
-    const double el = static_cast<double>(s.substep - t.set_at) * dt;
-    for (int a = 0; a < 3; ++a) poses[k][a] = t.c0[a] + el * t.lv[a];
-  }
+inline bool wall_node(const Scene& s, int i, int j, int k) {
+  const int lo = s.band, hi = s.n - 1 - s.band;
+  return i < lo || i > hi || j < lo || j > hi || k < lo || k > hi;
+}
+
+// Grid update: velocity, gravity, contact, walls (Algorithm 1, second loop).
+void grid_update(Scene& s) {
+  const double dx = s.dx, dt = s.dt;
+  double poses[kMaxTools][3], vels[kMaxTools][3];
+  for (int q = 0; q < kMaxTools; ++q) tool_kinematics(s, q, s.substep, poses[q], vels[q]);
   for (int i = 0; i < s.n; ++i)
     for (int j = 0; j < s.n; ++j)
       for (int k = 0; k < s.n; ++k) {
@@ -562,7 +591,7 @@ void substep(Scene& s) {
           const Tool& t = s.tools[q];
           if (t.type == TOOL_NONE) continue;
           double vnew[3] = {vI[0], vI[1], vI[2]};
-          if (!tool_node_contact(t.type, poses[q], t.R, t.size, t.lv, t.av, t.mu, t.drag, t.margin, xI,
+          if (!tool_node_contact(t.type, poses[q], t.R, t.size, vels[q], t.av, t.mu, t.drag, t.margin, xI,
                                  vnew))
             continue;
           for (int a = 0; a < 3; ++a) {
@@ -570,8 +599,7 @@ void substep(Scene& s) {
             vI[a] = vnew[a];
           }
         }
-        const int lo = s.band, hi = s.n - 1 - s.band;
-        if (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi) {
+        if (wall_node(s, i, j, k)) {
           for (int a = 0; a < 3; ++a) {
             s.impulse[kMaxTools][a] += m * (0.0 - vI[a]);
             vI[a] = 0.0;
@@ -579,8 +607,12 @@ void substep(Scene& s) {
         }
         for (int a = 0; a < 3; ++a) s.gv[3 * I + a] = vI[a];
       }
+}
 
-  // ---- G2P: velocity, affine matrix, F, position (Algorithm 1, third loop)
+// G2P: velocity, affine matrix, F, position (Algorithm 1, third loop).
+void g2p(Scene& s, const std::vector<char>& skip) {
+  const double dx = s.dx, dt = s.dt;
+  const double Minv = 4.0 / (dx * dx);
   for (long long p = 0; p < s.N; ++p) {
     if (skip[p]) continue;
     double* xp = &s.x[3 * p];
@@ -614,8 +646,514 @@ void substep(Scene& s) {
       xp[a] += dt * vn[a];
     }
   }
+}
+
+void substep(Scene& s) {
+  std::vector<char> skip;
+  p2g(s, skip);
+  grid_update(s);
+  g2p(s, skip);
   s.substep++;
-  (void)nn;
+}
+
+// ============================================================ adjoint
+// Reverse-mode derivative of the substep above (the differentiable rollout
+// the paper motivates in Sec. I and V: gradients of a loss on the final state
+// with respect to per-particle stiffness and the tools' per-substep
+// velocities). Each stage is differentiated as written, in reverse order;
+// contact sets, stencil bases and clamps are held fixed (derivatives are
+// taken where the forward map is smooth).
+
+// cof(F) = det(F) F^-T, the derivative of det F.
+void cofactor(const double* F, double* out) {
+  out[0] = F[4] * F[8] - F[5] * F[7];
+  out[1] = F[5] * F[6] - F[3] * F[8];
+  out[2] = F[3] * F[7] - F[4] * F[6];
+  out[3] = F[2] * F[7] - F[1] * F[8];
+  out[4] = F[0] * F[8] - F[2] * F[6];
+  out[5] = F[1] * F[6] - F[0] * F[7];
+  out[6] = F[1] * F[5] - F[2] * F[4];
+  out[7] = F[2] * F[3] - F[0] * F[5];
+  out[8] = F[0] * F[4] - F[1] * F[3];
+}
+
+// Solve the 3x3 system A y = b by Cramer's rule.
+void solve3(const double* A, const double* b, double* y) {
+  double cof[9];
+  cofactor(A, cof);
+  const double det = mat_det(A);
+  for (int i = 0; i < 3; ++i) y[i] = (cof[0 * 3 + i] * b[0] + cof[1 * 3 + i] * b[1] + cof[2 * 3 + i] * b[2]) / det;
+}
+
+// Adjoint of the rotation factor R of F = R S (S symmetric). Write dR = R W
+// with W = [w]x skew. R^T F = S stays symmetric, so with K = R^T dF,
+// K - K^T = W S + S W = [(tr(S) I - S) w]x, i.e. (tr(S) I - S) w = k(K) with
+// k(K) = (K21 - K12, K02 - K20, K10 - K01). For a cotangent Rb of R,
+// <Rb, dR> = <R^T Rb, W> = k(R^T Rb) . w = y . k(K) = <R [y]x, dF>, where
+// (tr(S) I - S) y = k(R^T Rb); hence Fb += R [y]x.
+void polar_adjoint(const double* F, const double* R, const double* Rb, double* Fb) {
+  double Rt[9], S[9], M[9];
+  mat_transpose(R, Rt);
+  mat_mul(Rt, F, S);
+  mat_mul(Rt, Rb, M);
+  const double m[3] = {M[7] - M[5], M[2] - M[6], M[3] - M[1]};
+  const double tr = S[0] + S[4] + S[8];
+  double G[9];
+  for (int i = 0; i < 9; ++i) G[i] = -0.5 * (S[i] + S[(i % 3) * 3 + i / 3]);
+  G[0] += tr, G[4] += tr, G[8] += tr;
+  double y[3];
+  solve3(G, m, y);
+  const double Y[9] = {0.0, -y[2], y[1], y[2], 0.0, -y[0], -y[1], y[0], 0.0};
+  double RY[9];
+  mat_mul(R, Y, RY);
+  for (int i = 0; i < 9; ++i) Fb[i] += RY[i];
+}
+
+// Adjoint of the Kirchhoff stress: for a cotangent taub of tau(F, E), adds
+// dL/dF to Fb and returns dL/d(log E) = taub : tau (tau is linear in E).
+double kirchhoff_adjoint(const double* F, double E, double nu, const double* taub, double* Fb) {
+  double mu, la, R[9], tau[9];
+  lame(E, nu, &mu, &la);
+  kirchhoff(F, E, nu, tau);
+  const double J = polar_rotation(F, R);
+  double th = 0.0;
+  for (int i = 0; i < 9; ++i) th += taub[i] * tau[i];
+  // tau1 = 2 mu (F - R) F^T: Fb += 2 mu (taub F + taub^T (F - R)), Rb = -2 mu taub F.
+  double tbF[9], tbt[9], D[9], tbtD[9];
+  mat_mul(taub, F, tbF);
+  mat_transpose(taub, tbt);
+  for (int i = 0; i < 9; ++i) D[i] = F[i] - R[i];
+  mat_mul(tbt, D, tbtD);
+  double Rb[9];
+  for (int i = 0; i < 9; ++i) {
+    Fb[i] += 2.0 * mu * (tbF[i] + tbtD[i]);
+    Rb[i] = -2.0 * mu * tbF[i];
+  }
+  polar_adjoint(F, R, Rb, Fb);
+  // tau2 = lambda (J^2 - J) I: Fb += lambda (2J - 1) tr(taub) cof(F).
+  double cof[9];
+  cofactor(F, cof);
+  const double k = la * (2.0 * J - 1.0) * (taub[0] + taub[4] + taub[8]);
+  for (int i = 0; i < 9; ++i) Fb[i] += k * cof[i];
+  return th;
+}
+
+// Derivative of the quadratic B-spline weights with respect to f.
+void bspline_dweights(double f, double* dw) {
+  dw[0] = -(1.5 - f);
+  dw[1] = -2.0 * (f - 1.0);
+  dw[2] = f - 0.5;
+}
+
+enum { LAW_NONE = 0, LAW_CORRECT = 1, LAW_TANGENT = 2, LAW_STICKY = 3 };
+
+// Contact frame of one node and one tool: which law applies, the outward
+// normal n and (1D geometries) the curve tangent tg, and their derivatives
+// Jn = dn/dxI, Jt = dtg/dxI (row-major, world frame). The geometry is the
+// one tool_node_contact evaluates; it is re-derived here with derivatives.
+int contact_frame(int type, const double* c, const double* R, const double* size, double margin,
+                  const double* xI, double* n, double* tg, double* Jn, double* Jt) {
+  const double r[3] = {xI[0] - c[0], xI[1] - c[1], xI[2] - c[2]};
+  double pl[3];
+  for (int i = 0; i < 3; ++i) pl[i] = R[0 * 3 + i] * r[0] + R[1 * 3 + i] * r[1] + R[2 * 3 + i] * r[2];
+  double nl[3] = {0.0, 1.0, 0.0}, tl[3] = {0.0, 0.0, 0.0};
+  double Jl[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Jtl[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int law = LAW_NONE;
+  // d(e/|e|)/dpl for e with de/dpl = De.
+  auto unit_jac = [](const double* e, double L, const double* De, double* nout, double* Jout) {
+    for (int i = 0; i < 3; ++i) nout[i] = e[i] / L;
+    double P[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P[3 * i + j] = ((i == j) ? 1.0 : 0.0) - nout[i] * nout[j];
+    mat_mul(P, De, Jout);
+    for (int i = 0; i < 9; ++i) Jout[i] /= L;
+  };
+  if (type == TOOL_CAPSULE || type == TOOL_SEGMENT) {
+    const double h = size[0];
+    const double reach = type == TOOL_CAPSULE ? size[1] + margin : size[1];
+    double t = pl[0];
+    if (t < -h) t = -h;
+    if (t > h) t = h;
+    const double e[3] = {pl[0] - t, pl[1], pl[2]};
+    const double L = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (!(L < reach)) return LAW_NONE;
+    if (type == TOOL_SEGMENT) {
+      tl[0] = 1.0;
+      law = LAW_TANGENT;
+    } else {
+      law = LAW_CORRECT;
+    }
+    if (L > 0.0) {
+      double De[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+      if (pl[0] > -h && pl[0] < h) De[0] = 0.0;
+      unit_jac(e, L, De, nl, Jl);
+    }
+  } else if (type == TOOL_BOX) {
+    double q[3], o[3];
+    for (int i = 0; i < 3; ++i) {
+      q[i] = std::fabs(pl[i]) - size[i];
+      o[i] = q[i] > 0.0 ? q[i] : 0.0;
+    }
+    const double L = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+    double qmax = q[0];
+    int k = 0;
+    for (int i = 1; i < 3; ++i)
+      if (q[i] > qmax) qmax = q[i], k = i;
+    const double phi = L + (qmax < 0.0 ? qmax : 0.0);
+    if (!(phi < margin)) return LAW_NONE;
+    law = LAW_CORRECT;
+    if (L > 0.0) {
+      const double e[3] = {pl[0] < 0.0 ? -o[0] : o[0], pl[1] < 0.0 ? -o[1] : o[1], pl[2] < 0.0 ? -o[2] : o[2]};
+      double De[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int i = 0; i < 3; ++i) De[4 * i] = q[i] > 0.0 ? 1.0 : 0.0;
+      unit_jac(e, L, De, nl, Jl);
+    } else {
+      nl[0] = nl[1] = nl[2] = 0.0;
+      nl[k] = (pl[k] < 0.0) ? -1.0 : 1.0;
+    }
+  } else if (type == TOOL_PLANE) {
+    if (!(pl[1] < margin)) return LAW_NONE;
+    law = LAW_CORRECT;
+  } else if (type == TOOL_SLICER) {
+    const double hx = size[0], hy = size[1];
+    const double qx = std::fabs(pl[0]) - hx > 0.0 ? std::fabs(pl[0]) - hx : 0.0;
+    const double qy = std::fabs(pl[1]) - hy > 0.0 ? std::fabs(pl[1]) - hy : 0.0;
+    const double d = std::sqrt(qx * qx + qy * qy + pl[2] * pl[2]);
+    if (!(d < margin)) return LAW_NONE;
+    if (pl[1] > hy) {
+      law = LAW_STICKY;
+    } else {
+      law = LAW_CORRECT;
+      nl[0] = 0.0, nl[1] = 0.0, nl[2] = pl[2] < 0.0 ? -1.0 : 1.0;
+    }
+  } else if (type == TOOL_ARC) {
+    const double ra = size[0], ha = size[1], thick = size[2];
+    double ang = std::atan2(pl[1], pl[0]);
+    const bool interior = !(ang > ha || ang < -ha);
+    if (!interior) {
+      const double e0[2] = {ra * std::cos(ha), ra * std::sin(ha)};
+      const double e1[2] = {ra * std::cos(-ha), ra * std::sin(-ha)};
+      const double d0 = (pl[0] - e0[0]) * (pl[0] - e0[0]) + (pl[1] - e0[1]) * (pl[1] - e0[1]);
+      const double d1 = (pl[0] - e1[0]) * (pl[0] - e1[0]) + (pl[1] - e1[1]) * (pl[1] - e1[1]);
+      ang = (d1 < d0) ? -ha : ha;
+    }
+    const double ca = std::cos(ang), sa = std::sin(ang);
+    const double e[3] = {pl[0] - ra * ca, pl[1] - ra * sa, pl[2]};
+    const double L = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (!(L < thick)) return LAW_NONE;
+    law = LAW_TANGENT;
+    tl[0] = -sa, tl[1] = ca, tl[2] = 0.0;
+    double ga[3] = {0.0, 0.0, 0.0};  // d ang / d pl on the open arc
+    if (interior) {
+      const double rho2 = pl[0] * pl[0] + pl[1] * pl[1];
+      ga[0] = -pl[1] / rho2, ga[1] = pl[0] / rho2;
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Jtl[3 * i + j] = (i == 0 ? -ca : i == 1 ? -sa : 0.0) * ga[j];
+    if (L > 0.0) {
+      double De[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) De[3 * i + j] = ((i == j) ? 1.0 : 0.0) - ra * tl[i] * ga[j];
+      unit_jac(e, L, De, nl, Jl);
+    } else {
+      nl[0] = -tl[1], nl[1] = tl[0], nl[2] = 0.0;
+    }
+  } else {
+    return LAW_NONE;
+  }
+  // World frame: n = R nl, dn/dxI = R Jl R^T (pl = R^T (xI - c)).
+  double Rt[9], T1[9];
+  mat_transpose(R, Rt);
+  rotate(R, nl, n);
+  rotate(R, tl, tg);
+  mat_mul(R, Jl, T1);
+  mat_mul(T1, Rt, Jn);
+  mat_mul(R, Jtl, T1);
+  mat_mul(T1, Rt, Jt);
+  return law;
+}
+
+// Forward of the contact law on relative velocity u, given the frame.
+void apply_law(int law, const double* n, const double* tg, const double* u, double mu, double drag, double* out) {
+  if (law == LAW_CORRECT) {
+    contact_correct(n, u, mu, drag, out);
+  } else if (law == LAW_TANGENT) {
+    contact_tangent(n, tg, u, mu, drag, out);
+  } else if (law == LAW_STICKY) {
+    out[0] = out[1] = out[2] = 0.0;
+  } else {
+    out[0] = u[0], out[1] = u[1], out[2] = u[2];
+  }
+}
+
+// Adjoint of apply_law: from the cotangent ob of its output, the cotangents
+// of u, n and tg (accumulated into ub, nb, tb).
+void law_adjoint(int law, const double* n, const double* tg, const double* u, double mu, double drag,
+                 const double* ob, double* ub, double* nb, double* tb) {
+  if (law == LAW_NONE) {
+    for (int a = 0; a < 3; ++a) ub[a] += ob[a];
+    return;
+  }
+  if (law == LAW_STICKY) return;
+  const double un = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+  if (!(un < 0.0)) {
+    for (int a = 0; a < 3; ++a) ub[a] += ob[a];
+    return;
+  }
+  double unb = 0.0;
+  if (law == LAW_CORRECT) {
+    // out = drag (t + mu un t/s), t = u - un n, s = |t|, while 1 + mu un/s > 0.
+    double t[3] = {u[0] - un * n[0], u[1] - un * n[1], u[2] - un * n[2]};
+    const double s = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    if (!(s > 0.0) || !(1.0 + mu * un / s > 0.0)) return;
+    const double th[3] = {t[0] / s, t[1] / s, t[2] / s};
+    const double tob = th[0] * ob[0] + th[1] * ob[1] + th[2] * ob[2];
+    double tbar[3];
+    for (int a = 0; a < 3; ++a) tbar[a] = drag * (ob[a] + mu * un * (ob[a] - th[a] * tob) / s);
+    unb = drag * mu * tob;
+    const double ntb = n[0] * tbar[0] + n[1] * tbar[1] + n[2] * tbar[2];
+    for (int a = 0; a < 3; ++a) {
+      ub[a] += tbar[a];
+      nb[a] -= un * tbar[a];
+    }
+    unb -= ntb;
+  } else {  // LAW_TANGENT: out = drag (ut + mu un sgn(ut)) tg while 1 + mu un/|ut| > 0.
+    const double ut = tg[0] * u[0] + tg[1] * u[1] + tg[2] * u[2];
+    const double s = std::fabs(ut);
+    if (!(s > 0.0) || !(1.0 + mu * un / s > 0.0)) return;
+    const double sg = ut < 0.0 ? -1.0 : 1.0;
+    const double amp = drag * (ut + mu * un * sg);
+    const double ab = tg[0] * ob[0] + tg[1] * ob[1] + tg[2] * ob[2];
+    const double utb = drag * ab;
+    unb = drag * mu * sg * ab;
+    for (int a = 0; a < 3; ++a) {
+      tb[a] += amp * ob[a] + utb * u[a];
+      ub[a] += utb * tg[a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    ub[a] += unb * n[a];
+    nb[a] += unb * u[a];
+  }
+}
+
+// Forward of one tool on one node through the frame (same result as
+// tool_node_contact up to rounding); returns the law applied.
+int frame_contact(const Tool& t, const double* c, const double* vel, const double* xI, double* vI) {
+  double n[3], tg[3], Jn[9], Jt[9];
+  const int law = contact_frame(t.type, c, t.R, t.size, t.margin, xI, n, tg, Jn, Jt);
+  if (law == LAW_NONE) return law;
+  const double r[3] = {xI[0] - c[0], xI[1] - c[1], xI[2] - c[2]};
+  const double vr[3] = {vel[0] + t.av[1] * r[2] - t.av[2] * r[1], vel[1] + t.av[2] * r[0] - t.av[0] * r[2],
+                        vel[2] + t.av[0] * r[1] - t.av[1] * r[0]};
+  const double u[3] = {vI[0] - vr[0], vI[1] - vr[1], vI[2] - vr[2]};
+  double o[3];
+  apply_law(law, n, tg, u, t.mu, t.drag, o);
+  for (int a = 0; a < 3; ++a) vI[a] = vr[a] + o[a];
+  return law;
+}
+
+// Adjoint of one tool's contact on one node: v_out = v_r + law(v_in - v_r),
+// v_r = vel + av x (xI - c), frame evaluated at xI - c. From vb (cotangent of
+// v_out, overwritten with that of v_in) accumulates the cotangents of the
+// tool centre c and of its linear velocity.
+void tool_contact_adjoint(const Tool& t, const double* c, const double* vel, const double* xI, const double* vin,
+                          double* vb, double* cb, double* velb) {
+  double n[3], tg[3], Jn[9], Jt[9];
+  const int law = contact_frame(t.type, c, t.R, t.size, t.margin, xI, n, tg, Jn, Jt);
+  if (law == LAW_NONE) return;
+  const double r[3] = {xI[0] - c[0], xI[1] - c[1], xI[2] - c[2]};
+  const double* w = t.av;
+  const double vr[3] = {vel[0] + w[1] * r[2] - w[2] * r[1], vel[1] + w[2] * r[0] - w[0] * r[2],
+                        vel[2] + w[0] * r[1] - w[1] * r[0]};
+  const double u[3] = {vin[0] - vr[0], vin[1] - vr[1], vin[2] - vr[2]};
+  double ub[3] = {0, 0, 0}, nb[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+  law_adjoint(law, n, tg, u, t.mu, t.drag, vb, ub, nb, tb);
+  double vrb[3];
+  for (int a = 0; a < 3; ++a) vrb[a] = vb[a] - ub[a];  // v_out = v_r + o, u = v_in - v_r
+  for (int a = 0; a < 3; ++a) vb[a] = ub[a];
+  for (int a = 0; a < 3; ++a) velb[a] += vrb[a];
+  // v_r depends on c through r = xI - c: cb += w x vrb.
+  cb[0] += w[1] * vrb[2] - w[2] * vrb[1];
+  cb[1] += w[2] * vrb[0] - w[0] * vrb[2];
+  cb[2] += w[0] * vrb[1] - w[1] * vrb[0];
+  // n(xI - c), tg(xI - c): cb -= Jn^T nb + Jt^T tb.
+  for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < 3; ++i) cb[j] -= Jn[3 * i + j] * nb[i] + Jt[3 * i + j] * tb[i];
+}
+
+// Particle-state cotangents, laid out like the state.
+struct Adj {
+  std::vector<double> x, v, C, F;
+};
+
+// Reverse of one substep from the state it started from. On entry `a` holds
+// the cotangent of the state after the substep; on exit, that of the state
+// before it. Adds to theta_bar (per particle, d/d log E) and to the
+// per-tool cotangents of the substep's linear velocity (velb) and centre (cb).
+void substep_adjoint(Scene& s, Adj& a, double* theta_bar, double (*velb)[3], double (*cb)[3]) {
+  const double dx = s.dx, dt = s.dt, inv_dx = s.inv_dx;
+  const double Minv = 4.0 / (dx * dx);
+  const size_t nn = static_cast<size_t>(s.n) * s.n * s.n;
+  // Recompute the forward grid of this substep (counters left untouched).
+  const long long c_inv = s.n_inverted, c_dom = s.n_domain, c_nf = s.n_nonfinite;
+  double imp_keep[kMaxTools + 1][3];
+  std::memcpy(imp_keep, s.impulse, sizeof(imp_keep));
+  std::vector<char> skip;
+  p2g(s, skip);
+  grid_update(s);
+  s.n_inverted = c_inv, s.n_domain = c_dom, s.n_nonfinite = c_nf;
+  std::memcpy(s.impulse, imp_keep, sizeof(imp_keep));
+
+  // ---- G2P adjoint: cotangent of the grid velocity, particle x and F.
+  std::vector<double> gvb(3 * nn, 0.0);
+  for (long long p = 0; p < s.N; ++p) {
+    if (skip[p]) continue;  // state passed through unchanged
+    const double* xp = &s.x[3 * p];
+    const double* Fp = &s.F[9 * p];
+    int base[3];
+    double f[3];
+    stencil(s, xp, base, f);
+    double w[3][3], dw[3][3];
+    for (int k = 0; k < 3; ++k) bspline_weights(f[k], w[k]), bspline_dweights(f[k], dw[k]);
+    // recompute C' for the F update
+    double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int oz = 0; oz < 3; ++oz) {
+          const double N = w[0][ox] * w[1][oy] * w[2][oz];
+          const double d[3] = {(ox - f[0]) * dx, (oy - f[1]) * dx, (oz - f[2]) * dx};
+          const size_t I = node_index(s, base[0] + ox, base[1] + oy, base[2] + oz);
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) B[3 * i + j] += N * s.gv[3 * I + i] * d[j];
+        }
+    double G[9], Gt[9];
+    for (int i = 0; i < 9; ++i) G[i] = dt * Minv * B[i] + ((i % 4 == 0) ? 1.0 : 0.0);
+    mat_transpose(G, Gt);
+    double* xb = &a.x[3 * p];
+    double* vb = &a.v[3 * p];
+    double* Cb = &a.C[9 * p];
+    double* Fb = &a.F[9 * p];
+    // x' = x + dt v', F' = G F, C' = Minv B, v' = sum N v_I.
+    double vnb[3], Ctb[9], Ft[9], FbFt[9], Fnew_b[9];
+    for (int k = 0; k < 3; ++k) vnb[k] = vb[k] + dt * xb[k];
+    mat_transpose(Fp, Ft);
+    mat_mul(Fb, Ft, FbFt);
+    for (int i = 0; i < 9; ++i) Ctb[i] = Cb[i] + dt * FbFt[i];
+    mat_mul(Gt, Fb, Fnew_b);
+    double Bb[9];
+    for (int i = 0; i < 9; ++i) Bb[i] = Minv * Ctb[i];
+    double xgrad[3] = {0.0, 0.0, 0.0};
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int oz = 0; oz < 3; ++oz) {
+          const double N = w[0][ox] * w[1][oy] * w[2][oz];
+          const double dN[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * inv_dx,
+                                w[0][ox] * w[1][oy] * dw[2][oz] * inv_dx};
+          const double d[3] = {(ox - f[0]) * dx, (oy - f[1]) * dx, (oz - f[2]) * dx};
+          const size_t I = node_index(s, base[0] + ox, base[1] + oy, base[2] + oz);
+          const double* vI = &s.gv[3 * I];
+          double Bbd[3];
+          for (int i = 0; i < 3; ++i) Bbd[i] = Bb[3 * i] * d[0] + Bb[3 * i + 1] * d[1] + Bb[3 * i + 2] * d[2];
+          double sc = 0.0;
+          for (int i = 0; i < 3; ++i) {
+            gvb[3 * I + i] += N * (vnb[i] + Bbd[i]);
+            sc += vI[i] * (vnb[i] + Bbd[i]);
+          }
+          for (int j = 0; j < 3; ++j) {
+            double BtV = Bb[0 * 3 + j] * vI[0] + Bb[1 * 3 + j] * vI[1] + Bb[2 * 3 + j] * vI[2];
+            xgrad[j] += dN[j] * sc - N * BtV;
+          }
+        }
+    for (int k = 0; k < 3; ++k) xb[k] += xgrad[k];
+    for (int i = 0; i < 9; ++i) Fb[i] = Fnew_b[i];
+    for (int k = 0; k < 3; ++k) vb[k] = 0.0;  // old v, C reach the output only through P2G
+    for (int i = 0; i < 9; ++i) Cb[i] = 0.0;
+  }
+
+  // ---- grid adjoint: walls, tools in reverse, then v_hat = p/m + dt g.
+  std::vector<double> gpb(3 * nn, 0.0), gmb(nn, 0.0);
+  double poses[kMaxTools][3], vels[kMaxTools][3];
+  for (int q = 0; q < kMaxTools; ++q) tool_kinematics(s, q, s.substep, poses[q], vels[q]);
+  for (int i = 0; i < s.n; ++i)
+    for (int j = 0; j < s.n; ++j)
+      for (int k = 0; k < s.n; ++k) {
+        const size_t I = node_index(s, i, j, k);
+        const double m = s.gm[I];
+        if (!(m > 0.0)) continue;
+        double vb[3] = {gvb[3 * I], gvb[3 * I + 1], gvb[3 * I + 2]};
+        if (wall_node(s, i, j, k)) continue;  // v = 0 whatever came before
+        const double xI[3] = {i * dx, j * dx, k * dx};
+        // replay the tool chain, keeping each tool's input velocity
+        double vin[kMaxTools][3];
+        double vI[3];
+        for (int a2 = 0; a2 < 3; ++a2) vI[a2] = s.gp[3 * I + a2] / m + dt * s.g[a2];
+        const double vhat[3] = {vI[0], vI[1], vI[2]};
+        for (int q = 0; q < kMaxTools; ++q) {
+          const Tool& t = s.tools[q];
+          for (int a2 = 0; a2 < 3; ++a2) vin[q][a2] = vI[a2];
+          if (t.type == TOOL_NONE) continue;
+          frame_contact(t, poses[q], vels[q], xI, vI);
+        }
+        for (int q = kMaxTools - 1; q >= 0; --q) {
+          const Tool& t = s.tools[q];
+          if (t.type == TOOL_NONE) continue;
+          tool_contact_adjoint(t, poses[q], vels[q], xI, vin[q], vb, cb[q], velb[q]);
+        }
+        for (int a2 = 0; a2 < 3; ++a2) gpb[3 * I + a2] = vb[a2] / m;
+        gmb[I] = -(vb[0] * (vhat[0] - dt * s.g[0]) + vb[1] * (vhat[1] - dt * s.g[1]) +
+                   vb[2] * (vhat[2] - dt * s.g[2])) / m;
+      }
+
+  // ---- P2G adjoint: gather, then the stress adjoint.
+  for (long long p = 0; p < s.N; ++p) {
+    if (skip[p]) continue;
+    const double* xp = &s.x[3 * p];
+    const double* vp = &s.v[3 * p];
+    const double* Cp = &s.C[9 * p];
+    const double* Fp = &s.F[9 * p];
+    const double Ep = s.E.empty() ? s.E_default : s.E[p];
+    int base[3];
+    double f[3];
+    stencil(s, xp, base, f);
+    double w[3][3], dw[3][3];
+    for (int k = 0; k < 3; ++k) bspline_weights(f[k], w[k]), bspline_dweights(f[k], dw[k]);
+    double tau[9];
+    kirchhoff(Fp, Ep, s.nu, tau);
+    const double sc_tau = dt * s.vol0 * Minv;
+    double A[9];
+    for (int i = 0; i < 9; ++i) A[i] = s.mass * Cp[i] - sc_tau * tau[i];
+    double vbar[3] = {0, 0, 0}, Ab[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, xgrad[3] = {0, 0, 0};
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int oz = 0; oz < 3; ++oz) {
+          const double N = w[0][ox] * w[1][oy] * w[2][oz];
+          const double dN[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * inv_dx,
+                                w[0][ox] * w[1][oy] * dw[2][oz] * inv_dx};
+          const double d[3] = {(ox - f[0]) * dx, (oy - f[1]) * dx, (oz - f[2]) * dx};
+          const size_t I = node_index(s, base[0] + ox, base[1] + oy, base[2] + oz);
+          const double* Pb = &gpb[3 * I];
+          double contrib = s.mass * gmb[I];
+          for (int i = 0; i < 3; ++i) {
+            const double Ad = A[3 * i] * d[0] + A[3 * i + 1] * d[1] + A[3 * i + 2] * d[2];
+            contrib += Pb[i] * (s.mass * vp[i] + Ad);
+            vbar[i] += N * s.mass * Pb[i];
+            for (int j = 0; j < 3; ++j) Ab[3 * i + j] += N * Pb[i] * d[j];
+          }
+          for (int j = 0; j < 3; ++j) {
+            const double AtP = A[0 * 3 + j] * Pb[0] + A[1 * 3 + j] * Pb[1] + A[2 * 3 + j] * Pb[2];
+            xgrad[j] += dN[j] * contrib - N * AtP;
+          }
+        }
+    double* xb = &a.x[3 * p];
+    double* vb = &a.v[3 * p];
+    double* Cb = &a.C[9 * p];
+    double* Fb = &a.F[9 * p];
+    for (int k = 0; k < 3; ++k) xb[k] += xgrad[k], vb[k] = vbar[k];
+    double taub[9];
+    for (int i = 0; i < 9; ++i) Cb[i] = s.mass * Ab[i], taub[i] = -sc_tau * Ab[i];
+    theta_bar[p] += kirchhoff_adjoint(Fp, Ep, s.nu, taub, Fb);
+  }
 }
 
 int status_of(const Scene& s) {
@@ -761,6 +1299,145 @@ int oracle_counters(void* h, long long* out) {
   out[1] = s->n_domain;
   out[2] = s->n_nonfinite;
   return ST_OK;
+}
+
+// FP64 particle state (for finite-difference checks of the adjoint). v, C,
+// F, E may be NULL (zero, zero, identity, E_default).
+int oracle_set_state_f64(void* h, long long n, const double* x, const double* v, const double* C,
+                         const double* F, const double* E, double mass, double vol0) {
+  Scene* s = static_cast<Scene*>(h);
+  if (!s || n < 0 || (n > 0 && !x)) return ST_EINVAL;
+  s->N = n;
+  s->mass = mass;
+  s->vol0 = vol0;
+  s->x.assign(x, x + 3 * n);
+  s->v.assign(3 * n, 0.0);
+  s->C.assign(9 * n, 0.0);
+  s->F.assign(9 * n, 0.0);
+  if (v) s->v.assign(v, v + 3 * n);
+  if (C) s->C.assign(C, C + 9 * n);
+  for (long long p = 0; p < n; ++p)
+    for (int i = 0; i < 9; ++i) s->F[9 * p + i] = F ? F[9 * p + i] : ((i % 4 == 0) ? 1.0 : 0.0);
+  s->E.clear();
+  if (E) s->E.assign(E, E + n);
+  s->n_inverted = s->n_domain = s->n_nonfinite = 0;
+  return ST_OK;
+}
+
+// Per-substep linear velocities of tool `id` (T rows of 3), starting at the
+// current substep; the tool is re-anchored at its current pose. T = 0 clears
+// the table (constant velocity from the current pose on).
+int oracle_set_velocity_table(void* h, int id, long long T, const double* table) {
+  Scene* s = static_cast<Scene*>(h);
+  if (!s || id < 0 || id >= kMaxTools || T < 0 || (T > 0 && !table)) return ST_EINVAL;
+  Tool& t = s->tools[id];
+  if (t.type == TOOL_NONE) return ST_EINVAL;
+  double pose[3], vel[3];
+  tool_kinematics(*s, id, s->substep, pose, vel);
+  for (int a = 0; a < 3; ++a) t.c0[a] = pose[a];
+  t.set_at = s->substep;
+  t.vtab.assign(table, table + 3 * T);
+  return ST_OK;
+}
+
+// Reverse-mode gradient of a T-substep rollout from the current state.
+// Seeds xb, vb, Cb, Fb (NULL = 0) are the cotangent of the state after the
+// rollout. Writes theta_bar[N] = dL/d log E_p, vel_bar[kMaxTools * T * 3] =
+// dL/d (linear velocity of tool q in substep j of the rollout), which acts
+// directly on contact and through the pose of every later substep, and,
+// where not NULL, the cotangent of the starting state (xb0, vb0, Cb0, Fb0).
+// Leaves the scene advanced by T substeps. Every state is kept in memory.
+int oracle_rollout_adjoint(void* h, int T, const double* xb, const double* vb, const double* Cb, const double* Fb,
+                           double* theta_bar, double* vel_bar, double* xb0, double* vb0, double* Cb0,
+                           double* Fb0) {
+  Scene* s = static_cast<Scene*>(h);
+  if (!s || T < 0 || !theta_bar || !vel_bar) return ST_EINVAL;
+  const long long N = s->N;
+  struct State {
+    std::vector<double> x, v, C, F;
+  };
+  std::vector<State> hist(static_cast<size_t>(T));
+  std::memset(s->impulse, 0, sizeof(s->impulse));
+  const long long start = s->substep;
+  for (int k = 0; k < T; ++k) {
+    hist[k] = {s->x, s->v, s->C, s->F};
+    substep(*s);
+  }
+  State end{s->x, s->v, s->C, s->F};
+  const long long end_sub = s->substep;
+  Adj a;
+  a.x.assign(3 * N, 0.0), a.v.assign(3 * N, 0.0), a.C.assign(9 * N, 0.0), a.F.assign(9 * N, 0.0);
+  if (xb) a.x.assign(xb, xb + 3 * N);
+  if (vb) a.v.assign(vb, vb + 3 * N);
+  if (Cb) a.C.assign(Cb, Cb + 9 * N);
+  if (Fb) a.F.assign(Fb, Fb + 9 * N);
+  std::fill(theta_bar, theta_bar + N, 0.0);
+  std::vector<double> cbar(static_cast<size_t>(T) * kMaxTools * 3, 0.0);
+  std::fill(vel_bar, vel_bar + static_cast<size_t>(kMaxTools) * T * 3, 0.0);
+  for (int k = T - 1; k >= 0; --k) {
+    s->x = hist[k].x, s->v = hist[k].v, s->C = hist[k].C, s->F = hist[k].F;
+    s->substep = start + k;
+    double velb[kMaxTools][3], cb[kMaxTools][3];
+    std::memset(velb, 0, sizeof(velb));
+    std::memset(cb, 0, sizeof(cb));
+    substep_adjoint(*s, a, theta_bar, velb, cb);
+    for (int q = 0; q < kMaxTools; ++q)
+      for (int c = 0; c < 3; ++c) {
+        vel_bar[(static_cast<size_t>(q) * T + k) * 3 + c] = velb[q][c];
+        cbar[(static_cast<size_t>(k) * kMaxTools + q) * 3 + c] = cb[q][c];
+      }
+  }
+  // The centre in substep i is c_start + dt * sum_{j < i} vel_j.
+  for (int q = 0; q < kMaxTools; ++q) {
+    double suffix[3] = {0.0, 0.0, 0.0};
+    for (int k = T - 1; k >= 0; --k) {
+      for (int c = 0; c < 3; ++c) vel_bar[(static_cast<size_t>(q) * T + k) * 3 + c] += s->dt * suffix[c];
+      for (int c = 0; c < 3; ++c) suffix[c] += cbar[(static_cast<size_t>(k) * kMaxTools + q) * 3 + c];
+    }
+  }
+  s->x = end.x, s->v = end.v, s->C = end.C, s->F = end.F;
+  s->substep = end_sub;
+  if (xb0) std::memcpy(xb0, a.x.data(), sizeof(double) * 3 * N);
+  if (vb0) std::memcpy(vb0, a.v.data(), sizeof(double) * 3 * N);
+  if (Cb0) std::memcpy(Cb0, a.C.data(), sizeof(double) * 9 * N);
+  if (Fb0) std::memcpy(Fb0, a.F.data(), sizeof(double) * 9 * N);
+  return status_of(*s);
+}
+
+// ---- unit adjoints (checked against finite differences)
+void oracle_polar_adjoint(const double* F, const double* Rb, double* Fb) {
+  double R[9];
+  polar_rotation(F, R);
+  for (int i = 0; i < 9; ++i) Fb[i] = 0.0;
+  polar_adjoint(F, R, Rb, Fb);
+}
+double oracle_kirchhoff_adjoint(const double* F, double E, double nu, const double* taub, double* Fb) {
+  for (int i = 0; i < 9; ++i) Fb[i] = 0.0;
+  return kirchhoff_adjoint(F, E, nu, taub, Fb);
+}
+// Node velocity after one tool through the differentiable frame (law code
+// returned), and the adjoint of that map: vb (in: cotangent of the output;
+// out: of the input velocity), cb and velb (cotangents of centre and linear
+// velocity).
+int oracle_frame_contact(int type, const double* center, const double* quat, const double* size,
+                         const double* lin_vel, const double* ang_vel, double mu, double drag, double margin,
+                         const double* xI, double* vI) {
+  Tool t;
+  t.type = type;
+  quat_to_matrix(quat, t.R);
+  for (int a = 0; a < 3; ++a) t.size[a] = size[a], t.av[a] = ang_vel[a];
+  t.mu = mu, t.drag = drag, t.margin = margin;
+  return frame_contact(t, center, lin_vel, xI, vI);
+}
+void oracle_contact_adjoint(int type, const double* center, const double* quat, const double* size,
+                            const double* lin_vel, const double* ang_vel, double mu, double drag, double margin,
+                            const double* xI, const double* vin, double* vb, double* cb, double* velb) {
+  Tool t;
+  t.type = type;
+  quat_to_matrix(quat, t.R);
+  for (int a = 0; a < 3; ++a) t.size[a] = size[a], t.av[a] = ang_vel[a], cb[a] = 0.0, velb[a] = 0.0;
+  t.mu = mu, t.drag = drag, t.margin = margin;
+  tool_contact_adjoint(t, center, lin_vel, xI, vin, vb, cb, velb);
 }
 
 // ---- unit entry points used by the invariant tests
