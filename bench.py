@@ -15,7 +15,12 @@ Also reported on the same JSON line:
 * substep_roofline: the whole substep against the HBM byte model
   N x 100 B + N_act x 72 B;
 * cpu_baseline: the FP64 oracle timed on the host for a bounded sample of
-  the same workload (a few substeps of the full scene).
+  the same workload (a few substeps of the full scene);
+* fwd_bwd: the differentiable press (65,536 particles on 64^3, a capsule
+  following a 200 x 3 per-substep velocity table, E_p = exp(theta_p)):
+  mpm_rollout_forward(200, checkpoints every 20) and mpm_rollout_backward
+  (gradients for theta, the velocity table and the starting state), timed
+  separately, with the ratio (fwd + bwd) / fwd.
 """
 import argparse
 import json
@@ -50,6 +55,62 @@ def cpu_baseline(scene, n_sub):
                       f"{scene.n_grid}^3 grid), FP64, one host thread; {dt:.1f} s"}
 
 
+def fwd_bwd(steps, checkpoint_every=20):
+    """Time the differentiable rollout of the press scene: forward with
+    checkpoints, then the reverse pass, each bracketed by device syncs."""
+    import torch
+    from paper_2502_18437_amd import mpm, scenes
+    s = scenes.make("c5")
+    T = s.n_substeps
+    dev = torch.device("cuda", 0)
+    theta = torch.from_numpy(s.theta).to(dev)
+    x_d = torch.from_numpy(s.x).to(dev)
+    rng = np.random.default_rng(0)
+    xb = torch.from_numpy(rng.standard_normal((s.N, 3)).astype(np.float32)).to(dev)
+    sim = mpm.Simulation(s.n_grid, s.dt, gravity=s.gravity, wall_band=s.wall_band, nu=s.nu,
+                         E_default=s.E_default, max_particles=s.N)
+    log(f"[bench] fwd+bwd: {s.name}, {s.N} particles, {s.n_grid}^3 grid, {T} substeps, "
+        f"checkpoints every {checkpoint_every}")
+
+    def forward():
+        sim.set_particles(x_d, None, None, None, None, s.mass, s.vol0)
+        for k, t in enumerate(s.tools):
+            sim.set_tool(k, t.type, **t.kwargs())
+        for k, tab in s.vel_tables.items():
+            sim.set_tool_velocity_table(k, tab)
+        sim.rollout_forward(T, checkpoint_every, theta=theta)
+
+    def backward():
+        return sim.rollout_backward(xb, want_state=False)
+
+    forward()
+    g = backward()
+    torch.cuda.synchronize()
+    t_f = t_b = 0.0
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_f += t1 - t0
+        t_b += t2 - t1
+    _, st = sim.read_state(out={}, allow_errors=True)
+    ok = bool(torch.isfinite(g["theta"]).all().item()) and bool(np.isfinite(g["vel"]).all())
+    sim.close()
+    t_f /= steps
+    t_b /= steps
+    ps = s.N * T
+    return {"workload": f"{s.name}: {s.N} particles, {s.n_grid}^3 grid, capsule with a {T} x 3 velocity "
+                        f"table, {T} substeps of dt={s.dt}, checkpoints every {checkpoint_every}",
+            "fwd_ms": 1e3 * t_f, "bwd_ms": 1e3 * t_b, "fwd_particle_substeps_per_s": ps / t_f,
+            "fwd_bwd_particle_substeps_per_s": ps / (t_f + t_b), "ratio_fwd_bwd_over_fwd": (t_f + t_b) / t_f,
+            "steps": steps, "status": int(st), "finite_gradients": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +122,8 @@ def main():
     ap.add_argument("--cpu-substeps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd measurement")
+    ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of MIB MiB (a kernel of known "
                          "traffic that scales hardware byte counters)")
@@ -150,6 +213,8 @@ def main():
                            "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
+    if not args.no_diff:
+        out["fwd_bwd"] = fwd_bwd(args.diff_steps)
     if not args.no_cpu:
         log(f"[bench] oracle CPU baseline: {args.cpu_substeps} substeps of the full scene ...")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_substeps)

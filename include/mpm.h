@@ -84,6 +84,28 @@ extern "C" {
 #define MPM_TOOL_BOX 2     /* oriented box; size = half extents in body axes */
 #define MPM_TOOL_PLANE 3   /* half space; body +y is the outward normal
                               through center; size unused */
+/* Cutting and suturing geometries (Sec. IV-B, IV-C): */
+#define MPM_TOOL_SLICER 4  /* blade: rectangle in the body x-y plane,
+                              size = {half_width (x), half_height (y), unused};
+                              its side is the sign of body z. Nodes within
+                              `margin` (> 0, the fattened region) of it get the
+                              contact law with normal +-body z on their own
+                              side, so material is parted rather than pushed;
+                              beyond the spine edge (body y > half_height) the
+                              field is the distance to the spine and the
+                              contact is sticky (relative velocity 0). The
+                              cutting edge is the body -y edge. */
+#define MPM_TOOL_SEGMENT 5 /* 1D line segment along body x (thread segment,
+                              straight needle); size = {half_length,
+                              thickness, unused} */
+#define MPM_TOOL_ARC 6     /* 1D circular arc in the body x-y plane centred
+                              on `center`, from angle -half_angle to
+                              +half_angle about body +x (suture needle);
+                              size = {radius, half_angle (rad, <= pi),
+                              thickness}. For segments and arcs, nodes within
+                              the thickness keep only the part of their
+                              relative velocity along the curve tangent
+                              (then friction and drag), unless separating. */
 
 typedef struct mpm_handle mpm_handle;
 
@@ -184,6 +206,14 @@ int mpm_read_state(mpm_handle* h, float* x, float* v, float* C, float* F, int32_
 /* Synchronise and fill *info. Errors: MPM_EINVAL, MPM_EHIP. */
 int mpm_get_info(mpm_handle* h, mpm_info* info);
 
+/* Two-way coupling (Sec. IV-A): the impulse (N s) exerted on each tool by the
+ * material during the most recent mpm_step call, i.e. minus the momentum the
+ * tool's velocity correction gave the grid nodes, summed over its substeps.
+ * out is (MPM_MAX_TOOLS + 1) x 3 doubles: rows 0..7 are the tools, row 8 the
+ * walls. A host application applies row k to its rigid body for tool k.
+ * Blocking. Errors: MPM_EINVAL (NULL), MPM_EHIP. */
+int mpm_read_tool_impulses(mpm_handle* h, double* out);
+
 /* Message of the most recent failure on this handle ("" if none). The
  * string is owned by the handle and valid until its next call. A NULL
  * handle gives the message of the last failed mpm_create. */
@@ -212,6 +242,53 @@ typedef struct mpm_kernel_times {
 int mpm_profile(mpm_handle* h, int32_t enable);
 /* Synchronise and return the totals accumulated since timing was enabled. */
 int mpm_profile_read(mpm_handle* h, mpm_kernel_times* out);
+
+/* ------------------------------------------------------ scripted tool motion */
+/* Per-substep linear velocities of tool `tool_id` (Sec. V: a shape's velocity
+ * is set for every step). `table` is n_rows x 3 doubles in host memory,
+ * copied. The tool is re-anchored at its current pose; during the j-th
+ * substep from now it moves with row j (j < n_rows) and its centre is the
+ * anchor plus dt times the sum of rows 0..j-1; afterwards lin_vel from
+ * mpm_set_tool_sdf applies again. n_rows = 0 removes the table. Applies to
+ * mpm_step and mpm_rollout_forward alike; a new mpm_set_tool_sdf clears it.
+ * Errors: MPM_EINVAL (no such tool, NULL table, non-finite entry). */
+int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, const double* table);
+
+/* ------------------------------------------------------ differentiable rollout
+ * Reverse-mode gradients of a rollout (the paper targets learning with the
+ * simulator, Sec. I and V). The rollout runs the same substep as mpm_step
+ * (Algorithm 1 with the contact of Sec. IV) on a dense n^3 grid with the
+ * particles in the caller's order, keeping a copy of the state every
+ * `checkpoint_every` substeps; the reverse pass recomputes each segment from
+ * its checkpoint and walks the substeps backwards through hand-written
+ * adjoint kernels. Device memory: (n_substeps / checkpoint_every + 1) plus
+ * checkpoint_every + 3 particle states of 96 bytes per particle, and
+ * 104 bytes per grid node. */
+
+/* Run n_substeps substeps from the current state and record the rollout.
+ * theta (device, N floats, caller order) sets E_p = exp(theta_p) for the
+ * rollout and afterwards; NULL keeps the current E. The particle state
+ * afterwards is that after the rollout (mpm_read_state reads it). The tool
+ * impulses are not recorded (they read zero). Not blocking.
+ * Errors: MPM_EINVAL (no particles, n_substeps < 0, checkpoint_every < 1),
+ * MPM_ENOMEM, MPM_EHIP; device errors are deferred as for mpm_step. */
+int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_every, const float* theta);
+
+/* Gradient of a scalar loss L through the recorded rollout. Inputs (device,
+ * caller order, NULL = zero): xb, vb, Cb, Fb = dL/d(final x, v, C, F) with the
+ * shapes of mpm_read_state. Outputs: theta_bar (device, N floats, required) =
+ * dL/d theta_p with E_p = exp(theta_p); vel_bar (host, MPM_MAX_TOOLS x
+ * n_substeps x 3 doubles, NULL to skip) = dL/d(linear velocity of tool q
+ * during substep j of the rollout), which acts on the contact of that
+ * substep and moves every later pose; xb0, vb0, Cb0, Fb0 (device, NULL to
+ * skip) = dL/d(state at the rollout start). Contact sets, stencil cells and
+ * clamps are held at the ones the forward pass took. The particle state is
+ * not changed; the call may be repeated with other seeds. Blocking when
+ * vel_bar is given. Errors: MPM_EINVAL (no recorded rollout: particles, tools,
+ * tables or the clock changed since mpm_rollout_forward; NULL theta_bar),
+ * MPM_ENOMEM, MPM_EHIP. */
+int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const float* Cb, const float* Fb,
+                         float* theta_bar, double* vel_bar, float* xb0, float* vb0, float* Cb0, float* Fb0);
 
 #ifdef __cplusplus
 }

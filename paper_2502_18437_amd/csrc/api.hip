@@ -32,6 +32,29 @@ struct HostTool {
   int64_t set_at = 0;
   double R[9];
   bool active = false;
+  std::vector<double> vtab;  // optional per-substep linear velocities (rows of 3) from set_at on
+  std::vector<double> vpre;  // prefix sums of vtab: vpre[3 j + a] = sum of rows < j
+};
+
+// Device buffers of the differentiable rollout (allocated on first use,
+// grown as needed) and the record of the last rollout.
+struct DiffBufs {
+  DiffGrid g;
+  int grid_n = 0;
+  int64_t part_cap = 0;   // particles the per-particle buffers hold
+  float* E = nullptr;     // E per particle, caller order
+  float* work = nullptr;  // two particle states
+  float* adj = nullptr;   // one adjoint state
+  float* ckpt = nullptr;
+  int64_t ckpt_slots = 0;
+  float* seg = nullptr;
+  int64_t seg_slots = 0;
+  double* tool_red = nullptr;
+  int64_t tool_red_n = 0;
+  bool valid = false;     // a rollout is recorded and nothing it depends on changed
+  int T = 0, K = 1;
+  int64_t start = 0;      // substep counter when the rollout began
+  int64_t N = 0;
 };
 
 struct ProfEvent {
@@ -71,6 +94,8 @@ struct mpm_handle {
   double prof_ms[MPM_KERNEL_KINDS] = {0, 0, 0, 0, 0};
   int64_t prof_n[MPM_KERNEL_KINDS] = {0, 0, 0, 0, 0};
   unsigned long long* scratch_u64 = nullptr;  // device word for on-demand reductions
+  double* imp_sum = nullptr;                  // device: impulse totals of the last mpm_step
+  DiffBufs d;
 };
 
 namespace {
@@ -113,8 +138,46 @@ void quat_to_R(const double* q, double* R) {
   R[8] = 1 - 2 * (x * x + y * y);
 }
 
-// Tools at the pose of global substep `k` (centre + elapsed * lin_vel in FP64,
-// then rounded to FP32).
+// Centre and linear velocity of a tool during global substep k (FP64). The
+// pose follows the velocities kinematically: closed form c + (k - set_at) dt v
+// without a table; with a table of T rows, substep set_at + j uses row j and
+// the centre is c plus dt times the sum of the earlier rows; after the table
+// the constant velocity resumes from where the table left the tool.
+void tool_kinematics(const HostTool& ht, int64_t k, double dt, double* pose, double* vel) {
+  const int64_t rel = k - ht.set_at;
+  const int64_t T = (int64_t)(ht.vtab.size() / 3);
+  if (T == 0) {
+    const double el = (double)rel * dt;
+    for (int a = 0; a < 3; ++a) pose[a] = ht.t.center[a] + el * ht.t.lin_vel[a], vel[a] = ht.t.lin_vel[a];
+    return;
+  }
+  const int64_t m = rel < T ? rel : T;
+  for (int a = 0; a < 3; ++a) {
+    pose[a] = ht.t.center[a] + dt * ht.vpre[3 * m + a] + (double)(rel - m) * dt * ht.t.lin_vel[a];
+    vel[a] = rel < T ? ht.vtab[3 * rel + a] : ht.t.lin_vel[a];
+  }
+}
+
+// Squared distance from the tool centre beyond which no point is in contact
+// (a conservative bound with slack for FP32 rounding); -1 for the unbounded
+// plane.
+float reach2_of(const mpm_tool& t) {
+  const double m = t.margin > 0.0f ? (double)t.margin : 0.0;
+  double r;
+  switch (t.type) {
+    case MPM_TOOL_CAPSULE: r = t.size[0] + t.size[1] + m; break;
+    case MPM_TOOL_BOX: r = std::sqrt(t.size[0] * t.size[0] + t.size[1] * t.size[1] + t.size[2] * t.size[2]) + m; break;
+    case MPM_TOOL_SLICER: r = std::sqrt(t.size[0] * t.size[0] + t.size[1] * t.size[1]) + m; break;
+    case MPM_TOOL_SEGMENT: r = t.size[0] + t.size[1]; break;
+    case MPM_TOOL_ARC: r = t.size[0] + t.size[2]; break;
+    default: return -1.0f;
+  }
+  r = r * 1.001 + 1e-6;
+  return (float)(r * r);
+}
+
+// Tools at the pose of global substep `k` (FP64 kinematics, then rounded to
+// FP32).
 ToolSetK tools_at(const mpm_handle* h, int64_t k) {
   ToolSetK ts;
   std::memset(&ts, 0, sizeof(ts));
@@ -128,17 +191,19 @@ ToolSetK tools_at(const mpm_handle* h, int64_t k) {
     }
     ts.n = i + 1;
     t.type = ht.t.type;
-    const double el = (double)(k - ht.set_at) * (double)h->p.dt;
+    double pose[3], vel[3];
+    tool_kinematics(ht, k, (double)h->p.dt, pose, vel);
     for (int a = 0; a < 3; ++a) {
-      t.c[a] = (float)(ht.t.center[a] + el * ht.t.lin_vel[a]);
+      t.c[a] = (float)pose[a];
       t.size[a] = (float)ht.t.size[a];
-      t.lv[a] = (float)ht.t.lin_vel[a];
+      t.lv[a] = (float)vel[a];
       t.av[a] = (float)ht.t.ang_vel[a];
     }
     for (int i2 = 0; i2 < 9; ++i2) t.R[i2] = (float)ht.R[i2];
     t.mu = ht.t.mu;
     t.drag = ht.t.drag;
     t.margin = ht.t.margin;
+    t.reach2 = reach2_of(ht.t);
   }
   return ts;
 }
@@ -193,11 +258,19 @@ void prof_collect(mpm_handle* h) {
 void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
                   b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.act_list, b.mark,
-                  b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
+                  b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.imp_slots, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
                   b.status};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   b = Buffers();
+}
+
+void free_diff(DiffBufs& d) {
+  void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.hat, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb,
+                  d.g.skip, d.E, d.work, d.adj, d.ckpt, d.seg, d.tool_red};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  d = DiffBufs();
 }
 
 __global__ void k_reset_status(Status* st) {
@@ -242,6 +315,69 @@ int sync(mpm_handle* h) {
 }  // namespace
 
 // ====================================================================== C ABI
+namespace {
+
+// (Re)allocate a device buffer to hold at least `need` elements of `elem`
+// bytes; `have` tracks the current capacity in elements.
+template <typename T>
+hipError_t ensure(T** p, int64_t* have, int64_t need, size_t elem = sizeof(T)) {
+  if (*p && *have >= need) return hipSuccess;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  hipError_t e = hipMalloc((void**)p, (size_t)(need > 0 ? need : 1) * elem);
+  if (e == hipSuccess) *have = need;
+  return e;
+}
+
+hipError_t diff_alloc_base(mpm_handle* h) {
+  DiffBufs& d = h->d;
+  const int n = h->p.n_grid;
+  const int64_t nn = (int64_t)n * n * n;
+  if (d.grid_n != n) {
+    void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.hat, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb};
+    for (void* q : ptrs)
+      if (q) (void)hipFree(q);
+    DiffGrid z;
+    z.skip = d.g.skip;
+    d.g = z;
+    d.grid_n = 0;
+    hipError_t e;
+    if ((e = hipMalloc((void**)&d.g.m, sizeof(float) * nn)) != hipSuccess) return e;
+    for (int a = 0; a < 3; ++a) {
+      if ((e = hipMalloc((void**)&d.g.p[a], sizeof(float) * nn)) != hipSuccess) return e;
+      if ((e = hipMalloc((void**)&d.g.vb[a], sizeof(float) * nn)) != hipSuccess) return e;
+    }
+    if ((e = hipMalloc((void**)&d.g.vel, sizeof(float4) * nn)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&d.g.hat, sizeof(float4) * nn)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&d.g.pb, sizeof(float4) * nn)) != hipSuccess) return e;
+    d.grid_n = n;
+  }
+  const int64_t N = h->N;
+  if (d.part_cap < N) {
+    void* ptrs[] = {d.g.skip, d.E, d.work, d.adj};
+    for (void* q : ptrs)
+      if (q) (void)hipFree(q);
+    d.g.skip = nullptr, d.E = nullptr, d.work = nullptr, d.adj = nullptr;
+    d.part_cap = 0;
+    hipError_t e;
+    if ((e = hipMalloc((void**)&d.g.skip, (size_t)N)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&d.E, sizeof(float) * N)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&d.work, sizeof(float) * 2 * kStateFloats * N)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&d.adj, sizeof(float) * kStateFloats * N)) != hipSuccess) return e;
+    d.part_cap = N;
+  }
+  // Accumulators the kernels expect to find cleared.
+  for (int a = 0; a < 3; ++a) {
+    launch_fill_f32(d.g.p[a], nn, 0.0f, h->stream);
+    launch_fill_f32(d.g.vb[a], nn, 0.0f, h->stream);
+  }
+  launch_fill_f32(d.g.m, nn, 0.0f, h->stream);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 extern "C" {
 
 int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
@@ -330,6 +466,8 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.node_cnt, sizeof(uint32_t) * h->n_blocks);
+  alloc((void**)&b.imp_slots, sizeof(float) * kGridSlots * kImpulseRows * 3);
+  alloc((void**)&h->imp_sum, sizeof(double) * kImpulseRows * 3);
   alloc((void**)&h->scratch_u64, sizeof(unsigned long long));
   const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
   alloc(&b.acc_m, sizeof(float) * grid_nodes);
@@ -339,6 +477,7 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   if (!ok) {
     free_buffers(b);
     if (h->scratch_u64) (void)hipFree(h->scratch_u64);
+    if (h->imp_sum) (void)hipFree(h->imp_sum);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
     g_create_error = "device allocation failed";
@@ -351,6 +490,7 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
                        (int64_t)(grid_nodes * mom_bytes / 4));
   hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
+  launch_clear_impulses(b, h->stream);
   e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
@@ -392,7 +532,9 @@ int mpm_destroy(mpm_handle* h) {
   }
   for (auto e : h->prof_pool) (void)hipEventDestroy(e);
   free_buffers(h->b);
+  free_diff(h->d);
   if (h->scratch_u64) (void)hipFree(h->scratch_u64);
+  if (h->imp_sum) (void)hipFree(h->imp_sum);
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return rc;
@@ -450,6 +592,7 @@ int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v, 
   h->sim.p_limit = (float)std::ldexp(1.0, 50 - shift);
   h->since_sort = 0;
   h->dirty = true;
+  h->d.valid = false;
   h->err.clear();
   return MPM_OK;
 }
@@ -460,9 +603,12 @@ int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t) {
   HostTool& ht = h->tools[tool_id];
   if (t->type == MPM_TOOL_NONE) {
     ht.active = false;
+    ht.vtab.clear();
+    ht.vpre.clear();
+    h->d.valid = false;
     return MPM_OK;
   }
-  if (t->type < MPM_TOOL_CAPSULE || t->type > MPM_TOOL_PLANE)
+  if (t->type < MPM_TOOL_CAPSULE || t->type > MPM_TOOL_ARC)
     return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: bad type");
   bool fin = std::isfinite(t->mu) && std::isfinite(t->drag) && std::isfinite(t->margin);
   for (int a = 0; a < 3; ++a)
@@ -479,10 +625,41 @@ int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t) {
     return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: capsule needs half_length >= 0, radius > 0");
   if (t->type == MPM_TOOL_BOX && (!(t->size[0] > 0.0) || !(t->size[1] > 0.0) || !(t->size[2] > 0.0)))
     return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: box needs positive half extents");
+  if (t->type == MPM_TOOL_SLICER && (!(t->size[0] > 0.0) || !(t->size[1] > 0.0) || !(t->margin > 0.0f)))
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: slicer needs positive half width, half height and margin");
+  if (t->type == MPM_TOOL_SEGMENT && (!(t->size[0] >= 0.0) || !(t->size[1] > 0.0)))
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: segment needs half_length >= 0, thickness > 0");
+  if (t->type == MPM_TOOL_ARC && (!(t->size[0] > 0.0) || !(t->size[1] > 0.0) || !(t->size[1] <= M_PI) ||
+                                  !(t->size[2] > 0.0)))
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: arc needs radius > 0, 0 < half angle <= pi, thickness > 0");
   ht.t = *t;
   ht.set_at = h->substep;
   quat_to_R(t->quat, ht.R);
   ht.active = true;
+  ht.vtab.clear();
+  ht.vpre.clear();
+  h->d.valid = false;
+  return MPM_OK;
+}
+
+int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, const double* table) {
+  if (!h) return MPM_EINVAL;
+  if (tool_id < 0 || tool_id >= kMaxTools || n_rows < 0 || (n_rows > 0 && !table))
+    return fail(h, MPM_EINVAL, "mpm_set_tool_velocity_table: bad argument");
+  HostTool& ht = h->tools[tool_id];
+  if (!ht.active) return fail(h, MPM_EINVAL, "mpm_set_tool_velocity_table: no tool with this id");
+  for (int64_t i = 0; i < 3 * n_rows; ++i)
+    if (!std::isfinite(table[i])) return fail(h, MPM_EINVAL, "mpm_set_tool_velocity_table: non-finite entry");
+  // Re-anchor at the current pose, then follow the table.
+  double pose[3], vel[3];
+  tool_kinematics(ht, h->substep, (double)h->p.dt, pose, vel);
+  for (int a = 0; a < 3; ++a) ht.t.center[a] = pose[a];
+  ht.set_at = h->substep;
+  ht.vtab.assign(table, table + 3 * n_rows);
+  ht.vpre.assign(3 * (n_rows + 1), 0.0);
+  for (int64_t j = 0; j < n_rows; ++j)
+    for (int a = 0; a < 3; ++a) ht.vpre[3 * (j + 1) + a] = ht.vpre[3 * j + a] + ht.vtab[3 * j + a];
+  h->d.valid = false;
   return MPM_OK;
 }
 
@@ -490,7 +667,10 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   if (!h) return MPM_EINVAL;
   if (n_substeps < 0) return fail(h, MPM_EINVAL, "mpm_step: n_substeps < 0");
   if (n_substeps == 0) return MPM_OK;
+  h->d.valid = false;
   if (h->N == 0) {
+    HIP_OR_RETURN(h, select_device(h));
+    launch_clear_impulses(h->b, h->stream);
     h->substep += n_substeps;
     return MPM_OK;
   }
@@ -498,6 +678,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   Buffers& b = h->b;
   const int64_t N = h->N;
   const int wgs = h->transfer_wgs;
+  launch_clear_impulses(b, h->stream);
   for (int k = 0; k < n_substeps; ++k) {
     const int parity = (int)(h->substep & 1);
     const bool rebin = h->dirty || h->since_sort >= h->resort_interval;
@@ -531,6 +712,123 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     launch_g2p(b, N, h->sim, wgs, h->stream);
   }
   HIP_OR_RETURN(h, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_every, const float* theta) {
+  if (!h) return MPM_EINVAL;
+  if (n_substeps < 0 || checkpoint_every < 1)
+    return fail(h, MPM_EINVAL, "mpm_rollout_forward: need n_substeps >= 0 and checkpoint_every >= 1");
+  if (h->N == 0) return fail(h, MPM_EINVAL, "mpm_rollout_forward: no particles");
+  HIP_OR_RETURN(h, select_device(h));
+  DiffBufs& d = h->d;
+  d.valid = false;
+  const int64_t N = h->N;
+  const int T = n_substeps, K = checkpoint_every;
+  const int64_t SF = (int64_t)kStateFloats * N;
+  HIP_OR_RETURN(h, diff_alloc_base(h));
+  HIP_OR_RETURN(h, ensure(&d.ckpt, &d.ckpt_slots, (int64_t)(T / K + 1), sizeof(float) * SF));
+  if (theta)
+    launch_exp(theta, d.E, N, h->stream);
+  else
+    launch_unpermute_E(h->b, N, h->sim, d.E, h->stream);
+  auto slot = [&](int k) -> DState {
+    if (k % K == 0) return dstate(d.ckpt + (int64_t)(k / K) * SF, N);
+    return dstate(d.work + (int64_t)(k % 2) * SF, N);
+  };
+  DState s0 = slot(0);
+  launch_unpermute(h->b, N, s0.x, s0.v, s0.C, s0.F, h->stream);
+  launch_clear_impulses(h->b, h->stream);
+  for (int k = 0; k < T; ++k) {
+    launch_diff_substep(d.g, h->sim, tools_at(h, h->substep), N, slot(k), d.E, slot(k + 1), true, false,
+                        h->b.status, h->stream);
+    h->substep++;
+  }
+  DState sT = slot(T);
+  const bool keep_E = theta || h->has_E;
+  launch_load_particles(h->b, N, sT.x, sT.v, sT.C, sT.F, keep_E ? d.E : nullptr, h->stream);
+  HIP_OR_RETURN(h, hipGetLastError());
+  if (theta) {
+    h->has_E = true;
+    h->sim.has_E = 1;
+  }
+  h->since_sort = 0;
+  h->dirty = true;
+  d.T = T, d.K = K, d.start = h->substep - T, d.N = N;
+  d.valid = true;
+  return MPM_OK;
+}
+
+int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const float* Cb, const float* Fb,
+                         float* theta_bar, double* vel_bar, float* xb0, float* vb0, float* Cb0, float* Fb0) {
+  if (!h) return MPM_EINVAL;
+  DiffBufs& d = h->d;
+  if (!d.valid || d.N != h->N)
+    return fail(h, MPM_EINVAL,
+                "mpm_rollout_backward: no rollout to differentiate (particles, tools or the clock changed since)");
+  if (!theta_bar) return fail(h, MPM_EINVAL, "mpm_rollout_backward: theta_bar is required");
+  HIP_OR_RETURN(h, select_device(h));
+  const int64_t N = d.N;
+  const int T = d.T, K = d.K;
+  const int64_t SF = (int64_t)kStateFloats * N;
+  HIP_OR_RETURN(h, ensure(&d.seg, &d.seg_slots, (int64_t)K, sizeof(float) * SF));
+  HIP_OR_RETURN(h, ensure(&d.tool_red, &d.tool_red_n, (int64_t)(T > 0 ? T : 1) * kMaxTools * 6));
+  DState adj = dstate(d.adj, N);
+  const float* seeds[4] = {xb, vb, Cb, Fb};
+  float* dst[4] = {adj.x, adj.v, adj.C, adj.F};
+  const int64_t len[4] = {3 * N, 3 * N, 9 * N, 9 * N};
+  for (int f = 0; f < 4; ++f) {
+    if (seeds[f])
+      HIP_OR_RETURN(h, hipMemcpyAsync(dst[f], seeds[f], sizeof(float) * len[f], hipMemcpyDeviceToDevice, h->stream));
+    else
+      launch_fill_f32(dst[f], len[f], 0.0f, h->stream);
+  }
+  launch_fill_f32(theta_bar, N, 0.0f, h->stream);
+  launch_fill_f64(d.tool_red, (int64_t)T * kMaxTools * 6, 0.0, h->stream);
+  const DState none = {nullptr, nullptr, nullptr, nullptr};
+  const int nseg = (T + K - 1) / K;
+  for (int a = nseg - 1; a >= 0; --a) {
+    const int s0 = a * K;
+    const int n_in = (T - s0) < K ? (T - s0) : K;
+    auto st = [&](int i) -> DState {
+      return i == 0 ? dstate(d.ckpt + (int64_t)a * SF, N) : dstate(d.seg + (int64_t)i * SF, N);
+    };
+    for (int i = 1; i < n_in; ++i)
+      launch_diff_substep(d.g, h->sim, tools_at(h, d.start + s0 + i - 1), N, st(i - 1), d.E, st(i), false, false,
+                          h->b.status, h->stream);
+    for (int i = n_in - 1; i >= 0; --i) {
+      const int j = s0 + i;
+      const ToolSetK ts = tools_at(h, d.start + j);
+      launch_diff_substep(d.g, h->sim, ts, N, st(i), d.E, none, false, true, h->b.status, h->stream);
+      launch_diff_adjoint(d.g, h->sim, ts, N, st(i), d.E, adj, theta_bar, d.tool_red + (int64_t)j * kMaxTools * 6,
+                          h->stream);
+    }
+  }
+  float* outs[4] = {xb0, vb0, Cb0, Fb0};
+  for (int f = 0; f < 4; ++f)
+    if (outs[f])
+      HIP_OR_RETURN(h, hipMemcpyAsync(outs[f], dst[f], sizeof(float) * len[f], hipMemcpyDeviceToDevice, h->stream));
+  HIP_OR_RETURN(h, hipGetLastError());
+  if (vel_bar) {
+    std::vector<double> red((size_t)T * kMaxTools * 6);
+    if (T > 0)
+      HIP_OR_RETURN(h, hipMemcpyAsync(red.data(), d.tool_red, sizeof(double) * red.size(), hipMemcpyDeviceToHost,
+                                      h->stream));
+    HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));
+    // The centre in substep i is the centre at the rollout start plus dt
+    // times the velocities of the substeps before i.
+    const double dt = (double)h->p.dt;
+    for (int q = 0; q < kMaxTools; ++q) {
+      double suffix[3] = {0.0, 0.0, 0.0};
+      for (int j = T - 1; j >= 0; --j) {
+        const double* r = &red[((size_t)j * kMaxTools + q) * 6];
+        for (int c = 0; c < 3; ++c) {
+          vel_bar[((size_t)q * T + j) * 3 + c] = r[c] + dt * suffix[c];
+          suffix[c] += r[3 + c];
+        }
+      }
+    }
+  }
   return MPM_OK;
 }
 
@@ -635,6 +933,19 @@ int mpm_eval_stress(int64_t n, const float* F, const float* E, float nu, float* 
   (void)hipFree(dE);
   (void)hipFree(dT);
   return e == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
+int mpm_read_tool_impulses(mpm_handle* h, double* out) {
+  if (!h || !out) return fail(h, MPM_EINVAL, "mpm_read_tool_impulses: NULL");
+  HIP_OR_RETURN(h, select_device(h));
+  launch_sum_impulses(h->b, h->imp_sum, h->stream);
+  double sums[kImpulseRows * 3];
+  HIP_OR_RETURN(h, hipMemcpyAsync(sums, h->imp_sum, sizeof(sums), hipMemcpyDeviceToHost, h->stream));
+  int rc = sync(h);
+  if (rc != MPM_OK) return rc;
+  // Slots hold the momentum given to the material; the tool receives the opposite.
+  for (int i = 0; i < kImpulseRows * 3; ++i) out[i] = -sums[i];
+  return MPM_OK;
 }
 
 int mpm_profile(mpm_handle* h, int32_t enable) {

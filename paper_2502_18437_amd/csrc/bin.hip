@@ -366,6 +366,23 @@ void launch_count_active_nodes(Buffers& b, int parity, unsigned long long* out, 
                      b.ovf_list[parity], b.status, parity, out);
 }
 
+__global__ void k_sum_impulses(const float* __restrict__ slots, double* __restrict__ out) {
+  // one thread per (row, component); slots are few (kGridSlots)
+  const int c = threadIdx.x;
+  if (c >= kImpulseRows * 3) return;
+  double s = 0.0;
+  for (int w = 0; w < kGridSlots; ++w) s += (double)slots[(size_t)w * (kImpulseRows * 3) + c];
+  out[c] = s;
+}
+
+void launch_clear_impulses(Buffers& b, hipStream_t st) {
+  fill_u32((uint32_t*)b.imp_slots, (int64_t)kGridSlots * kImpulseRows * 3, 0u, st);
+}
+
+void launch_sum_impulses(Buffers& b, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_impulses, dim3(1), dim3(64), 0, st, b.imp_slots, out);
+}
+
 // ------------------------------------------------------------------ marshalling
 __global__ void k_load(float* __restrict__ part, uint32_t* __restrict__ id, int64_t cap, int64_t N,
                        const float* __restrict__ x, const float* __restrict__ v,

@@ -22,8 +22,15 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
                                                   const uint32_t* __restrict__ act_list,
                                                   const uint32_t* __restrict__ ovf_list,
                                                   uint32_t* mark, uint32_t* __restrict__ node_cnt,
-                                                  Status* st, int parity, SimK s,
-                                                  ToolSetK tools) {
+                                                  float* __restrict__ imp_slots, Status* st, int parity,
+                                                  SimK s, ToolSetK tools) {
+  // Momentum given to the material by each tool and by the walls on the nodes
+  // this workgroup visits (two-way coupling, Sec. IV-A), summed per
+  // workgroup into its own slot at the end: the walls' in registers, the
+  // tools' (few nodes touch a tool) with LDS atomics.
+  __shared__ float imp_tools[kMaxTools * 3];
+  float imp_w[3] = {0.0f, 0.0f, 0.0f};
+  if (threadIdx.x < kMaxTools * 3) imp_tools[threadIdx.x] = 0.0f;
   const unsigned n_act = st->n_act;
   const unsigned total = n_act + st->ovf_count[parity];
   __shared__ unsigned blk_cnt;
@@ -71,9 +78,22 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
         const int j = bj * kTile + ((l >> kTileLog2) & (kTile - 1));
         const int k = bk * kTile + (l >> (2 * kTileLog2));
         const float xI[3] = {(float)i * s.dx, (float)j * s.dx, (float)k * s.dx};
-        for (int q = 0; q < tools.n; ++q)
-          if (tools.t[q].type != TOOL_NONE) tool_contact(tools.t[q], xI, v);
-        if (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi) v[0] = v[1] = v[2] = 0.0f;
+#pragma unroll 1
+        for (int q = 0; q < tools.n; ++q) {
+          if (tools.t[q].type == TOOL_NONE) continue;
+          const float vb[3] = {v[0], v[1], v[2]};
+          if (tool_contact(tools.t[q], xI, v)) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) atomicAdd(&imp_tools[3 * q + a], m * (v[a] - vb[a]));
+          }
+        }
+        if (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            imp_w[a] -= m * v[a];
+            v[a] = 0.0f;
+          }
+        }
       }
       vel[g] = make_float4(v[0], v[1], v[2], 0.0f);
     }
@@ -88,15 +108,38 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
   }
   // Clear the other parity's overflow list for the next substep.
   if (blockIdx.x == 0 && threadIdx.x == 0) st->ovf_count[parity ^ 1] = 0u;
+  // Workgroup sum of the impulses into this workgroup's slot (no other
+  // workgroup writes it, so a plain read-modify-write accumulates substeps).
+  __shared__ float red[kGridWG / 64][3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float x = imp_w[a];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wave][a] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kImpulseRows * 3) {
+    float x;
+    if (threadIdx.x < kMaxTools * 3) {
+      x = imp_tools[threadIdx.x];
+    } else {
+      x = 0.0f;
+#pragma unroll
+      for (int w = 0; w < kGridWG / 64; ++w) x += red[w][threadIdx.x - kMaxTools * 3];
+    }
+    imp_slots[(size_t)blockIdx.x * (kImpulseRows * 3) + threadIdx.x] += x;
+  }
 }
 
 void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
                  hipStream_t st) {
-  int wgs = max_act < 8192 ? max_act : 8192;
+  int wgs = max_act < kGridSlots ? max_act : kGridSlots;
   if (wgs < 1) wgs = 1;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
                      b.acc_p[2], b.vel, b.act_list,
-                     b.ovf_list[parity], b.mark, b.node_cnt, b.status, parity, s, tools);
+                     b.ovf_list[parity], b.mark, b.node_cnt, b.imp_slots, b.status, parity, s, tools);
 }
 
 }  // namespace mpm

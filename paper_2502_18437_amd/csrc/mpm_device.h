@@ -150,12 +150,19 @@ __device__ __forceinline__ void polar_svd_signfix(const float* F, float* R) {
     for (int c = 0; c < 3; ++c) R[3 * r + c] = u[0][r] * v[0][c] + u[1][r] * v[1][c] + u[2][r] * v[2][c];
 }
 
+// Derivatives of the weights above with respect to f.
+__device__ __forceinline__ void bspline_dw(float f, float dw[3]) {
+  dw[0] = f - 1.5f;
+  dw[1] = 2.0f * (1.0f - f);
+  dw[2] = f - 0.5f;
+}
+
 // Fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + la (J - 1) J I
 // (Stomakhin et al. 2012; the paper leaves the MLS-MPM constitutive law
-// open, Algorithm 1). Returns J = det F; *inverted is set when J <= 0.
-__device__ __forceinline__ float kirchhoff(const float* F, float mu, float la, float* tau,
-                                           bool* inverted) {
-  float R[9];
+// open, Algorithm 1), also returning the rotation factor R of F. Returns
+// J = det F; *inverted is set when J <= 0.
+__device__ __forceinline__ float kirchhoff_r(const float* F, float mu, float la, float* tau, float* R,
+                                             bool* inverted) {
   const float J = det3(F);
   bool ok = (J > 0.0f) && polar_newton(F, R);
   if (!ok) polar_svd_signfix(F, R);
@@ -171,6 +178,12 @@ __device__ __forceinline__ float kirchhoff(const float* F, float mu, float la, f
       tau[3 * r + c] = D[3 * r] * F[3 * c] + D[3 * r + 1] * F[3 * c + 1] + D[3 * r + 2] * F[3 * c + 2] +
                        (r == c ? vol : 0.0f);
   return J;
+}
+
+__device__ __forceinline__ float kirchhoff(const float* F, float mu, float la, float* tau,
+                                           bool* inverted) {
+  float R[9];
+  return kirchhoff_r(F, mu, la, tau, R, inverted);
 }
 
 // Signed distance of a tool at world point p and its unit outward normal.
@@ -225,28 +238,105 @@ __device__ __forceinline__ float tool_sdf(const ToolK& t, const float* p, float*
   return phi;
 }
 
-// Contact of one node with one tool (Sec. IV-A, eq. v_correction): the
-// relative velocity u = v - v_r is left alone when separating (u.n >= 0);
-// otherwise its normal part is removed and its tangential part t is scaled
-// by c_d max(1 + mu u.n / |t|, 0).
-__device__ __forceinline__ void tool_contact(const ToolK& t, const float* xI, float* v) {
-  float n[3];
-  const float phi = tool_sdf(t, xI, n);
-  if (!(phi < t.margin)) return;
+// Friction and drag of eq. v_correction on a kept tangential vector t of
+// length s, for an approaching node (u_n < 0): c_d max(1 + mu u_n / s, 0) t.
+__device__ __forceinline__ float friction_scale(const ToolK& t, float un, float s) {
+  return s > 0.0f ? t.drag * fmaxf(1.0f + t.mu * un / s, 0.0f) : 0.0f;
+}
+
+// Contact of one node with one tool. Regular geometries (Sec. IV-A, eq.
+// v_correction): the relative velocity u = v - v_r is left alone when
+// separating (u.n >= 0); otherwise its normal part is removed and its
+// tangential part t is scaled by c_d max(1 + mu u.n / |t|, 0).
+// Slicer (Sec. IV-B): a rectangle in the body x-y plane; within the fattened
+// distance `margin` the normal is +-body z on the node's side (material is
+// parted, not pushed), and beyond the spine edge (body y > half height) the
+// contact is sticky. Segment and arc (Sec. IV-C): within the thickness only
+// the part of u along the curve tangent is kept (then friction and drag),
+// unless the node separates. Returns true if the node was in contact.
+__device__ __forceinline__ bool tool_contact(const ToolK& t, const float* xI, float* v) {
   const float r0 = xI[0] - t.c[0], r1 = xI[1] - t.c[1], r2 = xI[2] - t.c[2];
+  if (t.reach2 >= 0.0f && r0 * r0 + r1 * r1 + r2 * r2 > t.reach2) return false;  // far from the tool
+  float n[3];
+  float tl[3] = {0.0f, 0.0f, 0.0f};  // curve tangent (body frame), 1D geometries only
+  bool sticky = false, curve = false;
+  if (t.type == TOOL_CAPSULE || t.type == TOOL_BOX || t.type == TOOL_PLANE) {
+    const float phi = tool_sdf(t, xI, n);
+    if (!(phi < t.margin)) return false;
+  } else {
+    float pl[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pl[i] = t.R[i] * r0 + t.R[3 + i] * r1 + t.R[6 + i] * r2;
+    float nl[3];
+    if (t.type == TOOL_SLICER) {
+      const float qx = fmaxf(fabsf(pl[0]) - t.size[0], 0.0f);
+      const float qy = fmaxf(fabsf(pl[1]) - t.size[1], 0.0f);
+      const float d = sqrtf(qx * qx + qy * qy + pl[2] * pl[2]);
+      if (!(d < t.margin)) return false;
+      sticky = pl[1] > t.size[1];
+      nl[0] = 0.0f, nl[1] = 0.0f, nl[2] = (pl[2] < 0.0f) ? -1.0f : 1.0f;
+    } else {  // segment or arc
+      float proj[3], thick;
+      if (t.type == TOOL_SEGMENT) {
+        thick = t.size[1];
+        proj[0] = fminf(fmaxf(pl[0], -t.size[0]), t.size[0]), proj[1] = 0.0f, proj[2] = 0.0f;
+        tl[0] = 1.0f;
+      } else {
+        const float ra = t.size[0], ha = t.size[1];
+        thick = t.size[2];
+        float ang = atan2f(pl[1], pl[0]);
+        if (ang > ha || ang < -ha) {  // nearer end point
+          float sh, ch;
+          sincosf(ha, &sh, &ch);
+          const float dp = (pl[0] - ra * ch) * (pl[0] - ra * ch) + (pl[1] - ra * sh) * (pl[1] - ra * sh);
+          const float dm = (pl[0] - ra * ch) * (pl[0] - ra * ch) + (pl[1] + ra * sh) * (pl[1] + ra * sh);
+          ang = (dm < dp) ? -ha : ha;
+        }
+        float sa, ca;
+        sincosf(ang, &sa, &ca);
+        proj[0] = ra * ca, proj[1] = ra * sa, proj[2] = 0.0f;
+        tl[0] = -sa, tl[1] = ca;
+      }
+      const float e0 = pl[0] - proj[0], e1 = pl[1] - proj[1], e2 = pl[2] - proj[2];
+      const float L = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+      if (!(L < thick)) return false;
+      if (L > 0.0f) {
+        nl[0] = e0 / L, nl[1] = e1 / L, nl[2] = e2 / L;
+      } else {
+        nl[0] = -tl[1], nl[1] = tl[0], nl[2] = 0.0f;
+      }
+      curve = true;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) n[i] = t.R[3 * i] * nl[0] + t.R[3 * i + 1] * nl[1] + t.R[3 * i + 2] * nl[2];
+  }
   const float vr0 = t.lv[0] + t.av[1] * r2 - t.av[2] * r1;
   const float vr1 = t.lv[1] + t.av[2] * r0 - t.av[0] * r2;
   const float vr2 = t.lv[2] + t.av[0] * r1 - t.av[1] * r0;
+  if (sticky) {
+    v[0] = vr0, v[1] = vr1, v[2] = vr2;
+    return true;
+  }
   const float u0 = v[0] - vr0, u1 = v[1] - vr1, u2 = v[2] - vr2;
   const float un = n[0] * u0 + n[1] * u1 + n[2] * u2;
-  if (!(un < 0.0f)) return;
-  const float t0 = u0 - un * n[0], t1 = u1 - un * n[1], t2 = u2 - un * n[2];
-  const float s = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
-  float k = 0.0f;
-  if (s > 0.0f) k = t.drag * fmaxf(1.0f + t.mu * un / s, 0.0f);
+  if (!(un < 0.0f)) return true;  // separating or tangential: unchanged
+  float t0, t1, t2, s;
+  if (curve) {
+    float tg[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tg[i] = t.R[3 * i] * tl[0] + t.R[3 * i + 1] * tl[1] + t.R[3 * i + 2] * tl[2];
+    const float ut = tg[0] * u0 + tg[1] * u1 + tg[2] * u2;
+    t0 = ut * tg[0], t1 = ut * tg[1], t2 = ut * tg[2];
+    s = fabsf(ut);
+  } else {
+    t0 = u0 - un * n[0], t1 = u1 - un * n[1], t2 = u2 - un * n[2];
+    s = sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
+  }
+  const float k = friction_scale(t, un, s);
   v[0] = vr0 + k * t0;
   v[1] = vr1 + k * t1;
   v[2] = vr2 + k * t2;
+  return true;
 }
 
 // Node (i, j, k) -> index in the blocked grid layout.

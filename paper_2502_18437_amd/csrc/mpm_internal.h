@@ -22,12 +22,14 @@ constexpr int kTileLo = -((kSlack + kTile - 1) / kTile);
 constexpr int kTileHi = (kTile + 1 + kSlack) / kTile;
 constexpr int kBlockNodes = kTile * kTile * kTile;  // 512
 constexpr int kMaxTools = 8;
+constexpr int kImpulseRows = kMaxTools + 1;  // tools, then the walls
+constexpr int kGridSlots = 8192;             // largest grid-update launch (impulse slots)
 constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA
 
 // Field offsets in the particle SoA (each field is `cap` floats).
 enum Field { FX = 0, FV = 3, FC = 6, FF = 15, FE = 24 };
 
-enum ToolType { TOOL_NONE = 0, TOOL_CAPSULE = 1, TOOL_BOX = 2, TOOL_PLANE = 3 };
+enum ToolType { TOOL_NONE = 0, TOOL_CAPSULE = 1, TOOL_BOX = 2, TOOL_PLANE = 3, TOOL_SLICER = 4, TOOL_SEGMENT = 5, TOOL_ARC = 6 };
 
 // One tool as the grid kernel sees it (FP32, pose of the current substep).
 struct ToolK {
@@ -38,6 +40,7 @@ struct ToolK {
   float lv[3];
   float av[3];
   float mu, drag, margin;
+  float reach2;    // squared radius around c outside which no node is in contact; < 0: unbounded
 };
 
 struct ToolSetK {
@@ -101,6 +104,7 @@ struct Buffers {
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
   uint32_t* node_cnt = nullptr;             // per block: nodes with mass, last grid update
+  float* imp_slots = nullptr;               // per grid workgroup: impulse sums (kImpulseRows x 3)
   uint32_t* ovf_list[2] = {nullptr, nullptr};
   void* acc_m = nullptr;                    // grid accumulator, mass channel (float or u32)
   void* acc_p[3] = {nullptr, nullptr, nullptr};  // momentum channels (float or int64)
@@ -126,6 +130,10 @@ void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, i
 // and overflow blocks of `parity`), written to *out (device memory).
 void launch_count_active_nodes(Buffers& b, int parity, unsigned long long* out, hipStream_t st);
 
+// Clear the impulse slots; sum them into out[kImpulseRows * 3] (device).
+void launch_clear_impulses(Buffers& b, hipStream_t st);
+void launch_sum_impulses(Buffers& b, double* out, hipStream_t st);
+
 // Stress evaluation (diagnostic entry point).
 void launch_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,
                         hipStream_t st);
@@ -136,5 +144,54 @@ void launch_unpermute(const Buffers& b, int64_t N, float* x, float* v, float* C,
 // Scatter caller AoS inputs into the SoA (identity order, id = index).
 void launch_load_particles(Buffers& b, int64_t N, const float* x, const float* v, const float* C,
                            const float* F, const float* E, hipStream_t st);
+
+// ---------------------------------------------------------------- differentiable rollout
+// A particle state in the caller's order: x (N x 3), v (N x 3), C (N x 9),
+// F (N x 9), consecutive in one block of kStateFloats * N floats. Adjoint
+// states use the same layout.
+constexpr int kStateFloats = 24;
+
+struct DState {
+  float* x;
+  float* v;
+  float* C;
+  float* F;
+};
+
+inline DState dstate(float* base, int64_t N) {
+  return {base, base + 3 * N, base + 6 * N, base + 15 * N};
+}
+
+// Dense-grid buffers of the differentiable path (n^3 nodes, node (i, j, k)
+// at index (i * n + j) * n + k).
+struct DiffGrid {
+  float* m = nullptr;                       // P2G mass accumulator
+  float* p[3] = {nullptr, nullptr, nullptr};  // P2G momentum accumulators
+  float4* vel = nullptr;                    // velocity after the grid update (w unused)
+  float4* hat = nullptr;                    // velocity before contact (xyz) and mass (w)
+  float* vb[3] = {nullptr, nullptr, nullptr};  // cotangent of vel (accumulated by G2P adjoint)
+  float4* pb = nullptr;                     // cotangent of momentum (xyz) and of mass (w)
+  uint8_t* skip = nullptr;                  // per particle: left unchanged this substep
+};
+
+// Forward substep on the dense grid: P2G from `in`, grid update (tools,
+// walls), G2P into `out`. Particles with a non-finite state or a stencil
+// outside the grid are copied unchanged (and counted when `count`).
+// With `keep_hat`, the pre-contact velocity and mass are kept in g.hat.
+// With out.x == nullptr only P2G and the grid update run.
+void launch_diff_substep(const DiffGrid& g, const SimK& s, const ToolSetK& tools, int64_t N, DState in,
+                         const float* E, DState out, bool count, bool keep_hat, Status* st, hipStream_t stream);
+// Reverse of one substep whose forward grid (g.vel, g.hat) has just been
+// recomputed from `in`: on entry `adj` is the cotangent of the state after the
+// substep, on exit that of `in`. Adds d/d log E to theta_bar and the tools'
+// centre and linear-velocity cotangents to tool_red[kMaxTools][6] (FP64).
+void launch_diff_adjoint(const DiffGrid& g, const SimK& s, const ToolSetK& tools, int64_t N, DState in,
+                         const float* E, DState adj, float* theta_bar, double* tool_red, hipStream_t stream);
+// Fill helpers.
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+void launch_exp(const float* theta, float* E, int64_t n, hipStream_t st);
+// E of the handle's particles in the caller's order (E_default when absent).
+void launch_unpermute_E(const Buffers& b, int64_t N, const SimK& s, float* E, hipStream_t st);
 
 }  // namespace mpm

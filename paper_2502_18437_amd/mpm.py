@@ -23,6 +23,7 @@ MPM_ERANGE = -7
 MPM_HOST, MPM_DEVICE = 0, 1
 MPM_ACCUM_F32, MPM_ACCUM_FIXED = 0, 1
 MPM_TOOL_NONE, MPM_TOOL_CAPSULE, MPM_TOOL_BOX, MPM_TOOL_PLANE = 0, 1, 2, 3
+MPM_TOOL_SLICER, MPM_TOOL_SEGMENT, MPM_TOOL_ARC = 4, 5, 6
 MPM_MAX_TOOLS = 8
 MPM_KERNEL_KINDS = 5
 KERNEL_NAMES = ("binning", "p2g", "g2p2g", "g2p", "grid")
@@ -32,7 +33,8 @@ STATUS_NAMES = {0: "MPM_OK", -1: "MPM_EINVAL", -2: "MPM_ENOMEM", -3: "MPM_EHIP",
 
 EXPORTED = ("mpm_create", "mpm_destroy", "mpm_set_particles", "mpm_set_tool_sdf", "mpm_step",
             "mpm_read_state", "mpm_get_info", "mpm_last_error", "mpm_eval_stress", "mpm_profile",
-            "mpm_profile_read")
+            "mpm_profile_read", "mpm_read_tool_impulses", "mpm_set_tool_velocity_table", "mpm_rollout_forward",
+            "mpm_rollout_backward")
 
 
 class mpm_params(ctypes.Structure):
@@ -81,6 +83,11 @@ _lib.mpm_last_error.restype = ctypes.c_char_p
 _lib.mpm_eval_stress.argtypes = [ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32]
 _lib.mpm_profile.argtypes = [_h, ctypes.c_int32]
 _lib.mpm_profile_read.argtypes = [_h, ctypes.POINTER(mpm_kernel_times)]
+_lib.mpm_read_tool_impulses.argtypes = [_h, ctypes.POINTER(ctypes.c_double)]
+_lib.mpm_set_tool_velocity_table.argtypes = [_h, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+_lib.mpm_rollout_forward.argtypes = [_h, ctypes.c_int32, ctypes.c_int32, _vp]
+_lib.mpm_rollout_backward.argtypes = [_h, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp,
+                                      _vp]
 
 # C names, re-exported
 mpm_create = _lib.mpm_create
@@ -94,6 +101,10 @@ mpm_last_error = _lib.mpm_last_error
 mpm_eval_stress = _lib.mpm_eval_stress
 mpm_profile = _lib.mpm_profile
 mpm_profile_read = _lib.mpm_profile_read
+mpm_read_tool_impulses = _lib.mpm_read_tool_impulses
+mpm_set_tool_velocity_table = _lib.mpm_set_tool_velocity_table
+mpm_rollout_forward = _lib.mpm_rollout_forward
+mpm_rollout_backward = _lib.mpm_rollout_backward
 
 
 class MPMError(RuntimeError):
@@ -123,6 +134,19 @@ def _arg(a, shape_tail, n):
     if a.size != n * int(np.prod(shape_tail)):
         raise ValueError(f"expected {n} x {shape_tail}, got {a.shape}")
     return a.ctypes.data, MPM_HOST, a
+
+
+def _device_f32(a, n):
+    """A contiguous float32 CUDA tensor of n elements holding `a` (host
+    arrays are copied to the device)."""
+    import torch
+    t = a if _is_torch(a) else torch.as_tensor(np.asarray(a, dtype=np.float32))
+    if not t.is_cuda:
+        t = t.to(torch.device("cuda", torch.cuda.current_device()))
+    t = t.detach().to(torch.float32).contiguous()
+    if t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {tuple(t.shape)}")
+    return t
 
 
 def _current_stream():
@@ -216,6 +240,55 @@ class Simulation:
         self._check(_lib.mpm_get_info(self.h, ctypes.byref(i)))
         return {name: getattr(i, name) for name, _ in mpm_info._fields_}
 
+    def tool_impulses(self):
+        """(MPM_MAX_TOOLS + 1, 3) impulses on each tool (last row: walls) over
+        the most recent step() call."""
+        out = np.zeros((MPM_MAX_TOOLS + 1, 3), np.float64)
+        self._check(_lib.mpm_read_tool_impulses(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set_tool_velocity_table(self, tool_id, table):
+        """Per-substep linear velocities (T x 3) of a tool from the current
+        substep on (re-anchored at its current pose)."""
+        t = np.ascontiguousarray(np.asarray(table, dtype=np.float64).reshape(-1, 3))
+        self._check(_lib.mpm_set_tool_velocity_table(self.h, int(tool_id), t.shape[0],
+                                                      t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def rollout_forward(self, n_substeps, checkpoint_every=20, theta=None):
+        """Run and record a differentiable rollout; theta (N,) sets E = exp(theta)."""
+        keep = None
+        ptr = None
+        if theta is not None:
+            keep = _device_f32(theta, self.N)
+            ptr = keep.data_ptr()
+        self._check(_lib.mpm_rollout_forward(self.h, int(n_substeps), int(checkpoint_every), ptr))
+        self._keep_theta = keep
+        self._rollout_T = int(n_substeps)
+
+    def rollout_backward(self, xb=None, vb=None, Cb=None, Fb=None, want_vel=True, want_state=True):
+        """Gradient through the recorded rollout for the cotangents of the
+        final x, v, C, F (None = 0). Returns a dict: theta (N,) and, when
+        asked for, vel (MPM_MAX_TOOLS, T, 3) host float64 and x0, v0, C0, F0
+        (device tensors, cotangents of the starting state)."""
+        import torch
+        n = self.N
+        seeds = [None if a is None else _device_f32(a, n * k) for a, k in ((xb, 3), (vb, 3), (Cb, 9), (Fb, 9))]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        theta_bar = torch.empty(n, dtype=torch.float32, device=dev)
+        T = getattr(self, "_rollout_T", 0)
+        vel = np.zeros((MPM_MAX_TOOLS, T, 3), np.float64) if want_vel else None
+        outs = [torch.empty(shape, dtype=torch.float32, device=dev) for shape in ((n, 3), (n, 3), (n, 3, 3), (n, 3, 3))] \
+            if want_state else [None] * 4
+        rc = _lib.mpm_rollout_backward(
+            self.h, *[None if a is None else a.data_ptr() for a in seeds], theta_bar.data_ptr(),
+            None if vel is None else vel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            *[None if a is None else a.data_ptr() for a in outs])
+        self._check(rc)
+        r = {"theta": theta_bar, "vel": vel}
+        for k, a in zip(("x0", "v0", "C0", "F0"), outs):
+            r[k] = a
+        return r
+
     def profile(self, enable=True):
         self._check(_lib.mpm_profile(self.h, int(bool(enable))))
 
@@ -254,4 +327,56 @@ def simulation_from_scene(scene, **kw):
     sim.set_particles(scene.x, scene.v, scene.C, scene.F, scene.E, scene.mass, scene.vol0)
     for k, t in enumerate(scene.tools):
         sim.set_tool(k, t.type, **t.kwargs())
+    for k, tab in scene.vel_tables.items():
+        sim.set_tool_velocity_table(k, tab)
     return sim
+
+
+def rollout(sim, n_substeps, theta, vel_table=None, tool_id=0, checkpoint_every=20):
+    """Differentiable rollout of `sim` (torch.autograd): returns the state
+    (x, v, C, F) after n_substeps as CUDA tensors. Gradients flow to theta
+    (E_p = exp(theta_p), shape (N,)) and to vel_table (n_substeps x 3 linear
+    velocities of tool `tool_id`, one row per substep), through the
+    hand-written adjoint kernels of the library."""
+    return _rollout_fn()(theta, vel_table, sim, int(n_substeps), int(tool_id), int(checkpoint_every))
+
+
+_ROLLOUT = None
+
+
+def _rollout_fn():
+    global _ROLLOUT
+    if _ROLLOUT is not None:
+        return _ROLLOUT.apply
+    import torch
+
+    class Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, theta, vel_table, sim, T, tool_id, K):
+            if vel_table is not None:
+                if tuple(vel_table.shape) != (T, 3):
+                    raise ValueError("vel_table must be n_substeps x 3")
+                sim.set_tool_velocity_table(tool_id, vel_table.detach().cpu().double().numpy())
+            sim.rollout_forward(T, K, theta=theta)
+            n = sim.N
+            dev = theta.device
+            out = {"x": torch.empty((n, 3), dtype=torch.float32, device=dev),
+                   "v": torch.empty((n, 3), dtype=torch.float32, device=dev),
+                   "C": torch.empty((n, 3, 3), dtype=torch.float32, device=dev),
+                   "F": torch.empty((n, 3, 3), dtype=torch.float32, device=dev)}
+            sim.read_state(out)
+            ctx.sim, ctx.tool_id = sim, tool_id
+            ctx.table = None if vel_table is None else (vel_table.dtype, vel_table.device)
+            ctx.theta_dtype = theta.dtype
+            return out["x"], out["v"], out["C"], out["F"]
+
+        @staticmethod
+        def backward(ctx, gx, gv, gC, gF):
+            g = ctx.sim.rollout_backward(gx, gv, gC, gF, want_vel=ctx.table is not None, want_state=False)
+            tb = None
+            if ctx.table is not None:
+                tb = torch.from_numpy(g["vel"][ctx.tool_id].copy()).to(dtype=ctx.table[0], device=ctx.table[1])
+            return g["theta"].to(ctx.theta_dtype), tb, None, None, None, None
+
+    _ROLLOUT = Rollout
+    return Rollout.apply

@@ -35,7 +35,7 @@ import math
 
 import numpy as np
 
-TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE = 0, 1, 2, 3
+TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE, TOOL_SLICER, TOOL_SEGMENT, TOOL_ARC = 0, 1, 2, 3, 4, 5, 6
 RHO = 1e3
 GRAVITY = (0.0, -9.8, 0.0)
 WALL_BAND = 3
@@ -77,6 +77,8 @@ class Scene:
     tools: list = field(default_factory=list)
     gravity: tuple = GRAVITY
     wall_band: int = WALL_BAND
+    theta: np.ndarray = None           # (N,) float32 log E, differentiable scenes
+    vel_tables: dict = field(default_factory=dict)  # tool id -> (T, 3) float64 per-substep velocities
 
     @property
     def N(self):
@@ -152,12 +154,19 @@ def _slab(n_grid, counts, seed, E_range=(2e3, 8e3)):
     return pts.astype(np.float32), E, vol0, top
 
 
+# Start offset of the press capsule off the node lattice, in units of dx. On
+# the lattice, nodes can lie exactly on the capsule surface (e.g. offsets
+# (0.4, 2.8, 1) dx from a cap centre are exactly r = 3 dx away), and whether
+# such a node is in contact is then decided by rounding.
+PRESS_OFFSET_DX = (0.0173, 0.0, 0.0291)
+
+
 def _press_capsule(n_grid, top, center_xz=(0.5, 0.5), axis="z", half_length=0.15, speed=0.05):
     dx = 1.0 / n_grid
     r = 3 * dx
     quat = (SQRT_HALF, 0.0, -SQRT_HALF, 0.0) if axis == "z" else (1.0, 0.0, 0.0, 0.0)
-    return Tool(TOOL_CAPSULE, (center_xz[0], top + r, center_xz[1]), quat, (half_length, r, 0.0),
-                (0.0, -speed, 0.0), mu=0.3)
+    c = (center_xz[0] + PRESS_OFFSET_DX[0] * dx, top + r, center_xz[1] + PRESS_OFFSET_DX[2] * dx)
+    return Tool(TOOL_CAPSULE, c, quat, (half_length, r, 0.0), (0.0, -speed, 0.0), mu=0.3)
 
 
 def scene_c2(seed=2, n_grid=128, counts=(128, 64, 128), n_substeps=1000):
@@ -174,10 +183,11 @@ def scene_c2s(seed=2):
 
 def _blade_and_grasper(n_grid, top):
     dx = 1.0 / n_grid
-    blade = Tool(TOOL_BOX, (0.1, top, 0.5), (1.0, 0.0, 0.0, 0.0), (0.15, 0.15, 0.25 * dx),
+    ox, oz = PRESS_OFFSET_DX[0] * dx, PRESS_OFFSET_DX[2] * dx  # off the node lattice (faces, caps)
+    blade = Tool(TOOL_BOX, (0.1 + ox, top, 0.5 + oz), (1.0, 0.0, 0.0, 0.0), (0.15, 0.15, 0.25 * dx),
                  (1.0, 0.0, 0.0), mu=0.3)
     r = 3 * dx
-    grasper = Tool(TOOL_CAPSULE, (0.7, top + r, 0.3), (1.0, 0.0, 0.0, 0.0), (0.1, r, 0.0),
+    grasper = Tool(TOOL_CAPSULE, (0.7 + ox, top + r, 0.3 + oz), (1.0, 0.0, 0.0, 0.0), (0.1, r, 0.0),
                    (0.0, -0.05, 0.0), mu=0.3)
     return [blade, grasper]
 
@@ -201,17 +211,33 @@ def scene_c3m(seed=3):
     return s
 
 
-def scene_c5(seed=5, n_substeps=200):
-    n = 64
-    dx = 1.0 / n
-    x, _, vol0, top = _slab(n, (64, 16, 64), seed)
+def press_table(n_substeps):
+    """Per-substep capsule velocities of the differentiable scenes: a downward
+    press of 0.5 m/s modulated by one period of a sideways and vertical wave."""
+    ph = 2.0 * math.pi * np.arange(n_substeps) / max(1, n_substeps)
+    return np.stack([0.1 * np.cos(ph), -0.5 + 0.2 * np.sin(ph), np.zeros(n_substeps)], axis=1)
+
+
+def scene_c5(seed=5, n_substeps=200, n_grid=64, counts=(64, 16, 64)):
+    """Differentiable press: a slab with E_p = exp(theta_p), theta_p =
+    ln(5e3) + U(-0.2, 0.2), pressed by a capsule that follows a per-substep
+    velocity table."""
+    x, _, vol0, top = _slab(n_grid, counts, seed)
     rng = np.random.default_rng(seed + 1000)
-    theta = math.log(5e3) + rng.uniform(-0.2, 0.2, size=x.shape[0])
-    E = np.exp(theta).astype(np.float32)
-    tool = _press_capsule(n, top)
-    tool.lin_vel = (0.0, -0.05, 0.0)
-    s = Scene("c5", n, 1e-4, n_substeps, 0.3, 5e3, RHO * vol0, vol0, x, E=E, tools=[tool])
-    s.theta = theta.astype(np.float32)
+    theta = (math.log(5e3) + rng.uniform(-0.2, 0.2, size=x.shape[0])).astype(np.float32)
+    E = np.exp(theta.astype(np.float64)).astype(np.float32)
+    tool = _press_capsule(n_grid, top)
+    tool.lin_vel = (0.0, 0.0, 0.0)
+    s = Scene("c5", n_grid, 1e-4, n_substeps, 0.3, 5e3, RHO * vol0, vol0, x, E=E, tools=[tool])
+    s.theta = theta
+    s.vel_tables = {0: press_table(n_substeps)}
+    return s
+
+
+def scene_c5s(seed=5):
+    """c5 at 32^3 with 8,192 particles and 40 substeps."""
+    s = scene_c5(seed, n_substeps=40, n_grid=32, counts=(32, 8, 32))
+    s.name = "c5s"
     return s
 
 
@@ -254,7 +280,7 @@ def tiny_block(n_grid=16, per_axis=6, seed=11, spacing_dx=0.5, center=(0.5, 0.5,
 
 SCENES = {
     "c1": scene_c1, "c1s": scene_c1s, "c2": scene_c2, "c2s": scene_c2s, "c3": scene_c3,
-    "c3s": scene_c3s, "c3m": scene_c3m, "c5": scene_c5, "cube": scene_cube,
+    "c3s": scene_c3s, "c3m": scene_c3m, "c5": scene_c5, "c5s": scene_c5s, "cube": scene_cube,
 }
 
 

@@ -30,6 +30,8 @@ def run_oracle(scene, n_substeps, idx=None):
                     scene.vol0)
     for k, t in enumerate(scene.tools):
         o.set_tool(k, t.type, **t.kwargs())
+    for k, tab in scene.vel_tables.items():
+        o.set_velocity_table(k, tab)
     st = o.step(n_substeps)
     r = o.read()
     r["status"] = st

@@ -96,3 +96,6 @@ def test_null_handle_calls_are_rejected_without_a_gpu():
     assert mpm._lib.mpm_set_tool_sdf(None, 0, None) == mpm.MPM_EINVAL
     assert mpm._lib.mpm_create(None, 0, None) == mpm.MPM_EINVAL
     assert mpm._lib.mpm_eval_stress(-1, None, None, 0.3, None, 0) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_set_tool_velocity_table(None, 0, 0, None) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_rollout_forward(None, 1, 1, None) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_rollout_backward(None, *([None] * 10)) == mpm.MPM_EINVAL
