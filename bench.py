@@ -20,7 +20,8 @@ Also reported on the same JSON line:
   following a 200 x 3 per-substep velocity table, E_p = exp(theta_p)):
   mpm_rollout_forward(200, checkpoints every 20) and mpm_rollout_backward
   (gradients for theta, the velocity table and the starting state), timed
-  separately, with the ratio (fwd + bwd) / fwd.
+  separately, with the ratio (fwd + bwd) / fwd; fwd_bwd_keep_all is the same
+  with a checkpoint (and the grid) kept at every substep.
 """
 import argparse
 import json
@@ -108,7 +109,7 @@ def fwd_bwd(steps, checkpoint_every=20):
                         f"table, {T} substeps of dt={s.dt}, checkpoints every {checkpoint_every}",
             "fwd_ms": 1e3 * t_f, "bwd_ms": 1e3 * t_b, "fwd_particle_substeps_per_s": ps / t_f,
             "fwd_bwd_particle_substeps_per_s": ps / (t_f + t_b), "ratio_fwd_bwd_over_fwd": (t_f + t_b) / t_f,
-            "steps": steps, "status": int(st), "finite_gradients": ok}
+            "checkpoint_every": checkpoint_every, "steps": steps, "status": int(st), "finite_gradients": ok}
 
 
 def main():
@@ -214,7 +215,8 @@ def main():
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
     if not args.no_diff:
-        out["fwd_bwd"] = fwd_bwd(args.diff_steps)
+        out["fwd_bwd"] = fwd_bwd(args.diff_steps, checkpoint_every=20)
+        out["fwd_bwd_keep_all"] = fwd_bwd(args.diff_steps, checkpoint_every=1)
     if not args.no_cpu:
         log(f"[bench] oracle CPU baseline: {args.cpu_substeps} substeps of the full scene ...")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_substeps)

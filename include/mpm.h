@@ -181,7 +181,7 @@ int mpm_destroy(mpm_handle* h);
  * order. Clears the deferred errors. The scene clock (substep counter) and
  * the tools are left as they are.
  * Errors: MPM_EINVAL (n < 0, n > max_particles, NULL x with n > 0,
- * mass or vol0 <= 0, bad where), MPM_EHIP. */
+ * mass or vol0 <= 0, bad where, a handle with several scenes), MPM_EHIP. */
 int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v,
                       const float* C, const float* F, const float* E,
                       float mass, float vol0, int32_t where);
@@ -243,6 +243,36 @@ int mpm_profile(mpm_handle* h, int32_t enable);
 /* Synchronise and return the totals accumulated since timing was enabled. */
 int mpm_profile_read(mpm_handle* h, mpm_kernel_times* out);
 
+/* ------------------------------------------------------ batches of scenes */
+/* A handle with n_scenes independent scenes that share the grid size, dt,
+ * gravity, wall band, material constants and accumulation mode. Each
+ * scene has its own particles, tools and n^3 grid. Every stage of mpm_step
+ * runs once for all scenes: the scene is the leading part of the grid-block
+ * id, so one launch per stage covers the batch and uneven particle counts
+ * balance across the GPU. mpm_create is mpm_create_batch with n_scenes = 1;
+ * the single-scene calls act on scene 0. max_particles is the capacity of
+ * the whole batch. Differentiable rollouts need n_scenes = 1.
+ * Errors: as mpm_create; MPM_EINVAL also for n_scenes < 1 or when
+ * n_scenes x ceil(n_grid / 8)^3 x 512 grid nodes reach 2^31. */
+int mpm_create_batch(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_handle** out);
+
+/* Replace the particles of every scene: counts[n_scenes] particles per scene,
+ * the arrays holding scene 0's particles, then scene 1's, and so on (layout,
+ * `where` and NULL rules as mpm_set_particles). mass and vol0 apply to every
+ * particle. mpm_read_state returns the state in the same order. Blocks the
+ * calling thread when n_scenes > 1 (it uploads the scene offsets).
+ * Errors: MPM_EINVAL (NULL counts, a negative count, total above
+ * max_particles, mass or vol0 not positive), MPM_EHIP. */
+int mpm_set_batch_particles(mpm_handle* h, const int64_t* counts, const float* x, const float* v, const float* C,
+                            const float* F, const float* E, float mass, float vol0, int32_t where);
+
+/* mpm_set_tool_sdf / mpm_set_tool_velocity_table / mpm_read_tool_impulses
+ * for scene `scene` (0 <= scene < n_scenes; otherwise MPM_EINVAL). */
+int mpm_set_scene_tool(mpm_handle* h, int32_t scene, int32_t tool_id, const mpm_tool* t);
+int mpm_set_scene_tool_velocity_table(mpm_handle* h, int32_t scene, int32_t tool_id, int64_t n_rows,
+                                      const double* table);
+int mpm_read_scene_tool_impulses(mpm_handle* h, int32_t scene, double* out);
+
 /* ------------------------------------------------------ scripted tool motion */
 /* Per-substep linear velocities of tool `tool_id` (Sec. V: a shape's velocity
  * is set for every step). `table` is n_rows x 3 doubles in host memory,
@@ -261,9 +291,12 @@ int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, 
  * particles in the caller's order, keeping a copy of the state every
  * `checkpoint_every` substeps; the reverse pass recomputes each segment from
  * its checkpoint and walks the substeps backwards through hand-written
- * adjoint kernels. Device memory: (n_substeps / checkpoint_every + 1) plus
- * checkpoint_every + 3 particle states of 96 bytes per particle, and
- * 104 bytes per grid node. */
+ * adjoint kernels. With checkpoint_every = 1 every substep's grid is kept as
+ * well and nothing is recomputed. Device memory: (n_substeps /
+ * checkpoint_every + 4) particle states of 96 bytes per particle, plus
+ * checkpoint_every more when checkpoint_every > 1; 60 bytes per grid node,
+ * plus 32 bytes per node for each kept grid (n_substeps of them when
+ * checkpoint_every = 1, else checkpoint_every during the reverse pass). */
 
 /* Run n_substeps substeps from the current state and record the rollout.
  * theta (device, N floats, caller order) sets E_p = exp(theta_p) for the

@@ -51,6 +51,9 @@ struct DiffBufs {
   int64_t seg_slots = 0;
   double* tool_red = nullptr;
   int64_t tool_red_n = 0;
+  float4* grids = nullptr;  // per substep: velocity after the grid update, then pre-contact velocity and mass
+  int64_t grid_slots = 0;
+  bool grids_kept = false;  // the forward kept the grid of every substep (checkpoint_every == 1)
   bool valid = false;     // a rollout is recorded and nothing it depends on changed
   int T = 0, K = 1;
   int64_t start = 0;      // substep counter when the rollout began
@@ -80,7 +83,11 @@ struct mpm_handle {
   bool has_E = false;
   float mass = 0.0f, vol0 = 0.0f;
   SimK sim{};
-  HostTool tools[kMaxTools];
+  int n_scenes = 1;
+  std::vector<HostTool> tools;                // n_scenes x kMaxTools (scene-major)
+  std::vector<double*> tool_tables;           // device copies of the velocity tables (vtab then vpre)
+  bool tools_dirty = true;                    // device tool descriptors need an upload
+  std::vector<int64_t> scene_n;               // particles per scene
   int64_t substep = 0;
   int64_t since_sort = 0;
   bool dirty = true;
@@ -258,16 +265,16 @@ void prof_collect(mpm_handle* h) {
 void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
                   b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.act_list, b.mark,
-                  b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.imp_slots, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
-                  b.status};
+                  b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.imp_blocks, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
+                  b.status, b.scene_off, b.tools};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   b = Buffers();
 }
 
 void free_diff(DiffBufs& d) {
-  void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.hat, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb,
-                  d.g.skip, d.E, d.work, d.adj, d.ckpt, d.seg, d.tool_red};
+  void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb,
+                  d.g.skip, d.E, d.work, d.adj, d.ckpt, d.seg, d.tool_red, d.grids};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DiffBufs();
@@ -319,6 +326,17 @@ namespace {
 
 // (Re)allocate a device buffer to hold at least `need` elements of `elem`
 // bytes; `have` tracks the current capacity in elements.
+int alloc_fail(mpm_handle* h, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(h, MPM_ENOMEM, std::string(what) + ": out of device memory");
+  return hip_fail(h, e, what);
+}
+
+#define ALLOC_OR_RETURN(h, expr)                         \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return alloc_fail(h, e_, #expr); \
+  } while (0)
+
 template <typename T>
 hipError_t ensure(T** p, int64_t* have, int64_t need, size_t elem = sizeof(T)) {
   if (*p && *have >= need) return hipSuccess;
@@ -335,7 +353,7 @@ hipError_t diff_alloc_base(mpm_handle* h) {
   const int n = h->p.n_grid;
   const int64_t nn = (int64_t)n * n * n;
   if (d.grid_n != n) {
-    void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.hat, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb};
+    void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb};
     for (void* q : ptrs)
       if (q) (void)hipFree(q);
     DiffGrid z;
@@ -349,7 +367,6 @@ hipError_t diff_alloc_base(mpm_handle* h) {
       if ((e = hipMalloc((void**)&d.g.vb[a], sizeof(float) * nn)) != hipSuccess) return e;
     }
     if ((e = hipMalloc((void**)&d.g.vel, sizeof(float4) * nn)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&d.g.hat, sizeof(float4) * nn)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&d.g.pb, sizeof(float4) * nn)) != hipSuccess) return e;
     d.grid_n = n;
   }
@@ -380,7 +397,9 @@ hipError_t diff_alloc_base(mpm_handle* h) {
 
 extern "C" {
 
-int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
+namespace {
+
+int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_handle** out) {
   g_create_error.clear();
   if (!out) {
     g_create_error = "out is NULL";
@@ -397,9 +416,18 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
       !(p->accum_mode == MPM_ACCUM_F32 || p->accum_mode == MPM_ACCUM_FIXED) ||
       !(p->tile == 0 || p->tile == kTile) ||
       p->resort_interval < 0 || p->max_particles < 0 || p->max_particles > 0x7fffffffLL ||
-      !std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2])) {
+      !std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2]) ||
+      n_scenes < 1) {
     g_create_error = "parameter out of range";
     return MPM_EINVAL;
+  }
+  {
+    // Node indices of the whole batch must fit an int.
+    const int64_t nb = (p->n_grid + kTile - 1) / kTile;
+    if ((int64_t)n_scenes * nb * nb * nb * kBlockNodes >= (1ll << 31)) {
+      g_create_error = "n_scenes x grid nodes exceeds 2^31";
+      return MPM_EINVAL;
+    }
   }
   mpm_handle* h = new (std::nothrow) mpm_handle();
   if (!h) {
@@ -408,6 +436,10 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   }
   h->p = *p;
   if (h->p.tile == 0) h->p.tile = kTile;
+  h->n_scenes = n_scenes;
+  h->tools.assign((size_t)n_scenes * kMaxTools, HostTool());
+  h->tool_tables.assign((size_t)n_scenes * kMaxTools, nullptr);
+  h->scene_n.assign((size_t)n_scenes, 0);
   h->resort_interval = p->resort_interval > 0 ? p->resort_interval : kDefaultResort;
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device);
@@ -429,7 +461,8 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   }
   const int n = p->n_grid;
   h->nb = (n + kTile - 1) / kTile;
-  h->n_blocks = (uint32_t)h->nb * h->nb * h->nb;
+  const uint32_t nb3 = (uint32_t)h->nb * h->nb * h->nb;
+  h->n_blocks = nb3 * (uint32_t)n_scenes;
   int bits = 1;
   while ((1u << bits) < h->n_blocks + 1u) ++bits;
   h->key_bits = bits;
@@ -466,7 +499,9 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.node_cnt, sizeof(uint32_t) * h->n_blocks);
-  alloc((void**)&b.imp_slots, sizeof(float) * kGridSlots * kImpulseRows * 3);
+  alloc((void**)&b.imp_blocks, sizeof(float) * (size_t)h->n_blocks * kImpulseRows * 3);
+  alloc((void**)&b.scene_off, sizeof(uint32_t) * ((size_t)n_scenes + 1));
+  alloc((void**)&b.tools, sizeof(ToolDesc) * (size_t)n_scenes * kMaxTools);
   alloc((void**)&h->imp_sum, sizeof(double) * kImpulseRows * 3);
   alloc((void**)&h->scratch_u64, sizeof(unsigned long long));
   const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
@@ -490,7 +525,14 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
                        (int64_t)(grid_nodes * mom_bytes / 4));
   hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
-  launch_clear_impulses(b, h->stream);
+  // Scene constants.
+  SimK& s = h->sim;
+  s.n = n;
+  s.nb = h->nb;
+  s.n_scenes = n_scenes;
+  s.nb3 = nb3;
+  s.n3 = (int)(nb3 * kBlockNodes);
+  launch_clear_impulses(b, s, h->stream);
   e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
@@ -500,10 +542,6 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
     delete h;
     return MPM_EHIP;
   }
-  // Scene constants.
-  SimK& s = h->sim;
-  s.n = n;
-  s.nb = h->nb;
   s.dx = (float)(1.0 / n);
   s.inv_dx = (float)n;
   s.dt = p->dt;
@@ -516,6 +554,16 @@ int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
   s.fixed = p->accum_mode == MPM_ACCUM_FIXED ? 1 : 0;
   *out = h;
   return MPM_OK;
+}
+
+}  // namespace
+
+int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out) {
+  return create_impl(p, 1, hip_stream, out);
+}
+
+int mpm_create_batch(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_handle** out) {
+  return create_impl(p, n_scenes, hip_stream, out);
 }
 
 int mpm_destroy(mpm_handle* h) {
@@ -533,6 +581,8 @@ int mpm_destroy(mpm_handle* h) {
   for (auto e : h->prof_pool) (void)hipEventDestroy(e);
   free_buffers(h->b);
   free_diff(h->d);
+  for (double* t : h->tool_tables)
+    if (t) (void)hipFree(t);
   if (h->scratch_u64) (void)hipFree(h->scratch_u64);
   if (h->imp_sum) (void)hipFree(h->imp_sum);
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
@@ -540,13 +590,28 @@ int mpm_destroy(mpm_handle* h) {
   return rc;
 }
 
-int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v, const float* C,
-                      const float* F, const float* E, float mass, float vol0, int32_t where) {
-  if (!h) return MPM_EINVAL;
-  if (n < 0 || n > h->b.cap || (n > 0 && !x) || !(mass > 0.0f) || !(vol0 > 0.0f) ||
+namespace {
+
+int set_particles_impl(mpm_handle* h, const int64_t* counts, const float* x, const float* v, const float* C,
+                       const float* F, const float* E, float mass, float vol0, int32_t where) {
+  int64_t n = 0;
+  for (int sc = 0; sc < h->n_scenes; ++sc) {
+    if (counts[sc] < 0) return fail(h, MPM_EINVAL, "mpm_set_particles: negative count");
+    n += counts[sc];
+  }
+  if (n > h->b.cap || (n > 0 && !x) || !(mass > 0.0f) || !(vol0 > 0.0f) ||
       !std::isfinite(mass) || !std::isfinite(vol0) || (where != MPM_HOST && where != MPM_DEVICE))
     return fail(h, MPM_EINVAL, "mpm_set_particles: argument out of range");
   HIP_OR_RETURN(h, select_device(h));
+  if (h->n_scenes > 1) {
+    // Scene offsets for the key generation (original particle order).
+    std::vector<uint32_t> off((size_t)h->n_scenes + 1, 0u);
+    for (int sc = 0; sc < h->n_scenes; ++sc) off[sc + 1] = off[sc] + (uint32_t)counts[sc];
+    HIP_OR_RETURN(h, hipMemcpyAsync(h->b.scene_off, off.data(), sizeof(uint32_t) * off.size(),
+                                    hipMemcpyHostToDevice, h->stream));
+    HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));
+  }
+  for (int sc = 0; sc < h->n_scenes; ++sc) h->scene_n[sc] = counts[sc];
   Buffers& b = h->b;
   const float* dx = x;
   const float* dv = v;
@@ -597,16 +662,29 @@ int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v, 
   return MPM_OK;
 }
 
-int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t) {
-  if (!h) return MPM_EINVAL;
-  if (tool_id < 0 || tool_id >= kMaxTools || !t) return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: bad id");
-  HostTool& ht = h->tools[tool_id];
+// Free the device copy of a tool's velocity table once the stream no longer
+// needs it.
+int drop_tool_table(mpm_handle* h, size_t slot) {
+  if (h->tool_tables[slot]) {
+    HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));
+    HIP_OR_RETURN(h, hipFree(h->tool_tables[slot]));
+    h->tool_tables[slot] = nullptr;
+  }
+  return MPM_OK;
+}
+
+int set_tool_impl(mpm_handle* h, int32_t scene, int32_t tool_id, const mpm_tool* t) {
+  if (scene < 0 || scene >= h->n_scenes || tool_id < 0 || tool_id >= kMaxTools || !t)
+    return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: bad scene or tool id");
+  const size_t slot = (size_t)scene * kMaxTools + tool_id;
+  HostTool& ht = h->tools[slot];
   if (t->type == MPM_TOOL_NONE) {
     ht.active = false;
     ht.vtab.clear();
     ht.vpre.clear();
     h->d.valid = false;
-    return MPM_OK;
+    h->tools_dirty = true;
+    return drop_tool_table(h, slot);
   }
   if (t->type < MPM_TOOL_CAPSULE || t->type > MPM_TOOL_ARC)
     return fail(h, MPM_EINVAL, "mpm_set_tool_sdf: bad type");
@@ -639,14 +717,16 @@ int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t) {
   ht.vtab.clear();
   ht.vpre.clear();
   h->d.valid = false;
-  return MPM_OK;
+  h->tools_dirty = true;
+  return drop_tool_table(h, slot);
 }
 
-int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, const double* table) {
-  if (!h) return MPM_EINVAL;
-  if (tool_id < 0 || tool_id >= kMaxTools || n_rows < 0 || (n_rows > 0 && !table))
+int set_table_impl(mpm_handle* h, int32_t scene, int32_t tool_id, int64_t n_rows, const double* table) {
+  if (scene < 0 || scene >= h->n_scenes || tool_id < 0 || tool_id >= kMaxTools || n_rows < 0 ||
+      (n_rows > 0 && !table))
     return fail(h, MPM_EINVAL, "mpm_set_tool_velocity_table: bad argument");
-  HostTool& ht = h->tools[tool_id];
+  const size_t slot = (size_t)scene * kMaxTools + tool_id;
+  HostTool& ht = h->tools[slot];
   if (!ht.active) return fail(h, MPM_EINVAL, "mpm_set_tool_velocity_table: no tool with this id");
   for (int64_t i = 0; i < 3 * n_rows; ++i)
     if (!std::isfinite(table[i])) return fail(h, MPM_EINVAL, "mpm_set_tool_velocity_table: non-finite entry");
@@ -660,7 +740,88 @@ int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, 
   for (int64_t j = 0; j < n_rows; ++j)
     for (int a = 0; a < 3; ++a) ht.vpre[3 * (j + 1) + a] = ht.vpre[3 * j + a] + ht.vtab[3 * j + a];
   h->d.valid = false;
+  h->tools_dirty = true;
+  int rc = drop_tool_table(h, slot);
+  if (rc != MPM_OK || n_rows == 0) return rc;
+  double* dev = nullptr;
+  const size_t nd = ht.vtab.size() + ht.vpre.size();
+  ALLOC_OR_RETURN(h, hipMalloc((void**)&dev, sizeof(double) * nd));
+  h->tool_tables[slot] = dev;
+  HIP_OR_RETURN(h, hipMemcpy(dev, ht.vtab.data(), sizeof(double) * ht.vtab.size(), hipMemcpyHostToDevice));
+  HIP_OR_RETURN(h, hipMemcpy(dev + ht.vtab.size(), ht.vpre.data(), sizeof(double) * ht.vpre.size(),
+                             hipMemcpyHostToDevice));
   return MPM_OK;
+}
+
+// Device descriptors of every scene's tools (uploaded when a tool changed).
+int upload_tools(mpm_handle* h) {
+  if (!h->tools_dirty) return MPM_OK;
+  std::vector<ToolDesc> desc((size_t)h->n_scenes * kMaxTools);
+  for (size_t slot = 0; slot < desc.size(); ++slot) {
+    const HostTool& ht = h->tools[slot];
+    ToolDesc& d = desc[slot];
+    std::memset(&d, 0, sizeof(d));
+    d.k.type = ht.active ? ht.t.type : TOOL_NONE;
+    if (!ht.active) continue;
+    for (int a = 0; a < 3; ++a) {
+      d.k.size[a] = (float)ht.t.size[a];
+      d.k.av[a] = (float)ht.t.ang_vel[a];
+      d.c0[a] = ht.t.center[a];
+      d.lv[a] = ht.t.lin_vel[a];
+    }
+    for (int i = 0; i < 9; ++i) d.k.R[i] = (float)ht.R[i];
+    d.k.mu = ht.t.mu;
+    d.k.drag = ht.t.drag;
+    d.k.margin = ht.t.margin;
+    d.k.reach2 = reach2_of(ht.t);
+    d.set_at = ht.set_at;
+    d.rows = (long long)(ht.vtab.size() / 3);
+    d.vtab = h->tool_tables[slot];
+    d.vpre = h->tool_tables[slot] ? h->tool_tables[slot] + ht.vtab.size() : nullptr;
+  }
+  // A pageable source is staged before the call returns, so `desc` may go.
+  HIP_OR_RETURN(h, hipMemcpyAsync(h->b.tools, desc.data(), sizeof(ToolDesc) * desc.size(), hipMemcpyHostToDevice,
+                                  h->stream));
+  h->tools_dirty = false;
+  return MPM_OK;
+}
+
+}  // namespace
+
+int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v, const float* C, const float* F,
+                      const float* E, float mass, float vol0, int32_t where) {
+  if (!h) return MPM_EINVAL;
+  if (h->n_scenes != 1) return fail(h, MPM_EINVAL, "mpm_set_particles: several scenes, use mpm_set_batch_particles");
+  if (n < 0) return fail(h, MPM_EINVAL, "mpm_set_particles: argument out of range");
+  return set_particles_impl(h, &n, x, v, C, F, E, mass, vol0, where);
+}
+
+int mpm_set_batch_particles(mpm_handle* h, const int64_t* counts, const float* x, const float* v, const float* C,
+                            const float* F, const float* E, float mass, float vol0, int32_t where) {
+  if (!h) return MPM_EINVAL;
+  if (!counts) return fail(h, MPM_EINVAL, "mpm_set_batch_particles: counts is NULL");
+  return set_particles_impl(h, counts, x, v, C, F, E, mass, vol0, where);
+}
+
+int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t) {
+  if (!h) return MPM_EINVAL;
+  return set_tool_impl(h, 0, tool_id, t);
+}
+
+int mpm_set_scene_tool(mpm_handle* h, int32_t scene, int32_t tool_id, const mpm_tool* t) {
+  if (!h) return MPM_EINVAL;
+  return set_tool_impl(h, scene, tool_id, t);
+}
+
+int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, const double* table) {
+  if (!h) return MPM_EINVAL;
+  return set_table_impl(h, 0, tool_id, n_rows, table);
+}
+
+int mpm_set_scene_tool_velocity_table(mpm_handle* h, int32_t scene, int32_t tool_id, int64_t n_rows,
+                                      const double* table) {
+  if (!h) return MPM_EINVAL;
+  return set_table_impl(h, scene, tool_id, n_rows, table);
 }
 
 int mpm_step(mpm_handle* h, int32_t n_substeps) {
@@ -670,7 +831,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   h->d.valid = false;
   if (h->N == 0) {
     HIP_OR_RETURN(h, select_device(h));
-    launch_clear_impulses(h->b, h->stream);
+    launch_clear_impulses(h->b, h->sim, h->stream);
     h->substep += n_substeps;
     return MPM_OK;
   }
@@ -678,7 +839,9 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   Buffers& b = h->b;
   const int64_t N = h->N;
   const int wgs = h->transfer_wgs;
-  launch_clear_impulses(b, h->stream);
+  int rc = upload_tools(h);
+  if (rc != MPM_OK) return rc;
+  launch_clear_impulses(b, h->sim, h->stream);
   for (int k = 0; k < n_substeps; ++k) {
     const int parity = (int)(h->substep & 1);
     const bool rebin = h->dirty || h->since_sort >= h->resort_interval;
@@ -702,7 +865,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     }
     {
       ProfScope ps(h, 4);
-      launch_grid(b, h->sim, tools_at(h, h->substep), parity, (int)h->n_blocks, h->stream);
+      launch_grid(b, h->sim, (long long)h->substep, parity, (int)h->n_blocks, h->stream);
     }
     h->substep++;
     h->since_sort++;
@@ -720,14 +883,20 @@ int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_ev
   if (n_substeps < 0 || checkpoint_every < 1)
     return fail(h, MPM_EINVAL, "mpm_rollout_forward: need n_substeps >= 0 and checkpoint_every >= 1");
   if (h->N == 0) return fail(h, MPM_EINVAL, "mpm_rollout_forward: no particles");
+  if (h->n_scenes != 1) return fail(h, MPM_EINVAL, "mpm_rollout_forward: one scene only");
   HIP_OR_RETURN(h, select_device(h));
   DiffBufs& d = h->d;
   d.valid = false;
   const int64_t N = h->N;
   const int T = n_substeps, K = checkpoint_every;
   const int64_t SF = (int64_t)kStateFloats * N;
-  HIP_OR_RETURN(h, diff_alloc_base(h));
-  HIP_OR_RETURN(h, ensure(&d.ckpt, &d.ckpt_slots, (int64_t)(T / K + 1), sizeof(float) * SF));
+  const int64_t nn = (int64_t)h->p.n_grid * h->p.n_grid * h->p.n_grid;
+  ALLOC_OR_RETURN(h, diff_alloc_base(h));
+  ALLOC_OR_RETURN(h, ensure(&d.ckpt, &d.ckpt_slots, (int64_t)(T / K + 1), sizeof(float) * SF));
+  // With a checkpoint at every substep the grids are kept too, and the
+  // reverse pass recomputes nothing.
+  d.grids_kept = (K == 1);
+  if (d.grids_kept) ALLOC_OR_RETURN(h, ensure(&d.grids, &d.grid_slots, (int64_t)(T > 0 ? T : 1), sizeof(float4) * 2 * nn));
   if (theta)
     launch_exp(theta, d.E, N, h->stream);
   else
@@ -738,9 +907,11 @@ int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_ev
   };
   DState s0 = slot(0);
   launch_unpermute(h->b, N, s0.x, s0.v, s0.C, s0.F, h->stream);
-  launch_clear_impulses(h->b, h->stream);
+  launch_clear_impulses(h->b, h->sim, h->stream);
   for (int k = 0; k < T; ++k) {
-    launch_diff_substep(d.g, h->sim, tools_at(h, h->substep), N, slot(k), d.E, slot(k + 1), true, false,
+    float4* vel = d.grids_kept ? d.grids + (int64_t)k * 2 * nn : d.g.vel;
+    float4* hat = d.grids_kept ? vel + nn : nullptr;
+    launch_diff_substep(d.g, vel, hat, h->sim, tools_at(h, h->substep), N, slot(k), d.E, slot(k + 1), true,
                         h->b.status, h->stream);
     h->substep++;
   }
@@ -771,8 +942,12 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
   const int64_t N = d.N;
   const int T = d.T, K = d.K;
   const int64_t SF = (int64_t)kStateFloats * N;
-  HIP_OR_RETURN(h, ensure(&d.seg, &d.seg_slots, (int64_t)K, sizeof(float) * SF));
-  HIP_OR_RETURN(h, ensure(&d.tool_red, &d.tool_red_n, (int64_t)(T > 0 ? T : 1) * kMaxTools * 6));
+  const int64_t nn = (int64_t)h->p.n_grid * h->p.n_grid * h->p.n_grid;
+  if (!d.grids_kept) {
+    ALLOC_OR_RETURN(h, ensure(&d.seg, &d.seg_slots, (int64_t)K, sizeof(float) * SF));
+    ALLOC_OR_RETURN(h, ensure(&d.grids, &d.grid_slots, (int64_t)K, sizeof(float4) * 2 * nn));
+  }
+  ALLOC_OR_RETURN(h, ensure(&d.tool_red, &d.tool_red_n, (int64_t)(T > 0 ? T : 1) * kMaxTools * 6));
   DState adj = dstate(d.adj, N);
   const float* seeds[4] = {xb, vb, Cb, Fb};
   float* dst[4] = {adj.x, adj.v, adj.C, adj.F};
@@ -785,23 +960,34 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
   }
   launch_fill_f32(theta_bar, N, 0.0f, h->stream);
   launch_fill_f64(d.tool_red, (int64_t)T * kMaxTools * 6, 0.0, h->stream);
-  const DState none = {nullptr, nullptr, nullptr, nullptr};
-  const int nseg = (T + K - 1) / K;
-  for (int a = nseg - 1; a >= 0; --a) {
-    const int s0 = a * K;
-    const int n_in = (T - s0) < K ? (T - s0) : K;
-    auto st = [&](int i) -> DState {
-      return i == 0 ? dstate(d.ckpt + (int64_t)a * SF, N) : dstate(d.seg + (int64_t)i * SF, N);
-    };
-    for (int i = 1; i < n_in; ++i)
-      launch_diff_substep(d.g, h->sim, tools_at(h, d.start + s0 + i - 1), N, st(i - 1), d.E, st(i), false, false,
-                          h->b.status, h->stream);
-    for (int i = n_in - 1; i >= 0; --i) {
-      const int j = s0 + i;
-      const ToolSetK ts = tools_at(h, d.start + j);
-      launch_diff_substep(d.g, h->sim, ts, N, st(i), d.E, none, false, true, h->b.status, h->stream);
-      launch_diff_adjoint(d.g, h->sim, ts, N, st(i), d.E, adj, theta_bar, d.tool_red + (int64_t)j * kMaxTools * 6,
-                          h->stream);
+  auto grid_of = [&](int slot_index) -> float4* { return d.grids + (int64_t)slot_index * 2 * nn; };
+  if (d.grids_kept) {
+    for (int j = T - 1; j >= 0; --j) {
+      float4* vel = grid_of(j);
+      launch_diff_adjoint(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, dstate(d.ckpt + (int64_t)j * SF, N),
+                          d.E, adj, theta_bar, d.tool_red + (int64_t)j * kMaxTools * 6, h->stream);
+    }
+  } else {
+    const DState none = {nullptr, nullptr, nullptr, nullptr};
+    const int nseg = (T + K - 1) / K;
+    for (int a = nseg - 1; a >= 0; --a) {
+      const int s0 = a * K;
+      const int n_in = (T - s0) < K ? (T - s0) : K;
+      auto st = [&](int i) -> DState {
+        return i == 0 ? dstate(d.ckpt + (int64_t)a * SF, N) : dstate(d.seg + (int64_t)i * SF, N);
+      };
+      // Recompute the segment from its checkpoint, keeping states and grids.
+      for (int i = 0; i < n_in; ++i) {
+        float4* vel = grid_of(i);
+        launch_diff_substep(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + s0 + i), N, st(i), d.E,
+                            i + 1 < n_in ? st(i + 1) : none, false, h->b.status, h->stream);
+      }
+      for (int i = n_in - 1; i >= 0; --i) {
+        const int j = s0 + i;
+        float4* vel = grid_of(i);
+        launch_diff_adjoint(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, st(i), d.E, adj, theta_bar,
+                            d.tool_red + (int64_t)j * kMaxTools * 6, h->stream);
+      }
     }
   }
   float* outs[4] = {xb0, vb0, Cb0, Fb0};
@@ -890,8 +1076,8 @@ int mpm_get_info(mpm_handle* h, mpm_info* info) {
   info->resort_interval = h->resort_interval;
   info->accum_mode = h->p.accum_mode;
   int nt = 0;
-  for (int i = 0; i < kMaxTools; ++i)
-    if (h->tools[i].active) nt++;
+  for (const HostTool& t : h->tools)
+    if (t.active) nt++;
   info->n_tools = nt;
   return MPM_OK;
 }
@@ -935,18 +1121,21 @@ int mpm_eval_stress(int64_t n, const float* F, const float* E, float nu, float* 
   return e == hipSuccess ? MPM_OK : MPM_EHIP;
 }
 
-int mpm_read_tool_impulses(mpm_handle* h, double* out) {
+int mpm_read_scene_tool_impulses(mpm_handle* h, int32_t scene, double* out) {
   if (!h || !out) return fail(h, MPM_EINVAL, "mpm_read_tool_impulses: NULL");
+  if (scene < 0 || scene >= h->n_scenes) return fail(h, MPM_EINVAL, "mpm_read_tool_impulses: bad scene");
   HIP_OR_RETURN(h, select_device(h));
-  launch_sum_impulses(h->b, h->imp_sum, h->stream);
+  launch_sum_impulses(h->b, h->sim, scene, h->imp_sum, h->stream);
   double sums[kImpulseRows * 3];
   HIP_OR_RETURN(h, hipMemcpyAsync(sums, h->imp_sum, sizeof(sums), hipMemcpyDeviceToHost, h->stream));
   int rc = sync(h);
   if (rc != MPM_OK) return rc;
-  // Slots hold the momentum given to the material; the tool receives the opposite.
+  // Block sums hold the momentum given to the material; the tool receives the opposite.
   for (int i = 0; i < kImpulseRows * 3; ++i) out[i] = -sums[i];
   return MPM_OK;
 }
+
+int mpm_read_tool_impulses(mpm_handle* h, double* out) { return mpm_read_scene_tool_impulses(h, 0, out); }
 
 int mpm_profile(mpm_handle* h, int32_t enable) {
   if (!h) return MPM_EINVAL;

@@ -115,7 +115,22 @@ static void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
 }
 
 // ------------------------------------------------------------------ keys
-__global__ void k_keygen(const float* __restrict__ part, int64_t cap, int64_t N, SimK s,
+// Scene of the particle with original index o: the last scene whose offset is
+// <= o (scene_off holds n_scenes + 1 ascending offsets).
+__device__ __forceinline__ uint32_t scene_of(const uint32_t* __restrict__ scene_off, int n_scenes, uint32_t o) {
+  int lo = 0, hi = n_scenes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (scene_off[mid] <= o)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
+__global__ void k_keygen(const float* __restrict__ part, const uint32_t* __restrict__ id,
+                         const uint32_t* __restrict__ scene_off, int64_t cap, int64_t N, SimK s,
                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t sentinel,
                          Status* st) {
   unsigned dom = 0, nf = 0;
@@ -131,7 +146,9 @@ __global__ void k_keygen(const float* __restrict__ part, int64_t cap, int64_t N,
       cell[a] = ok ? (int)b : 0;
     }
     if (ok && fin) {
-      key = (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb + (cell[0] >> kTileLog2));
+      const uint32_t scene = s.n_scenes > 1 ? scene_of(scene_off, s.n_scenes, id[i]) : 0u;
+      key = scene * s.nb3 +
+            (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb + (cell[0] >> kTileLog2));
     } else if (!fin) {
       nf++;
     } else {
@@ -252,18 +269,19 @@ __global__ void k_flag_occupied(const uint32_t* __restrict__ begin, const uint32
     flags[b] = end[b] > begin[b] ? 1u : 0u;
 }
 
+// Blocks a tile of an occupied block touches, within the same scene.
 __global__ void k_mark_dilated(const uint32_t* __restrict__ begin, const uint32_t* __restrict__ end,
-                               int nb, uint32_t* __restrict__ mark) {
-  const uint32_t n_blocks = (uint32_t)nb * nb * nb;
+                               int nb, uint32_t nb3, uint32_t n_blocks, uint32_t* __restrict__ mark) {
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x) {
     if (!(end[b] > begin[b])) continue;
-    const int bi = b % nb, bj = (b / nb) % nb, bk = b / (nb * nb);
+    const uint32_t scene = b / nb3, lb = b - scene * nb3;
+    const int bi = lb % nb, bj = (lb / nb) % nb, bk = lb / (nb * nb);
     for (int dk = kTileLo; dk <= kTileHi; ++dk)
       for (int dj = kTileLo; dj <= kTileHi; ++dj)
         for (int di = kTileLo; di <= kTileHi; ++di) {
           const int i = bi + di, j = bj + dj, k = bk + dk;
           if (i < 0 || j < 0 || k < 0 || i >= nb || j >= nb || k >= nb) continue;
-          mark[(k * nb + j) * nb + i] = 1u;
+          mark[scene * nb3 + (uint32_t)((k * nb + j) * nb + i)] = 1u;
         }
   }
 }
@@ -297,11 +315,11 @@ static unsigned grid_for(int64_t n, int wg) {
 }
 
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st) {
-  const uint32_t n_blocks = (uint32_t)s.nb * s.nb * s.nb;
+  const uint32_t n_blocks = s.nb3 * (uint32_t)s.n_scenes;
   const uint32_t sentinel = n_blocks;
-  // 1. keys
-  hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.cap, N, s,
-                     b.keys[0], b.vals[0], sentinel, b.status);
+  // 1. keys: scene-major block ids
+  hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur],
+                     b.scene_off, b.cap, N, s, b.keys[0], b.vals[0], sentinel, b.status);
   // 2. stable LSD radix sort, 8 bits per pass
   int src = 0;
   if (N > 0) {
@@ -334,7 +352,7 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStrea
   // 6. active list: occupied blocks dilated by one block
   fill_u32(b.mark, n_blocks, 0u, st);
   hipLaunchKernelGGL(k_mark_dilated, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,
-                     b.blk_end, s.nb, b.mark);
+                     b.blk_end, s.nb, s.nb3, n_blocks, b.mark);
   hipLaunchKernelGGL(k_flag_marked, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.mark, n_blocks,
                      b.flags);
   exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_act, st);
@@ -366,21 +384,31 @@ void launch_count_active_nodes(Buffers& b, int parity, unsigned long long* out, 
                      b.ovf_list[parity], b.status, parity, out);
 }
 
-__global__ void k_sum_impulses(const float* __restrict__ slots, double* __restrict__ out) {
-  // one thread per (row, component); slots are few (kGridSlots)
-  const int c = threadIdx.x;
-  if (c >= kImpulseRows * 3) return;
+// Impulse totals of one scene: the per-block sums of its nb^3 blocks. Thread
+// (r, c) of kSumRows x 27 adds component c of blocks r, r + kSumRows, ...
+constexpr int kSumRows = 8;
+__global__ void k_sum_impulses(const float* __restrict__ blocks, uint32_t first, uint32_t count,
+                               double* __restrict__ out) {
+  __shared__ double part[kSumRows][kImpulseRows * 3];
+  const int c = threadIdx.x % (kImpulseRows * 3), r = threadIdx.x / (kImpulseRows * 3);
   double s = 0.0;
-  for (int w = 0; w < kGridSlots; ++w) s += (double)slots[(size_t)w * (kImpulseRows * 3) + c];
-  out[c] = s;
+  for (uint32_t i = r; i < count; i += kSumRows) s += (double)blocks[(size_t)(first + i) * (kImpulseRows * 3) + c];
+  part[r][c] = s;
+  __syncthreads();
+  if (r == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kSumRows; ++k) t += part[k][c];
+    out[c] = t;
+  }
 }
 
-void launch_clear_impulses(Buffers& b, hipStream_t st) {
-  fill_u32((uint32_t*)b.imp_slots, (int64_t)kGridSlots * kImpulseRows * 3, 0u, st);
+void launch_clear_impulses(Buffers& b, const SimK& s, hipStream_t st) {
+  fill_u32((uint32_t*)b.imp_blocks, (int64_t)s.nb3 * s.n_scenes * kImpulseRows * 3, 0u, st);
 }
 
-void launch_sum_impulses(Buffers& b, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_impulses, dim3(1), dim3(64), 0, st, b.imp_slots, out);
+void launch_sum_impulses(Buffers& b, const SimK& s, int scene, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_impulses, dim3(1), dim3(kSumRows * kImpulseRows * 3), 0, st, b.imp_blocks,
+                     (uint32_t)scene * s.nb3, s.nb3, out);
 }
 
 // ------------------------------------------------------------------ marshalling

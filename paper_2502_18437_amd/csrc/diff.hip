@@ -61,6 +61,15 @@ __device__ __forceinline__ bool dense_stencil(const SimK& s, const float* x, int
   return ok;
 }
 
+// A particle takes part in a substep iff its state is finite and its stencil
+// lies in the grid (otherwise the substep leaves it unchanged); 1 = non-finite,
+// 2 = outside, 0 = live.
+__device__ __forceinline__ int particle_state(const SimK& s, const float* x, const float* v, const float* C,
+                                              const float* F, float e, int* base, float* f) {
+  if (!(finite_n(x, 3) && finite_n(v, 3) && finite_n(C, 9) && finite_n(F, 9) && finite_n(&e, 1))) return 1;
+  return dense_stencil(s, x, base, f) ? 0 : 2;
+}
+
 __device__ __forceinline__ int dense_index(const SimK& s, int i, int j, int k) {
   return (i * s.n + j) * s.n + k;
 }
@@ -70,6 +79,14 @@ __device__ __forceinline__ void load_state(DState S, int64_t p, float* x, float*
   for (int a = 0; a < 3; ++a) x[a] = S.x[3 * p + a], v[a] = S.v[3 * p + a];
 #pragma unroll
   for (int i = 0; i < 9; ++i) C[i] = S.C[9 * p + i], F[i] = S.F[9 * p + i];
+}
+
+// Particle of global thread gi when the particles are dealt to the 64 lanes
+// of each wave S apart (S = ceil(N / 64)): lane l of wave w takes l S + w.
+// Neighbouring particles scatter to the same nodes; spreading them over the
+// lanes keeps one wave's atomics on distinct addresses.
+__device__ __forceinline__ int64_t spread(int64_t gi, int64_t S) {
+  return (gi & 63) * S + (gi >> 6);
 }
 
 __device__ __forceinline__ void flush_status(Status* st, unsigned inv, unsigned dom, unsigned nf) {
@@ -83,23 +100,25 @@ __global__ __launch_bounds__(kDWG) void k_dp2g(SimK s, int64_t N, DState in, con
                                                float* gm, float* gp0, float* gp1, float* gp2,
                                                uint8_t* __restrict__ skip, Status* st, int count) {
   unsigned c_inv = 0, c_dom = 0, c_nf = 0;
-  for (int64_t p = blockIdx.x * (int64_t)kDWG + threadIdx.x; p < N; p += (int64_t)gridDim.x * kDWG) {
+  const int64_t S = (N + 63) / 64;
+  for (int64_t gi = blockIdx.x * (int64_t)kDWG + threadIdx.x; gi < 64 * S; gi += (int64_t)gridDim.x * kDWG) {
+    const int64_t p = spread(gi, S);
+    if (p >= N) continue;
     float x[3], v[3], C[9], F[9];
     load_state(in, p, x, v, C, F);
     const float e = E[p];
     int base[3];
     float f[3];
-    if (!(finite_n(x, 3) && finite_n(v, 3) && finite_n(C, 9) && finite_n(F, 9) && finite_n(&e, 1))) {
+    const int ps = particle_state(s, x, v, C, F, e, base, f);
+    skip[p] = ps != 0;
+    if (ps == 1) {
       c_nf++;
-      skip[p] = 1;
       continue;
     }
-    if (!dense_stencil(s, x, base, f)) {
+    if (ps == 2) {
       c_dom++;
-      skip[p] = 1;
       continue;
     }
-    skip[p] = 0;
     float w[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]);
@@ -477,20 +496,23 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 // ---------------------------------------------------------------- adjoint kernels
 // G2P reverse: scatter of the grid-velocity cotangent, x and F cotangents.
-__global__ __launch_bounds__(kDWG) void k_bg2p(SimK s, int64_t N, DState in, const float4* __restrict__ vel,
-                                               const uint8_t* __restrict__ skip, DState adj, float* gvb0,
+__global__ __launch_bounds__(kDWG) void k_bg2p(SimK s, int64_t N, DState in, const float* __restrict__ E,
+                                               const float4* __restrict__ vel, DState adj, float* gvb0,
                                                float* gvb1, float* gvb2) {
   const float Minv = 4.0f * s.inv_dx * s.inv_dx;
-  for (int64_t p = blockIdx.x * (int64_t)kDWG + threadIdx.x; p < N; p += (int64_t)gridDim.x * kDWG) {
-    if (skip[p]) continue;  // unchanged by the substep: cotangent passes through
+  const int64_t S = (N + 63) / 64;
+  for (int64_t gi = blockIdx.x * (int64_t)kDWG + threadIdx.x; gi < 64 * S; gi += (int64_t)gridDim.x * kDWG) {
+    const int64_t p = spread(gi, S);
+    if (p >= N) continue;
     float x[3], F[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = in.x[3 * p + a];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) F[i] = in.F[9 * p + i];
     int base[3];
     float f[3];
-    dense_stencil(s, x, base, f);
+    {
+      float v[3], C[9];
+      load_state(in, p, x, v, C, F);
+      // a skipped particle is unchanged by the substep: its cotangent passes through
+      if (particle_state(s, x, v, C, F, E[p], base, f) != 0) continue;
+    }
     float w[3][3], dw[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]), bspline_dw(f[a], dw[a]);
@@ -633,16 +655,15 @@ __global__ __launch_bounds__(kDWG) void k_bgrid(SimK s, ToolSetK ts, const float
 // adjoint. Writes the v and C cotangents, adds to those of x and F and to
 // d/d log E.
 __global__ __launch_bounds__(kDWG) void k_bp2g(SimK s, int64_t N, DState in, const float* __restrict__ E,
-                                               const float4* __restrict__ pb, const uint8_t* __restrict__ skip,
-                                               DState adj, float* __restrict__ theta_bar) {
+                                               const float4* __restrict__ pb, DState adj,
+                                               float* __restrict__ theta_bar) {
   for (int64_t p = blockIdx.x * (int64_t)kDWG + threadIdx.x; p < N; p += (int64_t)gridDim.x * kDWG) {
-    if (skip[p]) continue;
     float x[3], v[3], C[9], F[9];
     load_state(in, p, x, v, C, F);
     const float e = E[p];
     int base[3];
     float f[3];
-    dense_stencil(s, x, base, f);
+    if (particle_state(s, x, v, C, F, e, base, f) != 0) continue;
     float w[3][3], dw[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]), bspline_dw(f[a], dw[a]);
@@ -732,27 +753,29 @@ __global__ void k_unpermute_E(const float* __restrict__ part, const uint32_t* __
 
 }  // namespace
 
-void launch_diff_substep(const DiffGrid& g, const SimK& s, const ToolSetK& tools, int64_t N, DState in,
-                         const float* E, DState out, bool count, bool keep_hat, Status* st, hipStream_t stream) {
+void launch_diff_substep(const DiffGrid& g, float4* vel, float4* hat, const SimK& s, const ToolSetK& tools,
+                         int64_t N, DState in, const float* E, DState out, bool count, Status* st,
+                         hipStream_t stream) {
   const int64_t nn = (int64_t)s.n * s.n * s.n;
-  hipLaunchKernelGGL(k_dp2g, dim3(blocks_for(N)), dim3(kDWG), 0, stream, s, N, in, E, g.m, g.p[0], g.p[1], g.p[2],
-                     g.skip, st, count ? 1 : 0);
+  hipLaunchKernelGGL(k_dp2g, dim3(blocks_for(64 * ((N + 63) / 64))), dim3(kDWG), 0, stream, s, N, in, E, g.m,
+                     g.p[0], g.p[1], g.p[2], g.skip, st, count ? 1 : 0);
   hipLaunchKernelGGL(k_dgrid, dim3(blocks_for(nn)), dim3(kDWG), 0, stream, s, tools, g.m, g.p[0], g.p[1], g.p[2],
-                     g.vel, keep_hat ? g.hat : nullptr);
+                     vel, hat);
   if (out.x)
-    hipLaunchKernelGGL(k_dg2p, dim3(blocks_for(N)), dim3(kDWG), 0, stream, s, N, in, (const float4*)g.vel,
+    hipLaunchKernelGGL(k_dg2p, dim3(blocks_for(N)), dim3(kDWG), 0, stream, s, N, in, (const float4*)vel,
                        (const uint8_t*)g.skip, out);
 }
 
-void launch_diff_adjoint(const DiffGrid& g, const SimK& s, const ToolSetK& tools, int64_t N, DState in,
-                         const float* E, DState adj, float* theta_bar, double* tool_red, hipStream_t stream) {
+void launch_diff_adjoint(const DiffGrid& g, const float4* vel, const float4* hat, const SimK& s,
+                         const ToolSetK& tools, int64_t N, DState in, const float* E, DState adj, float* theta_bar,
+                         double* tool_red, hipStream_t stream) {
   const int64_t nn = (int64_t)s.n * s.n * s.n;
-  hipLaunchKernelGGL(k_bg2p, dim3(blocks_for(N)), dim3(kDWG), 0, stream, s, N, in, (const float4*)g.vel,
-                     (const uint8_t*)g.skip, adj, g.vb[0], g.vb[1], g.vb[2]);
-  hipLaunchKernelGGL(k_bgrid, dim3(blocks_for(nn)), dim3(kDWG), 0, stream, s, tools, (const float4*)g.hat, g.vb[0],
+  hipLaunchKernelGGL(k_bg2p, dim3(blocks_for(64 * ((N + 63) / 64))), dim3(kDWG), 0, stream, s, N, in, E, vel, adj,
+                     g.vb[0], g.vb[1], g.vb[2]);
+  hipLaunchKernelGGL(k_bgrid, dim3(blocks_for(nn)), dim3(kDWG), 0, stream, s, tools, hat, g.vb[0],
                      g.vb[1], g.vb[2], g.pb, tool_red);
-  hipLaunchKernelGGL(k_bp2g, dim3(blocks_for(N)), dim3(kDWG), 0, stream, s, N, in, E, (const float4*)g.pb,
-                     (const uint8_t*)g.skip, adj, theta_bar);
+  hipLaunchKernelGGL(k_bp2g, dim3(blocks_for(N)), dim3(kDWG), 0, stream, s, N, in, E, (const float4*)g.pb, adj,
+                     theta_bar);
 }
 
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {

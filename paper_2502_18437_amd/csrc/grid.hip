@@ -15,6 +15,33 @@
 namespace mpm {
 
 constexpr int kGridWG = 256;
+static_assert(kBlockNodes % kGridWG == 0, "every lane of the grid kernel must visit the same number of nodes");
+
+// Tool `d` at its pose of global substep k: the centre follows the constant
+// velocity from set_at, or the prefix sums of the velocity table and then the
+// constant velocity (FP64, each operation rounded as written).
+__device__ __forceinline__ ToolK tool_at(const ToolDesc& d, long long k, double dt) {
+  ToolK t = d.k;
+  const long long rel = k - d.set_at;
+  if (d.rows == 0) {
+    const double el = __dmul_rn((double)rel, dt);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      t.c[a] = (float)__dadd_rn(d.c0[a], __dmul_rn(el, d.lv[a]));
+      t.lv[a] = (float)d.lv[a];
+    }
+  } else {
+    const long long m = rel < d.rows ? rel : d.rows;
+    const double tail = __dmul_rn((double)(rel - m), dt);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double c = __dadd_rn(__dadd_rn(d.c0[a], __dmul_rn(dt, d.vpre[3 * m + a])), __dmul_rn(tail, d.lv[a]));
+      t.c[a] = (float)c;
+      t.lv[a] = (float)(rel < d.rows ? d.vtab[3 * rel + a] : d.lv[a]);
+    }
+  }
+  return t;
+}
 
 __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void* __restrict__ acc_p0,
                                                   void* __restrict__ acc_p1, void* __restrict__ acc_p2,
@@ -22,28 +49,34 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
                                                   const uint32_t* __restrict__ act_list,
                                                   const uint32_t* __restrict__ ovf_list,
                                                   uint32_t* mark, uint32_t* __restrict__ node_cnt,
-                                                  float* __restrict__ imp_slots, Status* st, int parity,
-                                                  SimK s, ToolSetK tools) {
+                                                  float* __restrict__ imp_blocks, const ToolDesc* __restrict__ tools,
+                                                  Status* st, int parity, long long substep, SimK s) {
   // Momentum given to the material by each tool and by the walls on the nodes
-  // this workgroup visits (two-way coupling, Sec. IV-A), summed per
-  // workgroup into its own slot at the end: the walls' in registers, the
-  // tools' (few nodes touch a tool) with LDS atomics.
-  __shared__ float imp_tools[kMaxTools * 3];
-  float imp_w[3] = {0.0f, 0.0f, 0.0f};
-  if (threadIdx.x < kMaxTools * 3) imp_tools[threadIdx.x] = 0.0f;
+  // of one block (two-way coupling, Sec. IV-A), added to the block's own
+  // sums. Each wave reduces its contributions with shuffles (a tool's only
+  // when one of its lanes touched the tool) and the waves' partial sums are
+  // added in a fixed order, so the sums do not depend on timing.
+  __shared__ float red_t[kGridWG / 64][kMaxTools * 3];
+  __shared__ float red[kGridWG / 64][3];
+  __shared__ unsigned blk_cnt;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned n_act = st->n_act;
   const unsigned total = n_act + st->ovf_count[parity];
-  __shared__ unsigned blk_cnt;
   const int lo = s.band, hi = s.n - 1 - s.band;
   for (unsigned li = blockIdx.x; li < total; li += gridDim.x) {
     const bool overflow = li >= n_act;
     const unsigned b = overflow ? ovf_list[li - n_act] : act_list[li];
-    const int bi = (int)(b % (unsigned)s.nb);
-    const int bj = (int)((b / (unsigned)s.nb) % (unsigned)s.nb);
-    const int bk = (int)(b / ((unsigned)s.nb * (unsigned)s.nb));
+    const unsigned scene = b / s.nb3;
+    const unsigned lb = b - scene * s.nb3;
+    const int bi = (int)(lb % (unsigned)s.nb);
+    const int bj = (int)((lb / (unsigned)s.nb) % (unsigned)s.nb);
+    const int bk = (int)(lb / ((unsigned)s.nb * (unsigned)s.nb));
+    const ToolDesc* td = tools + (size_t)scene * kMaxTools;
     if (threadIdx.x == 0) blk_cnt = 0u;
+    if (lane < kMaxTools * 3) red_t[wave][lane] = 0.0f;
     __syncthreads();
     unsigned cnt = 0;
+    float imp_w[3] = {0.0f, 0.0f, 0.0f};
     for (int l = threadIdx.x; l < kBlockNodes; l += kGridWG) {
       const size_t g = ((size_t)b << (3 * kTileLog2)) + (size_t)l;
       // Mass and momentum of the node (P2G result), then the reset.
@@ -68,31 +101,47 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
         ((float*)acc_p2)[g] = 0.0f;
       }
       float v[3] = {0.0f, 0.0f, 0.0f};
-      if (m > 0.0f) {
+      const bool live = m > 0.0f;
+      const int i = bi * kTile + (l & (kTile - 1));
+      const int j = bj * kTile + ((l >> kTileLog2) & (kTile - 1));
+      const int k = bk * kTile + (l >> (2 * kTileLog2));
+      if (live) {
         cnt++;
         const float im = 1.0f / m;
         v[0] = p0 * im + s.dt * s.g[0];
         v[1] = p1 * im + s.dt * s.g[1];
         v[2] = p2 * im + s.dt * s.g[2];
-        const int i = bi * kTile + (l & (kTile - 1));
-        const int j = bj * kTile + ((l >> kTileLog2) & (kTile - 1));
-        const int k = bk * kTile + (l >> (2 * kTileLog2));
-        const float xI[3] = {(float)i * s.dx, (float)j * s.dx, (float)k * s.dx};
+      }
+      // The tool loop runs on every lane (kBlockNodes is a multiple of the
+      // workgroup size), so the wave reductions see full waves.
+      const float xI[3] = {(float)i * s.dx, (float)j * s.dx, (float)k * s.dx};
 #pragma unroll 1
-        for (int q = 0; q < tools.n; ++q) {
-          if (tools.t[q].type == TOOL_NONE) continue;
+      for (int q = 0; q < kMaxTools; ++q) {
+        if (td[q].k.type == TOOL_NONE) continue;
+        float dm[3] = {0.0f, 0.0f, 0.0f};
+        if (live) {
+          const ToolK t = tool_at(td[q], substep, (double)s.dt);
           const float vb[3] = {v[0], v[1], v[2]};
-          if (tool_contact(tools.t[q], xI, v)) {
+          if (tool_contact(t, xI, v)) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) atomicAdd(&imp_tools[3 * q + a], m * (v[a] - vb[a]));
+            for (int a = 0; a < 3; ++a) dm[a] = m * (v[a] - vb[a]);
           }
         }
-        if (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi) {
+        if (__ballot(dm[0] != 0.0f || dm[1] != 0.0f || dm[2] != 0.0f) != 0) {
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
-            imp_w[a] -= m * v[a];
-            v[a] = 0.0f;
+            float x = dm[a];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+            if (lane == 0) red_t[wave][3 * q + a] += x;
           }
+        }
+      }
+      if (live && (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi)) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          imp_w[a] -= m * v[a];
+          v[a] = 0.0f;
         }
       }
       vel[g] = make_float4(v[0], v[1], v[2], 0.0f);
@@ -100,46 +149,44 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
     // Nodes with mass in this block (plain store, summed on demand by the host
     // call that reports it; a shared counter would serialise every workgroup).
     if (cnt) atomicAdd(&blk_cnt, cnt);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float x = imp_w[a];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (lane == 0) red[wave][a] = x;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       node_cnt[b] = blk_cnt;
       if (overflow) mark[b] = 0u;
     }
+    // The block's impulse sums (each block is visited once per substep).
+    if (threadIdx.x < kImpulseRows * 3) {
+      float x;
+      if (threadIdx.x < kMaxTools * 3) {
+        x = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kGridWG / 64; ++w) x += red_t[w][threadIdx.x];
+      } else {
+        x = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kGridWG / 64; ++w) x += red[w][threadIdx.x - kMaxTools * 3];
+      }
+      if (x != 0.0f) imp_blocks[(size_t)b * (kImpulseRows * 3) + threadIdx.x] += x;
+    }
+    __syncthreads();
   }
   // Clear the other parity's overflow list for the next substep.
   if (blockIdx.x == 0 && threadIdx.x == 0) st->ovf_count[parity ^ 1] = 0u;
-  // Workgroup sum of the impulses into this workgroup's slot (no other
-  // workgroup writes it, so a plain read-modify-write accumulates substeps).
-  __shared__ float red[kGridWG / 64][3];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float x = imp_w[a];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0) red[wave][a] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < kImpulseRows * 3) {
-    float x;
-    if (threadIdx.x < kMaxTools * 3) {
-      x = imp_tools[threadIdx.x];
-    } else {
-      x = 0.0f;
-#pragma unroll
-      for (int w = 0; w < kGridWG / 64; ++w) x += red[w][threadIdx.x - kMaxTools * 3];
-    }
-    imp_slots[(size_t)blockIdx.x * (kImpulseRows * 3) + threadIdx.x] += x;
-  }
 }
 
-void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
-                 hipStream_t st) {
+void launch_grid(Buffers& b, const SimK& s, long long substep, int parity, int max_act, hipStream_t st) {
   int wgs = max_act < kGridSlots ? max_act : kGridSlots;
   if (wgs < 1) wgs = 1;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
-                     b.acc_p[2], b.vel, b.act_list,
-                     b.ovf_list[parity], b.mark, b.node_cnt, b.imp_slots, b.status, parity, s, tools);
+                     b.acc_p[2], b.vel, b.act_list, b.ovf_list[parity], b.mark, b.node_cnt, b.imp_blocks,
+                     (const ToolDesc*)b.tools, b.status, parity, substep, s);
 }
 
 }  // namespace mpm

@@ -23,7 +23,7 @@ constexpr int kTileHi = (kTile + 1 + kSlack) / kTile;
 constexpr int kBlockNodes = kTile * kTile * kTile;  // 512
 constexpr int kMaxTools = 8;
 constexpr int kImpulseRows = kMaxTools + 1;  // tools, then the walls
-constexpr int kGridSlots = 8192;             // largest grid-update launch (impulse slots)
+constexpr int kGridSlots = 8192;             // largest grid-update launch
 constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA
 
 // Field offsets in the particle SoA (each field is `cap` floats).
@@ -48,6 +48,19 @@ struct ToolSetK {
   ToolK t[kMaxTools];
 };
 
+// One tool of one scene as the device keeps it: the constant part of ToolK
+// plus what its pose at any substep is computed from (FP64 kinematics, the
+// same formula as the host's).
+struct ToolDesc {
+  ToolK k;               // type, R, size, av, mu, drag, margin, reach2 (c and lv are per substep)
+  double c0[3];          // centre at set_at
+  double lv[3];          // constant linear velocity
+  long long set_at;      // substep counter when set (or re-anchored)
+  long long rows;        // velocity-table rows (0: none)
+  const double* vtab;    // rows x 3 (device)
+  const double* vpre;    // (rows + 1) x 3 prefix sums (device)
+};
+
 // Scene constants for the transfer kernels.
 //
 // P2G accumulates in integers (LDS float atomics are slow on gfx950, and
@@ -58,8 +71,11 @@ struct ToolSetK {
 // of a value to int64 is the round-to-nearest of an FP64 sum with 1.5 * 2^52,
 // exact for magnitudes below 2^51 units.
 struct SimK {
-  int n;           // nodes per axis
+  int n;           // nodes per axis (of every scene)
   int nb;          // blocks per axis
+  int n_scenes;    // scenes of the batch; scene s owns blocks [s nb^3, (s+1) nb^3) and nodes [s n^3, (s+1) n^3)
+  unsigned nb3;    // blocks per scene
+  int n3;          // nodes per scene
   float dx, inv_dx, dt;
   float mass;      // per particle
   float p2g_stress;  // dt * vol0 * 4 / dx^2
@@ -104,7 +120,9 @@ struct Buffers {
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
   uint32_t* node_cnt = nullptr;             // per block: nodes with mass, last grid update
-  float* imp_slots = nullptr;               // per grid workgroup: impulse sums (kImpulseRows x 3)
+  float* imp_blocks = nullptr;              // per grid block: impulse sums (kImpulseRows x 3)
+  uint32_t* scene_off = nullptr;            // n_scenes + 1 particle offsets (original order)
+  ToolDesc* tools = nullptr;                // n_scenes x kMaxTools
   uint32_t* ovf_list[2] = {nullptr, nullptr};
   void* acc_m = nullptr;                    // grid accumulator, mass channel (float or u32)
   void* acc_p[3] = {nullptr, nullptr, nullptr};  // momentum channels (float or int64)
@@ -122,17 +140,18 @@ void launch_p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, 
 void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st);
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
 
-// Grid update over active blocks and this parity's overflow blocks.
-void launch_grid(Buffers& b, const SimK& s, const ToolSetK& tools, int parity, int max_act,
-                 hipStream_t st);
+// Grid update over active blocks and this parity's overflow blocks, with
+// each scene's tools at their pose of global substep `substep`.
+void launch_grid(Buffers& b, const SimK& s, long long substep, int parity, int max_act, hipStream_t st);
 
 // Nodes with mass in the last grid update (sum of node_cnt over the active
 // and overflow blocks of `parity`), written to *out (device memory).
 void launch_count_active_nodes(Buffers& b, int parity, unsigned long long* out, hipStream_t st);
 
-// Clear the impulse slots; sum them into out[kImpulseRows * 3] (device).
-void launch_clear_impulses(Buffers& b, hipStream_t st);
-void launch_sum_impulses(Buffers& b, double* out, hipStream_t st);
+// Clear the per-block impulse sums; sum those of one scene into
+// out[kImpulseRows * 3] (device).
+void launch_clear_impulses(Buffers& b, const SimK& s, hipStream_t st);
+void launch_sum_impulses(Buffers& b, const SimK& s, int scene, double* out, hipStream_t st);
 
 // Stress evaluation (diagnostic entry point).
 void launch_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,
@@ -167,26 +186,28 @@ inline DState dstate(float* base, int64_t N) {
 struct DiffGrid {
   float* m = nullptr;                       // P2G mass accumulator
   float* p[3] = {nullptr, nullptr, nullptr};  // P2G momentum accumulators
-  float4* vel = nullptr;                    // velocity after the grid update (w unused)
-  float4* hat = nullptr;                    // velocity before contact (xyz) and mass (w)
+  float4* vel = nullptr;                    // velocity after the grid update when no grid is kept (w unused)
   float* vb[3] = {nullptr, nullptr, nullptr};  // cotangent of vel (accumulated by G2P adjoint)
   float4* pb = nullptr;                     // cotangent of momentum (xyz) and of mass (w)
   uint8_t* skip = nullptr;                  // per particle: left unchanged this substep
 };
 
 // Forward substep on the dense grid: P2G from `in`, grid update (tools,
-// walls), G2P into `out`. Particles with a non-finite state or a stencil
-// outside the grid are copied unchanged (and counted when `count`).
-// With `keep_hat`, the pre-contact velocity and mass are kept in g.hat.
-// With out.x == nullptr only P2G and the grid update run.
-void launch_diff_substep(const DiffGrid& g, const SimK& s, const ToolSetK& tools, int64_t N, DState in,
-                         const float* E, DState out, bool count, bool keep_hat, Status* st, hipStream_t stream);
-// Reverse of one substep whose forward grid (g.vel, g.hat) has just been
-// recomputed from `in`: on entry `adj` is the cotangent of the state after the
-// substep, on exit that of `in`. Adds d/d log E to theta_bar and the tools'
-// centre and linear-velocity cotangents to tool_red[kMaxTools][6] (FP64).
-void launch_diff_adjoint(const DiffGrid& g, const SimK& s, const ToolSetK& tools, int64_t N, DState in,
-                         const float* E, DState adj, float* theta_bar, double* tool_red, hipStream_t stream);
+// walls) into `vel` (and, if `hat` is not null, the pre-contact velocity and
+// the mass into `hat`), G2P into `out` (skipped when out.x is null).
+// Particles with a non-finite state or a stencil outside the grid are copied
+// unchanged (and counted when `count`); g.skip records them.
+void launch_diff_substep(const DiffGrid& g, float4* vel, float4* hat, const SimK& s, const ToolSetK& tools,
+                         int64_t N, DState in, const float* E, DState out, bool count, Status* st,
+                         hipStream_t stream);
+// Reverse of one substep from the state `in` it started from and its grid
+// (`vel`, `hat`) as its forward pass left them: on entry `adj` is
+// the cotangent of the state after the substep, on exit that of `in`. Adds
+// d/d log E to theta_bar and the tools' linear-velocity and centre cotangents
+// to tool_red[kMaxTools][6] (FP64).
+void launch_diff_adjoint(const DiffGrid& g, const float4* vel, const float4* hat, const SimK& s,
+                         const ToolSetK& tools, int64_t N, DState in, const float* E, DState adj, float* theta_bar,
+                         double* tool_red, hipStream_t stream);
 // Fill helpers.
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);

@@ -161,9 +161,10 @@ __device__ __forceinline__ void acc_add(const SimK& s, typename AccT<FIXED>::M* 
 // block its stencil touches that the current binning did not activate.
 template <bool FIXED>
 __device__ __forceinline__ void p2g_global(const SimK& s, const P2GIn& P, ACC_PARAMS, uint32_t* mark,
-                                        uint32_t* ovf, Status* st, int parity) {
+                                        uint32_t* ovf, Status* st, int parity, int scene) {
+  const int node_base = scene * s.n3;
   p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
-    const int g = grid_index(P.base[0] + ox, P.base[1] + oy, P.base[2] + oz, s.nb);
+    const int g = node_base + grid_index(P.base[0] + ox, P.base[1] + oy, P.base[2] + oz, s.nb);
     acc_add<FIXED>(s, ACC_ARGS, g, wq, p0, p1, p2);
   });
   const int b0[3] = {P.base[0] >> kTileLog2, P.base[1] >> kTileLog2, P.base[2] >> kTileLog2};
@@ -171,7 +172,7 @@ __device__ __forceinline__ void p2g_global(const SimK& s, const P2GIn& P, ACC_PA
   for (int bz = b0[2]; bz <= b1[2]; ++bz)
     for (int by = b0[1]; by <= b1[1]; ++by)
       for (int bx = b0[0]; bx <= b1[0]; ++bx) {
-        const unsigned b = (unsigned)((bz * s.nb + by) * s.nb + bx);
+        const unsigned b = (unsigned)scene * s.nb3 + (unsigned)((bz * s.nb + by) * s.nb + bx);
         if (__hip_atomic_load(&mark[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) continue;
         if (atomicCAS(&mark[b], 0u, 2u) == 0u) {
           const unsigned slot = atomicAdd(&st->ovf_count[parity], 1u);
@@ -221,9 +222,10 @@ __device__ __forceinline__ void g2p_sums(const float (*w)[3], Node&& node, float
 
 // G2P of one particle from the global velocity grid.
 __device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const float (*w)[3],
-                                        const float4* vel, float* S, float* T) {
+                                        const float4* vel, float* S, float* T, int scene) {
+  const int node_base = scene * s.n3;
   g2p_sums(w, [&](int ox, int oy, int oz) {
-    return vel[grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
+    return vel[node_base + grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
   }, S, T);
 }
 
@@ -295,7 +297,7 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
                        ((unsigned)l2 <= (unsigned)(kSpan - 3));
   if (!in_tile) {
     cnt.fb++;
-    p2g_global<FIXED>(s, P, ACC_ARGS, mark, ovf, st, parity);
+    p2g_global<FIXED>(s, P, ACC_ARGS, mark, ovf, st, parity, to[3]);
     return;
   }
   const int l = lds_index(l0, l1, l2);
@@ -329,7 +331,7 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
     g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
   } else {
     cnt.fb++;
-    g2p_global(s, base, w, vel, S, T);
+    g2p_global(s, base, w, vel, S, T, to[3]);
   }
   const float k = 4.0f * s.inv_dx;
 #pragma unroll
@@ -342,13 +344,18 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
 }
 
 // ------------------------------------------------------------------ tile helpers
+// Tile origin of block b (node coordinates within its scene) in to[0..2] and
+// the block's scene in to[3].
 __device__ __forceinline__ void block_origin(const SimK& s, unsigned b, int* to) {
-  const int bi = (int)(b % (unsigned)s.nb);
-  const int bj = (int)((b / (unsigned)s.nb) % (unsigned)s.nb);
-  const int bk = (int)(b / ((unsigned)s.nb * (unsigned)s.nb));
+  const unsigned scene = b / s.nb3;
+  const unsigned lb = b - scene * s.nb3;
+  const int bi = (int)(lb % (unsigned)s.nb);
+  const int bj = (int)((lb / (unsigned)s.nb) % (unsigned)s.nb);
+  const int bk = (int)(lb / ((unsigned)s.nb * (unsigned)s.nb));
   to[0] = bi * kTile - kSlack;
   to[1] = bj * kTile - kSlack;
   to[2] = bk * kTile - kSlack;
+  to[3] = (int)scene;
 }
 
 __device__ __forceinline__ void tile_clear(Lds& L) {
@@ -367,7 +374,7 @@ __device__ __forceinline__ void tile_stage_velocity(const SimK& s, const int* to
     const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
     float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if ((unsigned)gx < (unsigned)s.n && (unsigned)gy < (unsigned)s.n && (unsigned)gz < (unsigned)s.n)
-      val = vel[grid_index(gx, gy, gz, s.nb)];
+      val = vel[to[3] * s.n3 + grid_index(gx, gy, gz, s.nb)];
     L.v[i] = val;
   }
 }
@@ -384,7 +391,7 @@ __device__ __forceinline__ void tile_flush(const SimK& s, const int* to, const L
     // Only in-grid nodes can receive contributions (stencils are checked
     // against the grid); the test keeps the index in range regardless.
     if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
-    acc_add<FIXED>(s, ACC_ARGS, grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2);
+    acc_add<FIXED>(s, ACC_ARGS, to[3] * s.n3 + grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2);
   }
 }
 
@@ -407,7 +414,7 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
   xcd_walk(st->n_occ, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const unsigned b = occ_list[pos];
-    int to[3];
+    int to[4];
     block_origin(s, b, to);
     tile_clear(L);
     __syncthreads();
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
   xcd_walk(st->n_occ, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const unsigned b = occ_list[pos];
-    int to[3];
+    int to[4];
     block_origin(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     tile_clear(L);
@@ -498,7 +505,7 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
   xcd_walk(st->n_occ, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const unsigned b = occ_list[pos];
-    int to[3];
+    int to[4];
     block_origin(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     __syncthreads();

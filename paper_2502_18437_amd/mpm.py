@@ -34,7 +34,8 @@ STATUS_NAMES = {0: "MPM_OK", -1: "MPM_EINVAL", -2: "MPM_ENOMEM", -3: "MPM_EHIP",
 EXPORTED = ("mpm_create", "mpm_destroy", "mpm_set_particles", "mpm_set_tool_sdf", "mpm_step",
             "mpm_read_state", "mpm_get_info", "mpm_last_error", "mpm_eval_stress", "mpm_profile",
             "mpm_profile_read", "mpm_read_tool_impulses", "mpm_set_tool_velocity_table", "mpm_rollout_forward",
-            "mpm_rollout_backward")
+            "mpm_rollout_backward", "mpm_create_batch", "mpm_set_batch_particles", "mpm_set_scene_tool",
+            "mpm_set_scene_tool_velocity_table", "mpm_read_scene_tool_impulses")
 
 
 class mpm_params(ctypes.Structure):
@@ -86,6 +87,13 @@ _lib.mpm_profile_read.argtypes = [_h, ctypes.POINTER(mpm_kernel_times)]
 _lib.mpm_read_tool_impulses.argtypes = [_h, ctypes.POINTER(ctypes.c_double)]
 _lib.mpm_set_tool_velocity_table.argtypes = [_h, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
 _lib.mpm_rollout_forward.argtypes = [_h, ctypes.c_int32, ctypes.c_int32, _vp]
+_lib.mpm_create_batch.argtypes = [ctypes.POINTER(mpm_params), ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(_h)]
+_lib.mpm_set_batch_particles.argtypes = [_h, ctypes.POINTER(ctypes.c_int64), _vp, _vp, _vp, _vp, _vp, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_int32]
+_lib.mpm_set_scene_tool.argtypes = [_h, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mpm_tool)]
+_lib.mpm_set_scene_tool_velocity_table.argtypes = [_h, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                                   ctypes.POINTER(ctypes.c_double)]
+_lib.mpm_read_scene_tool_impulses.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
 _lib.mpm_rollout_backward.argtypes = [_h, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp,
                                       _vp]
 
@@ -105,6 +113,11 @@ mpm_read_tool_impulses = _lib.mpm_read_tool_impulses
 mpm_set_tool_velocity_table = _lib.mpm_set_tool_velocity_table
 mpm_rollout_forward = _lib.mpm_rollout_forward
 mpm_rollout_backward = _lib.mpm_rollout_backward
+mpm_create_batch = _lib.mpm_create_batch
+mpm_set_batch_particles = _lib.mpm_set_batch_particles
+mpm_set_scene_tool = _lib.mpm_set_scene_tool
+mpm_set_scene_tool_velocity_table = _lib.mpm_set_scene_tool_velocity_table
+mpm_read_scene_tool_impulses = _lib.mpm_read_scene_tool_impulses
 
 
 class MPMError(RuntimeError):
@@ -163,12 +176,16 @@ class Simulation:
     """One scene (mpm_handle)."""
 
     def __init__(self, n_grid, dt, gravity=(0.0, -9.8, 0.0), wall_band=3, nu=0.3, E_default=5e3,
-                 accum_mode=MPM_ACCUM_F32, tile=0, resort_interval=0, max_particles=0, stream=None):
+                 accum_mode=MPM_ACCUM_F32, tile=0, resort_interval=0, max_particles=0, stream=None, n_scenes=1):
         p = mpm_params(int(n_grid), float(dt), (ctypes.c_float * 3)(*gravity), int(wall_band), float(nu),
                        float(E_default), int(accum_mode), int(tile), int(resort_interval), int(max_particles))
         h = _h()
         s = _current_stream() if stream is None else int(stream)
-        rc = _lib.mpm_create(ctypes.byref(p), ctypes.c_uint64(s), ctypes.byref(h))
+        self.n_scenes = int(n_scenes)
+        if self.n_scenes == 1:
+            rc = _lib.mpm_create(ctypes.byref(p), ctypes.c_uint64(s), ctypes.byref(h))
+        else:
+            rc = _lib.mpm_create_batch(ctypes.byref(p), self.n_scenes, ctypes.c_uint64(s), ctypes.byref(h))
         if rc != MPM_OK:
             raise MPMError(rc, _lib.mpm_last_error(None).decode())
         self.h = h
@@ -208,12 +225,31 @@ class Simulation:
         self._check(rc)
         self.N = n
 
+    def set_batch_particles(self, counts, x, v=None, C=None, F=None, E=None, mass=1.0, vol0=1.0):
+        """All scenes' particles, concatenated scene after scene."""
+        counts = np.ascontiguousarray(np.asarray(counts, dtype=np.int64))
+        n = int(counts.sum())
+        args = [_arg(x, (3,), n), _arg(v, (3,), n), _arg(C, (3, 3), n), _arg(F, (3, 3), n), _arg(E, (), n)]
+        wheres = {w for _, w, _ in args if w is not None}
+        if len(wheres) > 1:
+            raise ValueError("all arrays must be host or all device")
+        where = wheres.pop() if wheres else MPM_HOST
+        self._keep = [k for _, _, k in args] + [counts]
+        rc = _lib.mpm_set_batch_particles(self.h, counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          *[p for p, _, _ in args], float(mass), float(vol0), where)
+        self._check(rc)
+        self.N = n
+        self.counts = counts.copy()
+
     def set_tool(self, tool_id, tool_type, center=(0, 0, 0), quat=(1, 0, 0, 0), size=(0, 0, 0),
-                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0):
+                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0, scene=0):
         t = mpm_tool(int(tool_type), (ctypes.c_double * 3)(*center), (ctypes.c_double * 4)(*quat),
                      (ctypes.c_double * 3)(*size), (ctypes.c_double * 3)(*lin_vel),
                      (ctypes.c_double * 3)(*ang_vel), float(mu), float(drag), float(margin))
-        self._check(_lib.mpm_set_tool_sdf(self.h, int(tool_id), ctypes.byref(t)))
+        if scene == 0:
+            self._check(_lib.mpm_set_tool_sdf(self.h, int(tool_id), ctypes.byref(t)))
+        else:
+            self._check(_lib.mpm_set_scene_tool(self.h, int(scene), int(tool_id), ctypes.byref(t)))
 
     def step(self, n):
         self._check(_lib.mpm_step(self.h, int(n)))
@@ -240,19 +276,20 @@ class Simulation:
         self._check(_lib.mpm_get_info(self.h, ctypes.byref(i)))
         return {name: getattr(i, name) for name, _ in mpm_info._fields_}
 
-    def tool_impulses(self):
-        """(MPM_MAX_TOOLS + 1, 3) impulses on each tool (last row: walls) over
-        the most recent step() call."""
+    def tool_impulses(self, scene=0):
+        """(MPM_MAX_TOOLS + 1, 3) impulses on each tool of a scene (last row:
+        walls) over the most recent step() call."""
         out = np.zeros((MPM_MAX_TOOLS + 1, 3), np.float64)
-        self._check(_lib.mpm_read_tool_impulses(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self._check(_lib.mpm_read_scene_tool_impulses(self.h, int(scene),
+                                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
-    def set_tool_velocity_table(self, tool_id, table):
+    def set_tool_velocity_table(self, tool_id, table, scene=0):
         """Per-substep linear velocities (T x 3) of a tool from the current
         substep on (re-anchored at its current pose)."""
         t = np.ascontiguousarray(np.asarray(table, dtype=np.float64).reshape(-1, 3))
-        self._check(_lib.mpm_set_tool_velocity_table(self.h, int(tool_id), t.shape[0],
-                                                      t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self._check(_lib.mpm_set_scene_tool_velocity_table(self.h, int(scene), int(tool_id), t.shape[0],
+                                                            t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def rollout_forward(self, n_substeps, checkpoint_every=20, theta=None):
         """Run and record a differentiable rollout; theta (N,) sets E = exp(theta)."""

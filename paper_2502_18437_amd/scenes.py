@@ -278,6 +278,94 @@ def tiny_block(n_grid=16, per_axis=6, seed=11, spacing_dx=0.5, center=(0.5, 0.5,
     return s
 
 
+def _unit_quat_to(axis):
+    """Unit quaternion (w, x, y, z) rotating body +x onto `axis`."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    ex = np.array([1.0, 0.0, 0.0])
+    c = float(np.dot(ex, a))
+    if c < -1.0 + 1e-12:
+        return (0.0, 0.0, 1.0, 0.0)
+    axis_r = np.cross(ex, a)
+    q = np.array([1.0 + c, axis_r[0], axis_r[1], axis_r[2]])
+    q /= np.linalg.norm(q)
+    return tuple(float(v) for v in q)
+
+
+@dataclass
+class Batch:
+    """Scenes that share the grid size, dt, material and walls (one batched
+    handle); each has its own particles and tools."""
+    name: str
+    scenes: list
+    n_grid: int
+    dt: float
+    n_substeps: int
+    nu: float
+    E_default: float
+    mass: float
+    vol0: float
+    gravity: tuple = GRAVITY
+    wall_band: int = WALL_BAND
+
+    @property
+    def counts(self):
+        return np.array([sc.N for sc in self.scenes], dtype=np.int64)
+
+    @property
+    def N(self):
+        return int(self.counts.sum())
+
+    def concat(self, field):
+        arrs = [getattr(sc, field) for sc in self.scenes]
+        if all(a is None for a in arrs):
+            return None
+        if any(a is None for a in arrs):
+            raise ValueError(f"{field} given for some scenes only")
+        return np.concatenate(arrs, axis=0)
+
+
+def batch_c4(n_scenes=256, seed=4, n_grid=64, n_substeps=200, k_range=(16, 40)):
+    """Many independent falling-cube scenes of uneven size: scene s holds a
+    k_s^3 cube lattice at spacing dx/2, k_s = round(exp(u/3)) with u uniform
+    in [3 ln k_lo, 3 ln k_hi] (so counts are log-uniform between k_lo^3 and
+    k_hi^3), centred in its 64^3 domain with U[0, 0.1 dx) jitter; E = 5e3,
+    nu = 0.3, dt = 1e-4. Each scene has one capsule (r = 3 dx, half length
+    0.1) whose centre is U(0.3, 1) r above the cube's top face (so it starts
+    in contact), with a uniformly random axis and a velocity of uniform
+    direction and speed U(0, 0.1) m/s."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n_grid
+    spacing = 0.5 * dx
+    vol0 = spacing ** 3
+    lo, hi = 3.0 * math.log(k_range[0]), 3.0 * math.log(k_range[1])
+    scenes = []
+    for sidx in range(n_scenes):
+        k = int(round(math.exp(rng.uniform(lo, hi) / 3.0)))
+        side = k * spacing
+        corner = tuple(0.5 - side / 2 for _ in range(3))
+        pts = lattice(corner, (k, k, k), (spacing,) * 3)
+        pts = (pts + jitter(rng, pts.shape[0], dx)).astype(np.float32)
+        axis = rng.normal(size=3)
+        direction = rng.normal(size=3)
+        speed = rng.uniform(0.0, 0.1)
+        vel = tuple(float(v) for v in speed * direction / np.linalg.norm(direction))
+        r = 3 * dx
+        center = (0.5 + rng.uniform(-0.05, 0.05), 0.5 + side / 2 + rng.uniform(0.3, 1.0) * r,
+                  0.5 + rng.uniform(-0.05, 0.05))
+        tool = Tool(TOOL_CAPSULE, center, _unit_quat_to(axis), (0.1, r, 0.0), vel, mu=0.3)
+        scenes.append(Scene(f"c4[{sidx}]", n_grid, 1e-4, n_substeps, 0.3, 5e3, RHO * vol0, vol0, pts,
+                            tools=[tool]))
+    return Batch("c4", scenes, n_grid, 1e-4, n_substeps, 0.3, 5e3, RHO * vol0, vol0)
+
+
+def batch_c4s(seed=4):
+    """c4 with 6 scenes on 32^3 grids (4^3 .. 12^3 particles), 40 substeps."""
+    b = batch_c4(n_scenes=6, seed=seed, n_grid=32, n_substeps=40, k_range=(4, 12))
+    b.name = "c4s"
+    return b
+
+
 SCENES = {
     "c1": scene_c1, "c1s": scene_c1s, "c2": scene_c2, "c2s": scene_c2s, "c3": scene_c3,
     "c3s": scene_c3s, "c3m": scene_c3m, "c5": scene_c5, "c5s": scene_c5s, "cube": scene_cube,
