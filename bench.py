@@ -21,7 +21,12 @@ Also reported on the same JSON line:
   mpm_rollout_forward(200, checkpoints every 20) and mpm_rollout_backward
   (gradients for theta, the velocity table and the starting state), timed
   separately, with the ratio (fwd + bwd) / fwd; fwd_bwd_keep_all is the same
-  with a checkpoint (and the grid) kept at every substep.
+  with a checkpoint (and the grid) kept at every substep;
+* batch (with --batch): 256 independent scenes of uneven size (16^3 .. 40^3
+  particle cubes, 5.85M particles, a 64^3 grid and a capsule each) advanced
+  together by one mpm_step(200) per step, as aggregate particle-substeps/s.
+  It is off by default so that the fused kernel's launches in a profile of
+  the default command all belong to the headline workload.
 """
 import argparse
 import json
@@ -54,6 +59,51 @@ def cpu_baseline(scene, n_sub):
     return {"value": scene.N * n_sub / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_sub} substeps of the full {scene.name} scene ({scene.N} particles, "
                       f"{scene.n_grid}^3 grid), FP64, one host thread; {dt:.1f} s"}
+
+
+def batch_throughput(steps, warmup=1):
+    """The batched workload: 256 independent scenes of uneven size (16^3 ..
+    40^3 particle cubes, each on its own 64^3 grid with one capsule), all
+    stepped by one mpm_step per benchmark step (200 substeps)."""
+    import torch
+    from paper_2502_18437_amd import mpm, scenes
+    b = scenes.batch_c4()
+    n_sub = b.n_substeps
+    dev = torch.device("cuda", 0)
+    x_d = torch.from_numpy(b.concat("x")).to(dev)
+    sim = mpm.Simulation(b.n_grid, b.dt, gravity=b.gravity, wall_band=b.wall_band, nu=b.nu, E_default=b.E_default,
+                         max_particles=b.N, n_scenes=len(b.scenes))
+    log(f"[bench] batch {b.name}: {len(b.scenes)} scenes, {b.N} particles, {n_sub} substeps/step")
+
+    def step():
+        sim.set_batch_particles(b.counts, x_d, None, None, None, None, b.mass, b.vol0)
+        for i, sc in enumerate(b.scenes):
+            for k, t in enumerate(sc.tools):
+                sim.set_tool(k, t.type, scene=i, **t.kwargs())
+        sim.step(n_sub)
+
+    for _ in range(warmup):
+        step()
+    sim.read_state(out={})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    _, st = sim.read_state(out={}, allow_errors=True)
+    info = sim.info()
+    sim.close()
+    per_substep = elapsed / (steps * n_sub)
+    n_act = int(info["active_nodes"])
+    model = b.N * B_PARTICLE + n_act * B_NODE_SUBSTEP
+    return {"workload": f"{b.name}: {len(b.scenes)} scenes, {b.N} particles ({int(b.counts.min())}..{int(b.counts.max())} "
+                        f"per scene), 64^3 grid each, one capsule each, {n_sub} substeps of dt={b.dt}",
+            "value": b.N * n_sub * steps / elapsed, "unit": "particle-substeps/s", "ms_per_step": 1e3 * elapsed / steps,
+            "steps": steps, "status": int(st), "active_nodes": n_act,
+            "substep_roofline": {"bound": "hbm", "model_bytes": model, "us_per_substep": 1e6 * per_substep,
+                                 "achieved": model / per_substep / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": model / per_substep / 1e9 / HBM_PEAK_GBS}}
 
 
 def fwd_bwd(steps, checkpoint_every=20):
@@ -124,6 +174,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd measurement")
+    ap.add_argument("--batch", action="store_true", help="also measure the 256-scene batch")
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of MIB MiB (a kernel of known "
@@ -214,6 +265,8 @@ def main():
                            "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
+    if args.batch:
+        out["batch"] = batch_throughput(args.diff_steps)
     if not args.no_diff:
         out["fwd_bwd"] = fwd_bwd(args.diff_steps, checkpoint_every=20)
         out["fwd_bwd_keep_all"] = fwd_bwd(args.diff_steps, checkpoint_every=1)

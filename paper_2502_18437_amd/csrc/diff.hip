@@ -34,6 +34,16 @@ namespace {
 
 constexpr int kDWG = 256;
 
+// Workgroups for a scatter kernel: a multiple of 8 with enough threads per
+// XCD for its range.
+unsigned scatter_blocks(int64_t N) {
+  const int64_t Nc = (N + 7) / 8;
+  int64_t per = (Nc + kDWG - 1) / kDWG;
+  if (per < 1) per = 1;
+  if (per > 8192) per = 8192;
+  return (unsigned)(8 * per);
+}
+
 unsigned blocks_for(int64_t n) {
   int64_t b = (n + kDWG - 1) / kDWG;
   if (b < 1) b = 1;
@@ -81,12 +91,32 @@ __device__ __forceinline__ void load_state(DState S, int64_t p, float* x, float*
   for (int i = 0; i < 9; ++i) C[i] = S.C[9 * p + i], F[i] = S.F[9 * p + i];
 }
 
-// Particle of global thread gi when the particles are dealt to the 64 lanes
-// of each wave S apart (S = ceil(N / 64)): lane l of wave w takes l S + w.
-// Neighbouring particles scatter to the same nodes; spreading them over the
-// lanes keeps one wave's atomics on distinct addresses.
-__device__ __forceinline__ int64_t spread(int64_t gi, int64_t S) {
-  return (gi & 63) * S + (gi >> 6);
+// Work split of the scatter kernels. Workgroups are dealt round-robin to the
+// 8 XCDs (workgroup w runs on XCD w % 8); XCD x takes the particles
+// [x Nc, (x + 1) Nc), Nc = ceil(N / 8), so that different XCDs, which do not
+// share an L2, rarely add into the same nodes. Inside its range an XCD's
+// threads take the particles dealt to the 64 lanes of each wave S apart
+// (S = ceil(Nc / 64)), so one wave's atomics hit distinct nodes. Returns -1
+// past the end.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int64_t scatter_particle(int64_t li, int64_t N) {
+  const int64_t Nc = (N + kXcd - 1) / kXcd;
+  const int64_t S = (Nc + 63) / 64;
+  const int64_t q = (li & 63) * S + (li >> 6);
+  const int64_t p = (int64_t)(blockIdx.x % kXcd) * Nc + q;
+  return (q < Nc && p < N) ? p : -1;
+}
+
+// Threads per XCD and this thread's first index in its XCD's range.
+__device__ __forceinline__ void xcd_thread(int64_t* first, int64_t* stride) {
+  const int64_t per = (int64_t)(gridDim.x / kXcd) * kDWG;
+  *first = (int64_t)(blockIdx.x / kXcd) * kDWG + threadIdx.x;
+  *stride = per;
+}
+
+__device__ __forceinline__ int64_t xcd_span(int64_t N) {
+  const int64_t Nc = (N + kXcd - 1) / kXcd;
+  return 64 * ((Nc + 63) / 64);
 }
 
 __device__ __forceinline__ void flush_status(Status* st, unsigned inv, unsigned dom, unsigned nf) {
@@ -100,10 +130,12 @@ __global__ __launch_bounds__(kDWG) void k_dp2g(SimK s, int64_t N, DState in, con
                                                float* gm, float* gp0, float* gp1, float* gp2,
                                                uint8_t* __restrict__ skip, Status* st, int count) {
   unsigned c_inv = 0, c_dom = 0, c_nf = 0;
-  const int64_t S = (N + 63) / 64;
-  for (int64_t gi = blockIdx.x * (int64_t)kDWG + threadIdx.x; gi < 64 * S; gi += (int64_t)gridDim.x * kDWG) {
-    const int64_t p = spread(gi, S);
-    if (p >= N) continue;
+  int64_t li0, lstride;
+  xcd_thread(&li0, &lstride);
+  const int64_t span = xcd_span(N);
+  for (int64_t li = li0; li < span; li += lstride) {
+    const int64_t p = scatter_particle(li, N);
+    if (p < 0) continue;
     float x[3], v[3], C[9], F[9];
     load_state(in, p, x, v, C, F);
     const float e = E[p];
@@ -500,10 +532,12 @@ __global__ __launch_bounds__(kDWG) void k_bg2p(SimK s, int64_t N, DState in, con
                                                const float4* __restrict__ vel, DState adj, float* gvb0,
                                                float* gvb1, float* gvb2) {
   const float Minv = 4.0f * s.inv_dx * s.inv_dx;
-  const int64_t S = (N + 63) / 64;
-  for (int64_t gi = blockIdx.x * (int64_t)kDWG + threadIdx.x; gi < 64 * S; gi += (int64_t)gridDim.x * kDWG) {
-    const int64_t p = spread(gi, S);
-    if (p >= N) continue;
+  int64_t li0, lstride;
+  xcd_thread(&li0, &lstride);
+  const int64_t span = xcd_span(N);
+  for (int64_t li = li0; li < span; li += lstride) {
+    const int64_t p = scatter_particle(li, N);
+    if (p < 0) continue;
     float x[3], F[9];
     int base[3];
     float f[3];
@@ -757,7 +791,7 @@ void launch_diff_substep(const DiffGrid& g, float4* vel, float4* hat, const SimK
                          int64_t N, DState in, const float* E, DState out, bool count, Status* st,
                          hipStream_t stream) {
   const int64_t nn = (int64_t)s.n * s.n * s.n;
-  hipLaunchKernelGGL(k_dp2g, dim3(blocks_for(64 * ((N + 63) / 64))), dim3(kDWG), 0, stream, s, N, in, E, g.m,
+  hipLaunchKernelGGL(k_dp2g, dim3(scatter_blocks(N)), dim3(kDWG), 0, stream, s, N, in, E, g.m,
                      g.p[0], g.p[1], g.p[2], g.skip, st, count ? 1 : 0);
   hipLaunchKernelGGL(k_dgrid, dim3(blocks_for(nn)), dim3(kDWG), 0, stream, s, tools, g.m, g.p[0], g.p[1], g.p[2],
                      vel, hat);
@@ -770,7 +804,7 @@ void launch_diff_adjoint(const DiffGrid& g, const float4* vel, const float4* hat
                          const ToolSetK& tools, int64_t N, DState in, const float* E, DState adj, float* theta_bar,
                          double* tool_red, hipStream_t stream) {
   const int64_t nn = (int64_t)s.n * s.n * s.n;
-  hipLaunchKernelGGL(k_bg2p, dim3(blocks_for(64 * ((N + 63) / 64))), dim3(kDWG), 0, stream, s, N, in, E, vel, adj,
+  hipLaunchKernelGGL(k_bg2p, dim3(scatter_blocks(N)), dim3(kDWG), 0, stream, s, N, in, E, vel, adj,
                      g.vb[0], g.vb[1], g.vb[2]);
   hipLaunchKernelGGL(k_bgrid, dim3(blocks_for(nn)), dim3(kDWG), 0, stream, s, tools, hat, g.vb[0],
                      g.vb[1], g.vb[2], g.pb, tool_red);
