@@ -11,7 +11,9 @@ substep, all in the HIP library). `value` = particles x substeps / second.
 Also reported on the same JSON line:
 * roofline: the dominant kernel (the fused G2P2G) against the HBM peak,
   from its algorithmic bytes per launch and its mean duration measured with
-  HIP events on the library's stream during the timed steps;
+  HIP events on the library's stream during the timed steps; `traffic` is
+  the kernel's HBM bytes per launch from hardware counters
+  (profiles/k_g2p2g_<scene>_counters.md), null once its sources changed;
 * substep_roofline: the whole substep against the HBM byte model
   N x 100 B + N_act x 72 B;
 * cpu_baseline: the FP64 oracle timed on the host for a bounded sample of
@@ -48,6 +50,30 @@ B_NODE_G2P2G = 28.0     # the fused kernel's share: velocity read 12 B + P2G res
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def counted_traffic(scene_name):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary, or None when there is none for this workload or the kernel's
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_g2p2g_{scene_name}_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256",
+                                                     "kernel_sources"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for f in fields["kernel_sources"].split():
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != fields["kernel_source_sha256"]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(scene, n_sub):
@@ -261,7 +287,7 @@ def main():
         bytes_launch = s.N * B_PARTICLE + n_act * B_NODE_G2P2G
         achieved = bytes_launch / avg_s / 1e9
         out["roofline"] = {"kernel": "k_g2p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(s.name),
                            "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
