@@ -250,6 +250,20 @@ def main():
     _, st = sim.read_state(out={})
     info = sim.info()
     prof = sim.profile_read() if not args.no_profile else None
+    graphs = None
+    if not args.no_profile:
+        # The per-kernel events above launch every kernel; the same steps with
+        # runs of substeps replayed as HIP graphs (the default when not timing
+        # kernels):
+        sim.profile(False)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        g_el = time.perf_counter() - g0
+        graphs = {"value": s.N * n_sub * args.steps / g_el, "ms_per_step": 1e3 * g_el / args.steps,
+                  "graph_chunk": sim.launch_config()["graph_chunk"]}
     sim.close()
     assert st == 0, st
 
@@ -296,6 +310,8 @@ def main():
     if not args.no_diff:
         out["fwd_bwd"] = fwd_bwd(args.diff_steps, checkpoint_every=20)
         out["fwd_bwd_keep_all"] = fwd_bwd(args.diff_steps, checkpoint_every=1)
+    if graphs is not None:
+        out["graph_replay"] = graphs
     if not args.no_cpu:
         log(f"[bench] oracle CPU baseline: {args.cpu_substeps} substeps of the full scene ...")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_substeps)

@@ -243,6 +243,33 @@ int mpm_profile(mpm_handle* h, int32_t enable);
 /* Synchronise and return the totals accumulated since timing was enabled. */
 int mpm_profile_read(mpm_handle* h, mpm_kernel_times* out);
 
+/* ------------------------------------------------------ launch configuration */
+/* How mpm_step launches its kernels. Results do not depend on it beyond the
+ * order of FP32 atomics (in MPM_ACCUM_FIXED mode not at all). */
+typedef struct mpm_launch_config {
+  int32_t resort_interval; /* substeps between particle re-binnings, >= 1 */
+  int32_t transfer_wgs;    /* workgroups of the persistent transfer kernels, a multiple of 8 in [8, 65536] */
+  int32_t graph_chunk;     /* runs of this many plain substeps (fused transfer + grid update) are
+                              recorded once as a HIP graph and replayed; 0 = launch every kernel */
+} mpm_launch_config;
+
+/* Read / replace the launch configuration (the defaults: resort_interval
+ * from mpm_params or 32, two workgroups per compute unit, graph_chunk 8).
+ * Errors: MPM_EINVAL (NULL, value out of range). */
+int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out);
+int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
+
+/* Autotuner: times mpm_step(trial_substeps) on the current scene for each
+ * candidate configuration (re-binning every 8, 16, 32 or 64 substeps; 1 to 4
+ * transfer workgroups per compute unit; graphs on or off), restoring the
+ * particles, their order, the device status and the clock before every
+ * trial, and keeps the fastest (written to *chosen if not NULL). The scene
+ * is left as it was, except that the next mpm_step re-bins and the tool
+ * impulses read zero. Blocking; 64 timed calls.
+ * Errors: MPM_EINVAL (no particles, trial_substeps < 1), MPM_ENOMEM (it
+ * needs a copy of the particle buffer), MPM_EHIP. */
+int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chosen);
+
 /* ------------------------------------------------------ batches of scenes */
 /* A handle with n_scenes independent scenes that share the grid size, dt,
  * gravity, wall band, material constants and accumulation mode. Each

@@ -26,6 +26,7 @@ using namespace mpm;
 namespace {
 
 constexpr int kDefaultResort = 32;
+constexpr int kDefaultGraphChunk = 8;
 
 struct HostTool {
   mpm_tool t;
@@ -103,6 +104,11 @@ struct mpm_handle {
   unsigned long long* scratch_u64 = nullptr;  // device word for on-demand reductions
   double* imp_sum = nullptr;                  // device: impulse totals of the last mpm_step
   DiffBufs d;
+  // Runs of plain substeps (fused transfer + grid update) replayed as HIP
+  // graphs: one instance per particle ping-pong half.
+  int graph_chunk = kDefaultGraphChunk;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -262,11 +268,19 @@ void prof_collect(mpm_handle* h) {
   h->prof_pending.clear();
 }
 
+void drop_graphs(mpm_handle* h) {
+  for (int i = 0; i < 2; ++i)
+    if (h->graph[i]) {
+      (void)hipGraphExecDestroy(h->graph[i]);
+      h->graph[i] = nullptr;
+    }
+}
+
 void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
                   b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.act_list, b.mark,
                   b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.imp_blocks, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
-                  b.status, b.scene_off, b.tools};
+                  b.status, b.scene_off, b.tools, b.clock};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   b = Buffers();
@@ -502,6 +516,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   alloc((void**)&b.imp_blocks, sizeof(float) * (size_t)h->n_blocks * kImpulseRows * 3);
   alloc((void**)&b.scene_off, sizeof(uint32_t) * ((size_t)n_scenes + 1));
   alloc((void**)&b.tools, sizeof(ToolDesc) * (size_t)n_scenes * kMaxTools);
+  alloc((void**)&b.clock, sizeof(Clock));
   alloc((void**)&h->imp_sum, sizeof(double) * kImpulseRows * 3);
   alloc((void**)&h->scratch_u64, sizeof(unsigned long long));
   const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
@@ -525,6 +540,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
                        (int64_t)(grid_nodes * mom_bytes / 4));
   hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
+  launch_set_clock(b, 0, h->stream);
   // Scene constants.
   SimK& s = h->sim;
   s.n = n;
@@ -579,6 +595,8 @@ int mpm_destroy(mpm_handle* h) {
     (void)hipEventDestroy(pe.b);
   }
   for (auto e : h->prof_pool) (void)hipEventDestroy(e);
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   free_buffers(h->b);
   free_diff(h->d);
   for (double* t : h->tool_tables)
@@ -658,6 +676,7 @@ int set_particles_impl(mpm_handle* h, const int64_t* counts, const float* x, con
   h->since_sort = 0;
   h->dirty = true;
   h->d.valid = false;
+  drop_graphs(h);  // the recorded launches hold the old scene constants
   h->err.clear();
   return MPM_OK;
 }
@@ -824,6 +843,32 @@ int mpm_set_scene_tool_velocity_table(mpm_handle* h, int32_t scene, int32_t tool
   return set_table_impl(h, scene, tool_id, n_rows, table);
 }
 
+namespace {
+
+// Record `chunk` plain substeps (fused transfer + grid update) as a graph
+// for the current particle half.
+int record_graph(mpm_handle* h) {
+  if (!h->cap_stream) HIP_OR_RETURN(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  Buffers& b = h->b;
+  hipGraph_t g = nullptr;
+  HIP_OR_RETURN(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < h->graph_chunk; ++i) {
+    launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, h->cap_stream);
+    launch_grid(b, h->sim, (int)h->n_blocks, h->cap_stream);
+  }
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&h->graph[b.cur], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph[b.cur] = nullptr;
+    return hip_fail(h, e, "hipGraphInstantiate");
+  }
+  return MPM_OK;
+}
+
+}  // namespace
+
 int mpm_step(mpm_handle* h, int32_t n_substeps) {
   if (!h) return MPM_EINVAL;
   if (n_substeps < 0) return fail(h, MPM_EINVAL, "mpm_step: n_substeps < 0");
@@ -842,8 +887,8 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   int rc = upload_tools(h);
   if (rc != MPM_OK) return rc;
   launch_clear_impulses(b, h->sim, h->stream);
-  for (int k = 0; k < n_substeps; ++k) {
-    const int parity = (int)(h->substep & 1);
+  launch_set_clock(b, (long long)h->substep, h->stream);
+  for (int k = 0; k < n_substeps;) {
     const bool rebin = h->dirty || h->since_sort >= h->resort_interval;
     if (k == 0 || rebin) {
       if (k > 0) {
@@ -857,24 +902,160 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
         h->since_sort = 0;
         h->resorts++;
       }
-      ProfScope ps(h, 1);
-      launch_p2g(b, N, h->sim, parity, wgs, h->stream);
+      {
+        ProfScope ps(h, 1);
+        launch_p2g(b, N, h->sim, wgs, h->stream);
+      }
     } else {
+      // Plain substeps until the next re-binning or the end of the call:
+      // whole chunks replay the recorded graph (not while timing kernels).
+      const int64_t run = std::min<int64_t>(n_substeps - k, h->resort_interval - h->since_sort);
+      if (!h->prof && h->graph_chunk > 0 && run >= h->graph_chunk) {
+        if (!h->graph[b.cur]) {
+          rc = record_graph(h);
+          if (rc != MPM_OK) return rc;
+        }
+        HIP_OR_RETURN(h, hipGraphLaunch(h->graph[b.cur], h->stream));
+        k += h->graph_chunk;
+        h->substep += h->graph_chunk;
+        h->since_sort += h->graph_chunk;
+        continue;
+      }
       ProfScope ps(h, 2);
-      launch_g2p2g(b, N, h->sim, parity, wgs, h->stream);
+      launch_g2p2g(b, N, h->sim, wgs, h->stream);
     }
     {
       ProfScope ps(h, 4);
-      launch_grid(b, h->sim, (long long)h->substep, parity, (int)h->n_blocks, h->stream);
+      launch_grid(b, h->sim, (int)h->n_blocks, h->stream);
     }
     h->substep++;
     h->since_sort++;
+    ++k;
   }
   {
     ProfScope ps(h, 3);
     launch_g2p(b, N, h->sim, wgs, h->stream);
   }
   HIP_OR_RETURN(h, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out) {
+  if (!h || !out) return MPM_EINVAL;
+  out->resort_interval = h->resort_interval;
+  out->transfer_wgs = h->transfer_wgs;
+  out->graph_chunk = h->graph_chunk;
+  return MPM_OK;
+}
+
+int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c) {
+  if (!h) return MPM_EINVAL;
+  if (!c || c->resort_interval < 1 || c->transfer_wgs < 8 || c->transfer_wgs % 8 != 0 || c->transfer_wgs > 65536 ||
+      c->graph_chunk < 0 || c->graph_chunk > 256)
+    return fail(h, MPM_EINVAL, "mpm_set_launch_config: value out of range");
+  h->resort_interval = c->resort_interval;
+  if (c->transfer_wgs != h->transfer_wgs || c->graph_chunk != h->graph_chunk) drop_graphs(h);
+  h->transfer_wgs = c->transfer_wgs;
+  h->graph_chunk = c->graph_chunk;
+  return MPM_OK;
+}
+
+int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chosen) {
+  if (!h) return MPM_EINVAL;
+  if (trial_substeps < 1) return fail(h, MPM_EINVAL, "mpm_autotune: trial_substeps < 1");
+  if (h->N == 0) return fail(h, MPM_EINVAL, "mpm_autotune: no particles");
+  HIP_OR_RETURN(h, select_device(h));
+  int rc = sync(h);
+  if (rc != MPM_OK) return rc;
+  Buffers& b = h->b;
+  // Save what the trials change: the particles (and their order), the status
+  // word and the clocks; restore them after every trial.
+  const size_t part_bytes = sizeof(float) * kFields * (size_t)b.cap;
+  float* save_part = nullptr;
+  uint32_t* save_id = nullptr;
+  Status* save_st = nullptr;
+  ALLOC_OR_RETURN(h, hipMalloc((void**)&save_part, part_bytes));
+  hipError_t e = hipMalloc((void**)&save_id, sizeof(uint32_t) * (size_t)b.cap);
+  if (e == hipSuccess) e = hipMalloc((void**)&save_st, sizeof(Status));
+  auto release = [&]() {
+    (void)hipFree(save_part);
+    (void)hipFree(save_id);
+    (void)hipFree(save_st);
+  };
+  if (e != hipSuccess) {
+    release();
+    return alloc_fail(h, e, "mpm_autotune");
+  }
+  const int cur0 = b.cur;
+  const int64_t substep0 = h->substep, since0 = h->since_sort, resorts0 = h->resorts;
+  const bool dirty0 = h->dirty, prof0 = h->prof;
+  const mpm_launch_config orig = {h->resort_interval, h->transfer_wgs, h->graph_chunk};
+  e = hipMemcpyAsync(save_part, b.part[cur0], part_bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(save_id, b.id[cur0], sizeof(uint32_t) * b.cap, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(save_st, b.status, sizeof(Status), hipMemcpyDeviceToDevice, h->stream);
+  auto restore = [&]() -> hipError_t {
+    b.cur = cur0;
+    hipError_t r = hipMemcpyAsync(b.part[cur0], save_part, part_bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (r == hipSuccess) r = hipMemcpyAsync(b.id[cur0], save_id, sizeof(uint32_t) * b.cap, hipMemcpyDeviceToDevice, h->stream);
+    if (r == hipSuccess) r = hipMemcpyAsync(b.status, save_st, sizeof(Status), hipMemcpyDeviceToDevice, h->stream);
+    h->substep = substep0;
+    h->since_sort = since0;
+    h->resorts = resorts0;
+    h->dirty = true;  // block lists are rebuilt for the restored order
+    return r;
+  };
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  h->prof = false;
+  // Candidates: re-binning interval, persistent workgroups per CU, graph
+  // replay on or off.
+  const int resorts[] = {8, 16, 32, 64};
+  const int per_cu[] = {1, 2, 3, 4};
+  const int chunks[] = {0, kDefaultGraphChunk};
+  mpm_launch_config best = orig;
+  float best_ms = 0.0f;
+  bool have = false;
+  for (int ri = 0; ri < 4 && e == hipSuccess && rc == MPM_OK; ++ri)
+    for (int wi = 0; wi < 4 && e == hipSuccess && rc == MPM_OK; ++wi)
+      for (int ci = 0; ci < 2 && e == hipSuccess && rc == MPM_OK; ++ci) {
+        mpm_launch_config c = {resorts[ri], (per_cu[wi] * h->cus + 7) / 8 * 8, chunks[ci]};
+        rc = mpm_set_launch_config(h, &c);
+        if (rc != MPM_OK) break;
+        e = restore();
+        if (e != hipSuccess) break;
+        // one untimed warm-up call (records graphs), then the timed one
+        rc = mpm_step(h, trial_substeps);
+        if (rc != MPM_OK) break;
+        e = restore();
+        if (e == hipSuccess) e = hipEventRecord(ev0, h->stream);
+        if (e != hipSuccess) break;
+        rc = mpm_step(h, trial_substeps);
+        if (rc != MPM_OK) break;
+        e = hipEventRecord(ev1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (e == hipSuccess && (!have || ms < best_ms)) {
+          best = c;
+          best_ms = ms;
+          have = true;
+        }
+      }
+  hipError_t e2 = restore();
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  release();
+  h->prof = prof0;
+  if (rc == MPM_OK && e == hipSuccess) rc = mpm_set_launch_config(h, have ? &best : &orig);
+  else (void)mpm_set_launch_config(h, &orig);
+  if (!dirty0) h->dirty = true;
+  launch_clear_impulses(b, h->sim, h->stream);
+  if (rc != MPM_OK) return rc;
+  if (e != hipSuccess) return hip_fail(h, e, "mpm_autotune");
+  if (chosen) *chosen = have ? best : orig;
   return MPM_OK;
 }
 

@@ -47,10 +47,14 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
                                                   void* __restrict__ acc_p1, void* __restrict__ acc_p2,
                                                   float4* __restrict__ vel,
                                                   const uint32_t* __restrict__ act_list,
-                                                  const uint32_t* __restrict__ ovf_list,
+                                                  const uint32_t* __restrict__ ovf0,
+                                                  const uint32_t* __restrict__ ovf1,
                                                   uint32_t* mark, uint32_t* __restrict__ node_cnt,
                                                   float* __restrict__ imp_blocks, const ToolDesc* __restrict__ tools,
-                                                  Status* st, int parity, long long substep, SimK s) {
+                                                  Status* st, Clock* clk, SimK s) {
+  const int parity = clk->parity;
+  const long long substep = clk->substep;
+  const uint32_t* __restrict__ ovf_list = parity ? ovf1 : ovf0;
   // Momentum given to the material by each tool and by the walls on the nodes
   // of one block (two-way coupling, Sec. IV-A), added to the block's own
   // sums. Each wave reduces its contributions with shuffles (a tool's only
@@ -181,12 +185,30 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
   if (blockIdx.x == 0 && threadIdx.x == 0) st->ovf_count[parity ^ 1] = 0u;
 }
 
-void launch_grid(Buffers& b, const SimK& s, long long substep, int parity, int max_act, hipStream_t st) {
+// Advance the clock after the grid update (a kernel of its own: a counter of
+// finished workgroups inside k_grid would serialise its thousands of
+// workgroups on one address).
+__global__ void k_advance_clock(Clock* clk) {
+  clk->substep += 1;
+  clk->parity ^= 1;
+}
+
+__global__ void k_set_clock(Clock* clk, long long substep) {
+  clk->substep = substep;
+  clk->parity = (int)(substep & 1);
+}
+
+void launch_set_clock(Buffers& b, long long substep, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(1), 0, st, b.clock, substep);
+}
+
+void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st) {
   int wgs = max_act < kGridSlots ? max_act : kGridSlots;
   if (wgs < 1) wgs = 1;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
-                     b.acc_p[2], b.vel, b.act_list, b.ovf_list[parity], b.mark, b.node_cnt, b.imp_blocks,
-                     (const ToolDesc*)b.tools, b.status, parity, substep, s);
+                     b.acc_p[2], b.vel, b.act_list, b.ovf_list[0], b.ovf_list[1], b.mark, b.node_cnt, b.imp_blocks,
+                     (const ToolDesc*)b.tools, b.status, b.clock, s);
+  hipLaunchKernelGGL(k_advance_clock, dim3(1), dim3(1), 0, st, b.clock);
 }
 
 }  // namespace mpm

@@ -103,6 +103,15 @@ struct Status {
   unsigned int ovf_count[2];        // overflow blocks claimed, per parity
 };
 
+// Substep clock on the device: the transfer and grid kernels read the
+// substep (tool poses) and its parity (overflow lists) from here rather than
+// from their arguments, so that a run of substeps can be recorded once and
+// replayed. A one-thread kernel after each grid update advances it.
+struct Clock {
+  long long substep;
+  int parity;
+};
+
 // Device buffers of one handle.
 struct Buffers {
   float* part[2] = {nullptr, nullptr};      // particle SoA ping-pong, kFields * cap
@@ -128,6 +137,7 @@ struct Buffers {
   void* acc_p[3] = {nullptr, nullptr, nullptr};  // momentum channels (float or int64)
   float4* vel = nullptr;                    // grid velocity
   Status* status = nullptr;
+  Clock* clock = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -135,14 +145,16 @@ struct Buffers {
 // ranges, occupied and active block lists. Resets the overflow lists.
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st);
 
-// Transfers. `first_substep`: parity of the overflow list used by P2G.
-void launch_p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st);
-void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st);
+// Transfers (the overflow list of the clock's parity takes drifted particles).
+void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
 
-// Grid update over active blocks and this parity's overflow blocks, with
-// each scene's tools at their pose of global substep `substep`.
-void launch_grid(Buffers& b, const SimK& s, long long substep, int parity, int max_act, hipStream_t st);
+// Grid update over active blocks and the clock parity's overflow blocks, with
+// each scene's tools at their pose of the clock's substep; advances the clock.
+void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st);
+// Set the device clock to `substep` (parity substep & 1).
+void launch_set_clock(Buffers& b, long long substep, hipStream_t st);
 
 // Nodes with mass in the last grid update (sum of node_cnt over the active
 // and overflow blocks of `parity`), written to *out (device memory).

@@ -407,7 +407,10 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint32_t* __restrict__ occ_list, Status* st,
-                                             ACC_PARAMS, uint32_t* mark, uint32_t* ovf, int parity, SimK s) {
+                                             ACC_PARAMS, uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
+                                             const Clock* __restrict__ clk, SimK s) {
+  const int parity = clk->parity;
+  uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds L;
   Counters cnt;
   unsigned pos, end, stride;
@@ -448,7 +451,10 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
                                                const uint32_t* __restrict__ blk_end,
                                                const uint32_t* __restrict__ occ_list, Status* st,
                                                ACC_PARAMS, const float4* __restrict__ vel,
-                                               uint32_t* mark, uint32_t* ovf, int parity, SimK s) {
+                                               uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
+                                               const Clock* __restrict__ clk, SimK s) {
+  const int parity = clk->parity;
+  uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds L;
   Counters cnt;
   unsigned pos, end, stride;
@@ -540,37 +546,37 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
 
 // ------------------------------------------------------------------ launchers
 template <bool FIXED>
-static void launch_p2g_t(Buffers& b, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
+static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
   hipLaunchKernelGGL(k_p2g<FIXED>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
                      b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
-                     (P*)b.acc_p[2], b.mark, b.ovf_list[parity], parity, s);
+                     (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
 }
 
 template <bool FIXED>
-static void launch_g2p2g_t(Buffers& b, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
+static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
   hipLaunchKernelGGL(k_g2p2g<FIXED>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
                      b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
-                     (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[parity], parity, s);
+                     (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
 }
 
-void launch_p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
+void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
   (void)N;
   if (s.fixed)
-    launch_p2g_t<true>(b, s, parity, grid_wgs, st);
+    launch_p2g_t<true>(b, s, grid_wgs, st);
   else
-    launch_p2g_t<false>(b, s, parity, grid_wgs, st);
+    launch_p2g_t<false>(b, s, grid_wgs, st);
 }
 
-void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int parity, int grid_wgs, hipStream_t st) {
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
   (void)N;
   if (s.fixed)
-    launch_g2p2g_t<true>(b, s, parity, grid_wgs, st);
+    launch_g2p2g_t<true>(b, s, grid_wgs, st);
   else
-    launch_g2p2g_t<false>(b, s, parity, grid_wgs, st);
+    launch_g2p2g_t<false>(b, s, grid_wgs, st);
 }
 
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {

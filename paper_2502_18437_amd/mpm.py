@@ -35,7 +35,8 @@ EXPORTED = ("mpm_create", "mpm_destroy", "mpm_set_particles", "mpm_set_tool_sdf"
             "mpm_read_state", "mpm_get_info", "mpm_last_error", "mpm_eval_stress", "mpm_profile",
             "mpm_profile_read", "mpm_read_tool_impulses", "mpm_set_tool_velocity_table", "mpm_rollout_forward",
             "mpm_rollout_backward", "mpm_create_batch", "mpm_set_batch_particles", "mpm_set_scene_tool",
-            "mpm_set_scene_tool_velocity_table", "mpm_read_scene_tool_impulses")
+            "mpm_set_scene_tool_velocity_table", "mpm_read_scene_tool_impulses", "mpm_get_launch_config",
+            "mpm_set_launch_config", "mpm_autotune")
 
 
 class mpm_params(ctypes.Structure):
@@ -57,6 +58,11 @@ class mpm_info(ctypes.Structure):
         "n_particles", "substeps", "resorts", "occupied_blocks", "active_blocks", "active_nodes",
         "n_inverted", "n_domain", "n_nonfinite", "n_fallback", "n_range")] + \
         [(n, ctypes.c_int32) for n in ("tile", "resort_interval", "accum_mode", "n_tools")]
+
+
+class mpm_launch_config(ctypes.Structure):
+    _fields_ = [("resort_interval", ctypes.c_int32), ("transfer_wgs", ctypes.c_int32),
+                ("graph_chunk", ctypes.c_int32)]
 
 
 class mpm_kernel_times(ctypes.Structure):
@@ -94,6 +100,9 @@ _lib.mpm_set_scene_tool.argtypes = [_h, ctypes.c_int32, ctypes.c_int32, ctypes.P
 _lib.mpm_set_scene_tool_velocity_table.argtypes = [_h, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                                    ctypes.POINTER(ctypes.c_double)]
 _lib.mpm_read_scene_tool_impulses.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+_lib.mpm_get_launch_config.argtypes = [_h, ctypes.POINTER(mpm_launch_config)]
+_lib.mpm_set_launch_config.argtypes = [_h, ctypes.POINTER(mpm_launch_config)]
+_lib.mpm_autotune.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(mpm_launch_config)]
 _lib.mpm_rollout_backward.argtypes = [_h, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp,
                                       _vp]
 
@@ -118,6 +127,9 @@ mpm_set_batch_particles = _lib.mpm_set_batch_particles
 mpm_set_scene_tool = _lib.mpm_set_scene_tool
 mpm_set_scene_tool_velocity_table = _lib.mpm_set_scene_tool_velocity_table
 mpm_read_scene_tool_impulses = _lib.mpm_read_scene_tool_impulses
+mpm_get_launch_config = _lib.mpm_get_launch_config
+mpm_set_launch_config = _lib.mpm_set_launch_config
+mpm_autotune = _lib.mpm_autotune
 
 
 class MPMError(RuntimeError):
@@ -325,6 +337,25 @@ class Simulation:
         for k, a in zip(("x0", "v0", "C0", "F0"), outs):
             r[k] = a
         return r
+
+    def launch_config(self):
+        c = mpm_launch_config()
+        self._check(_lib.mpm_get_launch_config(self.h, ctypes.byref(c)))
+        return {"resort_interval": c.resort_interval, "transfer_wgs": c.transfer_wgs, "graph_chunk": c.graph_chunk}
+
+    def set_launch_config(self, resort_interval=None, transfer_wgs=None, graph_chunk=None):
+        cur = self.launch_config()
+        c = mpm_launch_config(int(resort_interval if resort_interval is not None else cur["resort_interval"]),
+                              int(transfer_wgs if transfer_wgs is not None else cur["transfer_wgs"]),
+                              int(graph_chunk if graph_chunk is not None else cur["graph_chunk"]))
+        self._check(_lib.mpm_set_launch_config(self.h, ctypes.byref(c)))
+
+    def autotune(self, trial_substeps=32):
+        """Time the candidate launch configurations on the current scene and
+        keep the fastest; returns it."""
+        c = mpm_launch_config()
+        self._check(_lib.mpm_autotune(self.h, int(trial_substeps), ctypes.byref(c)))
+        return {"resort_interval": c.resort_interval, "transfer_wgs": c.transfer_wgs, "graph_chunk": c.graph_chunk}
 
     def profile(self, enable=True):
         self._check(_lib.mpm_profile(self.h, int(bool(enable))))

@@ -49,6 +49,8 @@ int main(void) {
   F(mpm_tool, ang_vel) F(mpm_tool, mu) F(mpm_tool, drag) F(mpm_tool, margin)
   printf("mpm_info SIZEOF %zu\n", sizeof(mpm_info));
   F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, n_range) F(mpm_info, tile) F(mpm_info, n_tools)
+  printf("mpm_launch_config SIZEOF %zu\n", sizeof(mpm_launch_config));
+  F(mpm_launch_config, resort_interval) F(mpm_launch_config, transfer_wgs) F(mpm_launch_config, graph_chunk)
   printf("mpm_kernel_times SIZEOF %zu\n", sizeof(mpm_kernel_times));
   F(mpm_kernel_times, total_ms) F(mpm_kernel_times, launches)
   return 0;
@@ -65,7 +67,7 @@ def test_struct_layouts_match_ctypes(tmp_path):
                    check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     structs = {"mpm_params": mpm.mpm_params, "mpm_tool": mpm.mpm_tool, "mpm_info": mpm.mpm_info,
-               "mpm_kernel_times": mpm.mpm_kernel_times}
+               "mpm_kernel_times": mpm.mpm_kernel_times, "mpm_launch_config": mpm.mpm_launch_config}
     for line in out:
         if not line:
             continue
@@ -99,3 +101,5 @@ def test_null_handle_calls_are_rejected_without_a_gpu():
     assert mpm._lib.mpm_set_tool_velocity_table(None, 0, 0, None) == mpm.MPM_EINVAL
     assert mpm._lib.mpm_rollout_forward(None, 1, 1, None) == mpm.MPM_EINVAL
     assert mpm._lib.mpm_rollout_backward(None, *([None] * 10)) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_set_launch_config(None, None) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_autotune(None, 1, None) == mpm.MPM_EINVAL

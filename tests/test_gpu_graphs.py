@@ -1,0 +1,90 @@
+"""Launch configurations: replaying runs of substeps as HIP graphs, the
+workgroup count and the re-binning interval change nothing but the order of
+FP32 atomics, so in the fixed-point mode every configuration gives the same
+bits; the autotuner leaves the scene as it found it."""
+import numpy as np
+import pytest
+
+from paper_2502_18437_amd import scenes
+from tests.parity import assert_parity, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def stepped(scene, calls, config, fixed=True):
+    """State after mpm_step(c) for c in calls, with a blocking read (eager
+    work on the stream) between the calls."""
+    from paper_2502_18437_amd import mpm
+    kw = {"accum_mode": mpm.MPM_ACCUM_FIXED} if fixed else {}
+    sim = mpm.simulation_from_scene(scene, **kw)
+    sim.set_launch_config(**config)
+    reads = []
+    for c in calls:
+        sim.step(c)
+        r, st = sim.read_state()
+        assert st == 0
+        reads.append(r)
+    imp = sim.tool_impulses()
+    sim.close()
+    return reads, imp
+
+
+@pytest.mark.parametrize("name", ["c3s", "c2s"])
+def test_graph_replay_is_bitwise_the_eager_launches(name):
+    s = scenes.make(name)
+    calls = [37, 5, 40]  # chunks, remainders and re-binnings inside and across calls
+    print(f"[graphs {name}]", flush=True)
+    eager, imp_e = stepped(s, calls, {"graph_chunk": 0, "resort_interval": 16})
+    for chunk in (4, 8):
+        graph, imp_g = stepped(s, calls, {"graph_chunk": chunk, "resort_interval": 16})
+        for r_e, r_g in zip(eager, graph):
+            for k in ("x", "v", "C", "F"):
+                assert np.array_equal(r_e[k], r_g[k]), (chunk, k)
+        assert np.array_equal(imp_e, imp_g)
+
+
+def test_launch_configurations_agree_in_fixed_mode():
+    s = scenes.make("c3s")
+    ref, _ = stepped(s, [30], {"graph_chunk": 8, "resort_interval": 32})
+    for cfg in ({"transfer_wgs": 8, "resort_interval": 7}, {"transfer_wgs": 2048, "resort_interval": 1},
+                {"transfer_wgs": 512, "graph_chunk": 16, "resort_interval": 64}):
+        got, _ = stepped(s, [30], cfg)
+        for k in ("x", "v", "C", "F"):
+            assert np.array_equal(ref[0][k], got[0][k]), (cfg, k)
+
+
+def test_graphs_in_fp32_mode_match_the_oracle():
+    s = scenes.make("c3s")
+    n = 40
+    reads, _ = stepped(s, [n], {"graph_chunk": 8, "resort_interval": 32}, fixed=False)
+    o = run_oracle(s, n)
+    assert_parity({k: v.astype(np.float64) for k, v in reads[0].items()}, o, s.x, n, "graphs fp32")
+
+
+def test_autotune_keeps_the_scene():
+    from paper_2502_18437_amd import mpm
+    s = scenes.make("c3s")
+    sim = mpm.simulation_from_scene(s, accum_mode=mpm.MPM_ACCUM_FIXED)
+    sim.step(10)
+    before, _ = sim.read_state()
+    chosen = sim.autotune(trial_substeps=8)
+    print(f"[autotune c3s] {chosen}", flush=True)
+    assert chosen["resort_interval"] in (8, 16, 32, 64)
+    assert chosen["transfer_wgs"] % 8 == 0 and chosen["graph_chunk"] in (0, 8)
+    assert sim.launch_config() == chosen
+    after, _ = sim.read_state()
+    for k in ("x", "v", "C", "F"):
+        assert np.array_equal(before[k], after[k]), k
+    sim.step(20)
+    tuned, _ = sim.read_state()
+    sim.close()
+    ref, _ = stepped(s, [10, 20], {"graph_chunk": 8, "resort_interval": 32})
+    for k in ("x", "v", "C", "F"):
+        assert np.array_equal(tuned[k], ref[1][k]), k
