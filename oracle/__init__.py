@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpm_oracle.so")
 
 TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE, TOOL_SLICER, TOOL_SEGMENT, TOOL_ARC = 0, 1, 2, 3, 4, 5, 6
+SOLVER_MLS, SOLVER_PIC, SOLVER_PB = 0, 1, 2
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EDOMAIN, ST_ENONFINITE, ST_EINVERTED = 0, -1, -2, -4, -5, -6
 
 _lib = None
@@ -61,6 +62,10 @@ def lib():
         L.oracle_rollout_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp,
                                              dp, dp]
         L.oracle_polar_adjoint.argtypes = [dp, dp, dp]
+        L.oracle_set_solver.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.oracle_neo_hookean.restype = ctypes.c_double
+        L.oracle_neo_hookean.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_pb_constraint.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp]
         L.oracle_kirchhoff_adjoint.restype = ctypes.c_double
         L.oracle_kirchhoff_adjoint.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.oracle_frame_contact.restype = ctypes.c_int
@@ -136,6 +141,23 @@ def node_contact(tool_type, center, quat, size, lin_vel, ang_vel, mu, drag, marg
     hit = lib().oracle_node_contact(int(tool_type), *[p for _, p in args], float(mu), float(drag),
                                     float(margin), px, pv)
     return v.copy(), bool(hit)
+
+
+def neo_hookean(F, E, nu):
+    """(Kirchhoff stress mu (F F^T - I) + lambda ln J I, J) of standard MPM."""
+    F, pF = _d(np.asarray(F).reshape(9))
+    t, pt = _d(np.zeros(9))
+    J = lib().oracle_neo_hookean(pF, float(E), float(nu), pt)
+    return t.reshape(3, 3), J
+
+
+def pb_constraint(F, C, dt, beta):
+    """C after the PB-MPM co-rotational constraint on one particle."""
+    F, pF = _d(np.asarray(F).reshape(9))
+    C, pC = _d(np.asarray(C).reshape(9))
+    o, po = _d(np.zeros(9))
+    lib().oracle_pb_constraint(pF, pC, float(dt), float(beta), po)
+    return o.reshape(3, 3)
 
 
 def polar_adjoint(F, Rb):
@@ -232,6 +254,12 @@ class Oracle:
         st = lib().oracle_set_state_f64(self.h, self.N, px, *ptrs, float(mass), float(vol0))
         if st != 0:
             raise ValueError(f"oracle_set_state_f64: status {st}")
+
+    def set_solver(self, kind, iterations=10, beta=0.5):
+        """0 MLS-MPM, 1 standard MPM (PIC, Neo-Hookean), 2 PB-MPM."""
+        st = lib().oracle_set_solver(self.h, int(kind), int(iterations), float(beta))
+        if st != 0:
+            raise ValueError(f"oracle_set_solver: status {st}")
 
     def set_velocity_table(self, tool_id, table):
         """Per-substep linear velocities (T x 3) of a tool from now on."""

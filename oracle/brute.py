@@ -17,12 +17,29 @@ Readings of the paper are the ones the C++ oracle states in its header.
 import numpy as np
 
 TOOL_NONE, TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE, TOOL_SLICER, TOOL_SEGMENT, TOOL_ARC = 0, 1, 2, 3, 4, 5, 6
+SOLVER_MLS, SOLVER_PIC, SOLVER_PB = 0, 1, 2
 
 
 def kernel(r):
     """Quadratic B-spline N(r) with support |r| < 3/2 (Sec. III-A)."""
     a = np.abs(r)
     return np.where(a < 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+
+
+def dkernel(r):
+    """Derivative of the quadratic B-spline kernel."""
+    a = np.abs(r)
+    return np.where(a < 0.5, -2.0 * r, np.where(a < 1.5, -(1.5 - a) * np.sign(r), 0.0))
+
+
+def neo_hookean(F, E, nu):
+    """Kirchhoff stress J sigma of eq. neo_hookean, batched."""
+    mu = E / (2 * (1 + nu))
+    la = E * nu / ((1 + nu) * (1 - 2 * nu))
+    J = np.linalg.det(F)
+    B = F @ np.swapaxes(F, -1, -2)
+    lnJ = np.log(np.maximum(J, 1e-6))
+    return mu[:, None, None] * (B - np.eye(3)) + (la * lnJ)[:, None, None] * np.eye(3)
 
 
 def quat_matrix(q):
@@ -180,6 +197,7 @@ class Brute:
         self.E_default = float(E_default)
         self.tools = {}
         self.substep = 0
+        self.solver, self.pb_iterations, self.pb_beta = SOLVER_MLS, 10, 0.5
         idx = np.arange(self.n)
         I, J, K = np.meshgrid(idx, idx, idx, indexing="ij")
         self.node_idx = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
@@ -207,6 +225,21 @@ class Brute:
                                    mu=float(mu), drag=float(drag), margin=float(margin),
                                    set_at=self.substep)
 
+    def set_solver(self, kind, iterations=10, beta=0.5):
+        self.solver, self.pb_iterations, self.pb_beta = int(kind), int(iterations), float(beta)
+
+    def weight_gradients(self, x):
+        """dW[a][p, I]: derivative of node I's weight with respect to x_p[a]."""
+        r = x / self.dx
+        idx = np.arange(self.n)
+        Wa = [kernel(r[:, a][:, None] - idx[None, :]) for a in range(3)]
+        dWa = [dkernel(r[:, a][:, None] - idx[None, :]) / self.dx for a in range(3)]
+        out = []
+        for a in range(3):
+            f = [dWa[b] if b == a else Wa[b] for b in range(3)]
+            out.append(np.einsum("pi,pj,pk->pijk", f[0], f[1], f[2]).reshape(x.shape[0], -1))
+        return out
+
     def weight_matrix(self, x):
         r = x / self.dx  # (N, 3)
         idx = np.arange(self.n)
@@ -216,7 +249,21 @@ class Brute:
 
     def step(self, nsub):
         for _ in range(nsub):
-            self._substep()
+            if self.solver == SOLVER_PIC:
+                self._substep_pic()
+            elif self.solver == SOLVER_PB:
+                self._step_pb()
+            else:
+                self._substep()
+            self.substep += 1
+
+    def _p2g_affine(self, W, x, v, A):
+        """m_I and sum_p W (m v + A (x_I - x_p)), regrouped."""
+        m = W.T @ np.full(x.shape[0], self.mass)
+        Ax = np.einsum("pab,pb->pa", A, x)
+        p = W.T @ (self.mass * v - Ax)
+        MA = np.einsum("pI,pab->Iab", W, A)
+        return m, p + np.einsum("Iab,Ib->Ia", MA, self.xI)
 
     def _substep(self):
         dt, dx = self.dt, self.dx
@@ -225,16 +272,66 @@ class Brute:
         W = self.weight_matrix(x)  # (N, nodes)
         tau = kirchhoff(F, self.E, self.nu)
         A = self.mass * C - dt * self.vol0 * Minv * tau  # (N, 3, 3)
-        # P2G
+        m, p = self._p2g_affine(W, x, v, A)
+        vI = self._grid(m, p, gravity=True)
+        # G2P
+        vn = W @ vI
+        B = np.einsum("pI,Ia,Ib->pab", W, vI, self.xI) - np.einsum("pa,pb->pab", vn, x)
+        self.C = Minv * B
+        self.F = (np.eye(3) + dt * self.C) @ F
+        self.v = vn
+        self.x = x + dt * vn
+
+    def _substep_pic(self):
+        """Standard MPM: PIC transfers, force -V0 tau grad N, L = sum v_I grad N^T."""
+        dt = self.dt
+        x, v, F = self.x, self.v, self.F
+        W = self.weight_matrix(x)
+        dW = self.weight_gradients(x)
+        tau = neo_hookean(F, self.E, self.nu)
         m = W.T @ np.full(x.shape[0], self.mass)
-        Ax = np.einsum("pab,pb->pa", A, x)
-        p = W.T @ (self.mass * v - Ax)
-        MA = np.einsum("pI,pab->Iab", W, A)
-        p = p + np.einsum("Iab,Ib->Ia", MA, self.xI)
-        # grid update
+        p = W.T @ (self.mass * v)
+        for b in range(3):  # f_I[a] = -sum_p V0 tau[a, b] dN/dx_b
+            p = p - dt * self.vol0 * (dW[b].T @ tau[:, :, b])
+        vI = self._grid(m, p, gravity=True)
+        vn = W @ vI
+        L = np.stack([dW[b] @ vI for b in range(3)], axis=-1)  # L[p, a, b]
+        self.C = L
+        self.F = (np.eye(3) + dt * L) @ F
+        self.v = vn
+        self.x = x + dt * vn
+
+    def _step_pb(self):
+        """PB-MPM step: gravity once, `iterations` of (constraint, APIC P2G,
+        grid without gravity, APIC G2P of v and C), then F and x."""
+        dt, dx = self.dt, self.dx
+        Minv = 4.0 / dx ** 2
+        x, F = self.x, self.F
+        W = self.weight_matrix(x)
+        v = self.v + dt * self.g
+        C = self.C
+        Finv = np.linalg.inv(F)
+        for it in range(self.pb_iterations):
+            Fs = (np.eye(3) + dt * C) @ F
+            R = rotation_part(Fs)
+            J = np.linalg.det(Fs)
+            T = self.pb_beta * R + (1.0 - self.pb_beta) * Fs / np.cbrt(J)[:, None, None]
+            C = (T @ Finv - np.eye(3)) / dt
+            m, p = self._p2g_affine(W, x, v, self.mass * C)
+            vI = self._grid(m, p, gravity=False)
+            v = W @ vI
+            B = np.einsum("pI,Ia,Ib->pab", W, vI, self.xI) - np.einsum("pa,pb->pab", v, x)
+            C = Minv * B
+        self.C = C
+        self.F = (np.eye(3) + dt * C) @ F
+        self.v = v
+        self.x = x + dt * v
+
+    def _grid(self, m, p, gravity):
+        dt = self.dt
         has = m > 0
         vI = np.zeros_like(p)
-        vI[has] = p[has] / m[has, None] + dt * self.g
+        vI[has] = p[has] / m[has, None] + (dt * self.g if gravity else 0.0)
         for tid in sorted(self.tools):
             t = self.tools[tid]
             c = t["center0"] + (self.substep - t["set_at"]) * dt * t["lv"]
@@ -261,14 +358,7 @@ class Brute:
         wall = np.any((self.node_idx < lo) | (self.node_idx > hi), axis=1)
         vI[wall] = 0.0
         self.grid = (m, p, vI)
-        # G2P
-        vn = W @ vI
-        B = np.einsum("pI,Ia,Ib->pab", W, vI, self.xI) - np.einsum("pa,pb->pab", vn, x)
-        self.C = Minv * B
-        self.F = (np.eye(3) + dt * self.C) @ F
-        self.v = vn
-        self.x = x + dt * vn
-        self.substep += 1
+        return vI
 
     def read(self):
         return {"x": self.x.copy(), "v": self.v.copy(), "C": self.C.copy(), "F": self.F.copy()}

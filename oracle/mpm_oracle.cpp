@@ -47,6 +47,19 @@
 //     distance to the curve; a node within the thickness keeps only the
 //     part of its relative velocity along the curve tangent, corrected by
 //     friction and drag, unless it separates.
+//   * Solver variants (Sec. III-A, III-C). Standard MPM: PIC transfers,
+//     internal force -V0 tau grad N with the Neo-Hookean Kirchhoff stress
+//     tau = J sigma = mu (F F^T - I) + lambda ln(J) I (eq. neo_hookean; J is
+//     clamped to >= 1e-6 inside the logarithm), G2P velocity gradient
+//     L = sum v_I grad N^T (kept in the C slot), F <- (I + dt L) F.
+//     PB-MPM: per step, gravity is added to the particle velocities once;
+//     then `iterations` times: the co-rotational constraint on each
+//     particle (F* = (I + dt C) F, R = polar(F*), F* <- beta R + (1 - beta)
+//     F* / det(F*)^(1/3), C <- (F* F^-1 - I) / dt; the printed formula
+//     divides by det(F*) itself, which is not a shape of unit volume, so the
+//     cube root is taken), APIC P2G without stress, the grid update without
+//     gravity (tools, walls), APIC G2P of v and C; finally F <- (I + dt C) F
+//     and x <- x + dt v. Tool impulses are those of the last iteration.
 //   * Errors: a particle whose stencil leaves the grid (EDOMAIN) or whose
 //     state is not finite (ENONFINITE) is left unchanged for that substep;
 //     det F <= 0 is counted (EINVERTED). Status precedence:
@@ -69,6 +82,7 @@ enum {
 };
 
 enum { TOOL_NONE = 0, TOOL_CAPSULE = 1, TOOL_BOX = 2, TOOL_PLANE = 3, TOOL_SLICER = 4, TOOL_SEGMENT = 5, TOOL_ARC = 6 };
+enum { SOLVER_MLS = 0, SOLVER_PIC = 1, SOLVER_PB = 2 };
 constexpr int kMaxTools = 8;
 
 // ---------------------------------------------------------------- 3x3 algebra
@@ -466,6 +480,9 @@ struct Scene {
   std::vector<double> gm, gp, gv;     // grid of the last substep: n^3, 3n^3, 3n^3
   double impulse[kMaxTools + 1][3];   // per tool, then walls; last oracle_step
   long long n_inverted = 0, n_domain = 0, n_nonfinite = 0;
+  int solver = SOLVER_MLS;
+  int pb_iterations = 10;
+  double pb_beta = 0.5;
 };
 
 inline size_t node_index(const Scene& s, int i, int j, int k) {
@@ -574,7 +591,9 @@ inline bool wall_node(const Scene& s, int i, int j, int k) {
 }
 
 // Grid update: velocity, gravity, contact, walls (Algorithm 1, second loop).
-void grid_update(Scene& s) {
+// `gravity` adds dt g; `record` adds the tools' and walls' momentum changes
+// to the impulses.
+void grid_update(Scene& s, bool gravity = true, bool record = true) {
   const double dx = s.dx, dt = s.dt;
   double poses[kMaxTools][3], vels[kMaxTools][3];
   for (int q = 0; q < kMaxTools; ++q) tool_kinematics(s, q, s.substep, poses[q], vels[q]);
@@ -585,7 +604,7 @@ void grid_update(Scene& s) {
         const double m = s.gm[I];
         double vI[3] = {0.0, 0.0, 0.0};
         if (!(m > 0.0)) continue;  // empty node: v = 0
-        for (int a = 0; a < 3; ++a) vI[a] = s.gp[3 * I + a] / m + dt * s.g[a];
+        for (int a = 0; a < 3; ++a) vI[a] = s.gp[3 * I + a] / m + (gravity ? dt * s.g[a] : 0.0);
         const double xI[3] = {i * dx, j * dx, k * dx};
         for (int q = 0; q < kMaxTools; ++q) {
           const Tool& t = s.tools[q];
@@ -595,13 +614,13 @@ void grid_update(Scene& s) {
                                  vnew))
             continue;
           for (int a = 0; a < 3; ++a) {
-            s.impulse[q][a] += m * (vnew[a] - vI[a]);
+            if (record) s.impulse[q][a] += m * (vnew[a] - vI[a]);
             vI[a] = vnew[a];
           }
         }
         if (wall_node(s, i, j, k)) {
           for (int a = 0; a < 3; ++a) {
-            s.impulse[kMaxTools][a] += m * (0.0 - vI[a]);
+            if (record) s.impulse[kMaxTools][a] += m * (0.0 - vI[a]);
             vI[a] = 0.0;
           }
         }
@@ -648,11 +667,266 @@ void g2p(Scene& s, const std::vector<char>& skip) {
   }
 }
 
+// ---------------------------------------------------------------- standard MPM
+// Kirchhoff stress of the Neo-Hookean model of eq. neo_hookean,
+// tau = J sigma = mu (F F^T - I) + lambda ln(J) I. Returns J.
+double neo_hookean(const double* F, double E, double nu, double* tau) {
+  double mu, la;
+  lame(E, nu, &mu, &la);
+  const double J = mat_det(F);
+  double Ft[9];
+  mat_transpose(F, Ft);
+  mat_mul(F, Ft, tau);
+  const double lnJ = std::log(J > 1e-6 ? J : 1e-6);
+  for (int i = 0; i < 9; ++i) tau[i] = mu * (tau[i] - ((i % 4 == 0) ? 1.0 : 0.0));
+  tau[0] += la * lnJ;
+  tau[4] += la * lnJ;
+  tau[8] += la * lnJ;
+  return J;
+}
+
+// Gradient of the weight of node (ox, oy, oz) with respect to the particle
+// position (per axis: w'(f) / dx times the other two weights).
+void weight_gradient(const double (*w)[3], const double (*dw)[3], int ox, int oy, int oz, double inv_dx,
+                     double* g) {
+  g[0] = dw[0][ox] * w[1][oy] * w[2][oz] * inv_dx;
+  g[1] = w[0][ox] * dw[1][oy] * w[2][oz] * inv_dx;
+  g[2] = w[0][ox] * w[1][oy] * dw[2][oz] * inv_dx;
+}
+
+void bspline_dweights(double f, double* dw);
+
+// P2G of standard MPM (Sec. III-A): m_I = sum N m, (mv)_I = sum N m v
+// + dt f_I with f_I = -sum V0 tau grad N (gravity is added by the grid
+// update).
+void p2g_pic(Scene& s, std::vector<char>& skip) {
+  const double dx = s.dx, dt = s.dt;
+  std::fill(s.gm.begin(), s.gm.end(), 0.0);
+  std::fill(s.gp.begin(), s.gp.end(), 0.0);
+  std::fill(s.gv.begin(), s.gv.end(), 0.0);
+  skip.assign(static_cast<size_t>(s.N), 0);
+  for (long long p = 0; p < s.N; ++p) {
+    const double* xp = &s.x[3 * p];
+    const double* vp = &s.v[3 * p];
+    const double* Fp = &s.F[9 * p];
+    const double Ep = s.E.empty() ? s.E_default : s.E[p];
+    if (!all_finite(xp, 3) || !all_finite(vp, 3) || !all_finite(&s.C[9 * p], 9) || !all_finite(Fp, 9) ||
+        !std::isfinite(Ep)) {
+      s.n_nonfinite++;
+      skip[p] = 1;
+      continue;
+    }
+    int base[3];
+    double f[3];
+    if (!stencil(s, xp, base, f)) {
+      s.n_domain++;
+      skip[p] = 1;
+      continue;
+    }
+    double w[3][3], dw[3][3];
+    for (int a = 0; a < 3; ++a) bspline_weights(f[a], w[a]), bspline_dweights(f[a], dw[a]);
+    double tau[9];
+    const double J = neo_hookean(Fp, Ep, s.nu, tau);
+    if (!(J > 0.0)) s.n_inverted++;
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int oz = 0; oz < 3; ++oz) {
+          const double N = w[0][ox] * w[1][oy] * w[2][oz];
+          double gN[3];
+          weight_gradient(w, dw, ox, oy, oz, s.inv_dx, gN);
+          const size_t I = node_index(s, base[0] + ox, base[1] + oy, base[2] + oz);
+          s.gm[I] += N * s.mass;
+          for (int a = 0; a < 3; ++a) {
+            const double tg = tau[3 * a] * gN[0] + tau[3 * a + 1] * gN[1] + tau[3 * a + 2] * gN[2];
+            s.gp[3 * I + a] += N * s.mass * vp[a] - dt * s.vol0 * tg;
+          }
+        }
+  }
+  (void)dx;
+}
+
+// G2P of standard MPM: v = sum N v_I, L = sum v_I grad N^T (kept in C),
+// F <- (I + dt L) F, x <- x + dt v.
+void g2p_pic(Scene& s, const std::vector<char>& skip) {
+  const double dt = s.dt;
+  for (long long p = 0; p < s.N; ++p) {
+    if (skip[p]) continue;
+    double* xp = &s.x[3 * p];
+    int base[3];
+    double f[3];
+    stencil(s, xp, base, f);
+    double w[3][3], dw[3][3];
+    for (int a = 0; a < 3; ++a) bspline_weights(f[a], w[a]), bspline_dweights(f[a], dw[a]);
+    double vn[3] = {0.0, 0.0, 0.0}, L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int oz = 0; oz < 3; ++oz) {
+          const double N = w[0][ox] * w[1][oy] * w[2][oz];
+          double gN[3];
+          weight_gradient(w, dw, ox, oy, oz, s.inv_dx, gN);
+          const size_t I = node_index(s, base[0] + ox, base[1] + oy, base[2] + oz);
+          for (int a = 0; a < 3; ++a) {
+            const double va = s.gv[3 * I + a];
+            vn[a] += N * va;
+            for (int b = 0; b < 3; ++b) L[3 * a + b] += va * gN[b];
+          }
+        }
+    double* Cp = &s.C[9 * p];
+    double* Fp = &s.F[9 * p];
+    for (int i = 0; i < 9; ++i) Cp[i] = L[i];
+    double G[9];
+    for (int i = 0; i < 9; ++i) G[i] = dt * L[i] + ((i % 4 == 0) ? 1.0 : 0.0);
+    mat_mul(G, Fp, Fp);
+    for (int a = 0; a < 3; ++a) {
+      s.v[3 * p + a] = vn[a];
+      xp[a] += dt * vn[a];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- PB-MPM
+// Co-rotational constraint of Sec. III-C on one particle: returns the new C.
+void pb_constraint(const double* F, const double* C, double dt, double beta, double* Cout) {
+  double G[9], Fs[9], R[9];
+  for (int i = 0; i < 9; ++i) G[i] = dt * C[i] + ((i % 4 == 0) ? 1.0 : 0.0);
+  mat_mul(G, F, Fs);
+  const double J = polar_rotation(Fs, R);
+  const double c = std::cbrt(J);
+  double T[9];
+  for (int i = 0; i < 9; ++i) T[i] = beta * R[i] + (1.0 - beta) * Fs[i] / c;
+  // C = (T F^-1 - I) / dt, with F^-1 = cof(F)^T / det F
+  double cof[9], Finv[9];
+  const double dF = mat_det(F);
+  // cofactor matrix of F
+  cof[0] = F[4] * F[8] - F[5] * F[7];
+  cof[1] = F[5] * F[6] - F[3] * F[8];
+  cof[2] = F[3] * F[7] - F[4] * F[6];
+  cof[3] = F[2] * F[7] - F[1] * F[8];
+  cof[4] = F[0] * F[8] - F[2] * F[6];
+  cof[5] = F[1] * F[6] - F[0] * F[7];
+  cof[6] = F[1] * F[5] - F[2] * F[4];
+  cof[7] = F[2] * F[3] - F[0] * F[5];
+  cof[8] = F[0] * F[4] - F[1] * F[3];
+  for (int r = 0; r < 3; ++r)
+    for (int cc = 0; cc < 3; ++cc) Finv[3 * r + cc] = cof[3 * cc + r] / dF;
+  double TF[9];
+  mat_mul(T, Finv, TF);
+  for (int i = 0; i < 9; ++i) Cout[i] = (TF[i] - ((i % 4 == 0) ? 1.0 : 0.0)) / dt;
+}
+
+// APIC P2G without stress (PB-MPM): (mv)_I = sum N m (v + C (x_I - x_p)).
+void p2g_apic(Scene& s, std::vector<char>& skip) {
+  const double dx = s.dx;
+  std::fill(s.gm.begin(), s.gm.end(), 0.0);
+  std::fill(s.gp.begin(), s.gp.end(), 0.0);
+  std::fill(s.gv.begin(), s.gv.end(), 0.0);
+  for (long long p = 0; p < s.N; ++p) {
+    if (skip[p]) continue;
+    const double* xp = &s.x[3 * p];
+    const double* vp = &s.v[3 * p];
+    const double* Cp = &s.C[9 * p];
+    int base[3];
+    double f[3];
+    stencil(s, xp, base, f);
+    double w[3][3];
+    for (int a = 0; a < 3; ++a) bspline_weights(f[a], w[a]);
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int oz = 0; oz < 3; ++oz) {
+          const double N = w[0][ox] * w[1][oy] * w[2][oz];
+          const double d[3] = {(ox - f[0]) * dx, (oy - f[1]) * dx, (oz - f[2]) * dx};
+          const size_t I = node_index(s, base[0] + ox, base[1] + oy, base[2] + oz);
+          s.gm[I] += N * s.mass;
+          for (int a = 0; a < 3; ++a) {
+            const double Cd = Cp[3 * a] * d[0] + Cp[3 * a + 1] * d[1] + Cp[3 * a + 2] * d[2];
+            s.gp[3 * I + a] += N * s.mass * (vp[a] + Cd);
+          }
+        }
+  }
+}
+
+// APIC G2P of v and C only (PB-MPM iterations).
+void g2p_apic_vc(Scene& s, const std::vector<char>& skip) {
+  const double dx = s.dx;
+  const double Minv = 4.0 / (dx * dx);
+  for (long long p = 0; p < s.N; ++p) {
+    if (skip[p]) continue;
+    const double* xp = &s.x[3 * p];
+    int base[3];
+    double f[3];
+    stencil(s, xp, base, f);
+    double w[3][3];
+    for (int a = 0; a < 3; ++a) bspline_weights(f[a], w[a]);
+    double vn[3] = {0.0, 0.0, 0.0}, B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int ox = 0; ox < 3; ++ox)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int oz = 0; oz < 3; ++oz) {
+          const double N = w[0][ox] * w[1][oy] * w[2][oz];
+          const double d[3] = {(ox - f[0]) * dx, (oy - f[1]) * dx, (oz - f[2]) * dx};
+          const size_t I = node_index(s, base[0] + ox, base[1] + oy, base[2] + oz);
+          for (int a = 0; a < 3; ++a) {
+            const double va = s.gv[3 * I + a];
+            vn[a] += N * va;
+            for (int b = 0; b < 3; ++b) B[3 * a + b] += N * va * d[b];
+          }
+        }
+    for (int a = 0; a < 3; ++a) s.v[3 * p + a] = vn[a];
+    for (int i = 0; i < 9; ++i) s.C[9 * p + i] = Minv * B[i];
+  }
+}
+
+// One PB-MPM step of length dt.
+void pb_step(Scene& s) {
+  std::vector<char> skip(static_cast<size_t>(s.N), 0);
+  // Particles that take part: finite state, stencil in the grid.
+  for (long long p = 0; p < s.N; ++p) {
+    int base[3];
+    double f[3];
+    if (!all_finite(&s.x[3 * p], 3) || !all_finite(&s.v[3 * p], 3) || !all_finite(&s.C[9 * p], 9) ||
+        !all_finite(&s.F[9 * p], 9)) {
+      s.n_nonfinite++;
+      skip[p] = 1;
+    } else if (!stencil(s, &s.x[3 * p], base, f)) {
+      s.n_domain++;
+      skip[p] = 1;
+    } else {
+      for (int a = 0; a < 3; ++a) s.v[3 * p + a] += s.dt * s.g[a];
+      if (!(mat_det(&s.F[9 * p]) > 0.0)) s.n_inverted++;
+    }
+  }
+  for (int it = 0; it < s.pb_iterations; ++it) {
+    for (long long p = 0; p < s.N; ++p) {
+      if (skip[p]) continue;
+      double Cn[9];
+      pb_constraint(&s.F[9 * p], &s.C[9 * p], s.dt, s.pb_beta, Cn);
+      for (int i = 0; i < 9; ++i) s.C[9 * p + i] = Cn[i];
+    }
+    p2g_apic(s, skip);
+    grid_update(s, false, it == s.pb_iterations - 1);
+    g2p_apic_vc(s, skip);
+  }
+  for (long long p = 0; p < s.N; ++p) {
+    if (skip[p]) continue;
+    double G[9];
+    for (int i = 0; i < 9; ++i) G[i] = s.dt * s.C[9 * p + i] + ((i % 4 == 0) ? 1.0 : 0.0);
+    mat_mul(G, &s.F[9 * p], &s.F[9 * p]);
+    for (int a = 0; a < 3; ++a) s.x[3 * p + a] += s.dt * s.v[3 * p + a];
+  }
+}
+
 void substep(Scene& s) {
   std::vector<char> skip;
-  p2g(s, skip);
-  grid_update(s);
-  g2p(s, skip);
+  if (s.solver == SOLVER_PIC) {
+    p2g_pic(s, skip);
+    grid_update(s);
+    g2p_pic(s, skip);
+  } else if (s.solver == SOLVER_PB) {
+    pb_step(s);
+  } else {
+    p2g(s, skip);
+    grid_update(s);
+    g2p(s, skip);
+  }
   s.substep++;
 }
 
@@ -1351,7 +1625,7 @@ int oracle_rollout_adjoint(void* h, int T, const double* xb, const double* vb, c
                            double* theta_bar, double* vel_bar, double* xb0, double* vb0, double* Cb0,
                            double* Fb0) {
   Scene* s = static_cast<Scene*>(h);
-  if (!s || T < 0 || !theta_bar || !vel_bar) return ST_EINVAL;
+  if (!s || T < 0 || !theta_bar || !vel_bar || s->solver != SOLVER_MLS) return ST_EINVAL;
   const long long N = s->N;
   struct State {
     std::vector<double> x, v, C, F;
@@ -1402,6 +1676,23 @@ int oracle_rollout_adjoint(void* h, int T, const double* xb, const double* vb, c
   if (Cb0) std::memcpy(Cb0, a.C.data(), sizeof(double) * 9 * N);
   if (Fb0) std::memcpy(Fb0, a.F.data(), sizeof(double) * 9 * N);
   return status_of(*s);
+}
+
+// Solver of the scene (Sec. III): 0 MLS-MPM, 1 standard MPM (PIC,
+// Neo-Hookean), 2 PB-MPM with `iterations` and stiffness `beta` in [0, 1].
+int oracle_set_solver(void* h, int kind, int iterations, double beta) {
+  Scene* s = static_cast<Scene*>(h);
+  if (!s || kind < SOLVER_MLS || kind > SOLVER_PB || iterations < 1 || !(beta >= 0.0 && beta <= 1.0))
+    return ST_EINVAL;
+  s->solver = kind;
+  s->pb_iterations = iterations;
+  s->pb_beta = beta;
+  return ST_OK;
+}
+
+double oracle_neo_hookean(const double* F, double E, double nu, double* tau) { return neo_hookean(F, E, nu, tau); }
+void oracle_pb_constraint(const double* F, const double* C, double dt, double beta, double* Cout) {
+  pb_constraint(F, C, dt, beta, Cout);
 }
 
 // ---- unit adjoints (checked against finite differences)
