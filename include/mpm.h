@@ -1,5 +1,6 @@
 /*
- * mpm.h -- C ABI of the MI355X explicit MLS-MPM substep library.
+ * mpm.h -- C ABI of the MI355X explicit MLS-MPM substep library (with the
+ * standard-MPM and PB-MPM solver variants, see mpm_set_solver).
  *
  * The library advances one scene of the material point method of
  * CRESSim-MPM (arXiv 2502.18437): per substep, P2G scatter of mass, APIC
@@ -311,6 +312,42 @@ int mpm_read_scene_tool_impulses(mpm_handle* h, int32_t scene, double* out);
  * Errors: MPM_EINVAL (no such tool, NULL table, non-finite entry). */
 int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, const double* table);
 
+/* ------------------------------------------------------ solvers */
+/* The three MPM solvers of Sec. III. Every one uses the quadratic B-spline
+ * stencil, the grid, the tools and the walls of mpm_step; they differ in the
+ * transfers, the material model and what one mpm_step "substep" is.
+ *  MPM_SOLVER_MLS (default): MLS-MPM, Algorithm 1 (Sec. III-B): APIC
+ *    transfers with the fixed-corotated stress folded into the affine
+ *    momentum.
+ *  MPM_SOLVER_PIC: standard MPM (Sec. III-A): PIC transfers; P2G adds the
+ *    internal force -dt V0 tau grad N of the Neo-Hookean Kirchhoff stress
+ *    tau = mu (F F^T - I) + lambda ln(J) I (eq. neo_hookean, J clamped to
+ *    >= 1e-6 inside the logarithm); G2P gives v and the velocity gradient
+ *    L = sum v_I grad N^T, which is stored where C is (mpm_read_state returns
+ *    L as C); F <- (I + dt L) F.
+ *  MPM_SOLVER_PB: PB-MPM (Sec. III-C): a substep is one step of length dt
+ *    made of `iterations` transfer passes. Gravity is added to the particle
+ *    velocities once per step; each pass projects C onto the co-rotational
+ *    constraint (F* = (I + dt C) F, target beta R + (1 - beta) F* /
+ *    det(F*)^(1/3) with R the rotation of F*, C <- (target F^-1 - I) / dt),
+ *    scatters mass and APIC momentum without stress, runs the grid update
+ *    without gravity (tools at the pose of the step, walls) and gathers v and
+ *    C; after the last pass F <- (I + dt C) F and x <- x + dt v. The tool and
+ *    wall impulses are those of the last pass. No stress model is used (E
+ *    is ignored).
+ * `iterations` (1..1024) and `beta` (in [0, 1]) are used by MPM_SOLVER_PB
+ * only. Takes effect at the next mpm_step; the differentiable rollout
+ * needs MPM_SOLVER_MLS.
+ * Errors: MPM_EINVAL (NULL handle, unknown solver, iterations or beta out of
+ * range for MPM_SOLVER_PB). */
+#define MPM_SOLVER_MLS 0
+#define MPM_SOLVER_PIC 1
+#define MPM_SOLVER_PB 2
+int mpm_set_solver(mpm_handle* h, int32_t solver, int32_t iterations, float beta);
+/* Read the solver settings (any output may be NULL). Errors: MPM_EINVAL
+ * (NULL handle). */
+int mpm_get_solver(const mpm_handle* h, int32_t* solver, int32_t* iterations, float* beta);
+
 /* ------------------------------------------------------ differentiable rollout
  * Reverse-mode gradients of a rollout (the paper targets learning with the
  * simulator, Sec. I and V). The rollout runs the same substep as mpm_step
@@ -331,7 +368,8 @@ int mpm_set_tool_velocity_table(mpm_handle* h, int32_t tool_id, int64_t n_rows, 
  * afterwards is that after the rollout (mpm_read_state reads it). The tool
  * impulses are not recorded (they read zero). Not blocking.
  * Errors: MPM_EINVAL (no particles, n_substeps < 0, checkpoint_every < 1),
- * MPM_ENOMEM, MPM_EHIP; device errors are deferred as for mpm_step. */
+ * MPM_ENOMEM, MPM_EHIP; device errors are deferred as for mpm_step.
+ * MPM_EINVAL also when the solver is not MPM_SOLVER_MLS. */
 int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_every, const float* theta);
 
 /* Gradient of a scalar loss L through the recorded rollout. Inputs (device,

@@ -90,6 +90,8 @@ struct mpm_handle {
   bool tools_dirty = true;                    // device tool descriptors need an upload
   std::vector<int64_t> scene_n;               // particles per scene
   int64_t substep = 0;
+  int64_t updates = 0;                        // grid updates since mpm_create (their parity picks the overflow list)
+  int pb_iterations = 10;                     // PB-MPM transfer passes per step
   int64_t since_sort = 0;
   bool dirty = true;
   int resort_interval = kDefaultResort;
@@ -540,7 +542,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
                        (int64_t)(grid_nodes * mom_bytes / 4));
   hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
-  launch_set_clock(b, 0, h->stream);
+  launch_set_clock(b, 0, 0, h->stream);
   // Scene constants.
   SimK& s = h->sim;
   s.n = n;
@@ -548,6 +550,8 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   s.n_scenes = n_scenes;
   s.nb3 = nb3;
   s.n3 = (int)(nb3 * kBlockNodes);
+  s.solver = SOLVER_MLS;
+  s.pb_beta = 0.5f;
   launch_clear_impulses(b, s, h->stream);
   e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) e = hipGetLastError();
@@ -666,6 +670,7 @@ int set_particles_impl(mpm_handle* h, const int64_t* counts, const float* x, con
   h->sim.mass = mass;
   h->sim.has_E = h->has_E ? 1 : 0;
   h->sim.p2g_stress = (float)((double)h->p.dt * (double)vol0 * 4.0 * (double)h->p.n_grid * (double)h->p.n_grid);
+  h->sim.pic_force = (float)((double)h->p.dt * (double)vol0 * (double)h->p.n_grid);
   // Fixed-point units: a weight is 2^-24; momentum units are chosen so that
   // one particle at 1 m/s is 2^40 units (exact powers of two).
   h->sim.m_unit = std::ldexp(mass, -24);
@@ -845,6 +850,17 @@ int mpm_set_scene_tool_velocity_table(mpm_handle* h, int32_t scene, int32_t tool
 
 namespace {
 
+// Grid updates per substep: the PB-MPM iterations, else one.
+int transfer_passes(const mpm_handle* h) { return h->sim.solver == SOLVER_PB ? h->pb_iterations : 1; }
+
+// Grid update `it` of `passes` in a substep: PB-MPM leaves gravity out (it
+// is added to the particles) and keeps the impulses of the last pass only;
+// the clock's substep advances after the last pass.
+void launch_grid_pass(mpm_handle* h, int it, int passes, hipStream_t st) {
+  const bool last = it == passes - 1;
+  launch_grid(h->b, h->sim, (int)h->n_blocks, st, h->sim.solver != SOLVER_PB, last, last);
+}
+
 // Record `chunk` plain substeps (fused transfer + grid update) as a graph
 // for the current particle half.
 int record_graph(mpm_handle* h) {
@@ -852,9 +868,13 @@ int record_graph(mpm_handle* h) {
   Buffers& b = h->b;
   hipGraph_t g = nullptr;
   HIP_OR_RETURN(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int passes = transfer_passes(h);
   for (int i = 0; i < h->graph_chunk; ++i) {
-    launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, h->cap_stream);
-    launch_grid(b, h->sim, (int)h->n_blocks, h->cap_stream);
+    launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, h->cap_stream, PB_FIRST);
+    for (int it = 0; it < passes; ++it) {
+      if (it > 0) launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, h->cap_stream, PB_ITER);
+      launch_grid_pass(h, it, passes, h->cap_stream);
+    }
   }
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
@@ -887,7 +907,8 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   int rc = upload_tools(h);
   if (rc != MPM_OK) return rc;
   launch_clear_impulses(b, h->sim, h->stream);
-  launch_set_clock(b, (long long)h->substep, h->stream);
+  launch_set_clock(b, (long long)h->substep, (int)(h->updates & 1), h->stream);
+  const int passes = transfer_passes(h);
   for (int k = 0; k < n_substeps;) {
     const bool rebin = h->dirty || h->since_sort >= h->resort_interval;
     if (k == 0 || rebin) {
@@ -918,16 +939,22 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
         HIP_OR_RETURN(h, hipGraphLaunch(h->graph[b.cur], h->stream));
         k += h->graph_chunk;
         h->substep += h->graph_chunk;
+        h->updates += (int64_t)h->graph_chunk * passes;
         h->since_sort += h->graph_chunk;
         continue;
       }
       ProfScope ps(h, 2);
-      launch_g2p2g(b, N, h->sim, wgs, h->stream);
+      launch_g2p2g(b, N, h->sim, wgs, h->stream, PB_FIRST);
     }
-    {
+    for (int it = 0; it < passes; ++it) {
+      if (it > 0) {
+        ProfScope ps(h, 2);
+        launch_g2p2g(b, N, h->sim, wgs, h->stream, PB_ITER);
+      }
       ProfScope ps(h, 4);
-      launch_grid(b, h->sim, (int)h->n_blocks, h->stream);
+      launch_grid_pass(h, it, passes, h->stream);
     }
+    h->updates += passes;
     h->substep++;
     h->since_sort++;
     ++k;
@@ -937,6 +964,32 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     launch_g2p(b, N, h->sim, wgs, h->stream);
   }
   HIP_OR_RETURN(h, hipGetLastError());
+  return MPM_OK;
+}
+
+int mpm_set_solver(mpm_handle* h, int32_t solver, int32_t iterations, float beta) {
+  if (!h) return MPM_EINVAL;
+  if (solver != MPM_SOLVER_MLS && solver != MPM_SOLVER_PIC && solver != MPM_SOLVER_PB)
+    return fail(h, MPM_EINVAL, "mpm_set_solver: unknown solver");
+  if (solver == MPM_SOLVER_PB && (iterations < 1 || iterations > 1024 || !(beta >= 0.0f && beta <= 1.0f)))
+    return fail(h, MPM_EINVAL, "mpm_set_solver: PB-MPM needs 1 <= iterations <= 1024 and 0 <= beta <= 1");
+  static_assert(MPM_SOLVER_MLS == SOLVER_MLS && MPM_SOLVER_PIC == SOLVER_PIC && MPM_SOLVER_PB == SOLVER_PB,
+                "solver codes");
+  h->sim.solver = solver;
+  if (solver == MPM_SOLVER_PB) {
+    h->pb_iterations = iterations;
+    h->sim.pb_beta = beta;
+  }
+  h->d.valid = false;
+  drop_graphs(h);  // the recorded launches are those of the previous solver
+  return MPM_OK;
+}
+
+int mpm_get_solver(const mpm_handle* h, int32_t* solver, int32_t* iterations, float* beta) {
+  if (!h) return MPM_EINVAL;
+  if (solver) *solver = h->sim.solver;
+  if (iterations) *iterations = h->pb_iterations;
+  if (beta) *beta = h->sim.pb_beta;
   return MPM_OK;
 }
 
@@ -1065,6 +1118,7 @@ int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_ev
     return fail(h, MPM_EINVAL, "mpm_rollout_forward: need n_substeps >= 0 and checkpoint_every >= 1");
   if (h->N == 0) return fail(h, MPM_EINVAL, "mpm_rollout_forward: no particles");
   if (h->n_scenes != 1) return fail(h, MPM_EINVAL, "mpm_rollout_forward: one scene only");
+  if (h->sim.solver != SOLVER_MLS) return fail(h, MPM_EINVAL, "mpm_rollout_forward: needs the MLS-MPM solver");
   HIP_OR_RETURN(h, select_device(h));
   DiffBufs& d = h->d;
   d.valid = false;
@@ -1242,7 +1296,7 @@ int mpm_get_info(mpm_handle* h, mpm_info* info) {
   info->active_blocks = st.n_act;
   info->active_nodes = 0;
   if (h->N > 0 && h->substep > 0 && !h->dirty) {
-    launch_count_active_nodes(h->b, (int)((h->substep - 1) & 1), h->scratch_u64, h->stream);
+    launch_count_active_nodes(h->b, (int)((h->updates - 1) & 1), h->scratch_u64, h->stream);
     unsigned long long cnt = 0;
     HIP_OR_RETURN(h, hipMemcpyAsync(&cnt, h->scratch_u64, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
     HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));

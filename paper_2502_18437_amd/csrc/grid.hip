@@ -1,6 +1,7 @@
 // Grid update of the explicit MLS-MPM substep (CRESSim-MPM Algorithm 1, second
 // loop): for every node with mass, v = (m v)/m + dt g (Sec. III-A, eq.
-// mls_mpm_grid), then the SDF contact of each tool in id order (Sec. IV-A,
+// mls_mpm_grid; PB-MPM iterations leave out g, which it adds to the particles
+// once per step), then the SDF contact of each tool in id order (Sec. IV-A,
 // eq. v_correction), then sticky walls (Sec. III-A, boundary conditions by
 // altering the momentum). Empty nodes get v = 0. The kernel also clears the
 // accumulator it has read, which is the grid reset of Algorithm 1 for the next
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
                                                   const uint32_t* __restrict__ ovf1,
                                                   uint32_t* mark, uint32_t* __restrict__ node_cnt,
                                                   float* __restrict__ imp_blocks, const ToolDesc* __restrict__ tools,
-                                                  Status* st, Clock* clk, SimK s) {
+                                                  Status* st, Clock* clk, int record, SimK s) {
   const int parity = clk->parity;
   const long long substep = clk->substep;
   const uint32_t* __restrict__ ovf_list = parity ? ovf1 : ovf0;
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
 #pragma unroll
         for (int w = 0; w < kGridWG / 64; ++w) x += red[w][threadIdx.x - kMaxTools * 3];
       }
-      if (x != 0.0f) imp_blocks[(size_t)b * (kImpulseRows * 3) + threadIdx.x] += x;
+      if (record && x != 0.0f) imp_blocks[(size_t)b * (kImpulseRows * 3) + threadIdx.x] += x;
     }
     __syncthreads();
   }
@@ -188,27 +189,29 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
 // Advance the clock after the grid update (a kernel of its own: a counter of
 // finished workgroups inside k_grid would serialise its thousands of
 // workgroups on one address).
-__global__ void k_advance_clock(Clock* clk) {
-  clk->substep += 1;
+__global__ void k_advance_clock(Clock* clk, int dsub) {
+  clk->substep += dsub;
   clk->parity ^= 1;
 }
 
-__global__ void k_set_clock(Clock* clk, long long substep) {
+__global__ void k_set_clock(Clock* clk, long long substep, int parity) {
   clk->substep = substep;
-  clk->parity = (int)(substep & 1);
+  clk->parity = parity;
 }
 
-void launch_set_clock(Buffers& b, long long substep, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(1), 0, st, b.clock, substep);
+void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(1), 0, st, b.clock, substep, parity & 1);
 }
 
-void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st) {
+void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st, bool gravity, bool record, bool last) {
   int wgs = max_act < kGridSlots ? max_act : kGridSlots;
   if (wgs < 1) wgs = 1;
+  SimK k = s;
+  if (!gravity) k.g[0] = k.g[1] = k.g[2] = 0.0f;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
                      b.acc_p[2], b.vel, b.act_list, b.ovf_list[0], b.ovf_list[1], b.mark, b.node_cnt, b.imp_blocks,
-                     (const ToolDesc*)b.tools, b.status, b.clock, s);
-  hipLaunchKernelGGL(k_advance_clock, dim3(1), dim3(1), 0, st, b.clock);
+                     (const ToolDesc*)b.tools, b.status, b.clock, record ? 1 : 0, k);
+  hipLaunchKernelGGL(k_advance_clock, dim3(1), dim3(1), 0, st, b.clock, last ? 1 : 0);
 }
 
 }  // namespace mpm

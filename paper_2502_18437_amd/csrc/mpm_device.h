@@ -1,6 +1,7 @@
-// Device-side per-particle and per-node arithmetic of the MLS-MPM substep
-// (FP32): quadratic B-spline weights, polar decomposition, fixed-corotated
-// Kirchhoff stress, tool SDFs and the contact law.
+// Device-side per-particle and per-node arithmetic of the MPM substep
+// (FP32): quadratic B-spline weights and their derivatives, polar
+// decomposition, the fixed-corotated and Neo-Hookean Kirchhoff stresses, the
+// PB-MPM constraint projection, tool SDFs and the contact law.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -184,6 +185,63 @@ __device__ __forceinline__ float kirchhoff(const float* F, float mu, float la, f
                                            bool* inverted) {
   float R[9];
   return kirchhoff_r(F, mu, la, tau, R, inverted);
+}
+
+// Neo-Hookean Kirchhoff stress of standard MPM (Sec. III-A, eq.
+// neo_hookean: sigma = (mu (F F^T - I) + lambda ln J I) / J, so tau = J sigma
+// drops the 1/J), with J clamped to >= 1e-6 inside the logarithm so that an
+// inverted or collapsed element still has a finite stress. Returns J.
+__device__ __forceinline__ float neo_hookean_tau(const float* F, float mu, float la, float* tau) {
+  const float J = det3(F);
+  const float vol = la * logf(fmaxf(J, 1e-6f));
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      tau[3 * r + c] = mu * (F[3 * r] * F[3 * c] + F[3 * r + 1] * F[3 * c + 1] + F[3 * r + 2] * F[3 * c + 2] -
+                             (r == c ? 1.0f : 0.0f)) +
+                       (r == c ? vol : 0.0f);
+  return J;
+}
+
+// Co-rotational constraint of PB-MPM (Sec. III-C) on one particle: with
+// F* = (I + dt C) F and R its rotation factor, the target shape is
+// T = beta R + (1 - beta) F* / det(F*)^(1/3) (a rotation blended with the
+// volume-preserving part of F*), and the returned C' satisfies
+// (I + dt C') F = T, i.e. C' = (T - F) F^-1 / dt. Returns det F.
+__device__ __forceinline__ float pb_constraint(const float* F, const float* C, float dt, float beta, float* Cn) {
+  float Fs[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      Fs[3 * r + c] = F[3 * r + c] + dt * (C[3 * r] * F[c] + C[3 * r + 1] * F[3 + c] + C[3 * r + 2] * F[6 + c]);
+  const float Js = det3(Fs);
+  float R[9];
+  if (!((Js > 0.0f) && polar_newton(Fs, R))) polar_svd_signfix(Fs, R);
+  const float sv = (1.0f - beta) / cbrtf(Js);
+  float D[9];  // T - F
+#pragma unroll
+  for (int i = 0; i < 9; ++i) D[i] = beta * R[i] + sv * Fs[i] - F[i];
+  float cof[9];
+  cof[0] = F[4] * F[8] - F[5] * F[7];
+  cof[1] = F[5] * F[6] - F[3] * F[8];
+  cof[2] = F[3] * F[7] - F[4] * F[6];
+  cof[3] = F[2] * F[7] - F[1] * F[8];
+  cof[4] = F[0] * F[8] - F[2] * F[6];
+  cof[5] = F[1] * F[6] - F[0] * F[7];
+  cof[6] = F[1] * F[5] - F[2] * F[4];
+  cof[7] = F[2] * F[3] - F[0] * F[5];
+  cof[8] = F[0] * F[4] - F[1] * F[3];
+  const float J = F[0] * cof[0] + F[1] * cof[1] + F[2] * cof[2];
+  const float k = 1.0f / (J * dt);
+  // F^-1 = cof(F)^T / J, so (D F^-1)[r][c] = sum_m D[r][m] cof[c][m] / J.
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      Cn[3 * r + c] = k * (D[3 * r] * cof[3 * c] + D[3 * r + 1] * cof[3 * c + 1] + D[3 * r + 2] * cof[3 * c + 2]);
+  return J;
 }
 
 // Signed distance of a tool at world point p and its unit outward normal.

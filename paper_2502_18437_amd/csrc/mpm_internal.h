@@ -89,7 +89,20 @@ struct SimK {
   double fx_p;       // 2^fx_shift (momentum units per kg m/s)
   double fx_p_inv;   // 2^-fx_shift
   float p_limit;     // largest |contribution| (kg m/s) kept in range
+  int solver;        // Solver: which transfer scheme and constitutive model the kernels run
+  float pic_force;   // standard MPM: dt * vol0 / dx (internal force per unit of tau grad N dx)
+  float pb_beta;     // PB-MPM: rotation weight of the co-rotational constraint
 };
+
+// Solvers of Sec. III: MLS-MPM (APIC transfers, fixed-corotated stress in the
+// affine momentum), standard MPM (PIC transfers, Neo-Hookean stress as a grid
+// force) and PB-MPM (iterated APIC transfers with a co-rotational constraint
+// projection of C, no stress).
+enum Solver { SOLVER_MLS = 0, SOLVER_PIC = 1, SOLVER_PB = 2 };
+
+// Which transfer pass a PB-MPM launch is: the first of a step (finishes the
+// previous step's F and x update, adds gravity) or a later iteration.
+enum PBPass { PB_FIRST = 0, PB_ITER = 1 };
 
 // Device status word (one per handle).
 struct Status {
@@ -104,9 +117,11 @@ struct Status {
 };
 
 // Substep clock on the device: the transfer and grid kernels read the
-// substep (tool poses) and its parity (overflow lists) from here rather than
-// from their arguments, so that a run of substeps can be recorded once and
-// replayed. A one-thread kernel after each grid update advances it.
+// substep (tool poses) and the parity of the grid update (overflow lists)
+// from here rather than from their arguments, so that a run of substeps can
+// be recorded once and replayed. A one-thread kernel after each grid update
+// flips the parity and advances the substep (PB-MPM: only after the last
+// iteration of a step).
 struct Clock {
   long long substep;
   int parity;
@@ -146,15 +161,21 @@ struct Buffers {
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st);
 
 // Transfers (the overflow list of the clock's parity takes drifted particles).
+// The solver is s.solver; `pass` selects the PB-MPM pass (PBPass) and is
+// ignored by the other solvers.
 void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
-void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st, int pass = PB_FIRST);
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
 
 // Grid update over active blocks and the clock parity's overflow blocks, with
-// each scene's tools at their pose of the clock's substep; advances the clock.
-void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st);
-// Set the device clock to `substep` (parity substep & 1).
-void launch_set_clock(Buffers& b, long long substep, hipStream_t st);
+// each scene's tools at their pose of the clock's substep; then flips the
+// clock's parity and, when `last`, advances its substep. `gravity` adds
+// dt g to the node velocities; `record` adds the tools' and walls' momentum
+// changes to the impulse sums.
+void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st, bool gravity = true, bool record = true,
+                 bool last = true);
+// Set the device clock to `substep` and `parity`.
+void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st);
 
 // Nodes with mass in the last grid update (sum of node_cnt over the active
 // and overflow blocks of `parity`), written to *out (device memory).

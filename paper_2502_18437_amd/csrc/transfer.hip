@@ -123,6 +123,50 @@ __device__ __forceinline__ void p2g_emit(const P2GIn& P, Sink&& sink) {
   }
 }
 
+// Per-particle inputs of the standard-MPM scatter (Sec. III-A): weights,
+// their derivatives, m v and the internal-force impulse coefficients
+// tk = (dt V0 / dx) tau, so that node I receives N m v - tk (grad N dx) with
+// grad N dx = (w'_x w_y w_z, w_x w'_y w_z, w_x w_y w'_z).
+struct PICIn {
+  int base[3];
+  float w[3][3], dw[3][3];
+  float mv[3];
+  float tk[9];
+  double fx_p;
+};
+
+template <class Sink>
+__device__ __forceinline__ void p2g_emit(const PICIn& P, Sink&& sink) {
+  // The x weights of the current offset move down a register queue, so the
+  // non-unrolled loop indexes no array.
+  float wx = P.w[0][0], wx1 = P.w[0][1], wx2 = P.w[0][2];
+  float dwx = P.dw[0][0], dwx1 = P.dw[0][1], dwx2 = P.dw[0][2];
+#pragma unroll 1
+  for (int ox = 0; ox < 3; ++ox) {
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) {
+      const float wxy = wx * P.w[1][oy], dxy = dwx * P.w[1][oy], xdy = wx * P.dw[1][oy];
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz) {
+        const float N = wxy * P.w[2][oz];
+        const float g0 = dxy * P.w[2][oz], g1 = xdy * P.w[2][oz], g2 = wxy * P.dw[2][oz];
+        const uint32_t wq = (uint32_t)fmaf(N, kWeightUnits, 0.5f);
+        long long q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float val = N * P.mv[a] - (P.tk[3 * a] * g0 + P.tk[3 * a + 1] * g1 + P.tk[3 * a + 2] * g2);
+          q[a] = fx_mul((double)val, P.fx_p);
+        }
+        sink(ox, oy, oz, wq, q[0], q[1], q[2]);
+      }
+    }
+    wx = wx1;
+    wx1 = wx2;
+    dwx = dwx1;
+    dwx1 = dwx2;
+  }
+}
+
 // ------------------------------------------------------------------ global accumulator
 // Channel types of the global accumulator: FP32 sums, or exact integer sums
 // (weights in 2^-24 units, momentum in 2^-fx_shift units).
@@ -159,8 +203,8 @@ __device__ __forceinline__ void acc_add(const SimK& s, typename AccT<FIXED>::M* 
 
 // P2G of one particle straight into the global accumulator; claims every
 // block its stencil touches that the current binning did not activate.
-template <bool FIXED>
-__device__ __forceinline__ void p2g_global(const SimK& s, const P2GIn& P, ACC_PARAMS, uint32_t* mark,
+template <bool FIXED, class In>
+__device__ __forceinline__ void p2g_global(const SimK& s, const In& P, ACC_PARAMS, uint32_t* mark,
                                         uint32_t* ovf, Status* st, int parity, int scene) {
   const int node_base = scene * s.n3;
   p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
@@ -220,6 +264,46 @@ __device__ __forceinline__ void g2p_sums(const float (*w)[3], Node&& node, float
   }
 }
 
+// Standard-MPM gather of one particle: S = sum N v_I and
+// T[a][b] = sum v_I[a] (grad N dx)[b], with the same separable order as
+// g2p_sums (w' are the weight derivatives).
+template <class Node>
+__device__ __forceinline__ void g2p_sums_pic(const float (*w)[3], const float (*dw)[3], Node&& node, float* S,
+                                             float* T) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) S[i] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) T[i] = 0.0f;
+  float wx = w[0][0], wx1 = w[0][1], wx2 = w[0][2];
+  float dwx = dw[0][0], dwx1 = dw[0][1], dwx2 = dw[0][2];
+#pragma unroll 1
+  for (int ox = 0; ox < 3; ++ox) {
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) {
+      const float4 v0 = node(ox, oy, 0), v1 = node(ox, oy, 1), v2 = node(ox, oy, 2);
+      float Z0[3], Zd[3];
+      Z0[0] = w[2][0] * v0.x + w[2][1] * v1.x + w[2][2] * v2.x;
+      Z0[1] = w[2][0] * v0.y + w[2][1] * v1.y + w[2][2] * v2.y;
+      Z0[2] = w[2][0] * v0.z + w[2][1] * v1.z + w[2][2] * v2.z;
+      Zd[0] = dw[2][0] * v0.x + dw[2][1] * v1.x + dw[2][2] * v2.x;
+      Zd[1] = dw[2][0] * v0.y + dw[2][1] * v1.y + dw[2][2] * v2.y;
+      Zd[2] = dw[2][0] * v0.z + dw[2][1] * v1.z + dw[2][2] * v2.z;
+      const float wxy = wx * w[1][oy], dxy = dwx * w[1][oy], xdy = wx * dw[1][oy];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        S[a] += wxy * Z0[a];
+        T[3 * a + 0] += dxy * Z0[a];
+        T[3 * a + 1] += xdy * Z0[a];
+        T[3 * a + 2] += wxy * Zd[a];
+      }
+    }
+    wx = wx1;
+    wx1 = wx2;
+    dwx = dwx1;
+    dwx1 = dwx2;
+  }
+}
+
 // G2P of one particle from the global velocity grid.
 __device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const float (*w)[3],
                                         const float4* vel, float* S, float* T, int scene) {
@@ -240,58 +324,11 @@ __device__ __forceinline__ int lds_index(int lx, int ly, int lz) {
   return (lz * kSpan + ly) * kSpan + lx;
 }
 
-// P2G of one particle (Algorithm 1, first loop): weight N and momentum
-// N [m v + (m C - dt V0 (4/dx^2) tau)(x_I - x_p)] to each of the 27 nodes.
-template <bool FIXED>
-__device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, const float* v,
-                                             const float* C, const float* F, float E,
-                                             const int* to, Lds& L, ACC_PARAMS, uint32_t* mark,
-                                             uint32_t* ovf, Status* st, int parity, Counters& cnt) {
-  P2GIn P;
-  float f[3];
-  if (!particle_stencil(s, x, P.base, f)) {
-    if (isfinite(x[0] + x[1] + x[2]))
-      cnt.dom++;
-    else
-      cnt.nf++;
-    return;
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) bspline_w(f[a], P.w[a]);
-  float tau[9];
-  bool inv;
-  kirchhoff(F, s.c_mu * E, s.c_la * E, tau, &inv);
-  float Af[9];
-  float chk = v[0] + v[1] + v[2];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    Af[i] = s.mass * C[i] - s.p2g_stress * tau[i];
-    chk += Af[i];
-  }
-  if (!isfinite(chk)) {
-    cnt.nf++;
-    return;
-  }
-  if (inv) cnt.inv++;
-  // Bound of |m v + A (x_I - x_p)| over the stencil (|x_I - x_p| <= 1.5 dx
-  // per axis): contributions beyond the fixed-point range are refused.
-  float bound = 0.0f;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float row = fabsf(Af[3 * a]) + fabsf(Af[3 * a + 1]) + fabsf(Af[3 * a + 2]);
-    bound = fmaxf(bound, fabsf(s.mass * v[a]) + 1.5f * s.dx * row);
-  }
-  if (!(bound < s.p_limit)) {
-    cnt.rng++;
-    return;
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float qa = s.mass * v[a] - (Af[3 * a] * f[0] + Af[3 * a + 1] * f[1] + Af[3 * a + 2] * f[2]) * s.dx;
-    P.q[a] = (double)qa * s.fx_p;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) P.Adx[3 * a + b] = (double)(Af[3 * a + b] * s.dx) * s.fx_p;
-  }
+// Commit one particle's scatter: into the LDS tile when its stencil lies in
+// the block's tile, else straight into the global accumulator.
+template <bool FIXED, class In>
+__device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int* to, Lds& L, ACC_PARAMS,
+                                           uint32_t* mark, uint32_t* ovf, Status* st, int parity, Counters& cnt) {
   const int l0 = P.base[0] - to[0], l1 = P.base[1] - to[1], l2 = P.base[2] - to[2];
   const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
                        ((unsigned)l2 <= (unsigned)(kSpan - 3));
@@ -310,9 +347,140 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
   });
 }
 
-// G2P of one particle (Algorithm 1, third loop): v' = sum N v_I,
-// C' = (4/dx^2) sum N v_I (x_I - x_p)^T. Returns false if the stencil is
-// outside the grid (the particle is then left unchanged).
+// P2G of one particle with the APIC affine momentum (Algorithm 1, first
+// loop): weight N and momentum N [m v + A (x_I - x_p)] to each of the 27
+// nodes, where
+//   MLS-MPM: A = m C - dt V0 (4/dx^2) tau (fixed-corotated tau);
+//   PB-MPM:  A = m C' with C' the constraint projection of C (Sec. III-C);
+//            on the first pass of a step v also receives dt g.
+// The PB-MPM iterations after the first count no errors (the first pass of
+// the step has counted them).
+template <bool FIXED, int SOL, int PASS>
+__device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, const float* v, const float* C,
+                                             const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
+                                             uint32_t* mark, uint32_t* ovf, Status* st, int parity, Counters& cnt) {
+  constexpr bool kCount = !(SOL == SOLVER_PB && PASS == PB_ITER);
+  P2GIn P;
+  float f[3];
+  if (!particle_stencil(s, x, P.base, f)) {
+    if (kCount) {
+      if (isfinite(x[0] + x[1] + x[2]))
+        cnt.dom++;
+      else
+        cnt.nf++;
+    }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) bspline_w(f[a], P.w[a]);
+  float Af[9];
+  float vp[3];
+  bool inv;
+  if constexpr (SOL == SOLVER_MLS) {
+    float tau[9];
+    kirchhoff(F, s.c_mu * E, s.c_la * E, tau, &inv);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Af[i] = s.mass * C[i] - s.p2g_stress * tau[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vp[a] = v[a];
+  } else {
+    float Cc[9];
+    const float J = pb_constraint(F, C, s.dt, s.pb_beta, Cc);
+    inv = !(J > 0.0f);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Af[i] = s.mass * Cc[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vp[a] = PASS == PB_FIRST ? v[a] + s.dt * s.g[a] : v[a];
+  }
+  float chk = vp[0] + vp[1] + vp[2];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) chk += Af[i];
+  if (!isfinite(chk)) {
+    if (kCount) cnt.nf++;
+    return;
+  }
+  if (kCount && inv) cnt.inv++;
+  // Bound of |m v + A (x_I - x_p)| over the stencil (|x_I - x_p| <= 1.5 dx
+  // per axis): contributions beyond the fixed-point range are refused.
+  float bound = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float row = fabsf(Af[3 * a]) + fabsf(Af[3 * a + 1]) + fabsf(Af[3 * a + 2]);
+    bound = fmaxf(bound, fabsf(s.mass * vp[a]) + 1.5f * s.dx * row);
+  }
+  if (!(bound < s.p_limit)) {
+    cnt.rng++;
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float qa = s.mass * vp[a] - (Af[3 * a] * f[0] + Af[3 * a + 1] * f[1] + Af[3 * a + 2] * f[2]) * s.dx;
+    P.q[a] = (double)qa * s.fx_p;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) P.Adx[3 * a + b] = (double)(Af[3 * a + b] * s.dx) * s.fx_p;
+  }
+  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+}
+
+// P2G of one particle for standard MPM (Sec. III-A): mass N m and momentum
+// N m v + dt f_I with the internal force f_I = -V0 tau grad N of the
+// Neo-Hookean stress (gravity is added by the grid update). C is not
+// transferred; it holds the velocity gradient and is only checked for being
+// finite.
+template <bool FIXED>
+__device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, const float* v, const float* C,
+                                                 const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
+                                                 uint32_t* mark, uint32_t* ovf, Status* st, int parity,
+                                                 Counters& cnt) {
+  PICIn P;
+  float f[3];
+  if (!particle_stencil(s, x, P.base, f)) {
+    if (isfinite(x[0] + x[1] + x[2]))
+      cnt.dom++;
+    else
+      cnt.nf++;
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bspline_w(f[a], P.w[a]);
+    bspline_dw(f[a], P.dw[a]);
+  }
+  float tau[9];
+  const float J = neo_hookean_tau(F, s.c_mu * E, s.c_la * E, tau);
+  float chk = v[0] + v[1] + v[2];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    P.tk[i] = s.pic_force * tau[i];
+    chk += P.tk[i] + C[i];
+  }
+  if (!isfinite(chk)) {
+    cnt.nf++;
+    return;
+  }
+  if (!(J > 0.0f)) cnt.inv++;
+  // |grad N dx| <= 9/16 per component, so |m v| + sum_b |tk[a][b]| bounds
+  // every contribution.
+  float bound = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.mv[a] = s.mass * v[a];
+    bound = fmaxf(bound, fabsf(P.mv[a]) + fabsf(P.tk[3 * a]) + fabsf(P.tk[3 * a + 1]) + fabsf(P.tk[3 * a + 2]));
+  }
+  if (!(bound < s.p_limit)) {
+    cnt.rng++;
+    return;
+  }
+  P.fx_p = s.fx_p;
+  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+}
+
+// G2P of one particle (Algorithm 1, third loop). APIC (MLS-MPM, PB-MPM):
+// v' = sum N v_I, C' = (4/dx^2) sum N v_I (x_I - x_p)^T. Standard MPM:
+// v' = sum N v_I and the velocity gradient L = sum v_I grad N^T in Cn.
+// Returns false if the stencil is outside the grid (the particle is then
+// left unchanged).
+template <int SOL>
 __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, const int* to,
                                              const Lds& L, const float4* vel, float* vn, float* Cn,
                                              Counters& cnt) {
@@ -322,23 +490,46 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
   float w[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]);
-  float S[3], T[9];  // T[a][b] = sum N v_a o_b
+  float S[3], T[9];
   const int l0 = base[0] - to[0], l1 = base[1] - to[1], l2 = base[2] - to[2];
   const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
                        ((unsigned)l2 <= (unsigned)(kSpan - 3));
-  if (in_tile) {
-    const int l = lds_index(l0, l1, l2);
-    g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
+  if constexpr (SOL == SOLVER_PIC) {
+    float dw[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) bspline_dw(f[a], dw[a]);
+    if (in_tile) {
+      const int l = lds_index(l0, l1, l2);
+      g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
+    } else {
+      cnt.fb++;
+      const int node_base = to[3] * s.n3;
+      g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) {
+        return vel[node_base + grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
+      }, S, T);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vn[a] = S[a];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Cn[3 * a + b] = s.inv_dx * T[3 * a + b];
+    }
   } else {
-    cnt.fb++;
-    g2p_global(s, base, w, vel, S, T, to[3]);
-  }
-  const float k = 4.0f * s.inv_dx;
+    // T[a][b] = sum N v_a o_b
+    if (in_tile) {
+      const int l = lds_index(l0, l1, l2);
+      g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
+    } else {
+      cnt.fb++;
+      g2p_global(s, base, w, vel, S, T, to[3]);
+    }
+    const float k = 4.0f * s.inv_dx;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    vn[a] = S[a];
+    for (int a = 0; a < 3; ++a) {
+      vn[a] = S[a];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) Cn[3 * a + b] = k * (T[3 * a + b] - S[a] * f[b]);
+      for (int b = 0; b < 3; ++b) Cn[3 * a + b] = k * (T[3 * a + b] - S[a] * f[b]);
+    }
   }
   return true;
 }
@@ -401,8 +592,20 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 }
 
 // ------------------------------------------------------------------ kernels
-// P2G from the materialised particle state (first substep after binning).
-template <bool FIXED>
+// Scatter of one particle by the solver's rule.
+template <bool FIXED, int SOL, int PASS>
+__device__ __forceinline__ void p2g_any(const SimK& s, const float* x, const float* v, const float* C,
+                                        const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
+                                        uint32_t* mark, uint32_t* ovf, Status* st, int parity, Counters& cnt) {
+  if constexpr (SOL == SOLVER_PIC)
+    p2g_particle_pic<FIXED>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+  else
+    p2g_particle<FIXED, SOL, PASS>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+}
+
+// P2G from the materialised particle state (first substep after binning; for
+// PB-MPM the first pass of a step).
+template <bool FIXED, int SOL>
 __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
@@ -434,8 +637,8 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
         C[i] = part[(FC + i) * cap + p];
         F[i] = part[(FF + i) * cap + p];
       }
-      p2g_particle<FIXED>(s, x, v, C, F, particle_E(s, part, cap, p), to, L, ACC_ARGS, mark, ovf, st, parity,
-                          cnt);
+      const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
+      p2g_any<FIXED, SOL, PB_FIRST>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
     }
     __syncthreads();
     tile_flush<FIXED>(s, to, L, ACC_ARGS);
@@ -445,7 +648,11 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
 }
 
 // Fused G2P (substep k-1) -> F, x update -> stress -> P2G (substep k).
-template <bool FIXED>
+// PB-MPM: PB_FIRST is the same fusion across a step boundary (the G2P of the
+// previous step's last iteration, its F and x update, then the first pass of
+// the new step); PB_ITER is G2P -> constraint -> P2G within a step, where x
+// and F do not change and nothing is written back.
+template <bool FIXED, int SOL, int PASS>
 __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int64_t cap,
                                                const uint32_t* __restrict__ blk_begin,
                                                const uint32_t* __restrict__ blk_end,
@@ -453,6 +660,7 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
                                                ACC_PARAMS, const float4* __restrict__ vel,
                                                uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
                                                const Clock* __restrict__ clk, SimK s) {
+  constexpr bool kIntegrate = !(SOL == SOLVER_PB && PASS == PB_ITER);
   const int parity = clk->parity;
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds L;
@@ -474,23 +682,27 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
 #pragma unroll
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
-      if (!g2p_particle(s, x, to, L, vel, vn, Cn, cnt)) continue;  // frozen (out of grid)
-      float Fn[9];
+      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, cnt)) continue;  // frozen (out of grid)
+      if constexpr (kIntegrate) {
+        float Fn[9];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b2 = 0; b2 < 3; ++b2)
-          Fn[3 * a + b2] = F[3 * a + b2] + s.dt * (Cn[3 * a] * F[b2] + Cn[3 * a + 1] * F[3 + b2] +
-                                                   Cn[3 * a + 2] * F[6 + b2]);
+          for (int b2 = 0; b2 < 3; ++b2)
+            Fn[3 * a + b2] = F[3 * a + b2] + s.dt * (Cn[3 * a] * F[b2] + Cn[3 * a + 1] * F[3 + b2] +
+                                                     Cn[3 * a + 2] * F[6 + b2]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        x[a] += s.dt * vn[a];
-        part[(FX + a) * cap + p] = x[a];
+        for (int a = 0; a < 3; ++a) {
+          x[a] += s.dt * vn[a];
+          part[(FX + a) * cap + p] = x[a];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
+        const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
+        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+      } else {
+        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
       }
-#pragma unroll
-      for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
-      p2g_particle<FIXED>(s, x, vn, Cn, Fn, particle_E(s, part, cap, p), to, L, ACC_ARGS, mark, ovf, st,
-                          parity, cnt);
     }
     __syncthreads();
     tile_flush<FIXED>(s, to, L, ACC_ARGS);
@@ -499,7 +711,9 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
   flush_counters(st, cnt);
 }
 
-// G2P that materialises the full state (x, v, C, F) in memory.
+// G2P that materialises the full state (x, v, C, F) in memory (the C slot
+// holds the velocity gradient for standard MPM).
+template <int SOL>
 __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
@@ -523,7 +737,7 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
 #pragma unroll
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
-      if (!g2p_particle(s, x, to, L, vel, vn, Cn, cnt)) continue;
+      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, cnt)) continue;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -545,44 +759,70 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
 }
 
 // ------------------------------------------------------------------ launchers
-template <bool FIXED>
+template <bool FIXED, int SOL>
 static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL(k_p2g<FIXED>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
+  hipLaunchKernelGGL((k_p2g<FIXED, SOL>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
                      b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
                      (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
 }
 
-template <bool FIXED>
+template <bool FIXED, int SOL, int PASS>
 static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL(k_g2p2g<FIXED>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
-                     b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
+  hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
+                     b.blk_begin, b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
                      (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
+}
+
+template <bool FIXED>
+static void launch_p2g_s(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+  if (s.solver == SOLVER_PIC)
+    launch_p2g_t<FIXED, SOLVER_PIC>(b, s, grid_wgs, st);
+  else if (s.solver == SOLVER_PB)
+    launch_p2g_t<FIXED, SOLVER_PB>(b, s, grid_wgs, st);
+  else
+    launch_p2g_t<FIXED, SOLVER_MLS>(b, s, grid_wgs, st);
+}
+
+template <bool FIXED>
+static void launch_g2p2g_s(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st, int pass) {
+  if (s.solver == SOLVER_PIC)
+    launch_g2p2g_t<FIXED, SOLVER_PIC, PB_FIRST>(b, s, grid_wgs, st);
+  else if (s.solver == SOLVER_PB && pass == PB_ITER)
+    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER>(b, s, grid_wgs, st);
+  else if (s.solver == SOLVER_PB)
+    launch_g2p2g_t<FIXED, SOLVER_PB, PB_FIRST>(b, s, grid_wgs, st);
+  else
+    launch_g2p2g_t<FIXED, SOLVER_MLS, PB_FIRST>(b, s, grid_wgs, st);
 }
 
 void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
   (void)N;
   if (s.fixed)
-    launch_p2g_t<true>(b, s, grid_wgs, st);
+    launch_p2g_s<true>(b, s, grid_wgs, st);
   else
-    launch_p2g_t<false>(b, s, grid_wgs, st);
+    launch_p2g_s<false>(b, s, grid_wgs, st);
 }
 
-void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st, int pass) {
   (void)N;
   if (s.fixed)
-    launch_g2p2g_t<true>(b, s, grid_wgs, st);
+    launch_g2p2g_s<true>(b, s, grid_wgs, st, pass);
   else
-    launch_g2p2g_t<false>(b, s, grid_wgs, st);
+    launch_g2p2g_s<false>(b, s, grid_wgs, st, pass);
 }
 
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
   (void)N;
-  hipLaunchKernelGGL(k_g2p, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
-                     b.blk_end, b.occ_list, b.status, b.vel, s);
+  if (s.solver == SOLVER_PIC)
+    hipLaunchKernelGGL(k_g2p<SOLVER_PIC>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
+                       b.blk_end, b.occ_list, b.status, b.vel, s);
+  else
+    hipLaunchKernelGGL(k_g2p<SOLVER_MLS>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
+                       b.blk_end, b.occ_list, b.status, b.vel, s);
 }
 
 }  // namespace mpm

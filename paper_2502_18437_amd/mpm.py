@@ -25,6 +25,7 @@ MPM_ACCUM_F32, MPM_ACCUM_FIXED = 0, 1
 MPM_TOOL_NONE, MPM_TOOL_CAPSULE, MPM_TOOL_BOX, MPM_TOOL_PLANE = 0, 1, 2, 3
 MPM_TOOL_SLICER, MPM_TOOL_SEGMENT, MPM_TOOL_ARC = 4, 5, 6
 MPM_MAX_TOOLS = 8
+MPM_SOLVER_MLS, MPM_SOLVER_PIC, MPM_SOLVER_PB = 0, 1, 2
 MPM_KERNEL_KINDS = 5
 KERNEL_NAMES = ("binning", "p2g", "g2p2g", "g2p", "grid")
 
@@ -36,7 +37,7 @@ EXPORTED = ("mpm_create", "mpm_destroy", "mpm_set_particles", "mpm_set_tool_sdf"
             "mpm_profile_read", "mpm_read_tool_impulses", "mpm_set_tool_velocity_table", "mpm_rollout_forward",
             "mpm_rollout_backward", "mpm_create_batch", "mpm_set_batch_particles", "mpm_set_scene_tool",
             "mpm_set_scene_tool_velocity_table", "mpm_read_scene_tool_impulses", "mpm_get_launch_config",
-            "mpm_set_launch_config", "mpm_autotune")
+            "mpm_set_launch_config", "mpm_autotune", "mpm_set_solver", "mpm_get_solver")
 
 
 class mpm_params(ctypes.Structure):
@@ -103,6 +104,9 @@ _lib.mpm_read_scene_tool_impulses.argtypes = [_h, ctypes.c_int32, ctypes.POINTER
 _lib.mpm_get_launch_config.argtypes = [_h, ctypes.POINTER(mpm_launch_config)]
 _lib.mpm_set_launch_config.argtypes = [_h, ctypes.POINTER(mpm_launch_config)]
 _lib.mpm_autotune.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(mpm_launch_config)]
+_lib.mpm_set_solver.argtypes = [_h, ctypes.c_int32, ctypes.c_int32, ctypes.c_float]
+_lib.mpm_get_solver.argtypes = [_h, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_float)]
 _lib.mpm_rollout_backward.argtypes = [_h, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp,
                                       _vp]
 
@@ -338,6 +342,17 @@ class Simulation:
             r[k] = a
         return r
 
+    def set_solver(self, solver, iterations=10, beta=0.5):
+        """MPM_SOLVER_MLS (default), MPM_SOLVER_PIC (standard MPM, Neo-Hookean)
+        or MPM_SOLVER_PB (PB-MPM with `iterations` passes per step and the
+        co-rotational constraint weight `beta`)."""
+        self._check(_lib.mpm_set_solver(self.h, int(solver), int(iterations), float(beta)))
+
+    def solver(self):
+        k, it, beta = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        self._check(_lib.mpm_get_solver(self.h, ctypes.byref(k), ctypes.byref(it), ctypes.byref(beta)))
+        return {"solver": k.value, "iterations": it.value, "beta": beta.value}
+
     def launch_config(self):
         c = mpm_launch_config()
         self._check(_lib.mpm_get_launch_config(self.h, ctypes.byref(c)))
@@ -397,6 +412,8 @@ def simulation_from_scene(scene, **kw):
         sim.set_tool(k, t.type, **t.kwargs())
     for k, tab in scene.vel_tables.items():
         sim.set_tool_velocity_table(k, tab)
+    if scene.solver is not None:
+        sim.set_solver(*scene.solver)
     return sim
 
 

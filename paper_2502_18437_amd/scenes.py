@@ -23,6 +23,13 @@ its one measured workload is a falling cube on a fixed 56^3 grid
   capsule tool, dt = 1e-4, 200 substeps (differentiable-rollout shape).
 * ``cube`` the paper's performance scene: falling cube, 56^3 grid,
   dt = 2e-3, 10 substeps per frame, ``n_particles`` chosen by the caller.
+* ``cube_pb`` the same cube for PB-MPM: one dt = 0.02 step per frame with
+  10 (or 20) constraint iterations.
+* ``pb_drop`` PB-MPM contact case: a 16^3 cube thrown at the sticky floor
+  under a pressing capsule, 32^3 grid, dt = 5e-3, 20 steps of 10 passes.
+
+A scene's ``solver`` is None (MLS-MPM) or (kind, iterations, beta) with kind
+0 MLS-MPM, 1 standard MPM, 2 PB-MPM.
 
 Every scene: domain [0, 1)^3, dx = 1/n, rho = 1e3, gravity (0, -9.8, 0),
 sticky walls 3 nodes thick, v0 = 0, C0 = 0, F0 = I unless stated,
@@ -79,6 +86,7 @@ class Scene:
     wall_band: int = WALL_BAND
     theta: np.ndarray = None           # (N,) float32 log E, differentiable scenes
     vel_tables: dict = field(default_factory=dict)  # tool id -> (T, 3) float64 per-substep velocities
+    solver: tuple = None               # (kind, iterations, beta); None: MLS-MPM
 
     @property
     def N(self):
@@ -256,6 +264,43 @@ def scene_cube(n_particles=1 << 16, seed=7, n_grid=56):
     return Scene("cube", n_grid, 2e-3, 10, 0.3, 5e3, RHO * vol0, vol0, pts)
 
 
+SOLVER_MLS, SOLVER_PIC, SOLVER_PB = 0, 1, 2
+
+
+def scene_cube_pb(n_particles=1 << 12, seed=7, n_grid=56, iterations=10, beta=0.5):
+    """The performance cube as the paper runs PB-MPM on it: one step of
+    dt = 0.02 per frame with `iterations` passes (Sec. III-D)."""
+    s = scene_cube(n_particles, seed, n_grid)
+    s.name = f"cube_pb{iterations}"
+    s.dt = 0.02
+    s.n_substeps = 1
+    s.solver = (SOLVER_PB, iterations, beta)
+    return s
+
+
+def scene_pb_drop(seed=8, n_grid=32, per_axis=16, n_substeps=20, iterations=10, beta=0.5):
+    """A PB-MPM contact case: a 16^3 cube (dx/2 spacing) thrown at the
+    floor at 1.5 m/s from 1.5 dx above the wall band while a capsule presses
+    its top, dt = 5e-3 per step; E = 5e3, nu = 0.3."""
+    dx = 1.0 / n_grid
+    spacing = 0.5 * dx
+    side = per_axis * spacing
+    rng = np.random.default_rng(seed)
+    lo = (0.5 - side / 2, (WALL_BAND + 1.5) * dx, 0.5 - side / 2)
+    pts = lattice(lo, (per_axis,) * 3, (spacing,) * 3)
+    pts = (pts + jitter(rng, pts.shape[0], dx)).astype(np.float32)
+    N = pts.shape[0]
+    vol0 = spacing ** 3
+    s = Scene("pb_drop", n_grid, 5e-3, n_substeps, 0.3, 5e3, RHO * vol0, vol0, pts)
+    s.v = np.tile(np.float32([0.2, -1.5, 0.0]), (N, 1))
+    top = lo[1] + side
+    # capsule along z over the cube's top face, off the node lattice
+    s.tools = [Tool(TOOL_CAPSULE, (0.5 + 0.31 * dx, top + 2.2 * dx, 0.5 + 0.17 * dx), (SQRT_HALF, 0.0, SQRT_HALF, 0.0),
+                    (0.15, 2.0 * dx, 0.0), (0.0, -2.5, 0.0), mu=0.3)]
+    s.solver = (SOLVER_PB, iterations, beta)
+    return s
+
+
 def tiny_block(n_grid=16, per_axis=6, seed=11, spacing_dx=0.5, center=(0.5, 0.5, 0.5),
                gravity=GRAVITY, with_state=True, E_range=None):
     """A small random block of particles for unit tests (<= a few hundred)."""
@@ -369,6 +414,7 @@ def batch_c4s(seed=4):
 SCENES = {
     "c1": scene_c1, "c1s": scene_c1s, "c2": scene_c2, "c2s": scene_c2s, "c3": scene_c3,
     "c3s": scene_c3s, "c3m": scene_c3m, "c5": scene_c5, "c5s": scene_c5s, "cube": scene_cube,
+    "cube_pb": scene_cube_pb, "pb_drop": scene_pb_drop,
 }
 
 

@@ -32,6 +32,8 @@ def run_oracle(scene, n_substeps, idx=None):
         o.set_tool(k, t.type, **t.kwargs())
     for k, tab in scene.vel_tables.items():
         o.set_velocity_table(k, tab)
+    if scene.solver is not None:
+        o.set_solver(*scene.solver)
     st = o.step(n_substeps)
     r = o.read()
     r["status"] = st

@@ -84,7 +84,8 @@ def test_status_codes_match_header():
     text = open(HEADER).read()
     for name in ("MPM_OK", "MPM_EINVAL", "MPM_ENOMEM", "MPM_EHIP", "MPM_EDOMAIN", "MPM_ENONFINITE",
                  "MPM_EINVERTED", "MPM_ERANGE", "MPM_HOST", "MPM_DEVICE", "MPM_TOOL_CAPSULE", "MPM_TOOL_BOX",
-                 "MPM_TOOL_PLANE", "MPM_ACCUM_FIXED", "MPM_KERNEL_KINDS", "MPM_MAX_TOOLS"):
+                 "MPM_TOOL_PLANE", "MPM_ACCUM_FIXED", "MPM_KERNEL_KINDS", "MPM_MAX_TOOLS", "MPM_SOLVER_MLS",
+                 "MPM_SOLVER_PIC", "MPM_SOLVER_PB"):
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, text)
         assert m, name
         assert getattr(mpm, name) == int(m.group(1)), name
@@ -103,3 +104,5 @@ def test_null_handle_calls_are_rejected_without_a_gpu():
     assert mpm._lib.mpm_rollout_backward(None, *([None] * 10)) == mpm.MPM_EINVAL
     assert mpm._lib.mpm_set_launch_config(None, None) == mpm.MPM_EINVAL
     assert mpm._lib.mpm_autotune(None, 1, None) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_set_solver(None, mpm.MPM_SOLVER_PB, 10, 0.5) == mpm.MPM_EINVAL
+    assert mpm._lib.mpm_get_solver(None, None, None, None) == mpm.MPM_EINVAL
