@@ -29,6 +29,11 @@ Also reported on the same JSON line:
   together by one mpm_step(200) per step, as aggregate particle-substeps/s.
   It is off by default so that the fused kernel's launches in a profile of
   the default command all belong to the headline workload.
+* solver_sweep (with --solver-sweep): the paper's solver comparison shape
+  (Sec. III-D): a cube falling on a fixed 56^3 grid, N = 2^14 .. 2^21
+  particles, one frame = 0.02 s: MLS-MPM and standard MPM take 10 substeps
+  of 2e-3, PB-MPM one step of 0.02 with 10 or 20 constraint passes; ms per
+  frame over the first frames of the fall.
 """
 import argparse
 import json
@@ -132,6 +137,53 @@ def batch_throughput(steps, warmup=1):
                                  "frac": model / per_substep / 1e9 / HBM_PEAK_GBS}}
 
 
+SWEEP_SIZES = (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21)
+
+
+def solver_sweep(frames=4, lead_frames=5, sizes=SWEEP_SIZES):
+    """ms per 0.02 s frame of the falling cube for each solver and size,
+    timed over `frames` frames after lead_frames + 1 untimed ones (the cube
+    is then falling at about 1.2 m/s and reaches the floor after the timed
+    frames). The launch configuration is the library autotuner's choice from
+    that state. The largest size keeps the densest cells below 256 particles
+    (the capacity of the 32-bit weight sums of the P2G tile)."""
+    import torch
+    from paper_2502_18437_amd import mpm, scenes
+    dev = torch.device("cuda", 0)
+    runs = (("mls", mpm.MPM_SOLVER_MLS, 1, 10, 2e-3), ("standard_pic", mpm.MPM_SOLVER_PIC, 1, 10, 2e-3),
+            ("pb10", mpm.MPM_SOLVER_PB, 10, 1, 2e-2), ("pb20", mpm.MPM_SOLVER_PB, 20, 1, 2e-2))
+    out = []
+    for n in sizes:
+        s = scenes.scene_cube(n)
+        x_d = torch.from_numpy(s.x).to(dev)
+        for label, kind, iters, sub, dt in runs:
+            sim = mpm.Simulation(s.n_grid, dt, gravity=s.gravity, wall_band=s.wall_band, nu=s.nu,
+                                 E_default=s.E_default, max_particles=s.N)
+            sim.set_particles(x_d, None, None, None, None, s.mass, s.vol0)
+            sim.set_solver(kind, iters, 0.5)
+            for _ in range(lead_frames):
+                sim.step(sub)
+            # trials long enough for the re-binning interval to matter
+            cfg = sim.autotune(trial_substeps=8 if kind == mpm.MPM_SOLVER_PB else 2 * sub)
+            sim.step(sub)  # one more untimed frame: graphs recorded with the chosen configuration
+            sim.read_state(out={})
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(frames):
+                sim.step(sub)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            _, st = sim.read_state(out={}, allow_errors=True)
+            sim.close()
+            passes = sub * iters
+            out.append({"particles": s.N, "solver": label, "substeps_per_frame": sub, "dt": dt, "launch_config": cfg,
+                        "grid_updates_per_frame": passes, "ms_per_frame": 1e3 * el / frames,
+                        "particle_passes_per_s": s.N * passes * frames / el, "status": int(st)})
+            log(f"[bench] sweep N={s.N} {label}: {1e3 * el / frames:.3f} ms/frame {cfg}")
+    return {"workload": f"falling cube (side 0.4) on a 56^3 grid, frames of 0.02 s; frames {lead_frames + 2}.."
+                        f"{lead_frames + 1 + frames} timed", "frames": frames, "runs": out}
+
+
 def fwd_bwd(steps, checkpoint_every=20):
     """Time the differentiable rollout of the press scene: forward with
     checkpoints, then the reverse pass, each bracketed by device syncs."""
@@ -202,6 +254,8 @@ def main():
     ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd measurement")
     ap.add_argument("--batch", action="store_true", help="also measure the 256-scene batch")
     ap.add_argument("--diff-steps", type=int, default=3)
+    ap.add_argument("--solver-sweep", action="store_true",
+                    help="also time the three solvers on the falling cube (paper's solver comparison shape)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of MIB MiB (a kernel of known "
                          "traffic that scales hardware byte counters)")
@@ -307,6 +361,8 @@ def main():
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
     if args.batch:
         out["batch"] = batch_throughput(args.diff_steps)
+    if args.solver_sweep:
+        out["solver_sweep"] = solver_sweep()
     if not args.no_diff:
         out["fwd_bwd"] = fwd_bwd(args.diff_steps, checkpoint_every=20)
         out["fwd_bwd_keep_all"] = fwd_bwd(args.diff_steps, checkpoint_every=1)

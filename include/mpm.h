@@ -261,12 +261,13 @@ int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out);
 int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
 
 /* Autotuner: times mpm_step(trial_substeps) on the current scene for each
- * candidate configuration (re-binning every 8, 16, 32 or 64 substeps; 1 to 4
- * transfer workgroups per compute unit; graphs on or off), restoring the
- * particles, their order, the device status and the clock before every
- * trial, and keeps the fastest (written to *chosen if not NULL). The scene
- * is left as it was, except that the next mpm_step re-bins and the tool
- * impulses read zero. Blocking; 64 timed calls.
+ * candidate configuration (re-binning every 1, 2, 4, 8, 16, 32 or 64
+ * substeps; 1 to 4 transfer workgroups per compute unit; graphs on or off),
+ * restoring the particles, their order, the device status and the clock
+ * before every trial, and keeps the fastest (written to *chosen if not
+ * NULL). The scene is left as it was, except that the next mpm_step re-bins
+ * and the tool impulses read zero. Blocking; 112 calls of mpm_step (one
+ * untimed and one timed per candidate).
  * Errors: MPM_EINVAL (no particles, trial_substeps < 1), MPM_ENOMEM (it
  * needs a copy of the particle buffer), MPM_EHIP. */
 int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chosen);

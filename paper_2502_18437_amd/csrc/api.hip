@@ -278,9 +278,24 @@ void drop_graphs(mpm_handle* h) {
     }
 }
 
+// Particles per transfer work item: about N / (4 x workgroups), so that
+// even a scene of a few dense blocks gives every persistent workgroup several
+// items, as a power of two in [kItemMin, kItemMax]. A change re-bins and
+// drops the recorded graphs.
+void choose_item_size(mpm_handle* h) {
+  const int64_t target = h->N / (4 * (int64_t)h->transfer_wgs);
+  unsigned item = kItemMin;
+  while (item < (unsigned)kItemMax && (int64_t)item * 2 <= target) item *= 2;
+  if (item != h->sim.item_particles) {
+    h->sim.item_particles = item;
+    h->dirty = true;
+    drop_graphs(h);
+  }
+}
+
 void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
-                  b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.act_list, b.mark,
+                  b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.work, b.act_list, b.mark,
                   b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.imp_blocks, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
                   b.status, b.scene_off, b.tools, b.clock};
   for (void* p : ptrs)
@@ -303,6 +318,7 @@ __global__ void k_reset_status(Status* st) {
   st->n_fallback = 0ull;
   st->n_range = 0ull;
   st->n_occ = 0u;
+  st->n_work = 0u;
   st->n_act = 0u;
   st->ovf_count[0] = 0u;
   st->ovf_count[1] = 0u;
@@ -512,6 +528,8 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   alloc((void**)&b.blk_end, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.flags, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.occ_list, sizeof(uint32_t) * h->n_blocks);
+  // at most one partial item per occupied block plus one per kItemMin particles
+  alloc((void**)&b.work, sizeof(uint2) * ((size_t)h->n_blocks + (size_t)(cap / kItemMin) + 1));
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.node_cnt, sizeof(uint32_t) * h->n_blocks);
@@ -552,6 +570,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   s.n3 = (int)(nb3 * kBlockNodes);
   s.solver = SOLVER_MLS;
   s.pb_beta = 0.5f;
+  s.item_particles = kItemMax;
   launch_clear_impulses(b, s, h->stream);
   e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) e = hipGetLastError();
@@ -682,6 +701,7 @@ int set_particles_impl(mpm_handle* h, const int64_t* counts, const float* x, con
   h->dirty = true;
   h->d.valid = false;
   drop_graphs(h);  // the recorded launches hold the old scene constants
+  choose_item_size(h);
   h->err.clear();
   return MPM_OK;
 }
@@ -1010,6 +1030,7 @@ int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c) {
   if (c->transfer_wgs != h->transfer_wgs || c->graph_chunk != h->graph_chunk) drop_graphs(h);
   h->transfer_wgs = c->transfer_wgs;
   h->graph_chunk = c->graph_chunk;
+  choose_item_size(h);  // the work list is rebuilt before the next transfer if the item size changed
   return MPM_OK;
 }
 
@@ -1063,13 +1084,16 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   h->prof = false;
   // Candidates: re-binning interval, persistent workgroups per CU, graph
   // replay on or off.
-  const int resorts[] = {8, 16, 32, 64};
+  // Fast-moving scenes leave their tiles within a few substeps (the global
+  // path then takes the scatter), so the short intervals are candidates too.
+  const int resorts[] = {1, 2, 4, 8, 16, 32, 64};
+  const int n_resorts = (int)(sizeof(resorts) / sizeof(resorts[0]));
   const int per_cu[] = {1, 2, 3, 4};
   const int chunks[] = {0, kDefaultGraphChunk};
   mpm_launch_config best = orig;
   float best_ms = 0.0f;
   bool have = false;
-  for (int ri = 0; ri < 4 && e == hipSuccess && rc == MPM_OK; ++ri)
+  for (int ri = 0; ri < n_resorts && e == hipSuccess && rc == MPM_OK; ++ri)
     for (int wi = 0; wi < 4 && e == hipSuccess && rc == MPM_OK; ++wi)
       for (int ci = 0; ci < 2 && e == hipSuccess && rc == MPM_OK; ++ci) {
         mpm_launch_config c = {resorts[ri], (per_cu[wi] * h->cus + 7) / 8 * 8, chunks[ci]};

@@ -2,10 +2,11 @@
 // method; it orders the work so that each grid block's particles are
 // contiguous): key = grid block of the particle's base cell, a stable LSD
 // radix sort of (key, index) with 8-bit digits, a gather of the particle SoA
-// into key order, per-block [begin, end) ranges, the list of occupied blocks
-// and the list of active blocks (each occupied block with the neighbours its
-// tile reaches). Also the host<->SoA marshalling
-// kernels and the diagnostic stress kernel.
+// into key order, per-block [begin, end) ranges, the list of occupied blocks,
+// the transfer work items (runs of at most s.item_particles particles of one
+// block) and the list of active blocks (each occupied block with the
+// neighbours its tile reaches). Also the host<->SoA marshalling kernels and
+// the diagnostic stress kernel.
 //
 // Every buffer is cleared with fill kernels (no memset nodes), so the whole
 // pipeline can be captured in a HIP graph.
@@ -292,6 +293,24 @@ __global__ void k_flag_marked(const uint32_t* __restrict__ mark, uint32_t n_bloc
     flags[b] = mark[b] == 1u ? 1u : 0u;
 }
 
+// Work items of each block (one per `item` particles or part of it).
+__global__ void k_item_counts(const uint32_t* __restrict__ begin, const uint32_t* __restrict__ end,
+                              uint32_t n_blocks, uint32_t item, uint32_t* __restrict__ counts) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x)
+    counts[b] = end[b] > begin[b] ? (end[b] - begin[b] + item - 1) / item : 0u;
+}
+
+// work[off[b] + j] = {b, begin[b] + j item}.
+__global__ void k_emit_items(const uint32_t* __restrict__ begin, const uint32_t* __restrict__ end,
+                             const uint32_t* __restrict__ off, uint32_t n_blocks, uint32_t item,
+                             uint2* __restrict__ work) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x) {
+    if (!(end[b] > begin[b])) continue;
+    uint32_t o = off[b];
+    for (uint32_t p = begin[b]; p < end[b]; p += item) work[o++] = make_uint2(b, p);
+  }
+}
+
 // list[pos[b]] = b for flagged blocks; flags and pos may not alias.
 __global__ void k_compact(const uint32_t* __restrict__ mark_or_range_b,
                           const uint32_t* __restrict__ range_e, const uint32_t* __restrict__ pos,
@@ -349,6 +368,12 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStrea
   exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_occ, st);
   hipLaunchKernelGGL(k_compact, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
                      b.flags, n_blocks, 0, b.occ_list);
+  // 5b. transfer work items (ascending block id, then particle runs)
+  hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     n_blocks, s.item_particles, b.flags);
+  exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_work, st);
+  hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     b.flags, n_blocks, s.item_particles, b.work);
   // 6. active list: occupied blocks dilated by one block
   fill_u32(b.mark, n_blocks, 0u, st);
   hipLaunchKernelGGL(k_mark_dilated, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,

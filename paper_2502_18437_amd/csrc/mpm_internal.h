@@ -25,6 +25,13 @@ constexpr int kMaxTools = 8;
 constexpr int kImpulseRows = kMaxTools + 1;  // tools, then the walls
 constexpr int kGridSlots = 8192;             // largest grid-update launch
 constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA
+// A transfer work item is one block's particles or, for a block holding more
+// than SimK::item_particles, a run of that many of them: dense blocks are
+// shared by several workgroups (each with its own LDS tile) instead of
+// serialising on one. The run length is a power of two in
+// [kItemMin, kItemMax] chosen from the particle and workgroup counts.
+constexpr int kItemMin = 512;
+constexpr int kItemMax = 2048;
 
 // Field offsets in the particle SoA (each field is `cap` floats).
 enum Field { FX = 0, FV = 3, FC = 6, FF = 15, FE = 24 };
@@ -92,6 +99,7 @@ struct SimK {
   int solver;        // Solver: which transfer scheme and constitutive model the kernels run
   float pic_force;   // standard MPM: dt * vol0 / dx (internal force per unit of tau grad N dx)
   float pb_beta;     // PB-MPM: rotation weight of the co-rotational constraint
+  unsigned item_particles;  // particles per transfer work item (at most)
 };
 
 // Solvers of Sec. III: MLS-MPM (APIC transfers, fixed-corotated stress in the
@@ -112,6 +120,7 @@ struct Status {
   unsigned long long n_fallback;
   unsigned long long n_range;      // P2G contributions outside the fixed-point range
   unsigned int n_occ;               // occupied blocks (this binning)
+  unsigned int n_work;              // transfer work items (this binning)
   unsigned int n_act;               // active blocks (this binning)
   unsigned int ovf_count[2];        // overflow blocks claimed, per parity
 };
@@ -141,6 +150,7 @@ struct Buffers {
   uint32_t* blk_end = nullptr;
   uint32_t* flags = nullptr;                // per block scratch for compaction
   uint32_t* occ_list = nullptr;             // occupied blocks
+  uint2* work = nullptr;                    // transfer work items {block, first particle}
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
   uint32_t* node_cnt = nullptr;             // per block: nodes with mass, last grid update

@@ -2,8 +2,9 @@
 // Sec. III-B, Algorithm 1), block-tiled for CDNA4.
 //
 // Particles are binned by the grid block (kTile^3 cells) of their base cell.
-// One workgroup owns one block at a time: it stages the grid velocities of the
-// block's tile (kSpan^3 nodes: the block's stencils plus kSlack cells of
+// One workgroup owns one work item at a time (a block's particles, or a run of
+// s.item_particles of them when the block is dense): it stages the grid
+// velocities of the block's tile (kSpan^3 nodes: the block's stencils plus kSlack cells of
 // drift) in LDS, gathers (G2P) from LDS, scatters (P2G) into an LDS
 // accumulator tile with integer LDS atomics, then flushes the non-empty tile
 // nodes into the global accumulator (FP32 or integer atomics, one per value).
@@ -607,9 +608,8 @@ __device__ __forceinline__ void p2g_any(const SimK& s, const float* x, const flo
 // PB-MPM the first pass of a step).
 template <bool FIXED, int SOL>
 __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, int64_t cap,
-                                             const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
-                                             const uint32_t* __restrict__ occ_list, Status* st,
+                                             const uint2* __restrict__ work, Status* st,
                                              ACC_PARAMS, uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
                                              const Clock* __restrict__ clk, SimK s) {
   const int parity = clk->parity;
@@ -617,15 +617,16 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
   __shared__ Lds L;
   Counters cnt;
   unsigned pos, end, stride;
-  xcd_walk(st->n_occ, &pos, &end, &stride);
+  xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
-    const unsigned b = occ_list[pos];
+    const uint2 item = work[pos];
+    const unsigned b = item.x;
     int to[4];
     block_origin(s, b, to);
     tile_clear(L);
     __syncthreads();
-    const unsigned pe = blk_end[b];
-    for (unsigned p = blk_begin[b] + threadIdx.x; p < pe; p += kWG) {
+    const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
+    for (unsigned p = item.y + threadIdx.x; p < pe; p += kWG) {
       float x[3], v[3], C[9], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -654,9 +655,8 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
 // and F do not change and nothing is written back.
 template <bool FIXED, int SOL, int PASS>
 __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int64_t cap,
-                                               const uint32_t* __restrict__ blk_begin,
                                                const uint32_t* __restrict__ blk_end,
-                                               const uint32_t* __restrict__ occ_list, Status* st,
+                                               const uint2* __restrict__ work, Status* st,
                                                ACC_PARAMS, const float4* __restrict__ vel,
                                                uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
                                                const Clock* __restrict__ clk, SimK s) {
@@ -666,16 +666,17 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
   __shared__ Lds L;
   Counters cnt;
   unsigned pos, end, stride;
-  xcd_walk(st->n_occ, &pos, &end, &stride);
+  xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
-    const unsigned b = occ_list[pos];
+    const uint2 item = work[pos];
+    const unsigned b = item.x;
     int to[4];
     block_origin(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     tile_clear(L);
     __syncthreads();
-    const unsigned pe = blk_end[b];
-    for (unsigned p = blk_begin[b] + threadIdx.x; p < pe; p += kWG) {
+    const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
+    for (unsigned p = item.y + threadIdx.x; p < pe; p += kWG) {
       float x[3], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = part[(FX + a) * cap + p];
@@ -715,22 +716,22 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
 // holds the velocity gradient for standard MPM).
 template <int SOL>
 __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_t cap,
-                                             const uint32_t* __restrict__ blk_begin,
                                              const uint32_t* __restrict__ blk_end,
-                                             const uint32_t* __restrict__ occ_list, Status* st,
+                                             const uint2* __restrict__ work, Status* st,
                                              const float4* __restrict__ vel, SimK s) {
   __shared__ Lds L;
   Counters cnt;
   unsigned pos, end, stride;
-  xcd_walk(st->n_occ, &pos, &end, &stride);
+  xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
-    const unsigned b = occ_list[pos];
+    const uint2 item = work[pos];
+    const unsigned b = item.x;
     int to[4];
     block_origin(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     __syncthreads();
-    const unsigned pe = blk_end[b];
-    for (unsigned p = blk_begin[b] + threadIdx.x; p < pe; p += kWG) {
+    const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
+    for (unsigned p = item.y + threadIdx.x; p < pe; p += kWG) {
       float x[3], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = part[(FX + a) * cap + p];
@@ -763,8 +764,8 @@ template <bool FIXED, int SOL>
 static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL((k_p2g<FIXED, SOL>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
-                     b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
+  hipLaunchKernelGGL((k_p2g<FIXED, SOL>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
+                     b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
                      (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
 }
 
@@ -773,7 +774,7 @@ static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t 
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
   hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
-                     b.blk_begin, b.blk_end, b.occ_list, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
+                     b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
                      (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
 }
 
@@ -818,11 +819,11 @@ void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
   (void)N;
   if (s.solver == SOLVER_PIC)
-    hipLaunchKernelGGL(k_g2p<SOLVER_PIC>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
-                       b.blk_end, b.occ_list, b.status, b.vel, s);
+    hipLaunchKernelGGL(k_g2p<SOLVER_PIC>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
+                       b.blk_end, b.work, b.status, b.vel, s);
   else
-    hipLaunchKernelGGL(k_g2p<SOLVER_MLS>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_begin,
-                       b.blk_end, b.occ_list, b.status, b.vel, s);
+    hipLaunchKernelGGL(k_g2p<SOLVER_MLS>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
+                       b.blk_end, b.work, b.status, b.vel, s);
 }
 
 }  // namespace mpm
