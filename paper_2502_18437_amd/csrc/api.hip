@@ -55,6 +55,7 @@ struct DiffBufs {
   float4* grids = nullptr;  // per substep: velocity after the grid update, then pre-contact velocity and mass
   int64_t grid_slots = 0;
   bool grids_kept = false;  // the forward kept the grid of every substep (checkpoint_every == 1)
+  uint32_t* order_info = nullptr;  // device: {work items, first position outside the grid} of the current order
   bool valid = false;     // a rollout is recorded and nothing it depends on changed
   int T = 0, K = 1;
   int64_t start = 0;      // substep counter when the rollout began
@@ -305,7 +306,7 @@ void free_buffers(Buffers& b) {
 
 void free_diff(DiffBufs& d) {
   void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb,
-                  d.g.skip, d.E, d.work, d.adj, d.ckpt, d.seg, d.tool_red, d.grids};
+                  d.g.skip, d.E, d.work, d.adj, d.ckpt, d.seg, d.tool_red, d.grids, d.order_info};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DiffBufs();
@@ -416,6 +417,10 @@ hipError_t diff_alloc_base(mpm_handle* h) {
     if ((e = hipMalloc((void**)&d.adj, sizeof(float) * kStateFloats * N)) != hipSuccess) return e;
     d.part_cap = N;
   }
+  if (!d.order_info) {
+    hipError_t e = hipMalloc((void**)&d.order_info, sizeof(uint32_t) * 2);
+    if (e != hipSuccess) return e;
+  }
   // Accumulators the kernels expect to find cleared.
   for (int a = 0; a < 3; ++a) {
     launch_fill_f32(d.g.p[a], nn, 0.0f, h->stream);
@@ -423,6 +428,17 @@ hipError_t diff_alloc_base(mpm_handle* h) {
   }
   launch_fill_f32(d.g.m, nn, 0.0f, h->stream);
   return hipGetLastError();
+}
+
+// Substeps that share one particle order in a rollout: a multiple of the
+// checkpoint interval (so that the state an order is taken from is a
+// checkpoint in the reverse pass too) near 16.
+int order_period(int K) { return K * std::max(1, 16 / K); }
+
+// Spatial order of the rollout state `x` (caller order) for the scatters.
+DiffOrder rollout_order(mpm_handle* h, const float* x) {
+  const uint32_t* o = launch_order(h->b, h->N, h->sim, x, h->key_bits, kItemRollout, h->d.order_info, h->stream);
+  return DiffOrder{o, h->b.blk_end, h->b.work, h->d.order_info};
 }
 
 }  // namespace
@@ -528,8 +544,9 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   alloc((void**)&b.blk_end, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.flags, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.occ_list, sizeof(uint32_t) * h->n_blocks);
-  // at most one partial item per occupied block plus one per kItemMin particles
-  alloc((void**)&b.work, sizeof(uint2) * ((size_t)h->n_blocks + (size_t)(cap / kItemMin) + 1));
+  // at most one partial item per occupied block plus one per kItemRollout
+  // (<= kItemMin) particles
+  alloc((void**)&b.work, sizeof(uint2) * ((size_t)h->n_blocks + (size_t)(cap / kItemRollout) + 1));
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.node_cnt, sizeof(uint32_t) * h->n_blocks);
@@ -1167,11 +1184,17 @@ int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_ev
   DState s0 = slot(0);
   launch_unpermute(h->b, N, s0.x, s0.v, s0.C, s0.F, h->stream);
   launch_clear_impulses(h->b, h->sim, h->stream);
+  // The binning scratch of the handle holds the rollout's particle orders;
+  // mpm_step re-bins afterwards.
+  h->dirty = true;
+  const int R = order_period(K);
+  DiffOrder ord{};
   for (int k = 0; k < T; ++k) {
+    if (k % R == 0) ord = rollout_order(h, slot(k).x);
     float4* vel = d.grids_kept ? d.grids + (int64_t)k * 2 * nn : d.g.vel;
     float4* hat = d.grids_kept ? vel + nn : nullptr;
     launch_diff_substep(d.g, vel, hat, h->sim, tools_at(h, h->substep), N, slot(k), d.E, slot(k + 1), true,
-                        h->b.status, h->stream);
+                        h->b.status, ord, h->stream);
     h->substep++;
   }
   DState sT = slot(T);
@@ -1206,7 +1229,11 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
     ALLOC_OR_RETURN(h, ensure(&d.seg, &d.seg_slots, (int64_t)K, sizeof(float) * SF));
     ALLOC_OR_RETURN(h, ensure(&d.grids, &d.grid_slots, (int64_t)K, sizeof(float4) * 2 * nn));
   }
-  ALLOC_OR_RETURN(h, ensure(&d.tool_red, &d.tool_red_n, (int64_t)(T > 0 ? T : 1) * kMaxTools * 6));
+  // per substep: kToolRedCopies partial sums, then (after them, for all
+  // substeps) the totals
+  const int64_t red_row = (int64_t)kMaxTools * 6;
+  ALLOC_OR_RETURN(h, ensure(&d.tool_red, &d.tool_red_n, (int64_t)(T > 0 ? T : 1) * red_row * (kToolRedCopies + 1)));
+  double* tool_tot = d.tool_red + (int64_t)T * red_row * kToolRedCopies;
   DState adj = dstate(d.adj, N);
   const float* seeds[4] = {xb, vb, Cb, Fb};
   float* dst[4] = {adj.x, adj.v, adj.C, adj.F};
@@ -1218,13 +1245,27 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
       launch_fill_f32(dst[f], len[f], 0.0f, h->stream);
   }
   launch_fill_f32(theta_bar, N, 0.0f, h->stream);
-  launch_fill_f64(d.tool_red, (int64_t)T * kMaxTools * 6, 0.0, h->stream);
+  launch_fill_f64(d.tool_red, (int64_t)T * red_row * kToolRedCopies, 0.0, h->stream);
   auto grid_of = [&](int slot_index) -> float4* { return d.grids + (int64_t)slot_index * 2 * nn; };
+  // Particle orders as in the forward pass: one per order_period(K)
+  // substeps, taken from the checkpoint that starts the period.
+  const int R = order_period(K);
+  int order_at = -1;
+  DiffOrder ord{};
+  auto order_for = [&](int j) {
+    const int r = j / R * R;
+    if (r != order_at) {
+      ord = rollout_order(h, dstate(d.ckpt + (int64_t)(r / K) * SF, N).x);
+      order_at = r;
+    }
+  };
+  h->dirty = true;
   if (d.grids_kept) {
     for (int j = T - 1; j >= 0; --j) {
       float4* vel = grid_of(j);
+      order_for(j);
       launch_diff_adjoint(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, dstate(d.ckpt + (int64_t)j * SF, N),
-                          d.E, adj, theta_bar, d.tool_red + (int64_t)j * kMaxTools * 6, h->stream);
+                          d.E, adj, theta_bar, d.tool_red + (int64_t)j * red_row * kToolRedCopies, ord, h->stream);
     }
   } else {
     const DState none = {nullptr, nullptr, nullptr, nullptr};
@@ -1236,16 +1277,18 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
         return i == 0 ? dstate(d.ckpt + (int64_t)a * SF, N) : dstate(d.seg + (int64_t)i * SF, N);
       };
       // Recompute the segment from its checkpoint, keeping states and grids.
+      // (A segment lies inside one order period.)
+      order_for(s0);
       for (int i = 0; i < n_in; ++i) {
         float4* vel = grid_of(i);
         launch_diff_substep(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + s0 + i), N, st(i), d.E,
-                            i + 1 < n_in ? st(i + 1) : none, false, h->b.status, h->stream);
+                            i + 1 < n_in ? st(i + 1) : none, false, h->b.status, ord, h->stream);
       }
       for (int i = n_in - 1; i >= 0; --i) {
         const int j = s0 + i;
         float4* vel = grid_of(i);
         launch_diff_adjoint(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, st(i), d.E, adj, theta_bar,
-                            d.tool_red + (int64_t)j * kMaxTools * 6, h->stream);
+                            d.tool_red + (int64_t)j * red_row * kToolRedCopies, ord, h->stream);
       }
     }
   }
@@ -1256,8 +1299,9 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
   HIP_OR_RETURN(h, hipGetLastError());
   if (vel_bar) {
     std::vector<double> red((size_t)T * kMaxTools * 6);
+    launch_sum_tool_copies(d.tool_red, T, tool_tot, h->stream);
     if (T > 0)
-      HIP_OR_RETURN(h, hipMemcpyAsync(red.data(), d.tool_red, sizeof(double) * red.size(), hipMemcpyDeviceToHost,
+      HIP_OR_RETURN(h, hipMemcpyAsync(red.data(), tool_tot, sizeof(double) * red.size(), hipMemcpyDeviceToHost,
                                       h->stream));
     HIP_OR_RETURN(h, hipStreamSynchronize(h->stream));
     // The centre in substep i is the centre at the rollout start plus dt

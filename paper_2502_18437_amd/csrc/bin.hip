@@ -333,13 +333,9 @@ static unsigned grid_for(int64_t n, int wg) {
   return (unsigned)g;
 }
 
-void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st) {
-  const uint32_t n_blocks = s.nb3 * (uint32_t)s.n_scenes;
-  const uint32_t sentinel = n_blocks;
-  // 1. keys: scene-major block ids
-  hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur],
-                     b.scene_off, b.cap, N, s, b.keys[0], b.vals[0], sentinel, b.status);
-  // 2. stable LSD radix sort, 8 bits per pass
+// Stable LSD radix sort of (b.keys[0], b.vals[0]), 8 bits per pass; returns
+// which ping-pong half holds the result.
+static int radix_sort(Buffers& b, int64_t N, int key_bits, hipStream_t st) {
   int src = 0;
   if (N > 0) {
     const int n_tiles = (int)((N + kSortTile - 1) / kSortTile);
@@ -352,6 +348,17 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStrea
       src ^= 1;
     }
   }
+  return src;
+}
+
+void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st) {
+  const uint32_t n_blocks = s.nb3 * (uint32_t)s.n_scenes;
+  const uint32_t sentinel = n_blocks;
+  // 1. keys: scene-major block ids
+  hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur],
+                     b.scene_off, b.cap, N, s, b.keys[0], b.vals[0], sentinel, b.status);
+  // 2. stable LSD radix sort, 8 bits per pass
+  const int src = radix_sort(b, N, key_bits, st);
   // 3. gather the particle state into key order
   const int n_fields = s.has_E ? kFields : kFields - 1;
   hipLaunchKernelGGL(k_permute, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.part[b.cur ^ 1],
@@ -384,6 +391,56 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStrea
   hipLaunchKernelGGL(k_compact, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.mark, nullptr,
                      b.flags, n_blocks, 1, b.act_list);
   hipLaunchKernelGGL(k_reset_epoch, dim3(1), dim3(1), 0, st, b.status);
+}
+
+// ------------------------------------------------------------------ rollout order
+// Keys of particles held as an AoS x (N x 3) in the caller's order: the block
+// of the base cell (one scene), or the sentinel when the stencil leaves the
+// grid or x is not finite.
+__global__ void k_order_keys(const float* __restrict__ x, int64_t N, SimK s, uint32_t sentinel,
+                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    int cell[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      const float r = x[3 * i + a] * s.inv_dx;
+      const float c = floorf(r - 0.5f);
+      ok = ok && (c >= 0.0f) && (c + 2.0f <= (float)(s.n - 1));  // false for NaN
+      cell[a] = ok ? (int)c : 0;
+    }
+    keys[i] = ok ? (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb + (cell[0] >> kTileLog2))
+                 : sentinel;
+    vals[i] = (uint32_t)i;
+  }
+}
+
+// First sorted position holding the sentinel key (left at N when there is
+// none).
+__global__ void k_first_sentinel(const uint32_t* __restrict__ keys, int64_t N, uint32_t sentinel,
+                                 uint32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    if (keys[i] >= sentinel && (i == 0 || keys[i - 1] < sentinel)) *out = (uint32_t)i;
+}
+
+const uint32_t* launch_order(Buffers& b, int64_t N, const SimK& s, const float* x, int key_bits, uint32_t item,
+                             uint32_t* info, hipStream_t st) {
+  const uint32_t n_blocks = s.nb3;
+  hipLaunchKernelGGL(k_order_keys, dim3(grid_for(N, 256)), dim3(256), 0, st, x, N, s, n_blocks, b.keys[0],
+                     b.vals[0]);
+  const int src = radix_sort(b, N, key_bits, st);
+  fill_u32(b.blk_begin, n_blocks, 0u, st);
+  fill_u32(b.blk_end, n_blocks, 0u, st);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks,
+                     b.blk_begin, b.blk_end);
+  hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     n_blocks, item, b.flags);
+  exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &info[0], st);
+  hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     b.flags, n_blocks, item, b.work);
+  fill_u32(&info[1], 1, (uint32_t)N, st);
+  hipLaunchKernelGGL(k_first_sentinel, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks,
+                     &info[1]);
+  return b.vals[src];
 }
 
 // ------------------------------------------------------------------ diagnostics

@@ -32,6 +32,9 @@ constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA
 // [kItemMin, kItemMax] chosen from the particle and workgroup counts.
 constexpr int kItemMin = 512;
 constexpr int kItemMax = 2048;
+// The differentiable rollout's scatters take runs of kItemRollout particles
+// (its scenes are small, so shorter runs keep every workgroup busy).
+constexpr int kItemRollout = 256;
 
 // Field offsets in the particle SoA (each field is `cap` floats).
 enum Field { FX = 0, FV = 3, FC = 6, FF = 15, FE = 24 };
@@ -187,6 +190,18 @@ void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st, bool gr
 // Set the device clock to `substep` and `parity`.
 void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st);
 
+// Spatial order of a one-scene particle set held as an AoS x (N x 3) in the
+// caller's order, for the rollout's tiled scatters: sorts the particles by the
+// grid block of their base cell (particles whose stencil leaves the grid or
+// whose x is not finite last) into the handle's binning scratch, fills
+// b.blk_begin / b.blk_end and the work items b.work (runs of at most `item`
+// particles of one block), writes info[0] = the number of items and
+// info[1] = the first sorted position of the particles left out, and returns
+// the sorted caller indices (b.keys / b.vals scratch, valid until the next
+// binning or order).
+const uint32_t* launch_order(Buffers& b, int64_t N, const SimK& s, const float* x, int key_bits, uint32_t item,
+                             uint32_t* info, hipStream_t st);
+
 // Nodes with mass in the last grid update (sum of node_cnt over the active
 // and overflow blocks of `parity`), written to *out (device memory).
 void launch_count_active_nodes(Buffers& b, int parity, unsigned long long* out, hipStream_t st);
@@ -212,6 +227,7 @@ void launch_load_particles(Buffers& b, int64_t N, const float* x, const float* v
 // F (N x 9), consecutive in one block of kStateFloats * N floats. Adjoint
 // states use the same layout.
 constexpr int kStateFloats = 24;
+constexpr int kToolRedCopies = 16;
 
 struct DState {
   float* x;
@@ -235,6 +251,20 @@ struct DiffGrid {
   uint8_t* skip = nullptr;                  // per particle: left unchanged this substep
 };
 
+// A spatial order of the rollout's particles (launch_order): the scatter
+// kernels walk `work` (info[0] items of at most kItemRollout sorted positions
+// of one block, whose LDS tile takes the block's stencils), then the sorted
+// positions from info[1] on, which hold the particles outside the grid.
+// Particles that move out of their block's tile after the order was taken
+// scatter straight into the global grid, so any order gives the same sums
+// up to the order of FP32 additions.
+struct DiffOrder {
+  const uint32_t* order;    // sorted position -> caller index
+  const uint32_t* blk_end;  // per block: end of its sorted positions
+  const uint2* work;        // {block, first sorted position}
+  const uint32_t* info;     // device: {items, first position outside the grid}
+};
+
 // Forward substep on the dense grid: P2G from `in`, grid update (tools,
 // walls) into `vel` (and, if `hat` is not null, the pre-contact velocity and
 // the mass into `hat`), G2P into `out` (skipped when out.x is null).
@@ -242,15 +272,19 @@ struct DiffGrid {
 // unchanged (and counted when `count`); g.skip records them.
 void launch_diff_substep(const DiffGrid& g, float4* vel, float4* hat, const SimK& s, const ToolSetK& tools,
                          int64_t N, DState in, const float* E, DState out, bool count, Status* st,
-                         hipStream_t stream);
+                         const DiffOrder& o, hipStream_t stream);
 // Reverse of one substep from the state `in` it started from and its grid
 // (`vel`, `hat`) as its forward pass left them: on entry `adj` is
 // the cotangent of the state after the substep, on exit that of `in`. Adds
 // d/d log E to theta_bar and the tools' linear-velocity and centre cotangents
-// to tool_red[kMaxTools][6] (FP64).
+// to tool_red[kToolRedCopies][kMaxTools * 6] (FP64): each workgroup adds its
+// sums into one of the copies, so that the FP64 atomics of the many
+// workgroups that touch a tool do not all meet on one address.
 void launch_diff_adjoint(const DiffGrid& g, const float4* vel, const float4* hat, const SimK& s,
                          const ToolSetK& tools, int64_t N, DState in, const float* E, DState adj, float* theta_bar,
-                         double* tool_red, hipStream_t stream);
+                         double* tool_red, const DiffOrder& o, hipStream_t stream);
+// out[j][c] = sum over the copies of parts[j][copy][c] (j < T, c < kMaxTools * 6).
+void launch_sum_tool_copies(const double* parts, int T, double* out, hipStream_t st);
 // Fill helpers.
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
