@@ -20,6 +20,7 @@
 
 #include "mpm.h"
 #include "mpm_internal.h"
+#include "diff_internal.h"
 
 using namespace mpm;
 

@@ -35,6 +35,7 @@
 
 #include "mpm_device.h"
 #include "mpm_internal.h"
+#include "diff_internal.h"
 #include "p2g_fixed.h"
 
 namespace mpm {
