@@ -30,7 +30,7 @@ Also reported on the same JSON line:
   It is off by default so that the fused kernel's launches in a profile of
   the default command all belong to the headline workload.
 * solver_sweep (with --solver-sweep): the paper's solver comparison shape
-  (Sec. III-D): a cube falling on a fixed 56^3 grid, N = 2^14 .. 2^21
+  (Sec. III-D): a cube falling on a fixed 56^3 grid, N = 2^14 .. 2^22
   particles, one frame = 0.02 s: MLS-MPM and standard MPM take 10 substeps
   of 2e-3, PB-MPM one step of 0.02 with 10 or 20 constraint passes; ms per
   frame over the first frames of the fall.
@@ -137,7 +137,7 @@ def batch_throughput(steps, warmup=1):
                                  "frac": model / per_substep / 1e9 / HBM_PEAK_GBS}}
 
 
-SWEEP_SIZES = (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21)
+SWEEP_SIZES = (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22)
 
 
 def solver_sweep(frames=4, lead_frames=5, sizes=SWEEP_SIZES):
@@ -145,8 +145,8 @@ def solver_sweep(frames=4, lead_frames=5, sizes=SWEEP_SIZES):
     timed over `frames` frames after lead_frames + 1 untimed ones (the cube
     is then falling at about 1.2 m/s and reaches the floor after the timed
     frames). The launch configuration is the library autotuner's choice from
-    that state. The largest size keeps the densest cells below 256 particles
-    (the capacity of the 32-bit weight sums of the P2G tile)."""
+    that state. At 2^22 particles the cube holds about 370 particles per
+    cell."""
     import torch
     from paper_2502_18437_amd import mpm, scenes
     dev = torch.device("cuda", 0)

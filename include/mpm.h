@@ -69,14 +69,16 @@ extern "C" {
 #define MPM_MAX_TOOLS 8
 
 /* Grid accumulation mode of the P2G scatter. Each particle's contributions
- * are rounded to fixed point (weights in units of 2^-24, momentum in units
+ * are rounded to fixed point (weights in units of 2^-22, momentum in units
  * of 2^-40 of the particle mass times 1 m/s) and summed exactly per block in
  * LDS; the modes differ in the global sum over blocks. */
 #define MPM_ACCUM_F32 0   /* block sums added with FP32 atomics: fastest; the
                              summation order of the FP32 adds varies */
 #define MPM_ACCUM_FIXED 1 /* block sums added with integer atomics: results
                              are bit-identical run to run, for any particle
-                             order and re-binning schedule */
+                             order and re-binning schedule. A node's 32-bit
+                             weight sum holds up to 1024 (about 1000 particles
+                             per cell) */
 
 /* Tool geometries (Sec. IV-A: one SDF per rigid shape). */
 #define MPM_TOOL_NONE 0    /* removes the tool */

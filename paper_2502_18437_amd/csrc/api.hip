@@ -558,7 +558,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   alloc((void**)&h->imp_sum, sizeof(double) * kImpulseRows * 3);
   alloc((void**)&h->scratch_u64, sizeof(unsigned long long));
   const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
-  alloc(&b.acc_m, sizeof(float) * grid_nodes);
+  alloc(&b.acc_m, sizeof(float) * grid_nodes);  // weights: float or u32
   for (int a = 0; a < 3; ++a) alloc(&b.acc_p[a], mom_bytes * grid_nodes);
   alloc((void**)&b.vel, sizeof(float4) * grid_nodes);
   alloc((void**)&b.status, sizeof(Status));
@@ -708,9 +708,9 @@ int set_particles_impl(mpm_handle* h, const int64_t* counts, const float* x, con
   h->sim.has_E = h->has_E ? 1 : 0;
   h->sim.p2g_stress = (float)((double)h->p.dt * (double)vol0 * 4.0 * (double)h->p.n_grid * (double)h->p.n_grid);
   h->sim.pic_force = (float)((double)h->p.dt * (double)vol0 * (double)h->p.n_grid);
-  // Fixed-point units: a weight is 2^-24; momentum units are chosen so that
+  // Fixed-point units: a weight is 2^-22; momentum units are chosen so that
   // one particle at 1 m/s is 2^40 units (exact powers of two).
-  h->sim.m_unit = std::ldexp(mass, -24);
+  h->sim.m_unit = std::ldexp(mass, -22);
   const int shift = 40 - std::ilogb(mass);
   h->sim.fx_p = std::ldexp(1.0, shift);
   h->sim.fx_p_inv = std::ldexp(1.0, -shift);

@@ -161,7 +161,7 @@ __device__ __forceinline__ void p2g_direct(const SimK& s, const int* base, const
 }
 
 struct P2GTile {
-  uint32_t m[kSpanNodes];  // weight sums (2^-24 units)
+  uint32_t m[kSpanNodes];  // weight sums (2^-22 units)
   long long p0[kSpanNodes], p1[kSpanNodes], p2[kSpanNodes];  // momentum (fixed point)
 };
 

@@ -75,7 +75,7 @@ struct ToolDesc {
 //
 // P2G accumulates in integers (LDS float atomics are slow on gfx950, and
 // integer sums are exact and order independent): the mass channel as the sum
-// of the B-spline weights in units of 2^-24 (u32), the momentum channels as
+// of the B-spline weights in units of 2^-22 (u32), the momentum channels as
 // int64 in units of 2^-fx_shift kg m/s, where fx_shift is chosen per scene
 // so that one particle moving at 1 m/s is about 2^40 units. The conversion
 // of a value to int64 is the round-to-nearest of an FP64 sum with 1.5 * 2^52,
@@ -95,7 +95,7 @@ struct SimK {
   int band;          // wall band
   float g[3];
   int fixed;         // global accumulator: 0 FP32, 1 integer (bit-reproducible)
-  float m_unit;      // kg per weight unit: mass * 2^-24
+  float m_unit;      // kg per weight unit: mass * 2^-22
   double fx_p;       // 2^fx_shift (momentum units per kg m/s)
   double fx_p_inv;   // 2^-fx_shift
   float p_limit;     // largest |contribution| (kg m/s) kept in range

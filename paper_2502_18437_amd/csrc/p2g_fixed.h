@@ -1,5 +1,5 @@
 // Fixed-point P2G contributions shared by the transfer kernels and the
-// differentiable rollout's scatter: B-spline weights in 2^-24 units (u32) and
+// differentiable rollout's scatter: B-spline weights in 2^-22 units (u32) and
 // the APIC affine momentum in 2^-fx_shift units (int64), each rounded to
 // nearest by an FP64 sum with 1.5 * 2^52. Integer sums are exact, so LDS
 // tiles can be accumulated with the fast integer LDS atomics in any order.
@@ -8,11 +8,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mpm_internal.h"
+
 namespace mpm {
 
 constexpr double kMagic = 6755399441055744.0;           // 1.5 * 2^52
 constexpr long long kMagicBits = 0x4338000000000000LL;  // its bit pattern
-constexpr float kWeightUnits = 16777216.0f;            // 2^24
+// 2^22 weight units per unit weight: a node's sum over the particles of one
+// work item (at most kItemMax, each weight at most 0.75^3) stays below 2^32.
+// Finer units would let a crowded node wrap; coarser ones add rounding noise
+// to p/m that the affine matrix C amplifies by 4/dx.
+constexpr float kWeightUnits = 4194304.0f;             // 2^22
+static_assert((double)kItemMax * 0.421875 * 4194304.0 + kItemMax < 4294967296.0,
+              "a work item cannot overflow a 32-bit weight sum");
 
 // ------------------------------------------------------------------ P2G values
 // Per-particle inputs of the P2G scatter: weights and the affine momentum

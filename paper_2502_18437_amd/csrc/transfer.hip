@@ -14,7 +14,9 @@
 //
 // P2G accumulates integers because LDS float atomics are slow on gfx950 while
 // ds_add_u32 / ds_add_u64 run near LDS bandwidth; integer sums are also exact,
-// so the result does not depend on the order of the atomics.
+// so the result does not depend on the order of the atomics. Weights are u32
+// in 2^-22 units: one work item (at most kItemMax particles, each adding at
+// most 0.75^3 to a node) cannot carry a node's sum past 2^32 - 1.
 //
 // k_g2p2g fuses the G2P of substep k-1 with the P2G of substep k: v and C never
 // leave registers between the two, so a fused substep streams x, F, E in and
@@ -116,7 +118,7 @@ __device__ __forceinline__ void p2g_emit(const PICIn& P, Sink&& sink) {
 
 // ------------------------------------------------------------------ global accumulator
 // Channel types of the global accumulator: FP32 sums, or exact integer sums
-// (weights in 2^-24 units, momentum in 2^-fx_shift units).
+// (weights in 2^-22 units as u32, momentum in 2^-fx_shift units as int64).
 template <bool FIXED> struct AccT;
 template <> struct AccT<false> {
   using M = float;
@@ -263,7 +265,7 @@ __device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const
 // ------------------------------------------------------------------ per particle
 struct Lds {
   float4 v[kSpanNodes];                                     // staged grid velocity
-  uint32_t m[kSpanNodes];                                   // weight sums (2^-24 units)
+  uint32_t m[kSpanNodes];                                   // weight sums (2^-22 units)
   long long p0[kSpanNodes], p1[kSpanNodes], p2[kSpanNodes];  // momentum (fixed point)
 };
 

@@ -84,3 +84,35 @@ def test_dense_cube_is_bitwise_across_workgroup_counts():
             continue
         for k in ("x", "v", "C", "F"):
             assert np.array_equal(ref[k], r[k]), (wgs, k)
+
+
+@pytest.mark.parametrize("fixed,n_particles", [(False, 1 << 16), (True, 3000)])
+def test_extreme_density_keeps_the_mass_sums(fixed, n_particles):
+    """Particles crowded into one cell: the FP32 case (65,536 particles, 8
+    transfer workgroups, so work items of 2048) puts about 600 units of
+    weight on a node from one work item, the fixed-point case (3,000
+    particles) about 900 units on a node in total; a 32-bit sum of 2^-24
+    units would wrap at 256. In free fall, away from the walls, every
+    particle must follow v = v0 + n dt g to FP32 rounding, with F = I."""
+    from paper_2502_18437_amd import mpm
+    n_grid = 32
+    dx = 1.0 / n_grid
+    rng = np.random.default_rng(21)
+    # base cell 10 on every axis
+    x = ((10.5 + rng.random((n_particles, 3))) * dx).astype(np.float32)
+    x = np.clip(x, np.float32(10.5 * dx), np.float32(11.49 * dx))
+    vol0 = dx ** 3 / n_particles
+    sim = mpm.Simulation(n_grid, 1e-4, gravity=(0.0, -9.8, 0.0), max_particles=n_particles,
+                         accum_mode=mpm.MPM_ACCUM_FIXED if fixed else mpm.MPM_ACCUM_F32)
+    v0 = np.float32([0.05, 0.0, 0.0])
+    sim.set_particles(x, np.tile(v0, (n_particles, 1)), None, None, None, 1e3 * vol0, vol0)
+    sim.set_launch_config(transfer_wgs=8, resort_interval=4)
+    n = 6
+    print(f"[dense extreme fixed={fixed} N={n_particles}]", flush=True)
+    sim.step(n)
+    r, st = sim.read_state()
+    sim.close()
+    assert st == 0
+    v_exp = v0.astype(np.float64) + n * 1e-4 * np.array([0.0, -9.8, 0.0])
+    np.testing.assert_allclose(r["v"], np.tile(v_exp, (n_particles, 1)), rtol=0, atol=1e-5)
+    np.testing.assert_allclose(r["F"], np.tile(np.eye(3), (n_particles, 1, 1)), rtol=0, atol=1e-5)
