@@ -164,6 +164,7 @@ def solver_sweep(frames=4, lead_frames=5, sizes=SWEEP_SIZES):
             for _ in range(lead_frames):
                 sim.step(sub)
             # trials long enough for the re-binning interval to matter
+            log(f"[bench] sweep N={s.N} {label}: autotuning")
             cfg = sim.autotune(trial_substeps=8 if kind == mpm.MPM_SOLVER_PB else 2 * sub)
             sim.step(sub)  # one more untimed frame: graphs recorded with the chosen configuration
             sim.read_state(out={})

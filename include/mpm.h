@@ -267,9 +267,12 @@ int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
  * substeps; 1 to 4 transfer workgroups per compute unit; graphs on or off),
  * restoring the particles, their order, the device status and the clock
  * before every trial, and keeps the fastest (written to *chosen if not
- * NULL). The scene is left as it was, except that the next mpm_step re-bins
- * and the tool impulses read zero. Blocking; 112 calls of mpm_step (one
- * untimed and one timed per candidate).
+ * NULL). For each workgroup count and graph setting the intervals are tried
+ * in increasing order, and a candidate over 3 times slower than the best so
+ * far ends that run. The scene is left as it was, except that the next
+ * mpm_step re-bins and the tool impulses read zero. Blocking; at most 112
+ * calls of mpm_step (a warm-up and a timed call per candidate). A trial
+ * shorter than the longer intervals cannot tell them apart.
  * Errors: MPM_EINVAL (no particles, trial_substeps < 1), MPM_ENOMEM (it
  * needs a copy of the particle buffer), MPM_EHIP. */
 int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chosen);

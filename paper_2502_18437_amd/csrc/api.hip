@@ -1111,30 +1111,43 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   mpm_launch_config best = orig;
   float best_ms = 0.0f;
   bool have = false;
-  for (int ri = 0; ri < n_resorts && e == hipSuccess && rc == MPM_OK; ++ri)
-    for (int wi = 0; wi < 4 && e == hipSuccess && rc == MPM_OK; ++wi)
-      for (int ci = 0; ci < 2 && e == hipSuccess && rc == MPM_OK; ++ci) {
+  // For each workgroup count and graph setting the re-binning intervals are
+  // tried in increasing order; a candidate more than kSlow times slower than
+  // the best so far ends that run of intervals (longer intervals only let more
+  // particles drift out of their tiles), and a warm-up call that slow skips
+  // the timed one. This bounds the cost of scenes whose particles move fast.
+  constexpr float kSlow = 3.0f;
+  auto timed_step = [&](float* ms) -> bool {
+    e = hipEventRecord(ev0, h->stream);
+    if (e != hipSuccess) return false;
+    rc = mpm_step(h, trial_substeps);
+    if (rc != MPM_OK) return false;
+    e = hipEventRecord(ev1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev0, ev1);
+    return e == hipSuccess;
+  };
+  for (int wi = 0; wi < 4 && e == hipSuccess && rc == MPM_OK; ++wi)
+    for (int ci = 0; ci < 2 && e == hipSuccess && rc == MPM_OK; ++ci)
+      for (int ri = 0; ri < n_resorts && e == hipSuccess && rc == MPM_OK; ++ri) {
         mpm_launch_config c = {resorts[ri], (per_cu[wi] * h->cus + 7) / 8 * 8, chunks[ci]};
         rc = mpm_set_launch_config(h, &c);
         if (rc != MPM_OK) break;
         e = restore();
         if (e != hipSuccess) break;
-        // one untimed warm-up call (records graphs), then the timed one
-        rc = mpm_step(h, trial_substeps);
-        if (rc != MPM_OK) break;
+        // a warm-up call (records graphs), then the timed one
+        float warm = 0.0f, ms = 0.0f;
+        if (!timed_step(&warm)) break;
+        if (have && warm > kSlow * best_ms) break;
         e = restore();
-        if (e == hipSuccess) e = hipEventRecord(ev0, h->stream);
         if (e != hipSuccess) break;
-        rc = mpm_step(h, trial_substeps);
-        if (rc != MPM_OK) break;
-        e = hipEventRecord(ev1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(ev1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-        if (e == hipSuccess && (!have || ms < best_ms)) {
+        if (!timed_step(&ms)) break;
+        if (!have || ms < best_ms) {
           best = c;
           best_ms = ms;
           have = true;
+        } else if (ms > kSlow * best_ms) {
+          break;
         }
       }
   hipError_t e2 = restore();
