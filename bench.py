@@ -257,13 +257,17 @@ def main():
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--solver-sweep", action="store_true",
                     help="also time the three solvers on the falling cube (paper's solver comparison shape)")
+    ap.add_argument("--sweep-sizes", default="",
+                    help="comma-separated particle counts for --solver-sweep (default: 2^14 .. 2^22)")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the solver sweep (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of MIB MiB (a kernel of known "
                          "traffic that scales hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
@@ -272,6 +276,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    sizes = tuple(int(v) for v in args.sweep_sizes.split(",") if v) or SWEEP_SIZES
+    if args.sweep_only:
+        print(json.dumps({"solver_sweep": solver_sweep(sizes=sizes)}), flush=True)
+        return
     s = scenes.make(args.scene)
     n_sub = args.substeps or s.n_substeps
     log(f"[bench] scene {s.name}: {s.N} particles, {s.n_grid}^3 grid, {n_sub} substeps/step")
@@ -363,7 +371,7 @@ def main():
     if args.batch:
         out["batch"] = batch_throughput(args.diff_steps)
     if args.solver_sweep:
-        out["solver_sweep"] = solver_sweep()
+        out["solver_sweep"] = solver_sweep(sizes=sizes)
     if not args.no_diff:
         out["fwd_bwd"] = fwd_bwd(args.diff_steps, checkpoint_every=20)
         out["fwd_bwd_keep_all"] = fwd_bwd(args.diff_steps, checkpoint_every=1)

@@ -300,14 +300,16 @@ __global__ void k_item_counts(const uint32_t* __restrict__ begin, const uint32_t
     counts[b] = end[b] > begin[b] ? (end[b] - begin[b] + item - 1) / item : 0u;
 }
 
-// work[off[b] + j] = {b, begin[b] + j item}.
+// work[off[b] + j] = {b, begin[b] + j item}, with kDenseFlag in b when the
+// block holds more than `dense` particles.
 __global__ void k_emit_items(const uint32_t* __restrict__ begin, const uint32_t* __restrict__ end,
-                             const uint32_t* __restrict__ off, uint32_t n_blocks, uint32_t item,
+                             const uint32_t* __restrict__ off, uint32_t n_blocks, uint32_t item, uint32_t dense,
                              uint2* __restrict__ work) {
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x) {
     if (!(end[b] > begin[b])) continue;
     uint32_t o = off[b];
-    for (uint32_t p = begin[b]; p < end[b]; p += item) work[o++] = make_uint2(b, p);
+    const uint32_t tag = (end[b] - begin[b] > dense) ? kDenseFlag : 0u;
+    for (uint32_t p = begin[b]; p < end[b]; p += item) work[o++] = make_uint2(b | tag, p);
   }
 }
 
@@ -380,7 +382,7 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStrea
                      n_blocks, s.item_particles, b.flags);
   exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_work, st);
   hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     b.flags, n_blocks, s.item_particles, b.work);
+                     b.flags, n_blocks, s.item_particles, kDenseBlock, b.work);
   // 6. active list: occupied blocks dilated by one block
   fill_u32(b.mark, n_blocks, 0u, st);
   hipLaunchKernelGGL(k_mark_dilated, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,
@@ -436,7 +438,7 @@ const uint32_t* launch_order(Buffers& b, int64_t N, const SimK& s, const float* 
                      n_blocks, item, b.flags);
   exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &info[0], st);
   hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     b.flags, n_blocks, item, b.work);
+                     b.flags, n_blocks, item, 0xffffffffu, b.work);  // never flagged
   fill_u32(&info[1], 1, (uint32_t)N, st);
   hipLaunchKernelGGL(k_first_sentinel, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks,
                      &info[1]);

@@ -32,6 +32,12 @@ constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA
 // [kItemMin, kItemMax] chosen from the particle and workgroup counts.
 constexpr int kItemMin = 512;
 constexpr int kItemMax = 2048;
+// Work items of a block holding more than kDenseBlock particles (8 per cell
+// on average) carry kDenseFlag in their block id: their particles are dealt
+// to the lanes of a wave 8 apart, so that one wave's LDS atomics do not pile
+// onto the same nodes.
+constexpr unsigned kDenseBlock = 8u * 512u;
+constexpr unsigned kDenseFlag = 0x80000000u;
 // The differentiable rollout's scatters take runs of kItemRollout particles
 // (its scenes are small, so shorter runs keep every workgroup busy).
 constexpr int kItemRollout = 256;

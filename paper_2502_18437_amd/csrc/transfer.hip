@@ -45,6 +45,14 @@ __device__ __forceinline__ void xcd_walk(unsigned n_items, unsigned* pos, unsign
   *stride = per;
 }
 
+// This thread's position in each run of kWG particles of a work item: its
+// own index, or for a dense block's items (kDenseFlag) lane l of wave w takes
+// position l * (kWG / 64) + w, so one wave's 64 particles lie 8 apart in the
+// block's order (different cells) instead of side by side.
+__device__ __forceinline__ unsigned item_lane(unsigned tagged_block) {
+  return (tagged_block & kDenseFlag) ? (threadIdx.x & 63u) * (kWG / 64) + (threadIdx.x >> 6) : threadIdx.x;
+}
+
 struct Counters {
   unsigned inv = 0, dom = 0, nf = 0, fb = 0, rng = 0;
 };
@@ -568,13 +576,14 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
   xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const uint2 item = work[pos];
-    const unsigned b = item.x;
+    const unsigned b = item.x & ~kDenseFlag;
+    const unsigned q = item_lane(item.x);
     int to[4];
     block_origin(s, b, to);
     tile_clear(L);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
-    for (unsigned p = item.y + threadIdx.x; p < pe; p += kWG) {
+    for (unsigned p = item.y + q; p < pe; p += kWG) {
       float x[3], v[3], C[9], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -617,14 +626,15 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
   xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const uint2 item = work[pos];
-    const unsigned b = item.x;
+    const unsigned b = item.x & ~kDenseFlag;
+    const unsigned q = item_lane(item.x);
     int to[4];
     block_origin(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     tile_clear(L);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
-    for (unsigned p = item.y + threadIdx.x; p < pe; p += kWG) {
+    for (unsigned p = item.y + q; p < pe; p += kWG) {
       float x[3], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = part[(FX + a) * cap + p];
@@ -673,13 +683,14 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
   xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const uint2 item = work[pos];
-    const unsigned b = item.x;
+    const unsigned b = item.x & ~kDenseFlag;
+    const unsigned q = item_lane(item.x);
     int to[4];
     block_origin(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
-    for (unsigned p = item.y + threadIdx.x; p < pe; p += kWG) {
+    for (unsigned p = item.y + q; p < pe; p += kWG) {
       float x[3], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = part[(FX + a) * cap + p];
