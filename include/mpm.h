@@ -2,8 +2,9 @@
  * mpm.h -- C ABI of the MI355X explicit MLS-MPM substep library (with the
  * standard-MPM and PB-MPM solver variants, see mpm_set_solver).
  *
- * The library advances one scene of the material point method of
- * CRESSim-MPM (arXiv 2502.18437): per substep, P2G scatter of mass, APIC
+ * The library advances a scene (or a batch of scenes, mpm_create_batch) of
+ * the material point method of CRESSim-MPM (arXiv 2502.18437): per substep,
+ * P2G scatter of mass, APIC
  * affine momentum and MLS stress (Sec. III-B, eq. mls_mpm_p2g_momentum_force),
  * a grid update with gravity, rigid-tool SDF contact with friction and drag
  * (Sec. IV-A, eq. v_correction) and sticky box walls (Sec. III-A, boundary

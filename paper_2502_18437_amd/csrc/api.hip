@@ -1,14 +1,19 @@
-// Host runtime and C ABI of the MLS-MPM substep library (declared in
-// include/mpm.h). One handle = one scene: device buffers, the stream, the
-// tool table, the binning schedule and the substep driver.
+// Host runtime and C ABI of the MPM substep library (declared in
+// include/mpm.h). One handle = one scene or a batch of scenes: device
+// buffers, the stream, the tool tables, the solver, the binning schedule, the
+// recorded graphs, the substep driver and the differentiable rollout.
 //
 // mpm_step(n) enqueues, for substeps k = 0..n-1 (Algorithm 1 of the paper):
 //   k == 0 or re-binning due:  [G2P(k-1)] -> binning -> P2G(k)
 //   otherwise:                 fused G2P(k-1) + P2G(k)
 //   then the grid update of substep k (tools at their substep-k pose),
 // and a final G2P, so that x, v, C, F are materialised when the call's work
-// completes. Nothing here waits on the device except mpm_read_state,
-// mpm_get_info, mpm_profile_read, mpm_eval_stress and mpm_destroy.
+// completes. A PB-MPM substep is one step of `iterations` passes: the first
+// as above, then iterations - 1 times fused G2P + P2G within the step, each
+// followed by a grid update. Runs of plain substeps replay a recorded HIP
+// graph. Nothing here waits on the device except mpm_read_state,
+// mpm_get_info, mpm_profile_read, mpm_eval_stress, mpm_autotune, the batch
+// particle upload and mpm_destroy.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

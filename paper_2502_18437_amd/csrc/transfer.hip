@@ -1,5 +1,6 @@
-// Particle <-> grid transfers of the explicit MLS-MPM substep (CRESSim-MPM
-// Sec. III-B, Algorithm 1), block-tiled for CDNA4.
+// Particle <-> grid transfers of the MPM substep (CRESSim-MPM Sec. III-B,
+// Algorithm 1, and the solver variants of Sec. III-A and III-C), block-tiled
+// for CDNA4.
 //
 // Particles are binned by the grid block (kTile^3 cells) of their base cell.
 // One workgroup owns one work item at a time (a block's particles, or a run of
@@ -20,7 +21,9 @@
 //
 // k_g2p2g fuses the G2P of substep k-1 with the P2G of substep k: v and C never
 // leave registers between the two, so a fused substep streams x, F, E in and
-// x, F out (100 B/particle).
+// x, F out (100 B/particle). A dense block's work items deal their particles
+// to a wave's lanes 8 apart (item_lane), so that one wave's atomics spread
+// over different cells.
 #include "mpm_device.h"
 #include "mpm_internal.h"
 #include "p2g_fixed.h"
