@@ -248,6 +248,22 @@ int mpm_profile(mpm_handle* h, int32_t enable);
 int mpm_profile_read(mpm_handle* h, mpm_kernel_times* out);
 
 /* ------------------------------------------------------ launch configuration */
+/* Positions a re-binning inside mpm_step sorts the particles by (the first
+ * substep of a call always sorts the state in memory):
+ *  - MPM_REBIN_ADVANCE: a G2P pass first writes v, C and the advanced x, F;
+ *    the sort takes those positions and a P2G pass scatters from the written
+ *    state, so no stencil leaves its tile in the first substep after it.
+ *  - MPM_REBIN_IN_PLACE: the sort takes the positions in memory (those the
+ *    next G2P reads) and the fused transfer goes on: no extra G2P and P2G
+ *    passes and no v, C to permute, but particles that cross a block
+ *    boundary in that substep scatter through global memory.
+ *  - MPM_REBIN_AUTO: in place for MLS-MPM and standard MPM with
+ *    resort_interval >= 4, else advance (fast scenes re-bin often; a PB-MPM
+ *    step's passes all scatter from the advanced positions). */
+#define MPM_REBIN_AUTO 0
+#define MPM_REBIN_ADVANCE 1
+#define MPM_REBIN_IN_PLACE 2
+
 /* How mpm_step launches its kernels. Results do not depend on it beyond the
  * order of FP32 atomics (in MPM_ACCUM_FIXED mode not at all). */
 typedef struct mpm_launch_config {
@@ -255,11 +271,12 @@ typedef struct mpm_launch_config {
   int32_t transfer_wgs;    /* workgroups of the persistent transfer kernels, a multiple of 8 in [8, 65536] */
   int32_t graph_chunk;     /* runs of this many plain substeps (fused transfer + grid update) are
                               recorded once as a HIP graph and replayed; 0 = launch every kernel */
+  int32_t rebin_mode;      /* MPM_REBIN_AUTO, MPM_REBIN_ADVANCE or MPM_REBIN_IN_PLACE */
 } mpm_launch_config;
 
 /* Read / replace the launch configuration (the defaults: resort_interval
- * from mpm_params or 32, two workgroups per compute unit, graph_chunk 8).
- * Errors: MPM_EINVAL (NULL, value out of range). */
+ * from mpm_params or 32, two workgroups per compute unit, graph_chunk 8,
+ * MPM_REBIN_AUTO). Errors: MPM_EINVAL (NULL, value out of range). */
 int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out);
 int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
 
@@ -270,10 +287,12 @@ int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
  * before every trial, and keeps the fastest (written to *chosen if not
  * NULL). For each workgroup count and graph setting the intervals are tried
  * in increasing order, and a candidate over 3 times slower than the best so
- * far ends that run. The scene is left as it was, except that the next
- * mpm_step re-bins and the tool impulses read zero. Blocking; at most 112
- * calls of mpm_step (a warm-up and a timed call per candidate). A trial
- * shorter than the longer intervals cannot tell them apart.
+ * far ends that run. These candidates use MPM_REBIN_AUTO; the fastest is
+ * then also timed with the re-binning mode AUTO did not pick. The scene is
+ * left as it was, except that the next mpm_step re-bins and the tool
+ * impulses read zero. Blocking; at most 114 calls of mpm_step (a warm-up and
+ * a timed call per candidate). A trial shorter than the longer intervals
+ * cannot tell them apart.
  * Errors: MPM_EINVAL (no particles, trial_substeps < 1), MPM_ENOMEM (it
  * needs a copy of the particle buffer), MPM_EHIP. */
 int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chosen);

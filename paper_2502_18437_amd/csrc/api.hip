@@ -116,6 +116,7 @@ struct mpm_handle {
   // Runs of plain substeps (fused transfer + grid update) replayed as HIP
   // graphs: one instance per particle ping-pong half.
   int graph_chunk = kDefaultGraphChunk;
+  int rebin_mode = MPM_REBIN_AUTO;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
@@ -582,6 +583,9 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
     hipLaunchKernelGGL(k_zero_u32, dim3(4096), dim3(256), 0, h->stream, (uint32_t*)b.acc_p[a],
                        (int64_t)(grid_nodes * mom_bytes / 4));
   hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
+  // Block ranges of the previous sort, read by the binning keys: none yet.
+  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_begin, (int64_t)h->n_blocks);
+  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_end, (int64_t)h->n_blocks);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
   launch_set_clock(b, 0, 0, h->stream);
   // Scene constants.
@@ -896,6 +900,13 @@ namespace {
 // Grid updates per substep: the PB-MPM iterations, else one.
 int transfer_passes(const mpm_handle* h) { return h->sim.solver == SOLVER_PB ? h->pb_iterations : 1; }
 
+// Whether a re-binning inside mpm_step sorts by the positions in memory
+// (MPM_REBIN_IN_PLACE) rather than after a G2P pass (MPM_REBIN_ADVANCE).
+bool rebin_in_place(const mpm_handle* h) {
+  if (h->rebin_mode != MPM_REBIN_AUTO) return h->rebin_mode == MPM_REBIN_IN_PLACE;
+  return h->sim.solver != SOLVER_PB && h->resort_interval >= 4;
+}
+
 // Grid update `it` of `passes` in a substep: PB-MPM leaves gravity out (it
 // is added to the particles) and keeps the impulses of the last pass only;
 // the clock's substep advances after the last pass.
@@ -952,24 +963,30 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   launch_clear_impulses(b, h->sim, h->stream);
   launch_set_clock(b, (long long)h->substep, (int)(h->updates & 1), h->stream);
   const int passes = transfer_passes(h);
+  const bool in_place = rebin_in_place(h);
   for (int k = 0; k < n_substeps;) {
     const bool rebin = h->dirty || h->since_sort >= h->resort_interval;
-    if (k == 0 || rebin) {
-      if (k > 0) {
-        ProfScope ps(h, 3);
-        launch_g2p(b, N, h->sim, wgs, h->stream);
-      }
-      if (rebin) {
-        ProfScope ps(h, 0);
-        launch_binning(b, N, h->sim, h->key_bits, h->stream);
-        h->dirty = false;
-        h->since_sort = 0;
-        h->resorts++;
-      }
-      {
-        ProfScope ps(h, 1);
-        launch_p2g(b, N, h->sim, wgs, h->stream);
-      }
+    // Within a call the particle memory holds x and F as the next G2P reads
+    // them (v and C live in registers between G2P and P2G). A re-binning in
+    // place sorts by those positions, so every G2P stencil of the next fused
+    // substep lies in its block's tile; otherwise a G2P pass first writes
+    // the advanced state and the P2G below scatters from it. At the first
+    // substep the memory holds the full state (v, C included).
+    const bool advance = rebin && k > 0 && !in_place;
+    if (advance) {
+      ProfScope ps(h, 3);
+      launch_g2p(b, N, h->sim, wgs, h->stream);
+    }
+    if (rebin) {
+      ProfScope ps(h, 0);
+      launch_binning(b, N, h->sim, h->key_bits, k == 0 || advance, h->stream);
+      h->dirty = false;
+      h->since_sort = 0;
+      h->resorts++;
+    }
+    if (k == 0 || advance) {
+      ProfScope ps(h, 1);
+      launch_p2g(b, N, h->sim, wgs, h->stream);
     } else {
       // Plain substeps until the next re-binning or the end of the call:
       // whole chunks replay the recorded graph (not while timing kernels).
@@ -1041,15 +1058,18 @@ int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out) {
   out->resort_interval = h->resort_interval;
   out->transfer_wgs = h->transfer_wgs;
   out->graph_chunk = h->graph_chunk;
+  out->rebin_mode = h->rebin_mode;
   return MPM_OK;
 }
 
 int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c) {
   if (!h) return MPM_EINVAL;
   if (!c || c->resort_interval < 1 || c->transfer_wgs < 8 || c->transfer_wgs % 8 != 0 || c->transfer_wgs > 65536 ||
-      c->graph_chunk < 0 || c->graph_chunk > 256)
+      c->graph_chunk < 0 || c->graph_chunk > 256 || c->rebin_mode < MPM_REBIN_AUTO ||
+      c->rebin_mode > MPM_REBIN_IN_PLACE)
     return fail(h, MPM_EINVAL, "mpm_set_launch_config: value out of range");
   h->resort_interval = c->resort_interval;
+  h->rebin_mode = c->rebin_mode;
   if (c->transfer_wgs != h->transfer_wgs || c->graph_chunk != h->graph_chunk) drop_graphs(h);
   h->transfer_wgs = c->transfer_wgs;
   h->graph_chunk = c->graph_chunk;
@@ -1086,7 +1106,7 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   const int cur0 = b.cur;
   const int64_t substep0 = h->substep, since0 = h->since_sort, resorts0 = h->resorts;
   const bool dirty0 = h->dirty, prof0 = h->prof;
-  const mpm_launch_config orig = {h->resort_interval, h->transfer_wgs, h->graph_chunk};
+  const mpm_launch_config orig = {h->resort_interval, h->transfer_wgs, h->graph_chunk, h->rebin_mode};
   e = hipMemcpyAsync(save_part, b.part[cur0], part_bytes, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save_id, b.id[cur0], sizeof(uint32_t) * b.cap, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save_st, b.status, sizeof(Status), hipMemcpyDeviceToDevice, h->stream);
@@ -1135,7 +1155,7 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   for (int wi = 0; wi < 4 && e == hipSuccess && rc == MPM_OK; ++wi)
     for (int ci = 0; ci < 2 && e == hipSuccess && rc == MPM_OK; ++ci)
       for (int ri = 0; ri < n_resorts && e == hipSuccess && rc == MPM_OK; ++ri) {
-        mpm_launch_config c = {resorts[ri], (per_cu[wi] * h->cus + 7) / 8 * 8, chunks[ci]};
+        mpm_launch_config c = {resorts[ri], (per_cu[wi] * h->cus + 7) / 8 * 8, chunks[ci], MPM_REBIN_AUTO};
         rc = mpm_set_launch_config(h, &c);
         if (rc != MPM_OK) break;
         e = restore();
@@ -1155,6 +1175,21 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
           break;
         }
       }
+  // The fastest candidate with the re-binning mode that AUTO did not pick.
+  if (have && e == hipSuccess && rc == MPM_OK) {
+    mpm_launch_config c = best;
+    rc = mpm_set_launch_config(h, &c);
+    if (rc == MPM_OK) {
+      c.rebin_mode = rebin_in_place(h) ? MPM_REBIN_ADVANCE : MPM_REBIN_IN_PLACE;
+      rc = mpm_set_launch_config(h, &c);
+    }
+    float warm = 0.0f, ms = 0.0f;
+    if (rc == MPM_OK && (e = restore()) == hipSuccess && timed_step(&warm) && warm <= kSlow * best_ms &&
+        (e = restore()) == hipSuccess && timed_step(&ms) && ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
   hipError_t e2 = restore();
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

@@ -130,14 +130,36 @@ __device__ __forceinline__ uint32_t scene_of(const uint32_t* __restrict__ scene_
   return (uint32_t)lo;
 }
 
+// Half (0 or 1) of the base cell that an offset r - 0.5 - floor(r - 0.5) in
+// [0, 1) falls in. Halves rather than finer classes: a lattice of two
+// particles per cell and axis sits at offsets near 1/4 and 3/4, away from the
+// boundary, so slow material keeps its classes and the next sort its order.
+__device__ __forceinline__ uint32_t sub_cell_half(float frac) { return frac >= 0.5f ? 1u : 0u; }
+
+// Binning keys: the block of the base cell (scene-major) in the high bits,
+// then the base cell's z layer in the block (3 bits) and the particle's
+// sub-cell class (its half of the base cell per axis, 3 bits). The stable
+// sort orders a block's particles layer by layer, so a work item covers a few
+// layers of the tile, and within a layer class by class, so consecutive
+// particles (the lanes of one wave) sit in different base cells and their LDS
+// atomics hit different nodes: at up to 8 particles per cell a class holds
+// about one particle of each cell. This applies to blocks that held 1 to
+// kDenseBlock particles at the previous sort (prev_begin / prev_end); the
+// others keep their order (at the first sort, the order given). In a denser
+// block a class still holds many particles of a cell; its work items deal
+// particles to lanes 8 apart (item_lane), which spreads particles given in a
+// lattice or random order better. Invalid particles get `sentinel`, which
+// sorts after every block.
 __global__ void k_keygen(const float* __restrict__ part, const uint32_t* __restrict__ id,
                          const uint32_t* __restrict__ scene_off, int64_t cap, int64_t N, SimK s,
+                         const uint32_t* __restrict__ prev_begin, const uint32_t* __restrict__ prev_end,
                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t sentinel,
                          Status* st) {
   unsigned dom = 0, nf = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t key = sentinel;
     int cell[3];
+    uint32_t cls = 0;
     bool ok = true, fin = true;
     for (int a = 0; a < 3; ++a) {
       const float r = part[(FX + a) * cap + i] * s.inv_dx;
@@ -145,11 +167,15 @@ __global__ void k_keygen(const float* __restrict__ part, const uint32_t* __restr
       const float b = floorf(r - 0.5f);
       ok = ok && (b >= 0.0f) && (b + 2.0f <= (float)(s.n - 1));
       cell[a] = ok ? (int)b : 0;
+      cls |= ok ? sub_cell_half(r - 0.5f - b) << a : 0u;
     }
     if (ok && fin) {
       const uint32_t scene = s.n_scenes > 1 ? scene_of(scene_off, s.n_scenes, id[i]) : 0u;
-      key = scene * s.nb3 +
-            (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb + (cell[0] >> kTileLog2));
+      const uint32_t blk = scene * s.nb3 + (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb +
+                                                      (cell[0] >> kTileLog2));
+      const uint32_t prev = prev_end[blk] - prev_begin[blk];
+      const bool layered = prev > 0u && prev <= kDenseBlock;
+      key = (blk << kClassBits) | (layered ? ((uint32_t)(cell[2] & (kTile - 1)) << 3) | cls : 0u);
     } else if (!fin) {
       nf++;
     } else {
@@ -244,23 +270,28 @@ __global__ __launch_bounds__(kSortWG) void k_radix_scatter(const uint32_t* __res
 }
 
 // ------------------------------------------------------------------ permutation, ranges
+// Gathers fields [0, n_fields) of the particle SoA into key order; with
+// skip_vc the v and C fields are left out (they are not live).
 __global__ void k_permute(const float* __restrict__ src, float* __restrict__ dst,
                           const uint32_t* __restrict__ id_src, uint32_t* __restrict__ id_dst,
-                          const uint32_t* __restrict__ perm, int64_t cap, int64_t N, int n_fields) {
+                          const uint32_t* __restrict__ perm, int64_t cap, int64_t N, int n_fields, int skip_vc) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t j = perm[i];
-    for (int f = 0; f < n_fields; ++f) dst[f * cap + i] = src[f * cap + j];
+    for (int f = 0; f < n_fields; ++f) {
+      if (skip_vc && f == FV) f = FF;
+      dst[f * cap + i] = src[f * cap + j];
+    }
     id_dst[i] = id_src[j];
   }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t N, uint32_t n_blocks,
+__global__ void k_ranges(const uint32_t* __restrict__ keys, int64_t N, uint32_t n_blocks, int shift,
                          uint32_t* __restrict__ begin, uint32_t* __restrict__ end) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = keys[i];
+    const uint32_t k = keys[i] >> shift;
     if (k >= n_blocks) continue;
-    if (i == 0 || keys[i - 1] != k) begin[k] = (uint32_t)i;
-    if (i == N - 1 || keys[i + 1] != k) end[k] = (uint32_t)(i + 1);
+    if (i == 0 || (keys[i - 1] >> shift) != k) begin[k] = (uint32_t)i;
+    if (i == N - 1 || (keys[i + 1] >> shift) != k) end[k] = (uint32_t)(i + 1);
   }
 }
 
@@ -353,23 +384,23 @@ static int radix_sort(Buffers& b, int64_t N, int key_bits, hipStream_t st) {
   return src;
 }
 
-void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st) {
+void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool with_vc, hipStream_t st) {
   const uint32_t n_blocks = s.nb3 * (uint32_t)s.n_scenes;
-  const uint32_t sentinel = n_blocks;
-  // 1. keys: scene-major block ids
+  const uint32_t sentinel = n_blocks << kClassBits;
+  // 1. keys: scene-major block ids, then sub-cell classes
   hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur],
-                     b.scene_off, b.cap, N, s, b.keys[0], b.vals[0], sentinel, b.status);
+                     b.scene_off, b.cap, N, s, b.blk_begin, b.blk_end, b.keys[0], b.vals[0], sentinel, b.status);
   // 2. stable LSD radix sort, 8 bits per pass
-  const int src = radix_sort(b, N, key_bits, st);
+  const int src = radix_sort(b, N, key_bits + kClassBits, st);
   // 3. gather the particle state into key order
   const int n_fields = s.has_E ? kFields : kFields - 1;
   hipLaunchKernelGGL(k_permute, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.part[b.cur ^ 1],
-                     b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N, n_fields);
+                     b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N, n_fields, with_vc ? 0 : 1);
   b.cur ^= 1;
   // 4. per-block ranges
   fill_u32(b.blk_begin, n_blocks, 0u, st);
   fill_u32(b.blk_end, n_blocks, 0u, st);
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks,
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks, kClassBits,
                      b.blk_begin, b.blk_end);
   // 5. occupied list (ascending block id: spatially ordered, x fastest)
   hipLaunchKernelGGL(k_flag_occupied, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,
@@ -432,7 +463,7 @@ const uint32_t* launch_order(Buffers& b, int64_t N, const SimK& s, const float* 
   const int src = radix_sort(b, N, key_bits, st);
   fill_u32(b.blk_begin, n_blocks, 0u, st);
   fill_u32(b.blk_end, n_blocks, 0u, st);
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks,
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks, 0,
                      b.blk_begin, b.blk_end);
   hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
                      n_blocks, item, b.flags);

@@ -14,6 +14,11 @@ namespace mpm {
 // Particles that drift further take the global-memory path.
 constexpr int kTile = 8;
 constexpr int kTileLog2 = 3;
+// Low bits of a binning key below the block id: the base cell's z layer in
+// the block (3 bits) and the particle's sub-cell class (a half of the base
+// cell per axis, 3 bits). Handles keep n_blocks below 2^22, so a key stays
+// below 2^28.
+constexpr int kClassBits = 6;
 constexpr int kSlack = 0;
 constexpr int kSpan = kTile + 2 + 2 * kSlack;  // 10
 constexpr int kSpanNodes = kSpan * kSpan * kSpan;  // 1000
@@ -175,9 +180,12 @@ struct Buffers {
 };
 
 // ---------------------------------------------------------------- launchers
-// Binning pipeline: keys from positions, radix sort, permutation, block
-// ranges, occupied and active block lists. Resets the overflow lists.
-void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st);
+// Binning pipeline: keys from positions (block, then sub-cell class), radix
+// sort, permutation, block ranges, occupied and active block lists. Resets
+// the overflow lists. key_bits: bits of a block id or the sentinel. with_vc:
+// also permute v and C (false between fused substeps, where only x, F, E are
+// held in memory).
+void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool with_vc, hipStream_t st);
 
 // Transfers (the overflow list of the clock's parity takes drifted particles).
 // The solver is s.solver; `pass` selects the PB-MPM pass (PBPass) and is

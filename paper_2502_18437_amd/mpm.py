@@ -26,6 +26,7 @@ MPM_TOOL_NONE, MPM_TOOL_CAPSULE, MPM_TOOL_BOX, MPM_TOOL_PLANE = 0, 1, 2, 3
 MPM_TOOL_SLICER, MPM_TOOL_SEGMENT, MPM_TOOL_ARC = 4, 5, 6
 MPM_MAX_TOOLS = 8
 MPM_SOLVER_MLS, MPM_SOLVER_PIC, MPM_SOLVER_PB = 0, 1, 2
+MPM_REBIN_AUTO, MPM_REBIN_ADVANCE, MPM_REBIN_IN_PLACE = 0, 1, 2
 MPM_KERNEL_KINDS = 5
 KERNEL_NAMES = ("binning", "p2g", "g2p2g", "g2p", "grid")
 
@@ -63,7 +64,10 @@ class mpm_info(ctypes.Structure):
 
 class mpm_launch_config(ctypes.Structure):
     _fields_ = [("resort_interval", ctypes.c_int32), ("transfer_wgs", ctypes.c_int32),
-                ("graph_chunk", ctypes.c_int32)]
+                ("graph_chunk", ctypes.c_int32), ("rebin_mode", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class mpm_kernel_times(ctypes.Structure):
@@ -356,13 +360,15 @@ class Simulation:
     def launch_config(self):
         c = mpm_launch_config()
         self._check(_lib.mpm_get_launch_config(self.h, ctypes.byref(c)))
-        return {"resort_interval": c.resort_interval, "transfer_wgs": c.transfer_wgs, "graph_chunk": c.graph_chunk}
+        return c.as_dict()
 
-    def set_launch_config(self, resort_interval=None, transfer_wgs=None, graph_chunk=None):
+    def set_launch_config(self, resort_interval=None, transfer_wgs=None, graph_chunk=None, rebin_mode=None):
+        """Replace the given fields of the launch configuration (MPM_REBIN_*
+        for rebin_mode); the others keep their values."""
         cur = self.launch_config()
-        c = mpm_launch_config(int(resort_interval if resort_interval is not None else cur["resort_interval"]),
-                              int(transfer_wgs if transfer_wgs is not None else cur["transfer_wgs"]),
-                              int(graph_chunk if graph_chunk is not None else cur["graph_chunk"]))
+        given = {"resort_interval": resort_interval, "transfer_wgs": transfer_wgs, "graph_chunk": graph_chunk,
+                 "rebin_mode": rebin_mode}
+        c = mpm_launch_config(**{k: int(v if v is not None else cur[k]) for k, v in given.items()})
         self._check(_lib.mpm_set_launch_config(self.h, ctypes.byref(c)))
 
     def autotune(self, trial_substeps=32):
@@ -370,7 +376,7 @@ class Simulation:
         keep the fastest; returns it."""
         c = mpm_launch_config()
         self._check(_lib.mpm_autotune(self.h, int(trial_substeps), ctypes.byref(c)))
-        return {"resort_interval": c.resort_interval, "transfer_wgs": c.transfer_wgs, "graph_chunk": c.graph_chunk}
+        return c.as_dict()
 
     def profile(self, enable=True):
         self._check(_lib.mpm_profile(self.h, int(bool(enable))))
@@ -402,11 +408,16 @@ def eval_stress(F, E, nu):
 
 
 def simulation_from_scene(scene, **kw):
-    """Create a Simulation holding a scenes.Scene (particles and tools)."""
+    """Create a Simulation holding a scenes.Scene (particles and tools).
+    Keywords are Simulation parameters or launch-configuration fields
+    (transfer_wgs, graph_chunk, rebin_mode)."""
+    launch = {k: kw.pop(k) for k in ("transfer_wgs", "graph_chunk", "rebin_mode") if k in kw}
     params = dict(n_grid=scene.n_grid, dt=scene.dt, gravity=scene.gravity, wall_band=scene.wall_band,
                   nu=scene.nu, E_default=scene.E_default, max_particles=max(1, scene.N))
     params.update(kw)
     sim = Simulation(**params)
+    if launch:
+        sim.set_launch_config(**launch)
     sim.set_particles(scene.x, scene.v, scene.C, scene.F, scene.E, scene.mass, scene.vol0)
     for k, t in enumerate(scene.tools):
         sim.set_tool(k, t.type, **t.kwargs())

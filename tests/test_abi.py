@@ -50,7 +50,7 @@ int main(void) {
   printf("mpm_info SIZEOF %zu\n", sizeof(mpm_info));
   F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, n_range) F(mpm_info, tile) F(mpm_info, n_tools)
   printf("mpm_launch_config SIZEOF %zu\n", sizeof(mpm_launch_config));
-  F(mpm_launch_config, resort_interval) F(mpm_launch_config, transfer_wgs) F(mpm_launch_config, graph_chunk)
+  F(mpm_launch_config, resort_interval) F(mpm_launch_config, transfer_wgs) F(mpm_launch_config, graph_chunk) F(mpm_launch_config, rebin_mode)
   printf("mpm_kernel_times SIZEOF %zu\n", sizeof(mpm_kernel_times));
   F(mpm_kernel_times, total_ms) F(mpm_kernel_times, launches)
   return 0;
@@ -85,7 +85,7 @@ def test_status_codes_match_header():
     for name in ("MPM_OK", "MPM_EINVAL", "MPM_ENOMEM", "MPM_EHIP", "MPM_EDOMAIN", "MPM_ENONFINITE",
                  "MPM_EINVERTED", "MPM_ERANGE", "MPM_HOST", "MPM_DEVICE", "MPM_TOOL_CAPSULE", "MPM_TOOL_BOX",
                  "MPM_TOOL_PLANE", "MPM_ACCUM_FIXED", "MPM_KERNEL_KINDS", "MPM_MAX_TOOLS", "MPM_SOLVER_MLS",
-                 "MPM_SOLVER_PIC", "MPM_SOLVER_PB"):
+                 "MPM_SOLVER_PIC", "MPM_SOLVER_PB", "MPM_REBIN_AUTO", "MPM_REBIN_ADVANCE", "MPM_REBIN_IN_PLACE"):
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, text)
         assert m, name
         assert getattr(mpm, name) == int(m.group(1)), name

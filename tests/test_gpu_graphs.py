@@ -54,7 +54,8 @@ def test_launch_configurations_agree_in_fixed_mode():
     s = scenes.make("c3s")
     ref, _ = stepped(s, [30], {"graph_chunk": 8, "resort_interval": 32})
     for cfg in ({"transfer_wgs": 8, "resort_interval": 7}, {"transfer_wgs": 2048, "resort_interval": 1},
-                {"transfer_wgs": 512, "graph_chunk": 16, "resort_interval": 64}):
+                {"transfer_wgs": 512, "graph_chunk": 16, "resort_interval": 64},
+                {"resort_interval": 3, "rebin_mode": 2}, {"resort_interval": 16, "rebin_mode": 1}):
         got, _ = stepped(s, [30], cfg)
         for k in ("x", "v", "C", "F"):
             assert np.array_equal(ref[0][k], got[0][k]), (cfg, k)
@@ -78,6 +79,7 @@ def test_autotune_keeps_the_scene():
     print(f"[autotune c3s] {chosen}", flush=True)
     assert chosen["resort_interval"] in (1, 2, 4, 8, 16, 32, 64)
     assert chosen["transfer_wgs"] % 8 == 0 and chosen["graph_chunk"] in (0, 8)
+    assert chosen["rebin_mode"] in (mpm.MPM_REBIN_AUTO, mpm.MPM_REBIN_ADVANCE, mpm.MPM_REBIN_IN_PLACE)
     assert sim.launch_config() == chosen
     after, _ = sim.read_state()
     for k in ("x", "v", "C", "F"):

@@ -210,3 +210,20 @@ def test_switching_solvers_mid_run_matches_the_oracle():
     o.set_solver(O.SOLVER_PIC)
     assert o.step(20) == 0
     assert_parity({k: v.astype(np.float64) for k, v in r.items()}, o.read(), s.x, 40, "MLS then PIC")
+
+
+@pytest.mark.parametrize("solver", [PIC, (O.SOLVER_PB, 5, 0.6)])
+def test_solvers_with_thin_tools_and_a_velocity_table(solver):
+    """The other solvers share the grid update, so the slicer, the segment and
+    a capsule following a per-substep velocity table act on them too."""
+    from tests.test_gpu_adjoint import three_tool_scene
+    s = three_tool_scene()
+    s.solver = solver
+    n = s.n_substeps
+    g, imp, _ = gpu_with_impulses(s, n)
+    o = run_oracle(s, n)
+    assert g["status"] == 0 and o["status"] == 0
+    assert_parity(g, o, s.x, n, f"thin tools {solver}")
+    for q in range(3):
+        assert np.abs(o["impulses"][q]).max() > 0, q  # every tool touched the material
+    check_impulses(imp, o["impulses"], f"thin tools {solver}")
