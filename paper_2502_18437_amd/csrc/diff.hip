@@ -457,8 +457,13 @@ __device__ __forceinline__ int contact_frame_dev(const ToolK& t, const float* xI
       for (int i = 0; i < 3; ++i) e[i] = copysignf(o[i], pl[i]), De[4 * i] = q[i] > 0.0f ? 1.0f : 0.0f;
       use_e = true;
     } else {
-      nl[0] = nl[1] = nl[2] = 0.0f;
-      nl[k] = (pl[k] < 0.0f) ? -1.0f : 1.0f;
+      // face normal of axis k (selects rather than nl[k], pl[k], so that
+      // the arrays stay in registers)
+      const float pk = k == 0 ? pl[0] : (k == 1 ? pl[1] : pl[2]);
+      const float sg = (pk < 0.0f) ? -1.0f : 1.0f;
+      nl[0] = k == 0 ? sg : 0.0f;
+      nl[1] = k == 1 ? sg : 0.0f;
+      nl[2] = k == 2 ? sg : 0.0f;
     }
   } else if (t.type == TOOL_PLANE) {
     if (!(pl[1] < t.margin)) return LAW_NONE;

@@ -15,8 +15,9 @@
 
 namespace mpm {
 
-constexpr int kGridWG = 256;
+constexpr int kGridWG = 128;
 static_assert(kBlockNodes % kGridWG == 0, "every lane of the grid kernel must visit the same number of nodes");
+constexpr int kNodesPerLane = kBlockNodes / kGridWG;
 
 // Tool `d` at its pose of global substep k: the centre follows the constant
 // velocity from set_at, or the prefix sums of the velocity table and then the
@@ -82,29 +83,56 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
     __syncthreads();
     unsigned cnt = 0;
     float imp_w[3] = {0.0f, 0.0f, 0.0f};
-    for (int l = threadIdx.x; l < kBlockNodes; l += kGridWG) {
-      const size_t g = ((size_t)b << (3 * kTileLog2)) + (size_t)l;
-      // Mass and momentum of the node (P2G result), then the reset.
-      float m, p0, p1, p2;
-      if (s.fixed) {
-        m = (float)((uint32_t*)acc_m)[g] * s.m_unit;
-        p0 = (float)((double)((long long*)acc_p0)[g] * s.fx_p_inv);
-        p1 = (float)((double)((long long*)acc_p1)[g] * s.fx_p_inv);
-        p2 = (float)((double)((long long*)acc_p2)[g] * s.fx_p_inv);
+    // Mass and momentum of this lane's nodes (P2G result), all loaded before
+    // any is used so that the loads are in flight together, then the reset.
+    const size_t g0 = ((size_t)b << (3 * kTileLog2)) + (size_t)threadIdx.x;
+    float nm[kNodesPerLane], np0[kNodesPerLane], np1[kNodesPerLane], np2[kNodesPerLane];
+    if (s.fixed) {
+      uint32_t um[kNodesPerLane];
+      long long q0[kNodesPerLane], q1[kNodesPerLane], q2[kNodesPerLane];
+#pragma unroll
+      for (int r = 0; r < kNodesPerLane; ++r) {
+        const size_t g = g0 + (size_t)r * kGridWG;
+        um[r] = ((uint32_t*)acc_m)[g];
+        q0[r] = ((long long*)acc_p0)[g];
+        q1[r] = ((long long*)acc_p1)[g];
+        q2[r] = ((long long*)acc_p2)[g];
+      }
+#pragma unroll
+      for (int r = 0; r < kNodesPerLane; ++r) {
+        const size_t g = g0 + (size_t)r * kGridWG;
         ((uint32_t*)acc_m)[g] = 0u;
         ((long long*)acc_p0)[g] = 0ll;
         ((long long*)acc_p1)[g] = 0ll;
         ((long long*)acc_p2)[g] = 0ll;
-      } else {
-        m = ((float*)acc_m)[g];
-        p0 = ((float*)acc_p0)[g];
-        p1 = ((float*)acc_p1)[g];
-        p2 = ((float*)acc_p2)[g];
+        nm[r] = (float)um[r] * s.m_unit;
+        np0[r] = (float)((double)q0[r] * s.fx_p_inv);
+        np1[r] = (float)((double)q1[r] * s.fx_p_inv);
+        np2[r] = (float)((double)q2[r] * s.fx_p_inv);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kNodesPerLane; ++r) {
+        const size_t g = g0 + (size_t)r * kGridWG;
+        nm[r] = ((float*)acc_m)[g];
+        np0[r] = ((float*)acc_p0)[g];
+        np1[r] = ((float*)acc_p1)[g];
+        np2[r] = ((float*)acc_p2)[g];
+      }
+#pragma unroll
+      for (int r = 0; r < kNodesPerLane; ++r) {
+        const size_t g = g0 + (size_t)r * kGridWG;
         ((float*)acc_m)[g] = 0.0f;
         ((float*)acc_p0)[g] = 0.0f;
         ((float*)acc_p1)[g] = 0.0f;
         ((float*)acc_p2)[g] = 0.0f;
       }
+    }
+#pragma unroll
+    for (int r = 0; r < kNodesPerLane; ++r) {
+      const int l = threadIdx.x + r * kGridWG;
+      const size_t g = g0 + (size_t)r * kGridWG;
+      const float m = nm[r], p0 = np0[r], p1 = np1[r], p2 = np2[r];
       float v[3] = {0.0f, 0.0f, 0.0f};
       const bool live = m > 0.0f;
       const int i = bi * kTile + (l & (kTile - 1));

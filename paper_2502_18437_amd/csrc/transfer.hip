@@ -60,6 +60,22 @@ struct Counters {
   unsigned inv = 0, dom = 0, nf = 0, fb = 0, rng = 0;
 };
 
+// Events of one particle as bits of one word, added to the thread's Counters
+// once per particle. The per-particle code sets bits of a single scalar: had
+// it incremented different Counters fields on different paths, the compiler
+// could merge those increments into one store through a computed field
+// offset, leaving Counters as a per-thread array that it then places in LDS
+// (indexed by the flat work-item id, read from the dispatch packet).
+enum : unsigned { kEvInv = 1u, kEvDom = 2u, kEvNf = 4u, kEvRng = 8u, kEvFbG2P = 16u, kEvFbP2G = 32u };
+
+__device__ __forceinline__ void count_events(Counters& c, unsigned ev) {
+  c.inv += ev & 1u;
+  c.dom += (ev >> 1) & 1u;
+  c.nf += (ev >> 2) & 1u;
+  c.rng += (ev >> 3) & 1u;
+  c.fb += ((ev >> 4) & 1u) + ((ev >> 5) & 1u);
+}
+
 __device__ __forceinline__ void flush_counters(Status* st, const Counters& c) {
   if (c.inv) atomicAdd(&st->n_inverted, (unsigned long long)c.inv);
   if (c.dom) atomicAdd(&st->n_domain, (unsigned long long)c.dom);
@@ -288,12 +304,12 @@ __device__ __forceinline__ int lds_index(int lx, int ly, int lz) {
 // the block's tile, else straight into the global accumulator.
 template <bool FIXED, class In>
 __device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int* to, Lds& L, ACC_PARAMS,
-                                           uint32_t* mark, uint32_t* ovf, Status* st, int parity, Counters& cnt) {
+                                           uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   const int l0 = P.base[0] - to[0], l1 = P.base[1] - to[1], l2 = P.base[2] - to[2];
   const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
                        ((unsigned)l2 <= (unsigned)(kSpan - 3));
   if (!in_tile) {
-    cnt.fb++;
+    ev |= kEvFbP2G;
     p2g_global<FIXED>(s, P, ACC_ARGS, mark, ovf, st, parity, to[3]);
     return;
   }
@@ -318,16 +334,16 @@ __device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int
 template <bool FIXED, int SOL, int PASS>
 __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, const float* v, const float* C,
                                              const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
-                                             uint32_t* mark, uint32_t* ovf, Status* st, int parity, Counters& cnt) {
+                                             uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   constexpr bool kCount = !(SOL == SOLVER_PB && PASS == PB_ITER);
   P2GIn P;
   float f[3];
   if (!particle_stencil(s, x, P.base, f)) {
     if (kCount) {
       if (isfinite(x[0] + x[1] + x[2]))
-        cnt.dom++;
+        ev |= kEvDom;
       else
-        cnt.nf++;
+        ev |= kEvNf;
     }
     return;
   }
@@ -356,10 +372,10 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
 #pragma unroll
   for (int i = 0; i < 9; ++i) chk += Af[i];
   if (!isfinite(chk)) {
-    if (kCount) cnt.nf++;
+    if (kCount) ev |= kEvNf;
     return;
   }
-  if (kCount && inv) cnt.inv++;
+  if (kCount && inv) ev |= kEvInv;
   // Bound of |m v + A (x_I - x_p)| over the stencil (|x_I - x_p| <= 1.5 dx
   // per axis): contributions beyond the fixed-point range are refused.
   float bound = 0.0f;
@@ -369,7 +385,7 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
     bound = fmaxf(bound, fabsf(s.mass * vp[a]) + 1.5f * s.dx * row);
   }
   if (!(bound < s.p_limit)) {
-    cnt.rng++;
+    ev |= kEvRng;
     return;
   }
 #pragma unroll
@@ -379,7 +395,7 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
 #pragma unroll
     for (int b = 0; b < 3; ++b) P.Adx[3 * a + b] = (double)(Af[3 * a + b] * s.dx) * s.fx_p;
   }
-  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
 }
 
 // P2G of one particle for standard MPM (Sec. III-A): mass N m and momentum
@@ -391,14 +407,14 @@ template <bool FIXED>
 __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, const float* v, const float* C,
                                                  const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
                                                  uint32_t* mark, uint32_t* ovf, Status* st, int parity,
-                                                 Counters& cnt) {
+                                                 unsigned& ev) {
   PICIn P;
   float f[3];
   if (!particle_stencil(s, x, P.base, f)) {
     if (isfinite(x[0] + x[1] + x[2]))
-      cnt.dom++;
+      ev |= kEvDom;
     else
-      cnt.nf++;
+      ev |= kEvNf;
     return;
   }
 #pragma unroll
@@ -415,10 +431,10 @@ __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, 
     chk += P.tk[i] + C[i];
   }
   if (!isfinite(chk)) {
-    cnt.nf++;
+    ev |= kEvNf;
     return;
   }
-  if (!(J > 0.0f)) cnt.inv++;
+  if (!(J > 0.0f)) ev |= kEvInv;
   // |grad N dx| <= 9/16 per component, so |m v| + sum_b |tk[a][b]| bounds
   // every contribution.
   float bound = 0.0f;
@@ -428,11 +444,11 @@ __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, 
     bound = fmaxf(bound, fabsf(P.mv[a]) + fabsf(P.tk[3 * a]) + fabsf(P.tk[3 * a + 1]) + fabsf(P.tk[3 * a + 2]));
   }
   if (!(bound < s.p_limit)) {
-    cnt.rng++;
+    ev |= kEvRng;
     return;
   }
   P.fx_p = s.fx_p;
-  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
 }
 
 // G2P of one particle (Algorithm 1, third loop). APIC (MLS-MPM, PB-MPM):
@@ -443,7 +459,7 @@ __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, 
 template <int SOL>
 __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, const int* to,
                                              const Lds& L, const float4* vel, float* vn, float* Cn,
-                                             Counters& cnt) {
+                                             unsigned& ev) {
   int base[3];
   float f[3];
   if (!particle_stencil(s, x, base, f)) return false;
@@ -462,7 +478,7 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
       const int l = lds_index(l0, l1, l2);
       g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
     } else {
-      cnt.fb++;
+      ev |= kEvFbG2P;
       const int node_base = to[3] * s.n3;
       g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) {
         return vel[node_base + grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
@@ -480,7 +496,7 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
       const int l = lds_index(l0, l1, l2);
       g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
     } else {
-      cnt.fb++;
+      ev |= kEvFbG2P;
       g2p_global(s, base, w, vel, S, T, to[3]);
     }
     const float k = 4.0f * s.inv_dx;
@@ -556,11 +572,11 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 template <bool FIXED, int SOL, int PASS>
 __device__ __forceinline__ void p2g_any(const SimK& s, const float* x, const float* v, const float* C,
                                         const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
-                                        uint32_t* mark, uint32_t* ovf, Status* st, int parity, Counters& cnt) {
+                                        uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   if constexpr (SOL == SOLVER_PIC)
-    p2g_particle_pic<FIXED>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+    p2g_particle_pic<FIXED>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
   else
-    p2g_particle<FIXED, SOL, PASS>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+    p2g_particle<FIXED, SOL, PASS>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
 }
 
 // P2G from the materialised particle state (first substep after binning; for
@@ -599,7 +615,9 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
         F[i] = part[(FF + i) * cap + p];
       }
       const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
-      p2g_any<FIXED, SOL, PB_FIRST>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+      unsigned ev = 0u;
+      p2g_any<FIXED, SOL, PB_FIRST>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+      count_events(cnt, ev);
     }
     __syncthreads();
     tile_flush<FIXED>(s, to, L, ACC_ARGS);
@@ -644,7 +662,8 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
 #pragma unroll
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
-      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, cnt)) continue;  // frozen (out of grid)
+      unsigned ev = 0u;
+      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, ev)) continue;  // frozen (out of grid), no events
       if constexpr (kIntegrate) {
         float Fn[9];
 #pragma unroll
@@ -661,10 +680,11 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
 #pragma unroll
         for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
         const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
-        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
       } else {
-        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, cnt);
+        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
       }
+      count_events(cnt, ev);
     }
     __syncthreads();
     tile_flush<FIXED>(s, to, L, ACC_ARGS);
@@ -700,7 +720,9 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
 #pragma unroll
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
-      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, cnt)) continue;
+      unsigned ev = 0u;
+      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, ev)) continue;  // no events
+      count_events(cnt, ev);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
