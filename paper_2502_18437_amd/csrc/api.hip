@@ -101,6 +101,7 @@ struct mpm_handle {
   int pb_iterations = 10;                     // PB-MPM transfer passes per step
   int64_t since_sort = 0;
   bool dirty = true;
+  bool fresh_order = true;                    // particles replaced since the last binning: no block counts yet
   int resort_interval = kDefaultResort;
   int64_t resorts = 0;
   int transfer_wgs = 512;
@@ -726,6 +727,7 @@ int set_particles_impl(mpm_handle* h, const int64_t* counts, const float* x, con
   h->sim.p_limit = (float)std::ldexp(1.0, 50 - shift);
   h->since_sort = 0;
   h->dirty = true;
+  h->fresh_order = true;
   h->d.valid = false;
   drop_graphs(h);  // the recorded launches hold the old scene constants
   choose_item_size(h);
@@ -979,6 +981,11 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     }
     if (rebin) {
       ProfScope ps(h, 0);
+      // Binning orders a block's particles by sub-cell class when the block
+      // held few enough particles at the previous sort; new particles are
+      // first sorted once to get those counts.
+      if (h->fresh_order) launch_binning(b, N, h->sim, h->key_bits, k == 0 || advance, h->stream);
+      h->fresh_order = false;
       launch_binning(b, N, h->sim, h->key_bits, k == 0 || advance, h->stream);
       h->dirty = false;
       h->since_sort = 0;
