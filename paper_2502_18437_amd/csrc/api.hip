@@ -61,7 +61,19 @@ struct DiffBufs {
   float4* grids = nullptr;  // per substep: velocity after the grid update, then pre-contact velocity and mass
   int64_t grid_slots = 0;
   bool grids_kept = false;  // the forward kept the grid of every substep (checkpoint_every == 1)
-  uint32_t* order_info = nullptr;  // device: {work items, first position outside the grid} of the current order
+  // Particle orders of the forward pass, one slot per order period (the
+  // reverse pass reuses them): sorted caller indices, block ranges, work
+  // items and {work items, first position outside the grid}.
+  uint32_t* ord_idx = nullptr;
+  int64_t ord_idx_n = 0;
+  uint32_t* ord_begin = nullptr;
+  int64_t ord_begin_n = 0;
+  uint32_t* ord_end = nullptr;
+  int64_t ord_end_n = 0;
+  uint2* ord_work = nullptr;
+  int64_t ord_work_n = 0;
+  uint32_t* ord_info = nullptr;
+  int64_t ord_info_n = 0;
   bool valid = false;     // a rollout is recorded and nothing it depends on changed
   int T = 0, K = 1;
   int64_t start = 0;      // substep counter when the rollout began
@@ -314,7 +326,8 @@ void free_buffers(Buffers& b) {
 
 void free_diff(DiffBufs& d) {
   void* ptrs[] = {d.g.m, d.g.p[0], d.g.p[1], d.g.p[2], d.g.vel, d.g.vb[0], d.g.vb[1], d.g.vb[2], d.g.pb,
-                  d.g.skip, d.E, d.work, d.adj, d.ckpt, d.seg, d.tool_red, d.grids, d.order_info};
+                  d.g.skip, d.E, d.work, d.adj, d.ckpt, d.seg, d.tool_red, d.grids,
+                  d.ord_idx, d.ord_begin, d.ord_end, d.ord_work, d.ord_info};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DiffBufs();
@@ -425,10 +438,6 @@ hipError_t diff_alloc_base(mpm_handle* h) {
     if ((e = hipMalloc((void**)&d.adj, sizeof(float) * kStateFloats * N)) != hipSuccess) return e;
     d.part_cap = N;
   }
-  if (!d.order_info) {
-    hipError_t e = hipMalloc((void**)&d.order_info, sizeof(uint32_t) * 2);
-    if (e != hipSuccess) return e;
-  }
   // Accumulators the kernels expect to find cleared.
   for (int a = 0; a < 3; ++a) {
     launch_fill_f32(d.g.p[a], nn, 0.0f, h->stream);
@@ -443,10 +452,37 @@ hipError_t diff_alloc_base(mpm_handle* h) {
 // checkpoint in the reverse pass too) near 16.
 int order_period(int K) { return K * std::max(1, 16 / K); }
 
-// Spatial order of the rollout state `x` (caller order) for the scatters.
-DiffOrder rollout_order(mpm_handle* h, const float* x) {
-  const uint32_t* o = launch_order(h->b, h->N, h->sim, x, h->key_bits, kItemRollout, h->d.order_info, h->stream);
-  return DiffOrder{o, h->b.blk_end, h->b.work, h->d.order_info};
+// Work items an order can hold: one partial run per block plus one per
+// kItemRollout particles.
+int64_t order_work_cap(const mpm_handle* h) { return (int64_t)h->sim.nb3 + h->N / kItemRollout + 1; }
+
+// Room for `periods` orders of the current particle set.
+hipError_t alloc_orders(mpm_handle* h, int periods) {
+  DiffBufs& d = h->d;
+  const int64_t P = periods > 0 ? periods : 1;
+  hipError_t e = ensure(&d.ord_idx, &d.ord_idx_n, P * (h->N > 0 ? h->N : 1));
+  if (e == hipSuccess) e = ensure(&d.ord_begin, &d.ord_begin_n, P * (int64_t)h->sim.nb3);
+  if (e == hipSuccess) e = ensure(&d.ord_end, &d.ord_end_n, P * (int64_t)h->sim.nb3);
+  if (e == hipSuccess) e = ensure(&d.ord_work, &d.ord_work_n, P * order_work_cap(h));
+  if (e == hipSuccess) e = ensure(&d.ord_info, &d.ord_info_n, P * 2);
+  return e;
+}
+
+// Order slot `period` as the scatter kernels take it.
+DiffOrder order_slot(const mpm_handle* h, int period) {
+  const DiffBufs& d = h->d;
+  return DiffOrder{d.ord_idx + (int64_t)period * h->N, d.ord_end + (int64_t)period * h->sim.nb3,
+                   d.ord_work + (int64_t)period * order_work_cap(h), d.ord_info + 2 * (int64_t)period};
+}
+
+// Spatial order of the rollout state `x` (caller order) for the scatters,
+// computed into order slot `period`.
+hipError_t rollout_order(mpm_handle* h, const float* x, int period) {
+  DiffBufs& d = h->d;
+  return launch_order(h->b, h->N, h->sim, x, h->key_bits, kItemRollout, d.ord_idx + (int64_t)period * h->N,
+                      d.ord_begin + (int64_t)period * h->sim.nb3, d.ord_end + (int64_t)period * h->sim.nb3,
+                      d.ord_work + (int64_t)period * order_work_cap(h), d.ord_info + 2 * (int64_t)period,
+                      h->stream);
 }
 
 }  // namespace
@@ -1245,13 +1281,17 @@ int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_ev
   DState s0 = slot(0);
   launch_unpermute(h->b, N, s0.x, s0.v, s0.C, s0.F, h->stream);
   launch_clear_impulses(h->b, h->sim, h->stream);
-  // The binning scratch of the handle holds the rollout's particle orders;
-  // mpm_step re-bins afterwards.
+  // The orders are sorted in the binning scratch of the handle; mpm_step
+  // re-bins afterwards.
   h->dirty = true;
   const int R = order_period(K);
+  ALLOC_OR_RETURN(h, alloc_orders(h, (T + R - 1) / R));
   DiffOrder ord{};
   for (int k = 0; k < T; ++k) {
-    if (k % R == 0) ord = rollout_order(h, slot(k).x);
+    if (k % R == 0) {
+      HIP_OR_RETURN(h, rollout_order(h, slot(k).x, k / R));
+      ord = order_slot(h, k / R);
+    }
     float4* vel = d.grids_kept ? d.grids + (int64_t)k * 2 * nn : d.g.vel;
     float4* hat = d.grids_kept ? vel + nn : nullptr;
     launch_diff_substep(d.g, vel, hat, h->sim, tools_at(h, h->substep), N, slot(k), d.E, slot(k + 1), true,
@@ -1308,18 +1348,10 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
   launch_fill_f32(theta_bar, N, 0.0f, h->stream);
   launch_fill_f64(d.tool_red, (int64_t)T * red_row * kToolRedCopies, 0.0, h->stream);
   auto grid_of = [&](int slot_index) -> float4* { return d.grids + (int64_t)slot_index * 2 * nn; };
-  // Particle orders as in the forward pass: one per order_period(K)
-  // substeps, taken from the checkpoint that starts the period.
+  // The forward pass's particle orders: one per order_period(K) substeps.
   const int R = order_period(K);
-  int order_at = -1;
   DiffOrder ord{};
-  auto order_for = [&](int j) {
-    const int r = j / R * R;
-    if (r != order_at) {
-      ord = rollout_order(h, dstate(d.ckpt + (int64_t)(r / K) * SF, N).x);
-      order_at = r;
-    }
-  };
+  auto order_for = [&](int j) { ord = order_slot(h, j / R); };
   h->dirty = true;
   if (d.grids_kept) {
     for (int j = T - 1; j >= 0; --j) {

@@ -455,25 +455,26 @@ __global__ void k_first_sentinel(const uint32_t* __restrict__ keys, int64_t N, u
     if (keys[i] >= sentinel && (i == 0 || keys[i - 1] < sentinel)) *out = (uint32_t)i;
 }
 
-const uint32_t* launch_order(Buffers& b, int64_t N, const SimK& s, const float* x, int key_bits, uint32_t item,
-                             uint32_t* info, hipStream_t st) {
+hipError_t launch_order(Buffers& b, int64_t N, const SimK& s, const float* x, int key_bits, uint32_t item,
+                        uint32_t* order, uint32_t* begin, uint32_t* end, uint2* work, uint32_t* info,
+                        hipStream_t st) {
   const uint32_t n_blocks = s.nb3;
   hipLaunchKernelGGL(k_order_keys, dim3(grid_for(N, 256)), dim3(256), 0, st, x, N, s, n_blocks, b.keys[0],
                      b.vals[0]);
   const int src = radix_sort(b, N, key_bits, st);
-  fill_u32(b.blk_begin, n_blocks, 0u, st);
-  fill_u32(b.blk_end, n_blocks, 0u, st);
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks, 0,
-                     b.blk_begin, b.blk_end);
-  hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     n_blocks, item, b.flags);
+  fill_u32(begin, n_blocks, 0u, st);
+  fill_u32(end, n_blocks, 0u, st);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks, 0, begin, end);
+  hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, begin, end, n_blocks, item,
+                     b.flags);
   exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &info[0], st);
-  hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     b.flags, n_blocks, item, 0xffffffffu, b.work);  // never flagged
+  hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, begin, end, b.flags, n_blocks,
+                     item, 0xffffffffu, work);  // never flagged
   fill_u32(&info[1], 1, (uint32_t)N, st);
   hipLaunchKernelGGL(k_first_sentinel, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks,
                      &info[1]);
-  return b.vals[src];
+  if (N == 0) return hipSuccess;
+  return hipMemcpyAsync(order, b.vals[src], sizeof(uint32_t) * (size_t)N, hipMemcpyDeviceToDevice, st);
 }
 
 // ------------------------------------------------------------------ diagnostics

@@ -205,16 +205,18 @@ void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st, bool gr
 void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st);
 
 // Spatial order of a one-scene particle set held as an AoS x (N x 3) in the
-// caller's order, for the rollout's tiled scatters: sorts the particles by the
+// caller's order, for the rollout's tiled scatters. Sorts the particles by the
 // grid block of their base cell (particles whose stencil leaves the grid or
-// whose x is not finite last) into the handle's binning scratch, fills
-// b.blk_begin / b.blk_end and the work items b.work (runs of at most `item`
-// particles of one block), writes info[0] = the number of items and
-// info[1] = the first sorted position of the particles left out, and returns
-// the sorted caller indices (b.keys / b.vals scratch, valid until the next
-// binning or order).
-const uint32_t* launch_order(Buffers& b, int64_t N, const SimK& s, const float* x, int key_bits, uint32_t item,
-                             uint32_t* info, hipStream_t st);
+// whose x is not finite last) in the handle's binning scratch, then writes the
+// sorted caller indices to order (N entries), the block ranges to begin / end
+// (nb3 entries each), the work items to work (runs of at most `item`
+// particles of one block; at most nb3 + N / item + 1 of them), info[0] = the
+// number of items and info[1] = the first sorted position of the particles
+// left out. Every output is caller-owned device memory. Returns the error of
+// the final copy (kernel launch errors show in hipGetLastError).
+hipError_t launch_order(Buffers& b, int64_t N, const SimK& s, const float* x, int key_bits, uint32_t item,
+                        uint32_t* order, uint32_t* begin, uint32_t* end, uint2* work, uint32_t* info,
+                        hipStream_t st);
 
 // Nodes with mass in the last grid update (sum of node_cnt over the active
 // and overflow blocks of `parity`), written to *out (device memory).
