@@ -1353,12 +1353,16 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
   DiffOrder ord{};
   auto order_for = [&](int j) { ord = order_slot(h, j / R); };
   h->dirty = true;
+  // The P2G reverse of substep j + 1 (its tail) runs inside the G2P reverse
+  // of substep j; only the tail of substep 0 runs on its own.
   if (d.grids_kept) {
     for (int j = T - 1; j >= 0; --j) {
       float4* vel = grid_of(j);
       order_for(j);
-      launch_diff_adjoint(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, dstate(d.ckpt + (int64_t)j * SF, N),
-                          d.E, adj, theta_bar, d.tool_red + (int64_t)j * red_row * kToolRedCopies, ord, h->stream);
+      const DState next = dstate(d.ckpt + (int64_t)(j + 1) * SF, N);
+      launch_adjoint_head(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, dstate(d.ckpt + (int64_t)j * SF, N),
+                          d.E, adj, theta_bar, d.tool_red + (int64_t)j * red_row * kToolRedCopies, ord,
+                          j + 1 < T ? &next : nullptr, h->stream);
     }
   } else {
     const DState none = {nullptr, nullptr, nullptr, nullptr};
@@ -1380,11 +1384,15 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
       for (int i = n_in - 1; i >= 0; --i) {
         const int j = s0 + i;
         float4* vel = grid_of(i);
-        launch_diff_adjoint(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, st(i), d.E, adj, theta_bar,
-                            d.tool_red + (int64_t)j * red_row * kToolRedCopies, ord, h->stream);
+        // the state after substep j: the next segment's checkpoint at the end
+        const DState next = i + 1 < n_in ? st(i + 1) : dstate(d.ckpt + (int64_t)(a + 1) * SF, N);
+        launch_adjoint_head(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, st(i), d.E, adj, theta_bar,
+                            d.tool_red + (int64_t)j * red_row * kToolRedCopies, ord, j + 1 < T ? &next : nullptr,
+                            h->stream);
       }
     }
   }
+  if (T > 0) launch_adjoint_tail(d.g, h->sim, N, dstate(d.ckpt, N), d.E, adj, theta_bar, h->stream);
   float* outs[4] = {xb0, vb0, Cb0, Fb0};
   for (int f = 0; f < 4; ++f)
     if (outs[f])

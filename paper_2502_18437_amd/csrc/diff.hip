@@ -626,6 +626,90 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // ---------------------------------------------------------------- adjoint kernels
+// P2G reverse of one particle: gather of the momentum and mass cotangents,
+// then the stress adjoint. Writes its v and C cotangents, adds to those of x
+// and F and to d/d log E, and returns the resulting x, v, C, F cotangents in
+// xb, vb, Cb, Fb; returns false (nothing changed) for a particle the
+// substep skipped.
+__device__ __forceinline__ bool bp2g_particle(const SimK& s, int64_t p, const DState& in,
+                                              const float* __restrict__ E, const float4* __restrict__ pb,
+                                              const DState& adj, float* __restrict__ theta_bar, float* xb,
+                                              float* vb, float* Cb, float* Fb) {
+  float x[3], v[3], C[9], F[9];
+  load_state(in, p, x, v, C, F);
+  const float e = E[p];
+  int base[3];
+  float f[3];
+  if (particle_state(s, x, v, C, F, e, base, f) != 0) return false;
+  float w[3][3], dw[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]), bspline_dw(f[a], dw[a]);
+  const float mu = s.c_mu * e, la = s.c_la * e;
+  float tau[9], R[9];
+  bool inv;
+  const float J = kirchhoff_r(F, mu, la, tau, R, &inv);
+  float A[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) A[i] = s.mass * C[i] - s.p2g_stress * tau[i];
+  float vbar[3] = {0.0f, 0.0f, 0.0f}, Ab[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, xg[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+  for (int ox = 0; ox < 3; ++ox)
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz) {
+        const float Nw = w[0][ox] * w[1][oy] * w[2][oz];
+        const float dN[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * s.inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * s.inv_dx,
+                             w[0][ox] * w[1][oy] * dw[2][oz] * s.inv_dx};
+        const float d[3] = {((float)ox - f[0]) * s.dx, ((float)oy - f[1]) * s.dx, ((float)oz - f[2]) * s.dx};
+        const float4 g = pb[dense_index(s, base[0] + ox, base[1] + oy, base[2] + oz)];
+        const float P[3] = {g.x, g.y, g.z};
+        float contrib = s.mass * g.w;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          contrib += P[a] * (s.mass * v[a] + A[3 * a] * d[0] + A[3 * a + 1] * d[1] + A[3 * a + 2] * d[2]);
+          vbar[a] += Nw * s.mass * P[a];
+#pragma unroll
+          for (int b = 0; b < 3; ++b) Ab[3 * a + b] += Nw * P[a] * d[b];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xg[j] += dN[j] * contrib - Nw * (A[j] * P[0] + A[3 + j] * P[1] + A[6 + j] * P[2]);
+      }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fb[i] = adj.F[9 * p + i];
+  // tau cotangent: A = m C - p2g_stress tau
+  float tb[9];
+  float th = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) tb[i] = -s.p2g_stress * Ab[i], th += tb[i] * tau[i];
+  // tau1 = 2 mu (F - R) F^T: Fb += 2 mu (tb F + tb^T (F - R)), Rb = -2 mu tb F
+  float tbF[9], Rb[9], D[9], tbtD[9];
+  mm3(tb, F, tbF);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) D[i] = F[i] - R[i];
+  mtm3(tb, D, tbtD);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fb[i] += 2.0f * mu * (tbF[i] + tbtD[i]), Rb[i] = -2.0f * mu * tbF[i];
+  polar_adjoint_dev(F, R, Rb, Fb);
+  // tau2 = la (J^2 - J) I: Fb += la (2J - 1) tr(tb) cof(F)
+  float cf[9];
+  cof3(F, cf);
+  const float kv = la * (2.0f * J - 1.0f) * (tb[0] + tb[4] + tb[8]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Fb[i] += kv * cf[i], adj.F[9 * p + i] = Fb[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    xb[a] = adj.x[3 * p + a] + xg[a];
+    adj.x[3 * p + a] = xb[a];
+    vb[a] = vbar[a];
+    adj.v[3 * p + a] = vb[a];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Cb[i] = s.mass * Ab[i], adj.C[9 * p + i] = Cb[i];
+  theta_bar[p] += th;
+  return true;
+}
+
 // G2P reverse: scatter of the grid-velocity cotangent, x and F cotangents.
 //
 // A work item has at most one particle per thread. The cotangent
@@ -644,9 +728,15 @@ struct BG2PTile {
   float wmax[kDWG / 64];
 };
 
+// With FUSED, the P2G reverse of the substep that follows (state `next`,
+// momentum and mass cotangents `pb`) runs first for each particle, in the
+// same thread: it reads only that particle's data, and a particle this
+// substep skips was skipped by the next one too (it did not move).
+template <bool FUSED>
 __global__ __launch_bounds__(kDWG) void k_bg2p(SimK s, int64_t N, DState in, const float* __restrict__ E,
                                                const float4* __restrict__ vel, DiffOrder o, DState adj,
-                                               float* gvb0, float* gvb1, float* gvb2) {
+                                               float* gvb0, float* gvb1, float* gvb2, DState next,
+                                               const float4* __restrict__ pb, float* __restrict__ theta_bar) {
   __shared__ BG2PTile T;
   const float Minv = 4.0f * s.inv_dx * s.inv_dx;
   unsigned pos, end, stride;
@@ -706,7 +796,8 @@ __global__ __launch_bounds__(kDWG) void k_bg2p(SimK s, int64_t N, DState in, con
           wx1 = wx2;
         }
         float vb[3], Cb[9], Fb[9];
-        load_state(adj, p, xb, vb, Cb, Fb);
+        if (!(FUSED && bp2g_particle(s, p, next, E, pb, adj, theta_bar, xb, vb, Cb, Fb)))
+          load_state(adj, p, xb, vb, Cb, Fb);
         // x' = x + dt v', F' = G F (G = I + dt C'), C' = Minv B, v' = sum N v_I.
 #pragma unroll
         for (int a = 0; a < 3; ++a) vnb[a] = vb[a] + s.dt * xb[a];
@@ -894,81 +985,14 @@ __global__ __launch_bounds__(kDWG) void k_bgrid(SimK s, ToolSetK ts, const float
   }
 }
 
-// P2G reverse: gather of the momentum and mass cotangents, then the stress
-// adjoint. Writes the v and C cotangents, adds to those of x and F and to
-// d/d log E.
+// P2G reverse of every particle (the last step of a substep's reverse when
+// no G2P reverse of the substep before follows it).
 __global__ __launch_bounds__(kDWG) void k_bp2g(SimK s, int64_t N, DState in, const float* __restrict__ E,
                                                const float4* __restrict__ pb, DState adj,
                                                float* __restrict__ theta_bar) {
   for (int64_t p = blockIdx.x * (int64_t)kDWG + threadIdx.x; p < N; p += (int64_t)gridDim.x * kDWG) {
-    float x[3], v[3], C[9], F[9];
-    load_state(in, p, x, v, C, F);
-    const float e = E[p];
-    int base[3];
-    float f[3];
-    if (particle_state(s, x, v, C, F, e, base, f) != 0) continue;
-    float w[3][3], dw[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]), bspline_dw(f[a], dw[a]);
-    const float mu = s.c_mu * e, la = s.c_la * e;
-    float tau[9], R[9];
-    bool inv;
-    const float J = kirchhoff_r(F, mu, la, tau, R, &inv);
-    float A[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) A[i] = s.mass * C[i] - s.p2g_stress * tau[i];
-    float vbar[3] = {0.0f, 0.0f, 0.0f}, Ab[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, xg[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll 1
-    for (int ox = 0; ox < 3; ++ox)
-#pragma unroll
-      for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-          const float Nw = w[0][ox] * w[1][oy] * w[2][oz];
-          const float dN[3] = {dw[0][ox] * w[1][oy] * w[2][oz] * s.inv_dx, w[0][ox] * dw[1][oy] * w[2][oz] * s.inv_dx,
-                               w[0][ox] * w[1][oy] * dw[2][oz] * s.inv_dx};
-          const float d[3] = {((float)ox - f[0]) * s.dx, ((float)oy - f[1]) * s.dx, ((float)oz - f[2]) * s.dx};
-          const float4 g = pb[dense_index(s, base[0] + ox, base[1] + oy, base[2] + oz)];
-          const float P[3] = {g.x, g.y, g.z};
-          float contrib = s.mass * g.w;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            contrib += P[a] * (s.mass * v[a] + A[3 * a] * d[0] + A[3 * a + 1] * d[1] + A[3 * a + 2] * d[2]);
-            vbar[a] += Nw * s.mass * P[a];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) Ab[3 * a + b] += Nw * P[a] * d[b];
-          }
-#pragma unroll
-          for (int j = 0; j < 3; ++j) xg[j] += dN[j] * contrib - Nw * (A[j] * P[0] + A[3 + j] * P[1] + A[6 + j] * P[2]);
-        }
-    float Fb[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Fb[i] = adj.F[9 * p + i];
-    // tau cotangent: A = m C - p2g_stress tau
-    float tb[9];
-    float th = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) tb[i] = -s.p2g_stress * Ab[i], th += tb[i] * tau[i];
-    // tau1 = 2 mu (F - R) F^T: Fb += 2 mu (tb F + tb^T (F - R)), Rb = -2 mu tb F
-    float tbF[9], Rb[9], D[9], tbtD[9];
-    mm3(tb, F, tbF);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) D[i] = F[i] - R[i];
-    mtm3(tb, D, tbtD);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Fb[i] += 2.0f * mu * (tbF[i] + tbtD[i]), Rb[i] = -2.0f * mu * tbF[i];
-    polar_adjoint_dev(F, R, Rb, Fb);
-    // tau2 = la (J^2 - J) I: Fb += la (2J - 1) tr(tb) cof(F)
-    float cf[9];
-    cof3(F, cf);
-    const float kv = la * (2.0f * J - 1.0f) * (tb[0] + tb[4] + tb[8]);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) adj.F[9 * p + i] = Fb[i] + kv * cf[i];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) adj.x[3 * p + a] += xg[a], adj.v[3 * p + a] = vbar[a];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) adj.C[9 * p + i] = s.mass * Ab[i];
-    theta_bar[p] += th;
+    float xb[3], vb[3], Cb[9], Fb[9];
+    (void)bp2g_particle(s, p, in, E, pb, adj, theta_bar, xb, vb, Cb, Fb);
   }
 }
 
@@ -1019,14 +1043,22 @@ void launch_diff_substep(const DiffGrid& g, float4* vel, float4* hat, const SimK
                        (const uint8_t*)g.skip, out);
 }
 
-void launch_diff_adjoint(const DiffGrid& g, const float4* vel, const float4* hat, const SimK& s,
+void launch_adjoint_head(const DiffGrid& g, const float4* vel, const float4* hat, const SimK& s,
                          const ToolSetK& tools, int64_t N, DState in, const float* E, DState adj, float* theta_bar,
-                         double* tool_red, const DiffOrder& o, hipStream_t stream) {
+                         double* tool_red, const DiffOrder& o, const DState* pending, hipStream_t stream) {
   const int64_t nn = (int64_t)s.n * s.n * s.n;
-  hipLaunchKernelGGL(k_bg2p, dim3(kScatterWGs), dim3(kDWG), 0, stream, s, N, in, E, vel, o, adj, g.vb[0], g.vb[1],
-                     g.vb[2]);
+  if (pending)
+    hipLaunchKernelGGL(k_bg2p<true>, dim3(kScatterWGs), dim3(kDWG), 0, stream, s, N, in, E, vel, o, adj, g.vb[0],
+                       g.vb[1], g.vb[2], *pending, (const float4*)g.pb, theta_bar);
+  else
+    hipLaunchKernelGGL(k_bg2p<false>, dim3(kScatterWGs), dim3(kDWG), 0, stream, s, N, in, E, vel, o, adj, g.vb[0],
+                       g.vb[1], g.vb[2], in, (const float4*)g.pb, theta_bar);
   hipLaunchKernelGGL(k_bgrid, dim3(blocks_for(nn)), dim3(kDWG), 0, stream, s, tools, hat, g.vb[0],
                      g.vb[1], g.vb[2], g.pb, tool_red);
+}
+
+void launch_adjoint_tail(const DiffGrid& g, const SimK& s, int64_t N, DState in, const float* E, DState adj,
+                         float* theta_bar, hipStream_t stream) {
   hipLaunchKernelGGL(k_bp2g, dim3(blocks_for(N)), dim3(kDWG), 0, stream, s, N, in, E, (const float4*)g.pb, adj,
                      theta_bar);
 }

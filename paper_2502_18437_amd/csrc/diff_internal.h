@@ -58,15 +58,22 @@ void launch_diff_substep(const DiffGrid& g, float4* vel, float4* hat, const SimK
                          int64_t N, DState in, const float* E, DState out, bool count, Status* st,
                          const DiffOrder& o, hipStream_t stream);
 // Reverse of one substep from the state `in` it started from and its grid
-// (`vel`, `hat`) as its forward pass left them: on entry `adj` is
-// the cotangent of the state after the substep, on exit that of `in`. Adds
-// d/d log E to theta_bar and the tools' linear-velocity and centre cotangents
-// to tool_red[kToolRedCopies][kMaxTools * 6] (FP64): each workgroup adds its
+// (`vel`, `hat`) as its forward pass left them, in two parts: the head (G2P
+// reverse, grid reverse) and the tail (P2G reverse). On entry `adj` is the
+// cotangent of the state after the substep, after the tail that of `in`.
+// The tail may be deferred: the head of the substep before, given that
+// substep's successor state as `pending`, runs it per particle inside its
+// G2P reverse (the grid cotangents in g.pb stay valid until the next head's
+// grid reverse). The last tail runs on its own. Adds d/d log E to theta_bar
+// and the tools' linear-velocity and centre cotangents to
+// tool_red[kToolRedCopies][kMaxTools * 6] (FP64): each workgroup adds its
 // sums into one of the copies, so that the FP64 atomics of the many
 // workgroups that touch a tool do not all meet on one address.
-void launch_diff_adjoint(const DiffGrid& g, const float4* vel, const float4* hat, const SimK& s,
+void launch_adjoint_head(const DiffGrid& g, const float4* vel, const float4* hat, const SimK& s,
                          const ToolSetK& tools, int64_t N, DState in, const float* E, DState adj, float* theta_bar,
-                         double* tool_red, const DiffOrder& o, hipStream_t stream);
+                         double* tool_red, const DiffOrder& o, const DState* pending, hipStream_t stream);
+void launch_adjoint_tail(const DiffGrid& g, const SimK& s, int64_t N, DState in, const float* E, DState adj,
+                         float* theta_bar, hipStream_t stream);
 // out[j][c] = sum over the copies of parts[j][copy][c] (j < T, c < kMaxTools * 6).
 void launch_sum_tool_copies(const double* parts, int T, double* out, hipStream_t st);
 // Fill helpers.
