@@ -892,6 +892,14 @@ int upload_tools(mpm_handle* h) {
   HIP_OR_RETURN(h, hipMemcpyAsync(h->b.tools, desc.data(), sizeof(ToolDesc) * desc.size(), hipMemcpyHostToDevice,
                                   h->stream));
   h->tools_dirty = false;
+  // The grid update scans the slots up to the highest one in use.
+  int slots = 0;
+  for (size_t slot = 0; slot < desc.size(); ++slot)
+    if (h->tools[slot].active) slots = std::max(slots, (int)(slot % kMaxTools) + 1);
+  if (slots != h->sim.tool_slots) {
+    h->sim.tool_slots = slots;
+    drop_graphs(h);  // the recorded launches hold the scene constants
+  }
   return MPM_OK;
 }
 

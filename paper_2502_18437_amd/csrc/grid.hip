@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
       // workgroup size), so the wave reductions see full waves.
       const float xI[3] = {(float)i * s.dx, (float)j * s.dx, (float)k * s.dx};
 #pragma unroll 1
-      for (int q = 0; q < kMaxTools; ++q) {
+      for (int q = 0; q < s.tool_slots; ++q) {
         if (td[q].k.type == TOOL_NONE) continue;
         float dm[3] = {0.0f, 0.0f, 0.0f};
         if (live) {

@@ -113,6 +113,7 @@ struct SimK {
   int solver;        // Solver: which transfer scheme and constitutive model the kernels run
   float pic_force;   // standard MPM: dt * vol0 / dx (internal force per unit of tau grad N dx)
   float pb_beta;     // PB-MPM: rotation weight of the co-rotational constraint
+  int tool_slots;    // 1 + the highest tool slot in use in any scene (0: no tools)
   unsigned item_particles;  // particles per transfer work item (at most)
 };
 
