@@ -128,56 +128,66 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
         ((float*)acc_p2)[g] = 0.0f;
       }
     }
+    // Grid velocities of this lane's nodes: v = p/m + dt g where there is
+    // mass (Sec. III-A), 0 elsewhere.
+    float v[kNodesPerLane][3];
+#pragma unroll
+    for (int r = 0; r < kNodesPerLane; ++r) {
+      v[r][0] = v[r][1] = v[r][2] = 0.0f;
+      if (nm[r] > 0.0f) {
+        cnt++;
+        const float im = 1.0f / nm[r];
+        v[r][0] = np0[r] * im + s.dt * s.g[0];
+        v[r][1] = np1[r] * im + s.dt * s.g[1];
+        v[r][2] = np2[r] * im + s.dt * s.g[2];
+      }
+    }
+    // Tools in id order, each applied to every node of the lane; the pose is
+    // computed once per tool. The loop runs on every lane (kBlockNodes is a
+    // multiple of the workgroup size), so the wave reductions see full waves.
+#pragma unroll 1
+    for (int q = 0; q < s.tool_slots; ++q) {
+      if (td[q].k.type == TOOL_NONE) continue;
+      const ToolK t = tool_at(td[q], substep, (double)s.dt);
+      float dm[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int r = 0; r < kNodesPerLane; ++r) {
+        if (!(nm[r] > 0.0f)) continue;
+        const int l = threadIdx.x + r * kGridWG;
+        const float xI[3] = {(float)(bi * kTile + (l & (kTile - 1))) * s.dx,
+                             (float)(bj * kTile + ((l >> kTileLog2) & (kTile - 1))) * s.dx,
+                             (float)(bk * kTile + (l >> (2 * kTileLog2))) * s.dx};
+        const float vb[3] = {v[r][0], v[r][1], v[r][2]};
+        if (tool_contact(t, xI, v[r])) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) dm[c] += nm[r] * (v[r][c] - vb[c]);
+        }
+      }
+      if (__ballot(dm[0] != 0.0f || dm[1] != 0.0f || dm[2] != 0.0f) != 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float x = dm[c];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+          if (lane == 0) red_t[wave][3 * q + c] = x;
+        }
+      }
+    }
+    // Sticky walls, then the velocities out.
 #pragma unroll
     for (int r = 0; r < kNodesPerLane; ++r) {
       const int l = threadIdx.x + r * kGridWG;
-      const size_t g = g0 + (size_t)r * kGridWG;
-      const float m = nm[r], p0 = np0[r], p1 = np1[r], p2 = np2[r];
-      float v[3] = {0.0f, 0.0f, 0.0f};
-      const bool live = m > 0.0f;
       const int i = bi * kTile + (l & (kTile - 1));
       const int j = bj * kTile + ((l >> kTileLog2) & (kTile - 1));
       const int k = bk * kTile + (l >> (2 * kTileLog2));
-      if (live) {
-        cnt++;
-        const float im = 1.0f / m;
-        v[0] = p0 * im + s.dt * s.g[0];
-        v[1] = p1 * im + s.dt * s.g[1];
-        v[2] = p2 * im + s.dt * s.g[2];
-      }
-      // The tool loop runs on every lane (kBlockNodes is a multiple of the
-      // workgroup size), so the wave reductions see full waves.
-      const float xI[3] = {(float)i * s.dx, (float)j * s.dx, (float)k * s.dx};
-#pragma unroll 1
-      for (int q = 0; q < s.tool_slots; ++q) {
-        if (td[q].k.type == TOOL_NONE) continue;
-        float dm[3] = {0.0f, 0.0f, 0.0f};
-        if (live) {
-          const ToolK t = tool_at(td[q], substep, (double)s.dt);
-          const float vb[3] = {v[0], v[1], v[2]};
-          if (tool_contact(t, xI, v)) {
+      if (nm[r] > 0.0f && (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi)) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) dm[a] = m * (v[a] - vb[a]);
-          }
-        }
-        if (__ballot(dm[0] != 0.0f || dm[1] != 0.0f || dm[2] != 0.0f) != 0) {
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            float x = dm[a];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-            if (lane == 0) red_t[wave][3 * q + a] += x;
-          }
+        for (int c = 0; c < 3; ++c) {
+          imp_w[c] -= nm[r] * v[r][c];
+          v[r][c] = 0.0f;
         }
       }
-      if (live && (i < lo || i > hi || j < lo || j > hi || k < lo || k > hi)) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          imp_w[a] -= m * v[a];
-          v[a] = 0.0f;
-        }
-      }
-      vel[g] = make_float4(v[0], v[1], v[2], 0.0f);
+      vel[g0 + (size_t)r * kGridWG] = make_float4(v[r][0], v[r][1], v[r][2], 0.0f);
     }
     // Nodes with mass in this block (plain store, summed on demand by the host
     // call that reports it; a shared counter would serialise every workgroup).
