@@ -270,18 +270,30 @@ __global__ __launch_bounds__(kSortWG) void k_radix_scatter(const uint32_t* __res
 }
 
 // ------------------------------------------------------------------ permutation, ranges
-// Gathers fields [0, n_fields) of the particle SoA into key order; with
-// skip_vc the v and C fields are left out (they are not live).
+// Gathers the particle SoA into key order: x, F, E (when stored) and, with
+// VC, v and C (between fused substeps they are not live). The field loops
+// are unrolled so that a lane's loads are all in flight before its stores.
+template <bool VC, bool HAS_E>
 __global__ void k_permute(const float* __restrict__ src, float* __restrict__ dst,
                           const uint32_t* __restrict__ id_src, uint32_t* __restrict__ id_dst,
-                          const uint32_t* __restrict__ perm, int64_t cap, int64_t N, int n_fields, int skip_vc) {
+                          const uint32_t* __restrict__ perm, int64_t cap, int64_t N) {
+  constexpr int kLo = VC ? FX : FF;  // fields [FX, FX + 3) and [kLo, kEnd)
+  constexpr int kEnd = HAS_E ? kFields : kFields - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t j = perm[i];
-    for (int f = 0; f < n_fields; ++f) {
-      if (skip_vc && f == FV) f = FF;
-      dst[f * cap + i] = src[f * cap + j];
-    }
-    id_dst[i] = id_src[j];
+    float x[3], r[kEnd - kLo];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) x[f] = src[(FX + f) * cap + j];
+#pragma unroll
+    for (int f = kLo; f < kEnd; ++f)
+      if (f >= FV) r[f - kLo] = src[f * cap + j];
+    const uint32_t id = id_src[j];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) dst[(FX + f) * cap + i] = x[f];
+#pragma unroll
+    for (int f = kLo; f < kEnd; ++f)
+      if (f >= FV) dst[f * cap + i] = r[f - kLo];
+    id_dst[i] = id;
   }
 }
 
@@ -393,9 +405,17 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool wit
   // 2. stable LSD radix sort, 8 bits per pass
   const int src = radix_sort(b, N, key_bits + kClassBits, st);
   // 3. gather the particle state into key order
-  const int n_fields = s.has_E ? kFields : kFields - 1;
-  hipLaunchKernelGGL(k_permute, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.part[b.cur ^ 1],
-                     b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N, n_fields, with_vc ? 0 : 1);
+  const dim3 pg(grid_for(N, 256)), pb(256);
+  const float* ps = b.part[b.cur];
+  float* pd = b.part[b.cur ^ 1];
+  if (with_vc && s.has_E)
+    hipLaunchKernelGGL((k_permute<true, true>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
+  else if (with_vc)
+    hipLaunchKernelGGL((k_permute<true, false>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
+  else if (s.has_E)
+    hipLaunchKernelGGL((k_permute<false, true>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
+  else
+    hipLaunchKernelGGL((k_permute<false, false>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
   b.cur ^= 1;
   // 4. per-block ranges
   fill_u32(b.blk_begin, n_blocks, 0u, st);

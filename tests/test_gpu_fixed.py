@@ -5,6 +5,7 @@ tolerances."""
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_2502_18437_amd import scenes
 from tests.parity import assert_parity, run_gpu, run_oracle
 
@@ -72,15 +73,18 @@ def test_fixed_mode_bit_identical_with_tile_fallback():
     same_bits(a, b)
 
 
-def test_rebin_modes_agree_bitwise_on_a_drifting_block():
+@pytest.mark.parametrize("solver", [None, (O.SOLVER_PIC, 1, 0.5), (O.SOLVER_PB, 3, 0.5)])
+def test_rebin_modes_agree_bitwise_on_a_drifting_block(solver):
     """Re-binning in place sorts by the positions of the coming G2P, so the
     particles that cross a block boundary in that substep scatter through
     global memory; re-binning after a G2P pass avoids that. The integer
-    contributions are the same either way."""
+    contributions are the same either way, for every solver."""
     s = scenes.tiny_block(n_grid=32, per_axis=8, seed=3, center=(0.35, 0.5, 0.4), with_state=False)
     s.dt = 1e-3
     s.gravity = (0.0, 0.0, 0.0)
     s.v = np.tile(np.array([12.0, 3.0, -6.0], np.float32), (s.N, 1))
+    if solver is not None:
+        s.solver = solver
     adv = fixed_run(s, 20, resort_interval=2, rebin_mode=1)
     for interval in (1, 2, 5):
         inp = fixed_run(s, 20, resort_interval=interval, rebin_mode=2)
