@@ -143,6 +143,12 @@ typedef struct mpm_tool {
   float mu;            /* kinetic friction coefficient mu_k >= 0 */
   float drag;          /* drag factor c_d in [0, 1]: 1 = no drag, 0 = sticky */
   float margin;        /* contact when phi(x_I) < margin (fattened region) */
+  int32_t push_out;    /* nonzero: particle push-out (Sec. IV-A, after the particle collisions of
+                          Stomakhin et al. 2013). After each substep's position update a particle
+                          inside the tool, phi(x) < 0 at the tool's pose of the next substep, moves
+                          to the surface along the unit outward normal: x <- x - phi n. Solid tools
+                          only (capsule, box, plane); ignored for the thin ones. v, C and F are
+                          unchanged. Not differentiated: rollouts refuse such a tool. */
 } mpm_tool;
 
 /* Counters, valid after a blocking call. */
@@ -395,7 +401,7 @@ int mpm_get_solver(const mpm_handle* h, int32_t* solver, int32_t* iterations, fl
  * impulses are not recorded (they read zero). Not blocking.
  * Errors: MPM_EINVAL (no particles, n_substeps < 0, checkpoint_every < 1),
  * MPM_ENOMEM, MPM_EHIP; device errors are deferred as for mpm_step.
- * MPM_EINVAL also when the solver is not MPM_SOLVER_MLS. */
+ * MPM_EINVAL also when the solver is not MPM_SOLVER_MLS or a tool has push_out on. */
 int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_every, const float* theta);
 
 /* Gradient of a scalar loss L through the recorded rollout. Inputs (device,

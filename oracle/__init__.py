@@ -38,6 +38,7 @@ def lib():
                                            ctypes.c_double, ctypes.c_double]
         L.oracle_set_tool.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp,
                                       dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_set_tool_push.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         L.oracle_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.oracle_read.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
         L.oracle_last_grid.argtypes = [ctypes.c_void_p, dp, dp, dp]
@@ -294,10 +295,12 @@ class Oracle:
         return r
 
     def set_tool(self, tool_id, tool_type, center=(0, 0, 0), quat=(1, 0, 0, 0), size=(0, 0, 0),
-                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0):
+                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0, push_out=False):
         arrs = [_d(a) for a in (center, quat, size, lin_vel, ang_vel)]
         st = lib().oracle_set_tool(self.h, int(tool_id), int(tool_type), *[p for _, p in arrs],
                                    float(mu), float(drag), float(margin))
+        if st == 0:
+            st = lib().oracle_set_tool_push(self.h, int(tool_id), int(bool(push_out)))
         if st != 0:
             raise ValueError(f"oracle_set_tool: status {st}")
 

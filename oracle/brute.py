@@ -215,7 +215,7 @@ class Brute:
         self.vol0 = float(vol0)
 
     def set_tool(self, tool_id, tool_type, center=(0, 0, 0), quat=(1, 0, 0, 0), size=(0, 0, 0),
-                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0):
+                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0, push_out=False):
         if tool_type == TOOL_NONE:
             self.tools.pop(tool_id, None)
             return
@@ -223,7 +223,7 @@ class Brute:
                                    quat=np.asarray(quat, np.float64), size=np.asarray(size, np.float64),
                                    lv=np.asarray(lin_vel, np.float64), av=np.asarray(ang_vel, np.float64),
                                    mu=float(mu), drag=float(drag), margin=float(margin),
-                                   set_at=self.substep)
+                                   set_at=self.substep, push=bool(push_out))
 
     def set_solver(self, kind, iterations=10, beta=0.5):
         self.solver, self.pb_iterations, self.pb_beta = int(kind), int(iterations), float(beta)
@@ -255,7 +255,21 @@ class Brute:
                 self._step_pb()
             else:
                 self._substep()
+            self._push_out()
             self.substep += 1
+
+    def _push_out(self):
+        """Particles inside a solid tool whose push-out is on move to its
+        surface, x - phi n where phi < 0; tools in id order, each where it is
+        one substep later."""
+        for q in sorted(self.tools):
+            t = self.tools[q]
+            if not t["push"] or t["type"] not in (TOOL_CAPSULE, TOOL_BOX, TOOL_PLANE):
+                continue
+            ahead = dict(t, center=t["center0"] + (self.substep + 1 - t["set_at"]) * self.dt * t["lv"])
+            phi, n = sdf_nodes(ahead, self.x)
+            inside = phi < 0.0
+            self.x[inside] = self.x[inside] - phi[inside, None] * n[inside]
 
     def _p2g_affine(self, W, x, v, A):
         """m_I and sum_p W (m v + A (x_I - x_p)), regrouped."""

@@ -278,6 +278,7 @@ struct Tool {
   double mu = 0.0, drag = 1.0, margin = 0.0;
   long long set_at = 0;       // substep counter when the tool was set
   std::vector<double> vtab;   // optional per-substep linear velocities (T x 3) from set_at on
+  int push = 0;               // particle push-out after each substep (solid tools only)
 };
 
 void quat_to_matrix(const double* q, double* R) {
@@ -876,6 +877,30 @@ void g2p_apic_vc(Scene& s, const std::vector<char>& skip) {
 }
 
 // One PB-MPM step of length dt.
+// Particle push-out (Sec. IV-A: the particles left inside a rigid shape are
+// pushed out, after the particle collision step of Stomakhin et al. 2013).
+// After the position update of substep k, a particle inside a solid tool
+// (capsule, box, plane) whose push-out is on, phi(x) < 0 with the tool at
+// its pose of substep k + 1 (where the tool is when the particles arrive),
+// moves to the surface along the unit outward normal: x <- x - phi n. Tools
+// in id order; v, C and F are unchanged. Skipped particles do not move.
+void push_out(Scene& s, const std::vector<char>& skip) {
+  for (int q = 0; q < kMaxTools; ++q) {
+    const Tool& t = s.tools[q];
+    if (!t.push || !(t.type == TOOL_CAPSULE || t.type == TOOL_BOX || t.type == TOOL_PLANE)) continue;
+    double c[3], vel[3];
+    tool_kinematics(s, q, s.substep + 1, c, vel);
+    for (long long p = 0; p < s.N; ++p) {
+      if (skip[p]) continue;
+      double* xp = &s.x[3 * p];
+      double g[3];
+      const double phi = tool_sdf(t.type, c, t.R, t.size, xp, g);
+      if (phi < 0.0)
+        for (int a = 0; a < 3; ++a) xp[a] -= phi * g[a];
+    }
+  }
+}
+
 void pb_step(Scene& s) {
   std::vector<char> skip(static_cast<size_t>(s.N), 0);
   // Particles that take part: finite state, stencil in the grid.
@@ -912,6 +937,7 @@ void pb_step(Scene& s) {
     mat_mul(G, &s.F[9 * p], &s.F[9 * p]);
     for (int a = 0; a < 3; ++a) s.x[3 * p + a] += s.dt * s.v[3 * p + a];
   }
+  push_out(s, skip);
 }
 
 void substep(Scene& s) {
@@ -920,12 +946,14 @@ void substep(Scene& s) {
     p2g_pic(s, skip);
     grid_update(s);
     g2p_pic(s, skip);
+    push_out(s, skip);
   } else if (s.solver == SOLVER_PB) {
     pb_step(s);
   } else {
     p2g(s, skip);
     grid_update(s);
     g2p(s, skip);
+    push_out(s, skip);
   }
   s.substep++;
 }
@@ -1520,6 +1548,15 @@ int oracle_set_tool(void* h, int id, int type, const double* center, const doubl
   t.drag = drag;
   t.margin = margin;
   t.set_at = s->substep;
+  return ST_OK;
+}
+
+// Particle push-out of tool `id` on (nonzero) or off; kept until the tool is
+// set again.
+int oracle_set_tool_push(void* h, int id, int push) {
+  Scene* s = static_cast<Scene*>(h);
+  if (!s || id < 0 || id >= kMaxTools) return ST_EINVAL;
+  s->tools[id].push = push ? 1 : 0;
   return ST_OK;
 }
 

@@ -883,6 +883,8 @@ int upload_tools(mpm_handle* h) {
     d.k.drag = ht.t.drag;
     d.k.margin = ht.t.margin;
     d.k.reach2 = reach2_of(ht.t);
+    d.k.push = (ht.t.push_out != 0 &&
+                (ht.t.type == TOOL_CAPSULE || ht.t.type == TOOL_BOX || ht.t.type == TOOL_PLANE)) ? 1 : 0;
     d.set_at = ht.set_at;
     d.rows = (long long)(ht.vtab.size() / 3);
     d.vtab = h->tool_tables[slot];
@@ -892,12 +894,16 @@ int upload_tools(mpm_handle* h) {
   HIP_OR_RETURN(h, hipMemcpyAsync(h->b.tools, desc.data(), sizeof(ToolDesc) * desc.size(), hipMemcpyHostToDevice,
                                   h->stream));
   h->tools_dirty = false;
-  // The grid update scans the slots up to the highest one in use.
-  int slots = 0;
-  for (size_t slot = 0; slot < desc.size(); ++slot)
+  // The grid update scans the slots up to the highest one in use; the
+  // transfer kernels check positions when some tool pushes particles out.
+  int slots = 0, push = 0;
+  for (size_t slot = 0; slot < desc.size(); ++slot) {
     if (h->tools[slot].active) slots = std::max(slots, (int)(slot % kMaxTools) + 1);
-  if (slots != h->sim.tool_slots) {
+    if (desc[slot].k.push) push = 1;
+  }
+  if (slots != h->sim.tool_slots || push != h->sim.push_out) {
     h->sim.tool_slots = slots;
+    h->sim.push_out = push;
     drop_graphs(h);  // the recorded launches hold the scene constants
   }
   return MPM_OK;
@@ -1265,6 +1271,9 @@ int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_ev
   if (h->N == 0) return fail(h, MPM_EINVAL, "mpm_rollout_forward: no particles");
   if (h->n_scenes != 1) return fail(h, MPM_EINVAL, "mpm_rollout_forward: one scene only");
   if (h->sim.solver != SOLVER_MLS) return fail(h, MPM_EINVAL, "mpm_rollout_forward: needs the MLS-MPM solver");
+  for (const HostTool& t : h->tools)
+    if (t.active && t.t.push_out)
+      return fail(h, MPM_EINVAL, "mpm_rollout_forward: particle push-out is not differentiated");
   HIP_OR_RETURN(h, select_device(h));
   DiffBufs& d = h->d;
   d.valid = false;

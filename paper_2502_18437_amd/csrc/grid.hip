@@ -19,32 +19,6 @@ constexpr int kGridWG = 128;
 static_assert(kBlockNodes % kGridWG == 0, "every lane of the grid kernel must visit the same number of nodes");
 constexpr int kNodesPerLane = kBlockNodes / kGridWG;
 
-// Tool `d` at its pose of global substep k: the centre follows the constant
-// velocity from set_at, or the prefix sums of the velocity table and then the
-// constant velocity (FP64, each operation rounded as written).
-__device__ __forceinline__ ToolK tool_at(const ToolDesc& d, long long k, double dt) {
-  ToolK t = d.k;
-  const long long rel = k - d.set_at;
-  if (d.rows == 0) {
-    const double el = __dmul_rn((double)rel, dt);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      t.c[a] = (float)__dadd_rn(d.c0[a], __dmul_rn(el, d.lv[a]));
-      t.lv[a] = (float)d.lv[a];
-    }
-  } else {
-    const long long m = rel < d.rows ? rel : d.rows;
-    const double tail = __dmul_rn((double)(rel - m), dt);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double c = __dadd_rn(__dadd_rn(d.c0[a], __dmul_rn(dt, d.vpre[3 * m + a])), __dmul_rn(tail, d.lv[a]));
-      t.c[a] = (float)c;
-      t.lv[a] = (float)(rel < d.rows ? d.vtab[3 * rel + a] : d.lv[a]);
-    }
-  }
-  return t;
-}
-
 __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void* __restrict__ acc_p0,
                                                   void* __restrict__ acc_p1, void* __restrict__ acc_p2,
                                                   float4* __restrict__ vel,

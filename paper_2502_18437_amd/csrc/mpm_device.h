@@ -296,6 +296,51 @@ __device__ __forceinline__ float tool_sdf(const ToolK& t, const float* p, float*
   return phi;
 }
 
+// Tool `d` at its pose of global substep k: the centre follows the constant
+// velocity from set_at, or the prefix sums of the velocity table and then the
+// constant velocity (FP64, each operation rounded as written).
+__device__ __forceinline__ ToolK tool_at(const ToolDesc& d, long long k, double dt) {
+  ToolK t = d.k;
+  const long long rel = k - d.set_at;
+  if (d.rows == 0) {
+    const double el = __dmul_rn((double)rel, dt);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      t.c[a] = (float)__dadd_rn(d.c0[a], __dmul_rn(el, d.lv[a]));
+      t.lv[a] = (float)d.lv[a];
+    }
+  } else {
+    const long long m = rel < d.rows ? rel : d.rows;
+    const double tail = __dmul_rn((double)(rel - m), dt);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double c = __dadd_rn(__dadd_rn(d.c0[a], __dmul_rn(dt, d.vpre[3 * m + a])), __dmul_rn(tail, d.lv[a]));
+      t.c[a] = (float)c;
+      t.lv[a] = (float)(rel < d.rows ? d.vtab[3 * rel + a] : d.lv[a]);
+    }
+  }
+  return t;
+}
+
+// Particle push-out (Sec. IV-A: particles left inside a rigid shape are
+// pushed out, after the particle collision step of Stomakhin et al. 2013):
+// a particle whose new position is inside a solid tool with push-out on,
+// phi(x) < 0 with the tool at its pose of substep k (the substep that the
+// new position starts), moves to the surface along the unit outward normal,
+// x <- x - phi n. Tools in id order.
+__device__ __forceinline__ void push_out(const SimK& s, const ToolDesc* td, long long k, float* x) {
+  for (int q = 0; q < s.tool_slots; ++q) {
+    if (!td[q].k.push) continue;
+    const ToolK t = tool_at(td[q], k, (double)s.dt);
+    float n[3];
+    const float phi = tool_sdf(t, x, n);
+    if (phi < 0.0f) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[a] -= phi * n[a];
+    }
+  }
+}
+
 // Friction and drag of eq. v_correction on a kept tangential vector t of
 // length s, for an approaching node (u_n < 0): c_d max(1 + mu u_n / s, 0) t.
 __device__ __forceinline__ float friction_scale(const ToolK& t, float un, float s) {

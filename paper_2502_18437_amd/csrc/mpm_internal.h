@@ -62,6 +62,7 @@ struct ToolK {
   float av[3];
   float mu, drag, margin;
   float reach2;    // squared radius around c outside which no node is in contact; < 0: unbounded
+  int push;        // particle push-out after each substep (solid tools only)
 };
 
 struct ToolSetK {
@@ -114,6 +115,7 @@ struct SimK {
   float pic_force;   // standard MPM: dt * vol0 / dx (internal force per unit of tau grad N dx)
   float pb_beta;     // PB-MPM: rotation weight of the co-rotational constraint
   int tool_slots;    // 1 + the highest tool slot in use in any scene (0: no tools)
+  int push_out;      // some tool pushes particles out: the transfer kernels check positions
   unsigned item_particles;  // particles per transfer work item (at most)
 };
 

@@ -631,15 +631,21 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
 // previous step's last iteration, its F and x update, then the first pass of
 // the new step); PB_ITER is G2P -> constraint -> P2G within a step, where x
 // and F do not change and nothing is written back.
-template <bool FIXED, int SOL, int PASS>
+// With PUSH, particles that the position update leaves inside a tool with
+// push-out on are moved to its surface (push_out) before the P2G.
+template <bool FIXED, int SOL, int PASS, bool PUSH>
 __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int64_t cap,
                                                const uint32_t* __restrict__ blk_end,
                                                const uint2* __restrict__ work, Status* st,
                                                ACC_PARAMS, const float4* __restrict__ vel,
                                                uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
-                                               const Clock* __restrict__ clk, SimK s) {
+                                               const Clock* __restrict__ clk,
+                                               const ToolDesc* __restrict__ tools, SimK s) {
   constexpr bool kIntegrate = !(SOL == SOLVER_PB && PASS == PB_ITER);
+  static_assert(!PUSH || kIntegrate, "push-out follows a position update");
   const int parity = clk->parity;
+  long long substep = 0;
+  if constexpr (PUSH) substep = clk->substep;
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds L;
   Counters cnt;
@@ -673,10 +679,10 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
             Fn[3 * a + b2] = F[3 * a + b2] + s.dt * (Cn[3 * a] * F[b2] + Cn[3 * a + 1] * F[3 + b2] +
                                                      Cn[3 * a + 2] * F[6 + b2]);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          x[a] += s.dt * vn[a];
-          part[(FX + a) * cap + p] = x[a];
-        }
+        for (int a = 0; a < 3; ++a) x[a] += s.dt * vn[a];
+        if constexpr (PUSH) push_out(s, tools + (size_t)to[3] * kMaxTools, substep, x);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) part[(FX + a) * cap + p] = x[a];
 #pragma unroll
         for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
         const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
@@ -695,12 +701,15 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
 
 // G2P that materialises the full state (x, v, C, F) in memory (the C slot
 // holds the velocity gradient for standard MPM).
-template <int SOL>
+template <int SOL, bool PUSH>
 __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint2* __restrict__ work, Status* st,
-                                             const float4* __restrict__ vel, SimK s) {
+                                             const float4* __restrict__ vel, const Clock* __restrict__ clk,
+                                             const ToolDesc* __restrict__ tools, SimK s) {
   __shared__ Lds L;
+  long long substep = 0;
+  if constexpr (PUSH) substep = clk->substep;
   Counters cnt;
   unsigned pos, end, stride;
   xcd_walk(st->n_work, &pos, &end, &stride);
@@ -731,8 +740,11 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
               F[3 * a + b2] +
               s.dt * (Cn[3 * a] * F[b2] + Cn[3 * a + 1] * F[3 + b2] + Cn[3 * a + 2] * F[6 + b2]);
 #pragma unroll
+      for (int a = 0; a < 3; ++a) x[a] += s.dt * vn[a];
+      if constexpr (PUSH) push_out(s, tools + (size_t)to[3] * kMaxTools, substep, x);
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
-        part[(FX + a) * cap + p] = x[a] + s.dt * vn[a];
+        part[(FX + a) * cap + p] = x[a];
         part[(FV + a) * cap + p] = vn[a];
       }
 #pragma unroll
@@ -753,13 +765,23 @@ static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st
                      (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
 }
 
-template <bool FIXED, int SOL, int PASS>
+template <bool FIXED, int SOL, int PASS, bool PUSH>
 static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
+  hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS, PUSH>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
                      b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
-                     (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
+                     (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock,
+                     (const ToolDesc*)b.tools, s);
+}
+
+// The integrating passes with or without push-out.
+template <bool FIXED, int SOL>
+static void launch_g2p2g_p(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+  if (s.push_out)
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, true>(b, s, grid_wgs, st);
+  else
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, false>(b, s, grid_wgs, st);
 }
 
 template <bool FIXED>
@@ -775,13 +797,13 @@ static void launch_p2g_s(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st
 template <bool FIXED>
 static void launch_g2p2g_s(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st, int pass) {
   if (s.solver == SOLVER_PIC)
-    launch_g2p2g_t<FIXED, SOLVER_PIC, PB_FIRST>(b, s, grid_wgs, st);
+    launch_g2p2g_p<FIXED, SOLVER_PIC>(b, s, grid_wgs, st);
   else if (s.solver == SOLVER_PB && pass == PB_ITER)
-    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER>(b, s, grid_wgs, st);
+    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER, false>(b, s, grid_wgs, st);
   else if (s.solver == SOLVER_PB)
-    launch_g2p2g_t<FIXED, SOLVER_PB, PB_FIRST>(b, s, grid_wgs, st);
+    launch_g2p2g_p<FIXED, SOLVER_PB>(b, s, grid_wgs, st);
   else
-    launch_g2p2g_t<FIXED, SOLVER_MLS, PB_FIRST>(b, s, grid_wgs, st);
+    launch_g2p2g_p<FIXED, SOLVER_MLS>(b, s, grid_wgs, st);
 }
 
 void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
@@ -800,14 +822,24 @@ void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_
     launch_g2p2g_s<false>(b, s, grid_wgs, st, pass);
 }
 
+template <int SOL>
+static void launch_g2p_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+  const Clock* clk = (const Clock*)b.clock;
+  const ToolDesc* tools = (const ToolDesc*)b.tools;
+  if (s.push_out)
+    hipLaunchKernelGGL((k_g2p<SOL, true>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_end,
+                       b.work, b.status, b.vel, clk, tools, s);
+  else
+    hipLaunchKernelGGL((k_g2p<SOL, false>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_end,
+                       b.work, b.status, b.vel, clk, tools, s);
+}
+
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
   (void)N;
   if (s.solver == SOLVER_PIC)
-    hipLaunchKernelGGL(k_g2p<SOLVER_PIC>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
-                       b.blk_end, b.work, b.status, b.vel, s);
+    launch_g2p_t<SOLVER_PIC>(b, s, grid_wgs, st);
   else
-    hipLaunchKernelGGL(k_g2p<SOLVER_MLS>, dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
-                       b.blk_end, b.work, b.status, b.vel, s);
+    launch_g2p_t<SOLVER_MLS>(b, s, grid_wgs, st);
 }
 
 }  // namespace mpm

@@ -52,7 +52,7 @@ class mpm_tool(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("center", ctypes.c_double * 3), ("quat", ctypes.c_double * 4),
                 ("size", ctypes.c_double * 3), ("lin_vel", ctypes.c_double * 3),
                 ("ang_vel", ctypes.c_double * 3), ("mu", ctypes.c_float), ("drag", ctypes.c_float),
-                ("margin", ctypes.c_float)]
+                ("margin", ctypes.c_float), ("push_out", ctypes.c_int32)]
 
 
 class mpm_info(ctypes.Structure):
@@ -262,10 +262,10 @@ class Simulation:
         self.counts = counts.copy()
 
     def set_tool(self, tool_id, tool_type, center=(0, 0, 0), quat=(1, 0, 0, 0), size=(0, 0, 0),
-                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0, scene=0):
+                 lin_vel=(0, 0, 0), ang_vel=(0, 0, 0), mu=0.0, drag=1.0, margin=0.0, push_out=False, scene=0):
         t = mpm_tool(int(tool_type), (ctypes.c_double * 3)(*center), (ctypes.c_double * 4)(*quat),
                      (ctypes.c_double * 3)(*size), (ctypes.c_double * 3)(*lin_vel),
-                     (ctypes.c_double * 3)(*ang_vel), float(mu), float(drag), float(margin))
+                     (ctypes.c_double * 3)(*ang_vel), float(mu), float(drag), float(margin), int(bool(push_out)))
         if scene == 0:
             self._check(_lib.mpm_set_tool_sdf(self.h, int(tool_id), ctypes.byref(t)))
         else:

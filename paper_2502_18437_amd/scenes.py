@@ -60,10 +60,12 @@ class Tool:
     mu: float = 0.3
     drag: float = 1.0
     margin: float = 0.0
+    push_out: bool = False
 
     def kwargs(self):
         return dict(center=self.center, quat=self.quat, size=self.size, lin_vel=self.lin_vel,
-                    ang_vel=self.ang_vel, mu=self.mu, drag=self.drag, margin=self.margin)
+                    ang_vel=self.ang_vel, mu=self.mu, drag=self.drag, margin=self.margin,
+                    push_out=self.push_out)
 
 
 @dataclass

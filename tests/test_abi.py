@@ -46,7 +46,7 @@ int main(void) {
   F(mpm_params, resort_interval) F(mpm_params, max_particles)
   printf("mpm_tool SIZEOF %zu\n", sizeof(mpm_tool));
   F(mpm_tool, type) F(mpm_tool, center) F(mpm_tool, quat) F(mpm_tool, size) F(mpm_tool, lin_vel)
-  F(mpm_tool, ang_vel) F(mpm_tool, mu) F(mpm_tool, drag) F(mpm_tool, margin)
+  F(mpm_tool, ang_vel) F(mpm_tool, mu) F(mpm_tool, drag) F(mpm_tool, margin) F(mpm_tool, push_out)
   printf("mpm_info SIZEOF %zu\n", sizeof(mpm_info));
   F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, n_range) F(mpm_info, tile) F(mpm_info, n_tools)
   printf("mpm_launch_config SIZEOF %zu\n", sizeof(mpm_launch_config));
