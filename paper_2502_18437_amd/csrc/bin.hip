@@ -137,16 +137,17 @@ __device__ __forceinline__ uint32_t scene_of(const uint32_t* __restrict__ scene_
 __device__ __forceinline__ uint32_t sub_cell_half(float frac) { return frac >= 0.5f ? 1u : 0u; }
 
 // Binning keys: the block of the base cell (scene-major) in the high bits,
-// then the base cell's z layer in the block (3 bits) and the particle's
-// sub-cell class (its half of the base cell per axis, 3 bits). The stable
-// sort orders a block's particles layer by layer, so a work item covers a few
-// layers of the tile, and within a layer class by class, so consecutive
-// particles (the lanes of one wave) sit in different base cells and their LDS
-// atomics hit different nodes: at up to 8 particles per cell a class holds
-// about one particle of each cell. This applies to blocks that held 1 to
-// kDenseBlock particles at the previous sort (prev_begin / prev_end); the
-// others keep their order (at the first sort, the order given). In a denser
-// block a class still holds many particles of a cell; its work items deal
+// then 6 bits from the particle's sub-cell class (its half of the base cell
+// per axis) and the base cell's z layer in the block. Within a class,
+// consecutive particles (the lanes of one wave) sit in different base cells,
+// so their LDS atomics hit different nodes: at up to 8 particles per cell a
+// class holds about one particle of each cell. A block that fits in one work
+// item is ordered class first (a class then spans all of the block's cells);
+// a larger one z layer first, so that each of its work items covers a few
+// layers of the tile. Block sizes come from the previous sort (prev_begin /
+// prev_end); blocks above kDenseBlock particles, and blocks without a count
+// (at the first sort, the order given), keep their order. In a denser block
+// a class still holds many particles of a cell; its work items deal
 // particles to lanes 8 apart (item_lane), which spreads particles given in a
 // lattice or random order better. Invalid particles get `sentinel`, which
 // sorts after every block.
@@ -174,8 +175,13 @@ __global__ void k_keygen(const float* __restrict__ part, const uint32_t* __restr
       const uint32_t blk = scene * s.nb3 + (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb +
                                                       (cell[0] >> kTileLog2));
       const uint32_t prev = prev_end[blk] - prev_begin[blk];
-      const bool layered = prev > 0u && prev <= kDenseBlock;
-      key = (blk << kClassBits) | (layered ? ((uint32_t)(cell[2] & (kTile - 1)) << 3) | cls : 0u);
+      const uint32_t z = (uint32_t)(cell[2] & (kTile - 1));
+      uint32_t sub = 0u;  // dense or new block: keep the order
+      if (prev > 0u && prev <= s.item_particles)
+        sub = (cls << 3) | z;  // one work item: class first, so a class spans the block's cells
+      else if (prev > 0u && prev <= kDenseBlock)
+        sub = (z << 3) | cls;  // several items: z layers first, so an item covers a few layers
+      key = (blk << kClassBits) | sub;
     } else if (!fin) {
       nf++;
     } else {

@@ -14,10 +14,10 @@ namespace mpm {
 // Particles that drift further take the global-memory path.
 constexpr int kTile = 8;
 constexpr int kTileLog2 = 3;
-// Low bits of a binning key below the block id: the base cell's z layer in
-// the block (3 bits) and the particle's sub-cell class (a half of the base
-// cell per axis, 3 bits). Handles keep n_blocks below 2^22, so a key stays
-// below 2^28.
+// Low bits of a binning key below the block id: the particle's sub-cell
+// class (a half of the base cell per axis, 3 bits) and the base cell's z
+// layer in the block (3 bits), in either order. Handles keep n_blocks below
+// 2^22, so a key stays below 2^28.
 constexpr int kClassBits = 6;
 constexpr int kSlack = 0;
 constexpr int kSpan = kTile + 2 + 2 * kSlack;  // 10
