@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--scene", default="c3")
     ap.add_argument("--substeps", type=int, default=0, help="substeps per step (default: the scene's)")
     ap.add_argument("--resort", type=int, default=0)
-    ap.add_argument("--cpu-substeps", type=int, default=2)
+    ap.add_argument("--cpu-substeps", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd measurement")
