@@ -221,10 +221,19 @@ __global__ __launch_bounds__(kSortWG) void k_radix_hist(const uint32_t* __restri
   for (int w = 0; w < kSortWG / 64; ++w) cnt[w][threadIdx.x] = 0u;
   __syncthreads();
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  // All of this thread's keys are loaded before the rounds, so the loads
+  // are in flight together.
+  uint32_t kr[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = tile0 + (int64_t)r * kSortWG + threadIdx.x;
+    kr[r] = i < N ? keys[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = tile0 + (int64_t)r * kSortWG + threadIdx.x;
     const bool valid = i < N;
-    const uint32_t d = valid ? ((keys[i] >> shift) & (kRadix - 1)) : 0u;
+    const uint32_t d = valid ? ((kr[r] >> shift) & (kRadix - 1)) : 0u;
     const uint64_t peers = match_digit(d, valid);
     if (valid && (peers & lanemask_lt()) == 0ull) cnt[wave][d] += (uint32_t)__popcll(peers);
   }
@@ -248,11 +257,21 @@ __global__ __launch_bounds__(kSortWG) void k_radix_scatter(const uint32_t* __res
   for (int w = 0; w < kSortWG / 64; ++w) wcnt[w][threadIdx.x] = 0u;
   __syncthreads();
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  // All of this thread's keys and values are loaded before the rounds, so
+  // the loads are in flight together.
+  uint32_t kr[kSortItems], vr[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = tile0 + (int64_t)r * kSortWG + threadIdx.x;
+    kr[r] = i < N ? kin[i] : 0u;
+    vr[r] = i < N ? vin[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = tile0 + (int64_t)r * kSortWG + threadIdx.x;
     const bool valid = i < N;
-    const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t v = valid ? vin[i] : 0u;
+    const uint32_t k = kr[r];
+    const uint32_t v = vr[r];
     const uint32_t d = (k >> shift) & (kRadix - 1);
     const uint64_t peers = match_digit(d, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
