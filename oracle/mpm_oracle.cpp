@@ -18,8 +18,7 @@
 //   * Sec. IV-A, grid-level SDF contact with friction and drag
 //     (eq. v_correction).
 //
-// Readings taken where the paper is garbled or silent (all listed in the
-// design notes of the repository):
+// Readings taken where the paper is garbled or silent:
 //   * The fused P2G equation is printed without the particle momentum term;
 //     the APIC/MLS form it cites is used: (mv)_I = sum N [m v + (m C -
 //     dt V0 M^-1 tau)(x_I - x_p)], M^-1 = 4/dx^2.
@@ -60,6 +59,10 @@
 //     cube root is taken), APIC P2G without stress, the grid update without
 //     gravity (tools, walls), APIC G2P of v and C; finally F <- (I + dt C) F
 //     and x <- x + dt v. Tool impulses are those of the last iteration.
+//   * Particle push-out (Sec. IV-A names it, after the particle collisions
+//     of Stomakhin et al. 2013): per tool, for solid tools only; after the
+//     position update a particle with phi(x) < 0, the tool at its pose of
+//     the next substep, moves to x - phi n; v, C and F are unchanged.
 //   * Errors: a particle whose stencil leaves the grid (EDOMAIN) or whose
 //     state is not finite (ENONFINITE) is left unchanged for that substep;
 //     det F <= 0 is counted (EINVERTED). Status precedence:

@@ -1,8 +1,8 @@
 """Shared helpers of the GPU parity tests: run a seeded scene on the oracle
 and on the HIP library, and compare element by element.
 
-Tolerances (the benchmark spec's bound is on positions; the others follow from
-FP32 arithmetic against the FP64 oracle, see the design notes):
+Tolerances (the parity bound of the substep is on positions; the others
+follow from FP32 arithmetic against the FP64 oracle):
 * positions: max |x_gpu - x_or| / max |x_or| <= 1e-4, and the displacement
   from x0 agrees to 1e-2 of the largest displacement plus the FP32 storage
   rounding of x (half an ulp of max |x| per substep, n substeps);
