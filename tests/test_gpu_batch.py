@@ -153,3 +153,27 @@ def test_c4_full_batch_runs_and_samples_match():
         sc = b.scenes[i]
         o = run_oracle(sc, n)
         assert_parity({k: v.astype(np.float64) for k, v in per[i].items()}, o, sc.x, n, f"c4 scene {i}")
+
+
+def test_push_out_in_one_scene_of_a_batch_in_fixed_mode():
+    """Scene 1's capsule pushes particles out; the batch still equals each
+    scene run alone, bit for bit (the push-out code path runs for every
+    scene but acts only where a tool has it on)."""
+    from paper_2502_18437_amd import mpm
+    b = scenes.batch_c4s()
+    t = b.scenes[1].tools[0]
+    t.push_out = True
+    t.lin_vel = (0.0, -2.0, 0.0)  # fast enough to end inside the capsule
+    n = 16
+    per, st, imp, _ = run_batch(b, n, accum_mode=mpm.MPM_ACCUM_FIXED)
+    assert st == 0
+    for i, sc in enumerate(b.scenes):
+        r, st1, imp1 = run_single(sc, n, accum_mode=mpm.MPM_ACCUM_FIXED)
+        assert st1 == 0
+        for k in ("x", "v", "C", "F"):
+            assert np.array_equal(per[i][k], r[k]), (i, k)
+        assert np.array_equal(imp[i], imp1), i
+    sc = b.scenes[1]
+    sc.tools[0].push_out = False
+    off, _, _ = run_single(sc, n, accum_mode=mpm.MPM_ACCUM_FIXED)
+    assert not np.array_equal(off["x"], per[1]["x"])  # the push-out acted in scene 1
