@@ -4,11 +4,15 @@
 // recorded graphs, the substep driver and the differentiable rollout.
 //
 // mpm_step(n) enqueues, for substeps k = 0..n-1 (Algorithm 1 of the paper):
-//   k == 0 or re-binning due:  [G2P(k-1)] -> binning -> P2G(k)
+//   k == 0:                    [binning] -> P2G(k)
+//   re-binning due, in place:  binning by the positions in memory -> fused
+//                              G2P(k-1) + P2G(k)
+//   re-binning due, advance:   G2P(k-1) -> binning -> P2G(k)
 //   otherwise:                 fused G2P(k-1) + P2G(k)
 //   then the grid update of substep k (tools at their substep-k pose),
 // and a final G2P, so that x, v, C, F are materialised when the call's work
-// completes. A PB-MPM substep is one step of `iterations` passes: the first
+// completes. Each G2P's position update is followed by the particle push-out
+// of the tools that have it on. A PB-MPM substep is one step of `iterations` passes: the first
 // as above, then iterations - 1 times fused G2P + P2G within the step, each
 // followed by a grid update. Runs of plain substeps replay a recorded HIP
 // graph. Nothing here waits on the device except mpm_read_state,

@@ -21,7 +21,8 @@
 //
 // k_g2p2g fuses the G2P of substep k-1 with the P2G of substep k: v and C never
 // leave registers between the two, so a fused substep streams x, F, E in and
-// x, F out (100 B/particle). A dense block's work items deal their particles
+// x, F out (100 B/particle). When a tool pushes particles out, an
+// instantiation with the push-out after the position update runs instead. A dense block's work items deal their particles
 // to a wave's lanes 8 apart (item_lane), so that one wave's atomics spread
 // over different cells.
 #include "mpm_device.h"
