@@ -60,6 +60,23 @@ def run_gpu(scene, n_substeps, chunks=None, **kw):
     return r
 
 
+def dyadic_poses(scene):
+    """The scene with a dyadic dt, tool centres and tool velocities, so that
+    every FP64 tool pose centre + k dt v is an exact sum, whichever substep
+    the count starts from (the resume tests compare bits)."""
+    scene.dt = 2.0 ** -14
+    for t in scene.tools:
+        t.center = tuple(round(c * 2 ** 20) / 2 ** 20 for c in t.center)
+        t.lin_vel = (0.0625, -0.25, 0.125)
+    return scene
+
+
+def advance_tools(scene, n_substeps):
+    """Move each tool's centre to its pose n_substeps later (linear motion)."""
+    for t in scene.tools:
+        t.center = tuple(c + n_substeps * scene.dt * v for c, v in zip(t.center, t.lin_vel))
+
+
 def errors(gpu, orc, x0):
     x0 = np.asarray(x0, np.float32).astype(np.float64)
     ex = np.max(np.abs(gpu["x"] - orc["x"])) / np.max(np.abs(orc["x"]))

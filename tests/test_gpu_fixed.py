@@ -2,12 +2,14 @@
 exact integer sum, so the state is bit-identical across runs, particle
 orders and re-binning schedules; it also matches the oracle to the FP32
 tolerances."""
+import copy
+
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2502_18437_amd import scenes
-from tests.parity import assert_parity, run_gpu, run_oracle
+from tests.parity import assert_parity, advance_tools, dyadic_poses, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -90,3 +92,25 @@ def test_rebin_modes_agree_bitwise_on_a_drifting_block(solver):
         inp = fixed_run(s, 20, resort_interval=interval, rebin_mode=2)
         assert inp["info"]["n_fallback"] > 0, interval
         same_bits(adv, inp)
+
+
+def test_resume_from_read_state_is_bitwise():
+    """Checkpoint and resume: the state read after n1 substeps, handed to a
+    new handle whose tools are set at the poses they have reached, goes on
+    bit for bit like the uninterrupted run (the new handle bins its
+    particles afresh; integer P2G sums do not depend on the order)."""
+    from paper_2502_18437_amd import mpm
+    s = dyadic_poses(scenes.scene_c2s())
+    n1, n2 = 25, 35
+    ref = fixed_run(s, n1 + n2)
+    sim = mpm.simulation_from_scene(s, accum_mode=mpm.MPM_ACCUM_FIXED)
+    sim.step(n1)
+    mid, st = sim.read_state(allow_errors=True)
+    sim.close()
+    assert st == 0 and ref["status"] == 0
+    t = copy.deepcopy(s)
+    t.x, t.v, t.C, t.F = (np.array(mid[k], np.float32) for k in ("x", "v", "C", "F"))
+    advance_tools(t, n1)
+    res = fixed_run(t, n2)
+    assert res["status"] == 0
+    same_bits(ref, res)

@@ -3,6 +3,7 @@ contact law of Sec. IV-A) against conservation laws, closed forms and an
 independent dense NumPy formulation. Each check is chosen so that a plausible
 slip (a dropped momentum term, a wrong sign, a transposed C, a wrong stencil
 offset) fails it."""
+import copy
 import json
 import os
 
@@ -12,6 +13,7 @@ import pytest
 import oracle as O
 from oracle.brute import Brute
 from paper_2502_18437_amd import scenes
+from tests.parity import advance_tools, dyadic_poses
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -254,3 +256,32 @@ def test_empty_scene():
     o.set_particles(np.zeros((0, 3), np.float32), mass=1.0, vol0=1.0)
     assert o.step(3) == 0
     assert o.read()["x"].shape == (0, 3)
+
+
+def test_resume_from_a_read_state_is_exact():
+    """The substep reads only x, v, C, F, the material and the tool poses: a
+    new oracle given the FP64 state read after n1 substeps, with its tools
+    set at the poses they have reached, ends bit for bit where the
+    uninterrupted run ends. A grid that is not cleared between substeps or a
+    pose counted from the wrong substep breaks it."""
+    s = dyadic_poses(scenes.scene_c2s())
+    n1, n2 = 6, 8
+    ref = make_oracle(s)
+    assert ref.step(n1 + n2) == 0
+    r = ref.read()
+    a = make_oracle(s)
+    assert a.step(n1) == 0
+    mid = a.read()
+    t = copy.deepcopy(s)
+    advance_tools(t, n1)
+    b = make_oracle(t)
+    b.set_state_f64(mid["x"], mid["v"], mid["C"], mid["F"], f64(s.E), s.mass, s.vol0)
+    assert b.step(n2) == 0
+    out = b.read()
+    for k in ("x", "v", "C", "F"):
+        assert np.array_equal(r[k], out[k]), k
+    # the check has teeth: resuming with the tools at their first poses differs
+    c = make_oracle(s)
+    c.set_state_f64(mid["x"], mid["v"], mid["C"], mid["F"], f64(s.E), s.mass, s.vol0)
+    assert c.step(n2) == 0
+    assert not np.array_equal(r["x"], c.read()["x"])
