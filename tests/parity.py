@@ -13,6 +13,7 @@ follow from FP32 arithmetic against the FP64 oracle):
 import numpy as np
 
 import oracle as O
+from paper_2502_18437_amd import scenes
 
 POS_REL = 1e-4
 DISP_REL = 1e-2
@@ -108,3 +109,32 @@ def subbox(x0, lo, hi):
     x0 = np.asarray(x0)
     m = np.all((x0 >= np.asarray(lo)) & (x0 < np.asarray(hi)), axis=1)
     return np.nonzero(m)[0]
+
+
+def blob_scene(n_grid, origin_cells, seed=5):
+    """A 12^3 lattice at half-cell spacing with a dyadic jitter and dyadic
+    random velocities, its corner at origin_cells * dx. Every position is a
+    multiple of 2^-16 below 1, so it is exact in FP32."""
+    dx = 1.0 / n_grid
+    rng = np.random.default_rng(seed)
+    g = np.arange(12, dtype=np.float64)
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) * 0.5 * dx
+    jit = rng.integers(0, 32, size=lat.shape) * 2.0 ** -16
+    x = np.asarray(origin_cells, np.float64) * dx + lat + jit
+    v = rng.integers(-64, 65, size=lat.shape) * 2.0 ** -10
+    vol0 = (0.5 * dx) ** 3
+    return scenes.Scene(name=f"blob{n_grid}", n_grid=n_grid, dt=2.0 ** -14, n_substeps=40, nu=0.3,
+                        E_default=2e4, mass=1e3 * vol0, vol0=vol0, x=x.astype(np.float32),
+                        v=v.astype(np.float32))
+
+
+def shifted_blobs(n_grid):
+    """A blob near the far corner (clear of the 3-node walls) and the same
+    blob moved down by whole 8-node blocks, a different number per axis,
+    both inside [0.5, 1) per axis; returns them and the shift in cells."""
+    hi = n_grid - 19
+    k = (hi - n_grid // 2) // 8
+    shift = np.array([8 * k, 8 * (k - 1), 8 * (k - 2)])
+    a = blob_scene(n_grid, (hi, hi, hi))
+    b = blob_scene(n_grid, (hi - shift[0], hi - shift[1], hi - shift[2]))
+    return a, b, shift

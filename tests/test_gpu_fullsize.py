@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from paper_2502_18437_amd import scenes
-from tests.parity import assert_parity, run_oracle, subbox
+from tests.parity import assert_parity, run_oracle, shifted_blobs, subbox
 
 pytestmark = pytest.mark.gpu
 
@@ -76,3 +76,36 @@ def test_c2_full_size_sampled():
         ((0.1, 0.02, 0.1), (0.16, 0.08, 0.16)),           # slab corner on the floor band
     ]
     check_cores(s, g, k, cores, "c2")
+
+
+@pytest.mark.parametrize("n_grid", [128, 1024])
+def test_largest_grid_is_translation_invariant_bitwise(n_grid):
+    """The largest grid, n_grid = 1024 (2^30 nodes, block ids up to 2^21 - 1),
+    against an exact property the oracle's dense grid is too large to check
+    there: a blob near the far corner and the same blob moved down by whole
+    8-node blocks, both inside [0.5, 1) per axis, give the same v, C, F and
+    the same x less the shift, bit for bit, in fixed-point mode. dx is a
+    power of two and the shift a multiple of the FP32 ulp of that binade, so
+    every rounding of the two runs lands on the same grid; nothing in the
+    substep (no tools, walls 3 nodes from the blob) depends on where the
+    blob is."""
+    from paper_2502_18437_amd import mpm
+    a, b, shift = shifted_blobs(n_grid)
+    assert np.all(b.x >= 0.5) and np.all(a.x < 1.0)
+
+    def run(s):
+        sim = mpm.simulation_from_scene(s, accum_mode=mpm.MPM_ACCUM_FIXED)
+        sim.step(s.n_substeps)
+        r, st = sim.read_state(allow_errors=True)
+        info = sim.info()
+        sim.close()
+        assert st == 0 and info["n_range"] == 0 and info["n_inverted"] == 0, (st, info)
+        return {f: np.asarray(r[f], np.float32) for f in ("x", "v", "C", "F")}
+
+    ra = run(a)
+    rb = run(b)
+    assert np.max(np.abs(ra["v"] - a.v)) > 1e-3  # the material responded
+    xa = (ra["x"].astype(np.float64) - shift / n_grid).astype(np.float32)
+    assert np.array_equal(xa.view(np.uint32), rb["x"].view(np.uint32))
+    for f in ("v", "C", "F"):
+        assert np.array_equal(ra[f].view(np.uint32), rb[f].view(np.uint32)), f

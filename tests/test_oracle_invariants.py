@@ -13,7 +13,7 @@ import pytest
 import oracle as O
 from oracle.brute import Brute
 from paper_2502_18437_amd import scenes
-from tests.parity import advance_tools, dyadic_poses
+from tests.parity import advance_tools, dyadic_poses, shifted_blobs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -285,3 +285,20 @@ def test_resume_from_a_read_state_is_exact():
     c.set_state_f64(mid["x"], mid["v"], mid["C"], mid["F"], f64(s.E), s.mass, s.vol0)
     assert c.step(n2) == 0
     assert not np.array_equal(r["x"], c.read()["x"])
+
+
+def test_translation_by_whole_blocks_is_exact():
+    """Nothing in the substep depends on where the material is, away from
+    tools and walls: a blob near the far corner of a 128^3 grid and the same
+    blob moved down by 40, 32 and 24 cells (positions dyadic, both inside
+    [0.5, 1), so the FP64 roundings land on the same grid) end with the same
+    v, C, F and the same x less the shift, bit for bit. An index slip tied
+    to the absolute cell (a base offset, a stencil origin) breaks it."""
+    a, b, shift = shifted_blobs(128)
+    oa, ob = make_oracle(a), make_oracle(b)
+    assert oa.step(40) == 0 and ob.step(40) == 0
+    ra, rb = oa.read(), ob.read()
+    assert np.max(np.abs(ra["v"] - f64(a.v))) > 1e-3
+    assert np.array_equal(ra["x"] - shift / 128, rb["x"])
+    for k in ("v", "C", "F"):
+        assert np.array_equal(ra[k], rb[k]), k
