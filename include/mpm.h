@@ -294,11 +294,14 @@ int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
  * NULL). For each workgroup count and graph setting the intervals are tried
  * in increasing order, and a candidate over 3 times slower than the best so
  * far ends that run. These candidates use MPM_REBIN_AUTO; the fastest is
- * then also timed with the re-binning mode AUTO did not pick. The scene is
- * left as it was, except that the next mpm_step re-bins and the tool
- * impulses read zero. Blocking; at most 114 calls of mpm_step (a warm-up and
- * a timed call per candidate). A trial shorter than the longer intervals
- * cannot tell them apart.
+ * then also timed with the re-binning mode AUTO did not pick. The
+ * configuration in use is timed first and kept unless the fastest candidate
+ * beats it by more than 5% (both timed once more at the end; the better of
+ * each one's two timings counts), since short trials cannot resolve smaller
+ * differences. The scene is left as it was, except that the next mpm_step
+ * re-bins and the tool impulses read zero. Blocking; at most 120 calls of
+ * mpm_step (a warm-up and a timed call per timing). A trial shorter than the
+ * longer intervals cannot tell them apart.
  * Errors: MPM_EINVAL (no particles, trial_substeps < 1), MPM_ENOMEM (it
  * needs a copy of the particle buffer), MPM_EHIP. */
 int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chosen);
