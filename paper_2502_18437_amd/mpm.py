@@ -373,7 +373,8 @@ class Simulation:
 
     def autotune(self, trial_substeps=32):
         """Time the candidate launch configurations on the current scene and
-        keep the fastest; returns it."""
+        keep the fastest, unless the configuration in use is within 5% of it
+        (then that one stays); returns the configuration kept."""
         c = mpm_launch_config()
         self._check(_lib.mpm_autotune(self.h, int(trial_substeps), ctypes.byref(c)))
         return c.as_dict()
