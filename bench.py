@@ -261,6 +261,8 @@ def main():
                     help="comma-separated particle counts for --solver-sweep (default: 2^14 .. 2^22)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the solver sweep (for profiling its kernels) and print its JSON")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 256-scene batch (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device-to-device copy of MIB MiB (a kernel of known "
                          "traffic that scales hardware byte counters)")
@@ -279,6 +281,9 @@ def main():
     sizes = tuple(int(v) for v in args.sweep_sizes.split(",") if v) or SWEEP_SIZES
     if args.sweep_only:
         print(json.dumps({"solver_sweep": solver_sweep(sizes=sizes)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": batch_throughput(args.diff_steps)}), flush=True)
         return
     s = scenes.make(args.scene)
     n_sub = args.substeps or s.n_substeps
