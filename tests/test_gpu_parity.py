@@ -1,12 +1,14 @@
 """Parity of the HIP substep (through the C ABI) with the FP64 oracle on the
 same seeded inputs, at sizes the oracle finishes in seconds (several grid
 blocks, ragged particle counts), plus edge cases and error codes."""
+import copy
+
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2502_18437_amd import scenes
-from tests.parity import assert_parity, errors, run_gpu, run_oracle
+from tests.parity import advance_tools, assert_parity, dyadic_poses, errors, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -106,6 +108,28 @@ def test_chunked_steps_match():
     g = run_gpu(s, s.n_substeps, chunks=[1, 2, 3, 10, 84])
     o = run_oracle(s, s.n_substeps)
     assert_parity(g, o, s.x, s.n_substeps, "c2s chunked")
+
+
+def test_resume_in_fp32_mode_matches_the_uninterrupted_oracle():
+    """Checkpoint and resume in the default FP32 mode: the state read after
+    40 substeps, given to a new handle with its tools at the poses they
+    reached, ends within the parity tolerances of the oracle's uninterrupted
+    100-substep run (float atomics make the bits order-dependent here)."""
+    from paper_2502_18437_amd import mpm
+    s = dyadic_poses(scenes.scene_c2s())
+    n1, n2 = 40, 60
+    sim = mpm.simulation_from_scene(s)
+    sim.step(n1)
+    mid, st = sim.read_state(allow_errors=True)
+    sim.close()
+    assert st == 0
+    t = copy.deepcopy(s)
+    t.x, t.v, t.C, t.F = (np.array(mid[k], np.float32) for k in ("x", "v", "C", "F"))
+    advance_tools(t, n1)
+    g = run_gpu(t, n2)
+    assert g["status"] == 0
+    o = run_oracle(s, n1 + n2)
+    assert_parity(g, o, s.x, n1 + n2, "c2s resumed")
 
 
 def test_shuffled_particle_order():
