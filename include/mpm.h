@@ -169,6 +169,9 @@ typedef struct mpm_info {
   int32_t resort_interval;
   int32_t accum_mode;
   int32_t n_tools;
+  int64_t rollouts;          /* rollouts recorded by mpm_rollout_forward since
+                                mpm_create; mpm_rollout_backward always
+                                differentiates the latest one */
 } mpm_info;
 
 /* Create a scene on the current HIP device. `hip_stream` is a hipStream_t
@@ -238,6 +241,7 @@ const char* mpm_last_error(const mpm_handle* h);
  * Errors: MPM_EINVAL, MPM_ENOMEM, MPM_EHIP. */
 int mpm_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,
                     int32_t where);
+
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every launch while enabled. Kinds, in order: 0 sort (binning pipeline),

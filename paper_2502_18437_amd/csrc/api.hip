@@ -50,6 +50,7 @@ struct HostTool {
 // Device buffers of the differentiable rollout (allocated on first use,
 // grown as needed) and the record of the last rollout.
 struct DiffBufs {
+  int64_t generation = 0;  // rollouts recorded since mpm_create
   DiffGrid g;
   int grid_n = 0;
   int64_t part_cap = 0;   // particles the per-particle buffers hold
@@ -131,11 +132,12 @@ struct mpm_handle {
   double* imp_sum = nullptr;                  // device: impulse totals of the last mpm_step
   DiffBufs d;
   // Runs of plain substeps (fused transfer + grid update) replayed as HIP
-  // graphs: one instance per particle ping-pong half.
+  // graphs: one instance per particle ping-pong half and parity of the first
+  // grid update of the run (the kernels take the parity as an argument).
   int graph_chunk = kDefaultGraphChunk;
   int rebin_mode = MPM_REBIN_AUTO;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 namespace {
@@ -297,10 +299,11 @@ void prof_collect(mpm_handle* h) {
 
 void drop_graphs(mpm_handle* h) {
   for (int i = 0; i < 2; ++i)
-    if (h->graph[i]) {
-      (void)hipGraphExecDestroy(h->graph[i]);
-      h->graph[i] = nullptr;
-    }
+    for (int p = 0; p < 2; ++p)
+      if (h->graph[i][p]) {
+        (void)hipGraphExecDestroy(h->graph[i][p]);
+        h->graph[i][p] = nullptr;
+      }
 }
 
 // Particles per transfer work item: about N / (4 x workgroups), so that
@@ -601,7 +604,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   alloc((void**)&b.imp_blocks, sizeof(float) * (size_t)h->n_blocks * kImpulseRows * 3);
   alloc((void**)&b.scene_off, sizeof(uint32_t) * ((size_t)n_scenes + 1));
   alloc((void**)&b.tools, sizeof(ToolDesc) * (size_t)n_scenes * kMaxTools);
-  alloc((void**)&b.clock, sizeof(Clock));
+  alloc((void**)&b.clock, 2 * sizeof(Clock));
   alloc((void**)&h->imp_sum, sizeof(double) * kImpulseRows * 3);
   alloc((void**)&h->scratch_u64, sizeof(unsigned long long));
   const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
@@ -963,35 +966,37 @@ bool rebin_in_place(const mpm_handle* h) {
   return h->sim.solver != SOLVER_PB && h->resort_interval >= 4;
 }
 
-// Grid update `it` of `passes` in a substep: PB-MPM leaves gravity out (it
-// is added to the particles) and keeps the impulses of the last pass only;
-// the clock's substep advances after the last pass.
-void launch_grid_pass(mpm_handle* h, int it, int passes, hipStream_t st) {
+// Grid update `it` of `passes` in a substep, of parity `parity`: PB-MPM
+// leaves gravity out (it is added to the particles) and keeps the impulses of
+// the last pass only; the clock's substep advances after the last pass.
+void launch_grid_pass(mpm_handle* h, int it, int passes, int parity, hipStream_t st) {
   const bool last = it == passes - 1;
-  launch_grid(h->b, h->sim, (int)h->n_blocks, st, h->sim.solver != SOLVER_PB, last, last);
+  launch_grid(h->b, h->sim, (int)h->n_blocks, parity, st, h->sim.solver != SOLVER_PB, last, last);
 }
 
 // Record `chunk` plain substeps (fused transfer + grid update) as a graph
-// for the current particle half.
-int record_graph(mpm_handle* h) {
+// for the current particle half, starting at grid-update parity `p0`.
+int record_graph(mpm_handle* h, int p0) {
   if (!h->cap_stream) HIP_OR_RETURN(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   Buffers& b = h->b;
   hipGraph_t g = nullptr;
   HIP_OR_RETURN(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   const int passes = transfer_passes(h);
+  int parity = p0;
   for (int i = 0; i < h->graph_chunk; ++i) {
-    launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, h->cap_stream, PB_FIRST);
+    launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, parity, h->cap_stream, PB_FIRST);
     for (int it = 0; it < passes; ++it) {
-      if (it > 0) launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, h->cap_stream, PB_ITER);
-      launch_grid_pass(h, it, passes, h->cap_stream);
+      if (it > 0) launch_g2p2g(b, h->N, h->sim, h->transfer_wgs, parity, h->cap_stream, PB_ITER);
+      launch_grid_pass(h, it, passes, parity, h->cap_stream);
+      parity ^= 1;
     }
   }
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&h->graph[b.cur], g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&h->graph[b.cur][p0], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    h->graph[b.cur] = nullptr;
+    h->graph[b.cur][p0] = nullptr;
     return hip_fail(h, e, "hipGraphInstantiate");
   }
   return MPM_OK;
@@ -1029,9 +1034,10 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     // the advanced state and the P2G below scatters from it. At the first
     // substep the memory holds the full state (v, C included).
     const bool advance = rebin && k > 0 && !in_place;
+    const int parity = (int)(h->updates & 1);
     if (advance) {
       ProfScope ps(h, 3);
-      launch_g2p(b, N, h->sim, wgs, h->stream);
+      launch_g2p(b, N, h->sim, wgs, parity, h->stream);
     }
     if (rebin) {
       ProfScope ps(h, 0);
@@ -1047,17 +1053,17 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     }
     if (k == 0 || advance) {
       ProfScope ps(h, 1);
-      launch_p2g(b, N, h->sim, wgs, h->stream);
+      launch_p2g(b, N, h->sim, wgs, parity, h->stream);
     } else {
       // Plain substeps until the next re-binning or the end of the call:
       // whole chunks replay the recorded graph (not while timing kernels).
       const int64_t run = std::min<int64_t>(n_substeps - k, h->resort_interval - h->since_sort);
       if (!h->prof && h->graph_chunk > 0 && run >= h->graph_chunk) {
-        if (!h->graph[b.cur]) {
-          rc = record_graph(h);
+        if (!h->graph[b.cur][parity]) {
+          rc = record_graph(h, parity);
           if (rc != MPM_OK) return rc;
         }
-        HIP_OR_RETURN(h, hipGraphLaunch(h->graph[b.cur], h->stream));
+        HIP_OR_RETURN(h, hipGraphLaunch(h->graph[b.cur][parity], h->stream));
         k += h->graph_chunk;
         h->substep += h->graph_chunk;
         h->updates += (int64_t)h->graph_chunk * passes;
@@ -1065,15 +1071,16 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
         continue;
       }
       ProfScope ps(h, 2);
-      launch_g2p2g(b, N, h->sim, wgs, h->stream, PB_FIRST);
+      launch_g2p2g(b, N, h->sim, wgs, parity, h->stream, PB_FIRST);
     }
     for (int it = 0; it < passes; ++it) {
+      const int pit = (parity + it) & 1;
       if (it > 0) {
         ProfScope ps(h, 2);
-        launch_g2p2g(b, N, h->sim, wgs, h->stream, PB_ITER);
+        launch_g2p2g(b, N, h->sim, wgs, pit, h->stream, PB_ITER);
       }
       ProfScope ps(h, 4);
-      launch_grid_pass(h, it, passes, h->stream);
+      launch_grid_pass(h, it, passes, pit, h->stream);
     }
     h->updates += passes;
     h->substep++;
@@ -1082,7 +1089,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   }
   {
     ProfScope ps(h, 3);
-    launch_g2p(b, N, h->sim, wgs, h->stream);
+    launch_g2p(b, N, h->sim, wgs, (int)(h->updates & 1), h->stream);
   }
   HIP_OR_RETURN(h, hipGetLastError());
   return MPM_OK;
@@ -1363,6 +1370,7 @@ int mpm_rollout_forward(mpm_handle* h, int32_t n_substeps, int32_t checkpoint_ev
   h->dirty = true;
   d.T = T, d.K = K, d.start = h->substep - T, d.N = N;
   d.valid = true;
+  d.generation++;
   return MPM_OK;
 }
 
@@ -1536,6 +1544,7 @@ int mpm_get_info(mpm_handle* h, mpm_info* info) {
   for (const HostTool& t : h->tools)
     if (t.active) nt++;
   info->n_tools = nt;
+  info->rollouts = h->d.generation;
   return MPM_OK;
 }
 

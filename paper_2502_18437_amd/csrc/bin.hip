@@ -298,10 +298,14 @@ __global__ __launch_bounds__(kSortWG) void k_radix_scatter(const uint32_t* __res
 // Gathers the particle SoA into key order: x, F, E (when stored) and, with
 // VC, v and C (between fused substeps they are not live). The field loops
 // are unrolled so that a lane's loads are all in flight before its stores.
+// Without VC, particles with the sentinel key (stencil outside the grid or
+// state not finite) still carry their v and C: no transfer kernel visits
+// them, so the values in memory are the ones read back for them.
 template <bool VC, bool HAS_E>
 __global__ void k_permute(const float* __restrict__ src, float* __restrict__ dst,
                           const uint32_t* __restrict__ id_src, uint32_t* __restrict__ id_dst,
-                          const uint32_t* __restrict__ perm, int64_t cap, int64_t N) {
+                          const uint32_t* __restrict__ perm, const uint32_t* __restrict__ keys,
+                          uint32_t sentinel, int64_t cap, int64_t N) {
   constexpr int kLo = VC ? FX : FF;  // fields [FX, FX + 3) and [kLo, kEnd)
   constexpr int kEnd = HAS_E ? kFields : kFields - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -318,6 +322,10 @@ __global__ void k_permute(const float* __restrict__ src, float* __restrict__ dst
 #pragma unroll
     for (int f = kLo; f < kEnd; ++f)
       if (f >= FV) dst[f * cap + i] = r[f - kLo];
+    if constexpr (!VC) {
+      if (keys[i] >= sentinel)
+        for (int f = FV; f < FF; ++f) dst[f * cap + i] = src[f * cap + j];
+    }
     id_dst[i] = id;
   }
 }
@@ -433,14 +441,19 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool wit
   const dim3 pg(grid_for(N, 256)), pb(256);
   const float* ps = b.part[b.cur];
   float* pd = b.part[b.cur ^ 1];
+  const uint32_t* kk = b.keys[src];
   if (with_vc && s.has_E)
-    hipLaunchKernelGGL((k_permute<true, true>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
+    hipLaunchKernelGGL((k_permute<true, true>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], kk,
+                       sentinel, b.cap, N);
   else if (with_vc)
-    hipLaunchKernelGGL((k_permute<true, false>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
+    hipLaunchKernelGGL((k_permute<true, false>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], kk,
+                       sentinel, b.cap, N);
   else if (s.has_E)
-    hipLaunchKernelGGL((k_permute<false, true>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
+    hipLaunchKernelGGL((k_permute<false, true>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], kk,
+                       sentinel, b.cap, N);
   else
-    hipLaunchKernelGGL((k_permute<false, false>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], b.cap, N);
+    hipLaunchKernelGGL((k_permute<false, false>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], kk,
+                       sentinel, b.cap, N);
   b.cur ^= 1;
   // 4. per-block ranges
   fill_u32(b.blk_begin, n_blocks, 0u, st);

@@ -27,9 +27,9 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
                                                   const uint32_t* __restrict__ ovf1,
                                                   uint32_t* mark, uint32_t* __restrict__ node_cnt,
                                                   float* __restrict__ imp_blocks, const ToolDesc* __restrict__ tools,
-                                                  Status* st, Clock* clk, int record, SimK s) {
-  const int parity = clk->parity;
-  const long long substep = clk->substep;
+                                                  Status* st, Clock* clk, int parity, int dsub, int record,
+                                                  SimK s) {
+  const long long substep = clk[parity].substep;
   const uint32_t* __restrict__ ovf_list = parity ? ovf1 : ovf0;
   // Momentum given to the material by each tool and by the walls on the nodes
   // of one block (two-way coupling, Sec. IV-A), added to the block's own
@@ -194,36 +194,30 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
     }
     __syncthreads();
   }
-  // Clear the other parity's overflow list for the next substep.
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->ovf_count[parity ^ 1] = 0u;
+  // Clear the other parity's overflow list for the next substep, and set the
+  // other parity's clock: every workgroup has read this parity's entry, and
+  // the kernels of the next grid update's parity read the other one.
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->ovf_count[parity ^ 1] = 0u;
+    clk[parity ^ 1].substep = substep + dsub;
+  }
 }
 
-// Advance the clock after the grid update (a kernel of its own: a counter of
-// finished workgroups inside k_grid would serialise its thousands of
-// workgroups on one address).
-__global__ void k_advance_clock(Clock* clk, int dsub) {
-  clk->substep += dsub;
-  clk->parity ^= 1;
-}
-
-__global__ void k_set_clock(Clock* clk, long long substep, int parity) {
-  clk->substep = substep;
-  clk->parity = parity;
-}
+__global__ void k_set_clock(Clock* clk, long long substep, int parity) { clk[parity].substep = substep; }
 
 void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st) {
   hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(1), 0, st, b.clock, substep, parity & 1);
 }
 
-void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st, bool gravity, bool record, bool last) {
+void launch_grid(Buffers& b, const SimK& s, int max_act, int parity, hipStream_t st, bool gravity, bool record,
+                 bool last) {
   int wgs = max_act < kGridSlots ? max_act : kGridSlots;
   if (wgs < 1) wgs = 1;
   SimK k = s;
   if (!gravity) k.g[0] = k.g[1] = k.g[2] = 0.0f;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
                      b.acc_p[2], b.vel, b.act_list, b.ovf_list[0], b.ovf_list[1], b.mark, b.node_cnt, b.imp_blocks,
-                     (const ToolDesc*)b.tools, b.status, b.clock, record ? 1 : 0, k);
-  hipLaunchKernelGGL(k_advance_clock, dim3(1), dim3(1), 0, st, b.clock, last ? 1 : 0);
+                     (const ToolDesc*)b.tools, b.status, b.clock, parity & 1, last ? 1 : 0, record ? 1 : 0, k);
 }
 
 }  // namespace mpm

@@ -72,83 +72,135 @@ __device__ inline bool polar_newton(const float* F, float* R) {
   return false;
 }
 
-// Rotation of the sign-fixed SVD F = U diag(s0, s1, +-s2) V^T (U, V
-// rotations; Irving et al. 2004), from a cyclic Jacobi eigen-decomposition
-// of F^T F (Golub & Van Loan, Sec. 8.5). Used only when det F <= 0, where
-// Newton's iteration does not give a rotation.
+// Givens-type rotation of the symmetric eigenproblem: the cosine and sine
+// that zero the (p, q) entry of a symmetric matrix with diagonal app, aqq and
+// off-diagonal apq (the classical Jacobi angle, |theta| <= pi/4).
+__device__ __forceinline__ void jacobi_angle(float app, float aqq, float apq, float* c, float* s) {
+  if (fabsf(apq) < 1e-30f) {
+    *c = 1.0f;
+    *s = 0.0f;
+    return;
+  }
+  const float tau = (aqq - app) / (2.0f * apq);
+  const float t = copysignf(1.0f, tau) / (fabsf(tau) + sqrtf(1.0f + tau * tau));
+  *c = rsqrtf(1.0f + t * t);
+  *s = t * *c;
+}
+
+// q <- q * (cos(phi/2), sin(phi/2) e_axis): composes a rotation by phi about
+// a coordinate axis on the right of the rotation held as unit quaternion q
+// (w, x, y, z), given cos(phi) = c and sin(phi) = s with |phi| <= pi/4.
+__device__ __forceinline__ void quat_turn(float* q, int axis, float c, float s) {
+  const float ch = sqrtf(0.5f * (1.0f + c));
+  const float sh = 0.5f * s / ch;
+  float e[3] = {0.0f, 0.0f, 0.0f};
+  e[axis] = sh;
+  const float w = q[0] * ch - (q[1] * e[0] + q[2] * e[1] + q[3] * e[2]);
+  const float x = q[0] * e[0] + ch * q[1] + (q[2] * e[2] - q[3] * e[1]);
+  const float y = q[0] * e[1] + ch * q[2] + (q[3] * e[0] - q[1] * e[2]);
+  const float z = q[0] * e[2] + ch * q[3] + (q[1] * e[1] - q[2] * e[0]);
+  q[0] = w, q[1] = x, q[2] = y, q[3] = z;
+}
+
+// Rotation U V^T of the sign-fixed SVD F = U diag(s0, s1, s2) V^T, with U
+// and V rotations, s0 >= s1 >= |s2| and s2 < 0 when det F < 0 (the sign
+// convention of Irving et al. 2004). The steps follow McAdams et al. 2011
+// ("Computing the singular value decomposition of 3x3 matrices with minimal
+// branching and elementary floating point operations"): a fixed number of
+// cyclic Jacobi sweeps on the symmetric F^T F with V kept as a unit
+// quaternion; B = F V with its columns sorted by decreasing norm (a swap
+// negates one column so V stays a rotation); then the QR decomposition of B
+// by Givens rotations, whose orthogonal factor is U and whose triangular
+// factor carries the singular values, the last with the sign of det F. Used
+// where Newton's polar iteration does not apply (det F <= 0).
 __device__ __forceinline__ void polar_svd_signfix(const float* F, float* R) {
-  float A[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  // symmetric S = F^T F
+  float S[3][3];
+#pragma unroll
   for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      A[3 * r + c] = F[r] * F[c] + F[3 + r] * F[3 + c] + F[6 + r] * F[6 + c];
-  for (int sweep = 0; sweep < 10; ++sweep) {
-    for (int pi = 0; pi < 3; ++pi) {
-      const int p = (pi == 2) ? 1 : 0;
-      const int q = (pi == 0) ? 1 : 2;
-      const float apq = A[3 * p + q];
-      if (fabsf(apq) < 1e-30f) continue;
-      const float th = (A[3 * q + q] - A[3 * p + p]) / (2.0f * apq);
-      const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(th * th + 1.0f));
-      const float c = rsqrtf(t * t + 1.0f), s = t * c;
-      for (int k = 0; k < 3; ++k) {  // columns p, q of A and V
-        const float akp = A[3 * k + p], akq = A[3 * k + q];
-        A[3 * k + p] = c * akp - s * akq;
-        A[3 * k + q] = s * akp + c * akq;
-        const float vkp = V[3 * k + p], vkq = V[3 * k + q];
-        V[3 * k + p] = c * vkp - s * vkq;
-        V[3 * k + q] = s * vkp + c * vkq;
-      }
-      for (int k = 0; k < 3; ++k) {  // rows p, q of A
-        const float apk = A[3 * p + k], aqk = A[3 * q + k];
-        A[3 * p + k] = c * apk - s * aqk;
-        A[3 * q + k] = s * apk + c * aqk;
-      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[r][c] = F[r] * F[c] + F[3 + r] * F[3 + c] + F[6 + r] * F[6 + c];
+  float q[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+  // Jacobi rotation J in the (p, q) plane (J_pp = J_qq = c, J_pq = s,
+  // J_qp = -s): S <- J^T S J, V <- V J. J is the turn by -theta about the
+  // third axis for the cyclic pairs (0, 1) and (1, 2), by +theta about y for
+  // the pair (0, 2).
+  for (int sweep = 0; sweep < 5; ++sweep) {
+#pragma unroll
+    for (int pair = 0; pair < 3; ++pair) {
+      const int p = pair == 2 ? 1 : 0, qq = pair == 0 ? 1 : 2, r = 3 - p - qq;
+      float c, s;
+      jacobi_angle(S[p][p], S[qq][qq], S[p][qq], &c, &s);
+      const float t = s / c;
+      const float apq = S[p][qq];
+      S[p][p] -= t * apq;
+      S[qq][qq] += t * apq;
+      S[p][qq] = S[qq][p] = 0.0f;
+      const float arp = S[r][p], arq = S[r][qq];
+      S[r][p] = S[p][r] = c * arp - s * arq;
+      S[r][qq] = S[qq][r] = s * arp + c * arq;
+      quat_turn(q, r, c, pair == 1 ? s : -s);
     }
   }
-  float lam[3] = {A[0], A[4], A[8]};
-  int o[3] = {0, 1, 2};
-  for (int i = 0; i < 3; ++i)
-    for (int j = i + 1; j < 3; ++j)
-      if (lam[o[j]] > lam[o[i]]) {
-        const int t = o[i];
-        o[i] = o[j];
-        o[j] = t;
-      }
-  float v[3][3], u[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < 3; ++k) v[i][k] = V[3 * k + o[i]];
-  const float dv = v[0][0] * (v[1][1] * v[2][2] - v[1][2] * v[2][1]) -
-                   v[0][1] * (v[1][0] * v[2][2] - v[1][2] * v[2][0]) +
-                   v[0][2] * (v[1][0] * v[2][1] - v[1][1] * v[2][0]);
-  if (dv < 0.0f)
-    for (int k = 0; k < 3; ++k) v[2][k] = -v[2][k];
-  for (int i = 0; i < 2; ++i)
-    for (int r = 0; r < 3; ++r)
-      u[i][r] = F[3 * r] * v[i][0] + F[3 * r + 1] * v[i][1] + F[3 * r + 2] * v[i][2];
-  float n0 = sqrtf(u[0][0] * u[0][0] + u[0][1] * u[0][1] + u[0][2] * u[0][2]);
-  if (n0 > 0.0f) {
-    for (int r = 0; r < 3; ++r) u[0][r] /= n0;
-  } else {
-    u[0][0] = 1.0f, u[0][1] = 0.0f, u[0][2] = 0.0f;
-  }
-  const float d01 = u[0][0] * u[1][0] + u[0][1] * u[1][1] + u[0][2] * u[1][2];
-  for (int r = 0; r < 3; ++r) u[1][r] -= d01 * u[0][r];
-  float n1 = sqrtf(u[1][0] * u[1][0] + u[1][1] * u[1][1] + u[1][2] * u[1][2]);
-  if (n1 > 1e-30f) {
-    for (int r = 0; r < 3; ++r) u[1][r] /= n1;
-  } else {
-    float a[3] = {0.0f, 0.0f, 0.0f};
-    a[fabsf(u[0][0]) < 0.9f ? 0 : 1] = 1.0f;
-    const float d = a[0] * u[0][0] + a[1] * u[0][1] + a[2] * u[0][2];
-    for (int r = 0; r < 3; ++r) a[r] -= d * u[0][r];
-    const float na = sqrtf(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
-    for (int r = 0; r < 3; ++r) u[1][r] = a[r] / na;
-  }
-  u[2][0] = u[0][1] * u[1][2] - u[0][2] * u[1][1];
-  u[2][1] = u[0][2] * u[1][0] - u[0][0] * u[1][2];
-  u[2][2] = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+  // V from the quaternion (renormalised)
+  const float qn = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float w = q[0] * qn, x = q[1] * qn, y = q[2] * qn, z = q[3] * qn;
+  float V[3][3] = {{1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y)},
+                   {2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x)},
+                   {2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)}};
+  // B = F V, columns sorted by decreasing norm
+  float B[3][3];
+#pragma unroll
   for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) R[3 * r + c] = u[0][r] * v[0][c] + u[1][r] * v[1][c] + u[2][r] * v[2][c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) B[r][c] = F[3 * r] * V[0][c] + F[3 * r + 1] * V[1][c] + F[3 * r + 2] * V[2][c];
+  float n2[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) n2[c] = B[0][c] * B[0][c] + B[1][c] * B[1][c] + B[2][c] * B[2][c];
+  auto swap_cols = [&](int a, int b) {  // exchange columns a, b; negate the new b
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float tb = B[r][a], tv = V[r][a];
+      B[r][a] = B[r][b], V[r][a] = V[r][b];
+      B[r][b] = -tb, V[r][b] = -tv;
+    }
+    const float tn = n2[a];
+    n2[a] = n2[b], n2[b] = tn;
+  };
+  if (n2[1] > n2[0]) swap_cols(0, 1);
+  if (n2[2] > n2[0]) swap_cols(0, 2);
+  if (n2[2] > n2[1]) swap_cols(1, 2);
+  // QR of B by Givens rotations on rows (0,1), (0,2), (1,2): B = U T with T
+  // upper triangular, U = G1^T G2^T G3^T accumulated as a matrix.
+  float U[3][3] = {{1.0f, 0.0f, 0.0f}, {0.0f, 1.0f, 0.0f}, {0.0f, 0.0f, 1.0f}};
+#pragma unroll
+  for (int step = 0; step < 3; ++step) {
+    const int i = step == 2 ? 1 : 0, k = step == 0 ? 1 : 2;  // zero B[k][i] against B[i][i]
+    const float a = B[i][i], b = B[k][i];
+    const float rho2 = a * a + b * b;
+    float c = 1.0f, s = 0.0f;
+    if (rho2 > 1e-36f) {
+      const float ir = rsqrtf(rho2);
+      c = a * ir;
+      s = b * ir;
+    }
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {  // rows i, k of B
+      const float bi = B[i][col], bk = B[k][col];
+      B[i][col] = c * bi + s * bk;
+      B[k][col] = c * bk - s * bi;
+    }
+#pragma unroll
+    for (int row = 0; row < 3; ++row) {  // columns i, k of U (U <- U G^T)
+      const float ui = U[row][i], uk = U[row][k];
+      U[row][i] = c * ui + s * uk;
+      U[row][k] = c * uk - s * ui;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[3 * r + c] = U[r][0] * V[c][0] + U[r][1] * V[c][1] + U[r][2] * V[c][2];
 }
 
 // Derivatives of the weights above with respect to f.

@@ -142,15 +142,15 @@ struct Status {
   unsigned int ovf_count[2];        // overflow blocks claimed, per parity
 };
 
-// Substep clock on the device: the transfer and grid kernels read the
-// substep (tool poses) and the parity of the grid update (overflow lists)
-// from here rather than from their arguments, so that a run of substeps can
-// be recorded once and replayed. A one-thread kernel after each grid update
-// flips the parity and advances the substep (PB-MPM: only after the last
-// iteration of a step).
+// Substep clock on the device, one entry per parity of the grid update
+// (grid updates alternate the parity, which also picks the overflow list):
+// the transfer and grid kernels of parity p read the substep (tool poses)
+// from entry p rather than from their arguments, so that a run of substeps
+// can be recorded once and replayed. The grid update of parity p writes entry
+// p ^ 1 for the kernels after it: the same substep, or the next one after the
+// last grid update of a substep (PB-MPM runs several per substep).
 struct Clock {
   long long substep;
-  int parity;
 };
 
 // Device buffers of one handle.
@@ -179,7 +179,7 @@ struct Buffers {
   void* acc_p[3] = {nullptr, nullptr, nullptr};  // momentum channels (float or int64)
   float4* vel = nullptr;                    // grid velocity
   Status* status = nullptr;
-  Clock* clock = nullptr;
+  Clock* clock = nullptr;                   // two entries, by parity
 };
 
 // ---------------------------------------------------------------- launchers
@@ -190,21 +190,24 @@ struct Buffers {
 // held in memory).
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool with_vc, hipStream_t st);
 
-// Transfers (the overflow list of the clock's parity takes drifted particles).
-// The solver is s.solver; `pass` selects the PB-MPM pass (PBPass) and is
-// ignored by the other solvers.
-void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
-void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st, int pass = PB_FIRST);
-void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st);
+// Transfers before the grid update of parity `parity` (its overflow list
+// takes drifted particles; push-out reads its clock entry). The solver is
+// s.solver; `pass` selects the PB-MPM pass (PBPass) and is ignored by the
+// other solvers.
+void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st);
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st,
+                  int pass = PB_FIRST);
+void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st);
 
-// Grid update over active blocks and the clock parity's overflow blocks, with
-// each scene's tools at their pose of the clock's substep; then flips the
-// clock's parity and, when `last`, advances its substep. `gravity` adds
-// dt g to the node velocities; `record` adds the tools' and walls' momentum
-// changes to the impulse sums.
-void launch_grid(Buffers& b, const SimK& s, int max_act, hipStream_t st, bool gravity = true, bool record = true,
-                 bool last = true);
-// Set the device clock to `substep` and `parity`.
+// Grid update of parity `parity` over active blocks and that parity's
+// overflow blocks, with each scene's tools at their pose of the clock
+// entry's substep; it sets the other parity's clock entry to the same
+// substep or, when `last`, the next. `gravity` adds dt g to the node
+// velocities; `record` adds the tools' and walls' momentum changes to the
+// impulse sums.
+void launch_grid(Buffers& b, const SimK& s, int max_act, int parity, hipStream_t st, bool gravity = true,
+                 bool record = true, bool last = true);
+// Set the clock entry of `parity` to `substep`.
 void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st);
 
 // Spatial order of a one-scene particle set held as an AoS x (N x 3) in the

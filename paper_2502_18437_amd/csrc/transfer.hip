@@ -587,8 +587,7 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
                                              const uint32_t* __restrict__ blk_end,
                                              const uint2* __restrict__ work, Status* st,
                                              ACC_PARAMS, uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
-                                             const Clock* __restrict__ clk, SimK s) {
-  const int parity = clk->parity;
+                                             int parity, SimK s) {
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds L;
   Counters cnt;
@@ -640,13 +639,12 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
                                                const uint2* __restrict__ work, Status* st,
                                                ACC_PARAMS, const float4* __restrict__ vel,
                                                uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
-                                               const Clock* __restrict__ clk,
+                                               const Clock* __restrict__ clk, int parity,
                                                const ToolDesc* __restrict__ tools, SimK s) {
   constexpr bool kIntegrate = !(SOL == SOLVER_PB && PASS == PB_ITER);
   static_assert(!PUSH || kIntegrate, "push-out follows a position update");
-  const int parity = clk->parity;
   long long substep = 0;
-  if constexpr (PUSH) substep = clk->substep;
+  if constexpr (PUSH) substep = clk[parity].substep;
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds L;
   Counters cnt;
@@ -688,6 +686,15 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
         for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
         const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
         p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+        // An update that moved the particle out of the grid (or left its
+        // state not finite) is its last: the particle is left unchanged from
+        // then on, so its v and C of this update are kept in memory with it.
+        if (ev & (kEvDom | kEvNf)) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) part[(FV + a) * cap + p] = vn[a];
+#pragma unroll
+          for (int i = 0; i < 9; ++i) part[(FC + i) * cap + p] = Cn[i];
+        }
       } else {
         p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
       }
@@ -707,10 +714,10 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
                                              const uint32_t* __restrict__ blk_end,
                                              const uint2* __restrict__ work, Status* st,
                                              const float4* __restrict__ vel, const Clock* __restrict__ clk,
-                                             const ToolDesc* __restrict__ tools, SimK s) {
+                                             int parity, const ToolDesc* __restrict__ tools, SimK s) {
   __shared__ Lds L;
   long long substep = 0;
-  if constexpr (PUSH) substep = clk->substep;
+  if constexpr (PUSH) substep = clk[parity].substep;
   Counters cnt;
   unsigned pos, end, stride;
   xcd_walk(st->n_work, &pos, &end, &stride);
@@ -758,89 +765,89 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
 
 // ------------------------------------------------------------------ launchers
 template <bool FIXED, int SOL>
-static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
   hipLaunchKernelGGL((k_p2g<FIXED, SOL>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
                      b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
-                     (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock, s);
+                     (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], parity, s);
 }
 
 template <bool FIXED, int SOL, int PASS, bool PUSH>
-static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
   hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS, PUSH>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
                      b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
                      (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock,
-                     (const ToolDesc*)b.tools, s);
+                     parity, (const ToolDesc*)b.tools, s);
 }
 
 // The integrating passes with or without push-out.
 template <bool FIXED, int SOL>
-static void launch_g2p2g_p(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+static void launch_g2p2g_p(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   if (s.push_out)
-    launch_g2p2g_t<FIXED, SOL, PB_FIRST, true>(b, s, grid_wgs, st);
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, true>(b, s, grid_wgs, parity, st);
   else
-    launch_g2p2g_t<FIXED, SOL, PB_FIRST, false>(b, s, grid_wgs, st);
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, false>(b, s, grid_wgs, parity, st);
 }
 
 template <bool FIXED>
-static void launch_p2g_s(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+static void launch_p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   if (s.solver == SOLVER_PIC)
-    launch_p2g_t<FIXED, SOLVER_PIC>(b, s, grid_wgs, st);
+    launch_p2g_t<FIXED, SOLVER_PIC>(b, s, grid_wgs, parity, st);
   else if (s.solver == SOLVER_PB)
-    launch_p2g_t<FIXED, SOLVER_PB>(b, s, grid_wgs, st);
+    launch_p2g_t<FIXED, SOLVER_PB>(b, s, grid_wgs, parity, st);
   else
-    launch_p2g_t<FIXED, SOLVER_MLS>(b, s, grid_wgs, st);
+    launch_p2g_t<FIXED, SOLVER_MLS>(b, s, grid_wgs, parity, st);
 }
 
 template <bool FIXED>
-static void launch_g2p2g_s(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st, int pass) {
+static void launch_g2p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass) {
   if (s.solver == SOLVER_PIC)
-    launch_g2p2g_p<FIXED, SOLVER_PIC>(b, s, grid_wgs, st);
+    launch_g2p2g_p<FIXED, SOLVER_PIC>(b, s, grid_wgs, parity, st);
   else if (s.solver == SOLVER_PB && pass == PB_ITER)
-    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER, false>(b, s, grid_wgs, st);
+    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER, false>(b, s, grid_wgs, parity, st);
   else if (s.solver == SOLVER_PB)
-    launch_g2p2g_p<FIXED, SOLVER_PB>(b, s, grid_wgs, st);
+    launch_g2p2g_p<FIXED, SOLVER_PB>(b, s, grid_wgs, parity, st);
   else
-    launch_g2p2g_p<FIXED, SOLVER_MLS>(b, s, grid_wgs, st);
+    launch_g2p2g_p<FIXED, SOLVER_MLS>(b, s, grid_wgs, parity, st);
 }
 
-void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
+void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   (void)N;
   if (s.fixed)
-    launch_p2g_s<true>(b, s, grid_wgs, st);
+    launch_p2g_s<true>(b, s, grid_wgs, parity, st);
   else
-    launch_p2g_s<false>(b, s, grid_wgs, st);
+    launch_p2g_s<false>(b, s, grid_wgs, parity, st);
 }
 
-void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st, int pass) {
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass) {
   (void)N;
   if (s.fixed)
-    launch_g2p2g_s<true>(b, s, grid_wgs, st, pass);
+    launch_g2p2g_s<true>(b, s, grid_wgs, parity, st, pass);
   else
-    launch_g2p2g_s<false>(b, s, grid_wgs, st, pass);
+    launch_g2p2g_s<false>(b, s, grid_wgs, parity, st, pass);
 }
 
 template <int SOL>
-static void launch_g2p_t(Buffers& b, const SimK& s, int grid_wgs, hipStream_t st) {
+static void launch_g2p_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   const Clock* clk = (const Clock*)b.clock;
   const ToolDesc* tools = (const ToolDesc*)b.tools;
   if (s.push_out)
     hipLaunchKernelGGL((k_g2p<SOL, true>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_end,
-                       b.work, b.status, b.vel, clk, tools, s);
+                       b.work, b.status, b.vel, clk, parity, tools, s);
   else
     hipLaunchKernelGGL((k_g2p<SOL, false>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_end,
-                       b.work, b.status, b.vel, clk, tools, s);
+                       b.work, b.status, b.vel, clk, parity, tools, s);
 }
 
-void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, hipStream_t st) {
+void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   (void)N;
   if (s.solver == SOLVER_PIC)
-    launch_g2p_t<SOLVER_PIC>(b, s, grid_wgs, st);
+    launch_g2p_t<SOLVER_PIC>(b, s, grid_wgs, parity, st);
   else
-    launch_g2p_t<SOLVER_MLS>(b, s, grid_wgs, st);
+    launch_g2p_t<SOLVER_MLS>(b, s, grid_wgs, parity, st);
 }
 
 }  // namespace mpm

@@ -59,7 +59,8 @@ class mpm_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_particles", "substeps", "resorts", "occupied_blocks", "active_blocks", "active_nodes",
         "n_inverted", "n_domain", "n_nonfinite", "n_fallback", "n_range")] + \
-        [(n, ctypes.c_int32) for n in ("tile", "resort_interval", "accum_mode", "n_tools")]
+        [(n, ctypes.c_int32) for n in ("tile", "resort_interval", "accum_mode", "n_tools")] + \
+        [("rollouts", ctypes.c_int64)]
 
 
 class mpm_launch_config(ctypes.Structure):
@@ -462,6 +463,9 @@ def _rollout_fn():
                    "C": torch.empty((n, 3, 3), dtype=torch.float32, device=dev),
                    "F": torch.empty((n, 3, 3), dtype=torch.float32, device=dev)}
             sim.read_state(out)
+            # The library differentiates only its latest rollout: remember
+            # which one this node recorded.
+            ctx.generation = sim.info()["rollouts"]
             ctx.sim, ctx.tool_id = sim, tool_id
             ctx.table = None if vel_table is None else (vel_table.dtype, vel_table.device)
             ctx.theta_dtype = theta.dtype
@@ -469,6 +473,10 @@ def _rollout_fn():
 
         @staticmethod
         def backward(ctx, gx, gv, gC, gF):
+            if ctx.sim.info()["rollouts"] != ctx.generation:
+                raise RuntimeError("mpm.rollout: the simulation recorded another rollout after this one; "
+                                   "its backward would use the later rollout's checkpoints (call backward "
+                                   "before the next rollout on the same Simulation)")
             g = ctx.sim.rollout_backward(gx, gv, gC, gF, want_vel=ctx.table is not None, want_state=False)
             tb = None
             if ctx.table is not None:

@@ -48,7 +48,7 @@ int main(void) {
   F(mpm_tool, type) F(mpm_tool, center) F(mpm_tool, quat) F(mpm_tool, size) F(mpm_tool, lin_vel)
   F(mpm_tool, ang_vel) F(mpm_tool, mu) F(mpm_tool, drag) F(mpm_tool, margin) F(mpm_tool, push_out)
   printf("mpm_info SIZEOF %zu\n", sizeof(mpm_info));
-  F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, n_range) F(mpm_info, tile) F(mpm_info, n_tools)
+  F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, n_range) F(mpm_info, tile) F(mpm_info, n_tools) F(mpm_info, rollouts)
   printf("mpm_launch_config SIZEOF %zu\n", sizeof(mpm_launch_config));
   F(mpm_launch_config, resort_interval) F(mpm_launch_config, transfer_wgs) F(mpm_launch_config, graph_chunk) F(mpm_launch_config, rebin_mode)
   printf("mpm_kernel_times SIZEOF %zu\n", sizeof(mpm_kernel_times));

@@ -212,6 +212,40 @@ def test_empty_scene_and_single_particle():
     sim.close()
 
 
+@pytest.mark.parametrize("rebin_mode", ["in_place", "advance"])
+def test_particles_leaving_the_grid_keep_their_last_state(rebin_mode):
+    """A block falling through the floor of a grid without walls: its
+    particles leave the grid one layer after another, and from then on each
+    is left unchanged (EDOMAIN) with the v, C, F and x of the substep that
+    moved it out, as in the oracle. The re-binnings every 3 substeps (in
+    place, then also after a G2P pass) sort those particles last, with a
+    sentinel key; their state must travel with them."""
+    m = mpm()
+    s = scenes.tiny_block(n_grid=32, per_axis=6, seed=21, center=(0.5, 0.2, 0.5))
+    s.wall_band = 0
+    s.dt = 5e-4
+    # falling at 30 m/s and spinning at 20 rad/s about z, so that particles
+    # of one block differ in velocity by up to a few m/s: a particle that
+    # carried another's v would be far outside the bar
+    w = 20.0
+    r = s.x.astype(np.float64) - np.array([0.5, 0.2, 0.5])
+    spin = np.stack([-w * r[:, 1], w * r[:, 0], np.zeros(s.N)], axis=1)
+    s.v = (s.v + spin + np.array([0.0, -30.0, 0.0])).astype(np.float32)
+    s.C = (s.C + np.array([[0.0, -w, 0.0], [w, 0.0, 0.0], [0.0, 0.0, 0.0]])).astype(np.float32)
+    k = 13  # the lowest layers leave from about substep 10 on
+    mode = m.MPM_REBIN_IN_PLACE if rebin_mode == "in_place" else m.MPM_REBIN_ADVANCE
+    g = run_gpu(s, k, resort_interval=3, rebin_mode=mode)
+    o = run_oracle(s, k)
+    assert g["status"] == m.MPM_EDOMAIN and o["status"] == O.ST_EDOMAIN
+    gone = np.nonzero(o["x"][:, 1] / s.dx - 0.5 < 0.0)[0]
+    assert 20 < gone.size < s.N  # some left early, some stay in the grid
+    assert g["info"]["resorts"] >= 4
+    assert_parity(g, o, s.x, k, f"leaving the grid ({rebin_mode}, {gone.size} left)")
+    # the particles that left, on their own: each carries its own last state
+    sub = lambda r: {f: r[f][gone] for f in ("x", "v", "C", "F")}  # noqa: E731
+    assert_parity(sub(g), sub(o), s.x[gone], k, f"the {gone.size} particles that left ({rebin_mode})")
+
+
 def test_error_codes():
     m = mpm()
     with pytest.raises(m.MPMError) as e:
