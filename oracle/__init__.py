@@ -44,6 +44,8 @@ def lib():
         L.oracle_last_grid.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.oracle_impulses.argtypes = [ctypes.c_void_p, dp]
         L.oracle_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)]
+        L.oracle_set_tie_band.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
+        L.oracle_read_ties.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong), dp]
         L.oracle_weights.argtypes = [ctypes.c_double, dp]
         L.oracle_polar.restype = ctypes.c_double
         L.oracle_polar.argtypes = [dp, dp]
@@ -328,6 +330,22 @@ class Oracle:
         o, po = _d(np.zeros((9, 3)))
         lib().oracle_impulses(self.h, po)
         return o
+
+    def set_tie_band(self, eta, policy=0):
+        """Record contact decisions within eta (m) of their threshold (ties
+        that rounding decides) and decide them by policy: 0 as computed, +1 in
+        contact, -1 not in contact; eta < 0 turns tracking off. MLS-MPM."""
+        assert lib().oracle_set_tie_band(self.h, float(eta), int(policy)) == 0
+
+    def ties(self):
+        """(taint, n_tie, max_jump): the particles whose state depends on a
+        recorded tie decision (bool, N), the number of tie decisions and the
+        largest velocity jump (m/s) one of them could make at its node."""
+        t = np.zeros(self.N, dtype=np.uint8)
+        n = ctypes.c_longlong(0)
+        j, pj = _d(np.zeros(1))
+        lib().oracle_read_ties(self.h, t.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n), pj)
+        return t.astype(bool), int(n.value), float(j[0])
 
     def counters(self):
         o = np.zeros(3, dtype=np.int64)

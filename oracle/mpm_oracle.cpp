@@ -392,11 +392,33 @@ void rotate(const double* R, const double* a, double* out) {
   for (int i = 0; i < 3; ++i) out[i] = R[3 * i] * a[0] + R[3 * i + 1] * a[1] + R[3 * i + 2] * a[2];
 }
 
+// The contact decision "value below threshold" of Sec. IV-A (the node is
+// inside the rigid geometry, or within the fattened margin). Test
+// diagnostics only: with a tie band eta >= 0, a value within eta of the
+// threshold is a tie -- its side is decided by rounding, so an FP32
+// implementation may take the other one -- and is reported through *tied and
+// decided by `policy` (0: as computed, +1: in contact, -1: not in contact).
+struct TieRule {
+  double eta = -1.0;
+  int policy = 0;
+};
+
+bool below(double value, double threshold, const TieRule* tie, bool* tied) {
+  if (tie && tie->eta >= 0.0 && std::fabs(value - threshold) <= tie->eta) {
+    *tied = true;
+    if (tie->policy != 0) return tie->policy > 0;
+  }
+  return value < threshold;
+}
+
 // Contact of one node (position xI, velocity vI) with one tool centred at c.
 // Returns true when the tool changed the velocity field (node in contact).
+// `tie` (may be null) and `tied` report contact decisions within a tie band.
 bool tool_node_contact(int type, const double* c, const double* R, const double* size, const double* lv,
                        const double* av, double mu, double drag, double margin, const double* xI,
-                       double* vI) {
+                       double* vI, const TieRule* tie = nullptr, bool* tied = nullptr) {
+  bool tied_local = false;
+  if (!tied) tied = &tied_local;
   const double r[3] = {xI[0] - c[0], xI[1] - c[1], xI[2] - c[2]};
   double pl[3];
   for (int i = 0; i < 3; ++i) pl[i] = R[0 * 3 + i] * r[0] + R[1 * 3 + i] * r[1] + R[2 * 3 + i] * r[2];
@@ -407,7 +429,7 @@ bool tool_node_contact(int type, const double* c, const double* R, const double*
   if (type == TOOL_CAPSULE || type == TOOL_BOX || type == TOOL_PLANE) {
     double grad[3];
     const double phi = tool_sdf(type, c, R, size, xI, grad);
-    if (!(phi < margin)) return false;
+    if (!below(phi, margin, tie, tied)) return false;
     const double gn = std::sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
     const double nrm[3] = {grad[0] / gn, grad[1] / gn, grad[2] / gn};
     contact_correct(nrm, u, mu, drag, un);
@@ -416,7 +438,7 @@ bool tool_node_contact(int type, const double* c, const double* R, const double*
     const double qx = std::fabs(pl[0]) - hx > 0.0 ? std::fabs(pl[0]) - hx : 0.0;
     const double qy = std::fabs(pl[1]) - hy > 0.0 ? std::fabs(pl[1]) - hy : 0.0;
     const double d = std::sqrt(qx * qx + qy * qy + pl[2] * pl[2]);
-    if (!(d < margin)) return false;
+    if (!below(d, margin, tie, tied)) return false;
     if (pl[1] > hy) {
       un[0] = un[1] = un[2] = 0.0;  // spine side: sticky
     } else {
@@ -452,7 +474,7 @@ bool tool_node_contact(int type, const double* c, const double* R, const double*
     }
     double e[3] = {pl[0] - proj[0], pl[1] - proj[1], pl[2] - proj[2]};
     const double L = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-    if (!(L < thick)) return false;
+    if (!below(L, thick, tie, tied)) return false;
     double nl[3];
     if (L > 0.0) {
       nl[0] = e[0] / L, nl[1] = e[1] / L, nl[2] = e[2] / L;
@@ -487,6 +509,16 @@ struct Scene {
   int solver = SOLVER_MLS;
   int pb_iterations = 10;
   double pb_beta = 0.5;
+  // Tie tracking (test diagnostics, off unless set; MLS-MPM transfers): the
+  // contact decisions within tie.eta of their threshold, the nodes whose
+  // velocity such a decision may have changed in the current substep, and
+  // the particles whose state depends on one (through G2P, then through
+  // their P2G contributions in the next substeps).
+  TieRule tie;
+  std::vector<char> node_taint;   // n^3
+  std::vector<char> taint;        // N
+  long long n_tie = 0;            // tie decisions seen
+  double tie_jump = 0.0;          // largest |v in contact - v not in contact| at a tie
 };
 
 inline size_t node_index(const Scene& s, int i, int j, int k) {
@@ -546,6 +578,11 @@ void p2g(Scene& s, std::vector<char>& skip) {
   std::fill(s.gm.begin(), s.gm.end(), 0.0);
   std::fill(s.gp.begin(), s.gp.end(), 0.0);
   std::fill(s.gv.begin(), s.gv.end(), 0.0);
+  const bool ties = s.tie.eta >= 0.0;
+  if (ties) {
+    s.node_taint.assign(s.gm.size(), 0);
+    s.taint.resize(static_cast<size_t>(s.N), 0);
+  }
   skip.assign(static_cast<size_t>(s.N), 0);
   for (long long p = 0; p < s.N; ++p) {
     const double* xp = &s.x[3 * p];
@@ -585,6 +622,7 @@ void p2g(Scene& s, std::vector<char>& skip) {
             const double Ad = A[3 * a + 0] * d[0] + A[3 * a + 1] * d[1] + A[3 * a + 2] * d[2];
             s.gp[3 * I + a] += N * (s.mass * vp[a] + Ad);
           }
+          if (ties && s.taint[p]) s.node_taint[I] = 1;
         }
   }
 }
@@ -614,9 +652,22 @@ void grid_update(Scene& s, bool gravity = true, bool record = true) {
           const Tool& t = s.tools[q];
           if (t.type == TOOL_NONE) continue;
           double vnew[3] = {vI[0], vI[1], vI[2]};
-          if (!tool_node_contact(t.type, poses[q], t.R, t.size, vels[q], t.av, t.mu, t.drag, t.margin, xI,
-                                 vnew))
-            continue;
+          bool tied = false;
+          const bool hit = tool_node_contact(t.type, poses[q], t.R, t.size, vels[q], t.av, t.mu, t.drag, t.margin,
+                                             xI, vnew, &s.tie, &tied);
+          if (tied) {
+            // the velocity this node would take in contact, against the one it has
+            const TieRule in_contact{s.tie.eta, +1};
+            double vin[3] = {vI[0], vI[1], vI[2]};
+            tool_node_contact(t.type, poses[q], t.R, t.size, vels[q], t.av, t.mu, t.drag, t.margin, xI, vin,
+                              &in_contact, &tied);
+            const double jump = std::sqrt((vin[0] - vI[0]) * (vin[0] - vI[0]) + (vin[1] - vI[1]) * (vin[1] - vI[1]) +
+                                          (vin[2] - vI[2]) * (vin[2] - vI[2]));
+            if (jump > s.tie_jump) s.tie_jump = jump;
+            s.n_tie++;
+            if (!s.node_taint.empty()) s.node_taint[I] = 1;
+          }
+          if (!hit) continue;
           for (int a = 0; a < 3; ++a) {
             if (record) s.impulse[q][a] += m * (vnew[a] - vI[a]);
             vI[a] = vnew[a];
@@ -636,12 +687,18 @@ void grid_update(Scene& s, bool gravity = true, bool record = true) {
 void g2p(Scene& s, const std::vector<char>& skip) {
   const double dx = s.dx, dt = s.dt;
   const double Minv = 4.0 / (dx * dx);
+  const bool ties = s.tie.eta >= 0.0 && !s.node_taint.empty();
   for (long long p = 0; p < s.N; ++p) {
     if (skip[p]) continue;
     double* xp = &s.x[3 * p];
     int base[3];
     double f[3];
     stencil(s, xp, base, f);
+    if (ties)
+      for (int ox = 0; ox < 3; ++ox)
+        for (int oy = 0; oy < 3; ++oy)
+          for (int oz = 0; oz < 3; ++oz)
+            if (s.node_taint[node_index(s, base[0] + ox, base[1] + oy, base[2] + oz)]) s.taint[p] = 1;
     double w[3][3];
     for (int a = 0; a < 3; ++a) bspline_weights(f[a], w[a]);
     double vn[3] = {0.0, 0.0, 0.0};
@@ -1510,6 +1567,7 @@ int oracle_set_particles(void* h, long long n, const float* x, const float* v,
   s->N = n;
   s->mass = mass;
   s->vol0 = vol0;
+  s->taint.assign(static_cast<size_t>(n), 0);
   s->x.assign(3 * n, 0.0);
   s->v.assign(3 * n, 0.0);
   s->C.assign(9 * n, 0.0);
@@ -1606,6 +1664,33 @@ int oracle_impulses(void* h, double* out) {
 }
 
 // Error counters: inverted, out-of-domain, non-finite particle-substeps.
+// Tie tracking (test diagnostics): contact decisions within eta (m) of their
+// threshold are recorded and decided by policy (0 as computed, +1 in contact,
+// -1 not in contact); eta < 0 turns it off. Clears the particle marks.
+int oracle_set_tie_band(void* h, double eta, int policy) {
+  Scene* s = static_cast<Scene*>(h);
+  if (!s || policy < -1 || policy > 1) return ST_EINVAL;
+  s->tie.eta = eta;
+  s->tie.policy = policy;
+  s->taint.assign(static_cast<size_t>(s->N), 0);
+  s->node_taint.clear();
+  s->n_tie = 0;
+  s->tie_jump = 0.0;
+  return ST_OK;
+}
+
+// Particles whose state depends on a recorded tie decision (N bytes), the
+// number of tie decisions and the largest velocity jump one could make.
+int oracle_read_ties(void* h, unsigned char* taint, long long* n_tie, double* max_jump) {
+  Scene* s = static_cast<Scene*>(h);
+  if (!s) return ST_EINVAL;
+  if (taint)
+    for (long long p = 0; p < s->N; ++p) taint[p] = (size_t)p < s->taint.size() && s->taint[p] ? 1 : 0;
+  if (n_tie) *n_tie = s->n_tie;
+  if (max_jump) *max_jump = s->tie_jump;
+  return ST_OK;
+}
+
 int oracle_counters(void* h, long long* out) {
   Scene* s = static_cast<Scene*>(h);
   if (!s || !out) return ST_EINVAL;

@@ -269,6 +269,26 @@ def scene_cube(n_particles=1 << 16, seed=7, n_grid=56):
 SOLVER_MLS, SOLVER_PIC, SOLVER_PB = 0, 1, 2
 
 
+def scene_on_lattice(seed=9, n_grid=64, counts=(64, 16, 64), n_substeps=4):
+    """Tools placed ON the node lattice, so that nodes lie exactly on their
+    surfaces (in exact arithmetic) and the contact decision of those nodes is
+    a rounding tie: a capsule along z (turned by a quaternion, radius 5 dx,
+    half length 6 dx, centre on a node), whose cylinder and caps pass through
+    nodes at integer offsets (0, 5), (3, 4), (4, 3) dx, pressing down at
+    0.05 m/s; and a box turned a quarter turn about y (half extents 4, 3, 2
+    dx, centre on a node), whose faces lie on node planes, moving along x at
+    0.1 m/s. Both start slightly inside the c5-shaped slab (64^3, 65,536
+    particles). The tools move off the lattice after the first substep."""
+    x, E, vol0, top = _slab(n_grid, counts, seed)
+    dx = 1.0 / n_grid
+    top_node = math.floor(top / dx)
+    cap = Tool(TOOL_CAPSULE, ((n_grid // 2 - 8) * dx, (top_node + 4) * dx, (n_grid // 2) * dx),
+               (SQRT_HALF, 0.0, -SQRT_HALF, 0.0), (6 * dx, 5 * dx, 0.0), (0.0, -0.05, 0.0), mu=0.3)
+    box = Tool(TOOL_BOX, ((n_grid // 2 + 10) * dx, (top_node + 3) * dx, (n_grid // 2 - 6) * dx),
+               (SQRT_HALF, 0.0, SQRT_HALF, 0.0), (4 * dx, 3 * dx, 2 * dx), (0.1, 0.0, 0.0), mu=0.3)
+    return Scene("on_lattice", n_grid, 1e-4, n_substeps, 0.3, 5e3, RHO * vol0, vol0, x, E=E, tools=[cap, box])
+
+
 def scene_cube_pb(n_particles=1 << 12, seed=7, n_grid=56, iterations=10, beta=0.5):
     """The performance cube as the paper runs PB-MPM on it: one step of
     dt = 0.02 per frame with `iterations` passes (Sec. III-D)."""
@@ -416,7 +436,7 @@ def batch_c4s(seed=4):
 SCENES = {
     "c1": scene_c1, "c1s": scene_c1s, "c2": scene_c2, "c2s": scene_c2s, "c3": scene_c3,
     "c3s": scene_c3s, "c3m": scene_c3m, "c5": scene_c5, "c5s": scene_c5s, "cube": scene_cube,
-    "cube_pb": scene_cube_pb, "pb_drop": scene_pb_drop,
+    "cube_pb": scene_cube_pb, "pb_drop": scene_pb_drop, "on_lattice": scene_on_lattice,
 }
 
 

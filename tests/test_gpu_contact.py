@@ -124,3 +124,45 @@ def test_rollout_refuses_push_out():
         sim.rollout_forward(2, 1, theta=torch.as_tensor(s.theta, device="cuda"))
     assert e.value.code == mpm.MPM_EINVAL
     sim.close()
+
+
+def test_tools_on_the_node_lattice_tie_decisions():
+    """The tie case of the contact decision (Sec. IV-A, eq. v_correction: a
+    node is corrected when it is inside the tool): a capsule and a box placed
+    on the node lattice, so that nodes lie exactly on their surfaces and FP32
+    and FP64 may decide those nodes either way (both are correct results).
+    The oracle records every decision within 2e-6 m of its threshold and the
+    particles whose state depends on one (their cone of influence). Those
+    unmarked are held to the strict parity bar; the marked ones must be
+    finite and within the change a tie can make: node velocities move by at
+    most the largest jump J of a tie (G2P and P2G average them), C by the
+    affine moment of that (|x_I - x_p| <= 1.5 sqrt(3) dx, times 4/dx^2), F and
+    x by dt times those over the substeps."""
+    s = scenes.scene_on_lattice()
+    k = s.n_substeps
+    eta = 2e-6
+    o = O.Oracle(s.n_grid, s.dt, gravity=s.gravity, wall_band=s.wall_band, nu=s.nu, E_default=s.E_default)
+    o.set_particles(s.x, s.v, s.C, s.F, s.E, s.mass, s.vol0)
+    for q, t in enumerate(s.tools):
+        o.set_tool(q, t.type, **t.kwargs())
+    o.set_tie_band(eta, 0)
+    assert o.step(k) == 0
+    orc = o.read()
+    taint, n_tie, J = o.ties()
+    assert n_tie > 100 and 1000 < taint.sum() < s.N - 1000
+    from tests.parity import run_gpu
+    g = run_gpu(s, k)
+    assert g["status"] == 0
+    keep = ~taint
+    sub = lambda r: {f: r[f][keep] for f in ("x", "v", "C", "F")}  # noqa: E731
+    assert_parity(sub(g), sub(orc), s.x[keep], k, f"on-lattice tools, {keep.sum()} particles outside tie cones")
+    dv = 2.0 * J
+    dC = 4.0 * 1.5 * np.sqrt(3.0) / s.dx * dv
+    bounds = {"v": dv + 1e-5, "C": dC + 2e-3, "x": k * s.dt * dv + 1e-6,
+              "F": k * s.dt * dC * np.abs(orc["F"]).max() + 1e-4}
+    for f, b in bounds.items():
+        a = g[f][taint]
+        assert np.isfinite(a).all(), f
+        d = np.abs(a - orc[f][taint]).max()
+        print(f"[ties] {f}: largest difference over {taint.sum()} marked particles {d:.3e} (bound {b:.3e})")
+        assert d <= b, (f, d, b)

@@ -186,3 +186,71 @@ def test_thin_tools_momentum_budget():
     M = s.mass * s.N
     expect = P0 + n * M * np.asarray(s.gravity) * s.dt + o.impulses().sum(axis=0)
     np.testing.assert_allclose(P1, expect, rtol=0, atol=1e-12 * M)
+
+
+# ---------------------------------------------------------------- tie decisions
+# Nodes on a tool surface (in exact arithmetic) make the contact decision of
+# Sec. IV-A ("inside the rigid geometry") a rounding tie. The oracle's tie
+# tracking records such decisions within a band of the threshold and the
+# particles whose state depends on one; the GPU parity test of the tie case
+# holds the other particles to the strict bar.
+TIE_ETA = 2e-6  # m: far above FP32 rounding of an SDF at these coordinates, below a substep's tool motion
+
+
+def _tie_run(s, eta=None, policy=0):
+    o = O.Oracle(s.n_grid, s.dt, gravity=s.gravity, wall_band=s.wall_band, nu=s.nu, E_default=s.E_default)
+    o.set_particles(s.x, s.v, s.C, s.F, s.E, s.mass, s.vol0)
+    for k, t in enumerate(s.tools):
+        o.set_tool(k, t.type, **t.kwargs())
+    if eta is not None:
+        o.set_tie_band(eta, policy)
+    o.step(s.n_substeps)
+    r = o.read()
+    if eta is not None:
+        r["taint"], r["n_tie"], r["jump"] = o.ties()
+    return r
+
+
+def _small_on_lattice():
+    return scenes.scene_on_lattice(n_grid=32, counts=(32, 8, 32))
+
+
+def test_tie_band_changes_no_result():
+    s = _small_on_lattice()
+    a = _tie_run(s)
+    b = _tie_run(s, TIE_ETA, 0)
+    assert b["n_tie"] > 0
+    for k in ("x", "v", "C", "F"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_tie_decisions_reach_only_the_tainted_particles():
+    """Both tools on the node lattice: every tie decided as contact, then as
+    no contact. The two runs agree bit for bit on every particle the tie
+    tracking leaves unmarked (so its cone of influence is complete), and
+    differ on marked ones by more than the GPU parity bar on F (so the tie
+    case is a real edge case of the method, not rounding noise)."""
+    s = _small_on_lattice()
+    a = _tie_run(s, TIE_ETA, +1)
+    b = _tie_run(s, TIE_ETA, -1)
+    assert a["n_tie"] == b["n_tie"] > 100
+    taint = a["taint"] | b["taint"]
+    assert 0 < taint.sum() < s.N
+    for k in ("x", "v", "C", "F"):
+        d = np.abs(a[k] - b[k]).reshape(s.N, -1).max(axis=1)
+        assert d[~taint].max() == 0.0, k
+    dF = np.abs(a["F"] - b["F"]).reshape(s.N, -1).max(axis=1)
+    assert dF[taint].max() > 1e-4
+    # the largest jump a tie makes is about the moving box's speed (0.1 m/s)
+    assert 0.05 < a["jump"] < 0.2
+
+
+def test_tools_off_the_lattice_make_no_ties():
+    s = _small_on_lattice()
+    dx = s.dx
+    for t in s.tools:  # off the lattice along every axis
+        t.center = (t.center[0] + 0.0173 * dx, t.center[1] + 0.0219 * dx, t.center[2] + 0.0291 * dx)
+    # (two substeps: later, a moving tool can pass within the band of a node by chance)
+    s.n_substeps = 2
+    r = _tie_run(s, TIE_ETA, 0)
+    assert r["n_tie"] == 0 and not r["taint"].any()
