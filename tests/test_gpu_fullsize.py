@@ -1,6 +1,9 @@
 """Parity at the full benchmark sizes (c2: 1,048,576 particles on 128^3;
 c3: 4,194,304 particles on 256^3) in the library's default launch
-configuration, on sampled outputs the oracle can compute.
+configuration, on sampled outputs the oracle can compute: over the
+100-substep window against stored oracle runs of the whole scene
+(tests/golden/make_fullsize.py), and over 10 substeps against live oracle
+runs of core boxes.
 
 A particle's update in one substep reads the 27 nodes of its stencil, and
 those nodes hold contributions of particles whose base cells lie within
@@ -76,6 +79,52 @@ def test_c2_full_size_sampled():
         ((0.1, 0.02, 0.1), (0.16, 0.08, 0.16)),           # slab corner on the floor band
     ]
     check_cores(s, g, k, cores, "c2")
+
+
+def golden(name):
+    """The oracle's 100-substep state of a full scene on sampled particles
+    (tests/golden/make_fullsize.py); refused if the generator changed."""
+    import os
+    from tests.golden.make_fullsize import input_digest
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"fullsize_{name}_100.npz")
+    z = np.load(path, allow_pickle=False)
+    s = scenes.make(name)
+    assert input_digest(s) == str(z["input_sha256"]), "scene generator changed: rerun make_fullsize.py"
+    return s, z
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_full_size_100_substeps_default_launch(name):
+    """The whole scene for the 100-substep parity window in the library's
+    default launch configuration (re-binning every 32 substeps, the
+    re-binning mode chosen automatically, runs of substeps replayed as HIP
+    graphs), against the FP64 oracle's run of the same full scene on a
+    sample of particles (uniform, plus particles along each tool's path),
+    with the tool impulses of the 100 substeps."""
+    from paper_2502_18437_amd import mpm
+    s, z = golden(name)
+    k = int(z["n_substeps"])
+    sim = mpm.simulation_from_scene(s)
+    cfg = sim.launch_config()
+    assert cfg["resort_interval"] == 32 and cfg["rebin_mode"] == mpm.MPM_REBIN_AUTO and cfg["graph_chunk"] > 0
+    sim.step(k)
+    r, st = sim.read_state()
+    info = sim.info()
+    imp = sim.tool_impulses()
+    sim.close()
+    assert st == 0 and int(z["status"]) == 0
+    idx = z["idx"]
+    g = {kk: r[kk][idx].astype(np.float64) for kk in ("x", "v", "C", "F")}
+    o = {kk: z[kk] for kk in ("x", "v", "C", "F")}
+    print(f"[{name}] resorts={info['resorts']} fallback particle-substeps={info['n_fallback']} "
+          f"active nodes={info['active_nodes']}", flush=True)
+    assert info["resorts"] >= 4
+    assert_parity(g, o, s.x[idx], k, f"{name} full scene, 100 substeps, {idx.size} sampled")
+    # impulses on the tools are minus the momentum the tools gave the material
+    oi = z["impulses"]
+    scale = np.abs(oi).max()
+    assert scale > 0
+    np.testing.assert_allclose(imp, -oi, rtol=0, atol=2e-3 * scale)
 
 
 @pytest.mark.parametrize("n_grid", [128, 1024])
