@@ -24,11 +24,12 @@ Also reported on the same JSON line:
   (gradients for theta, the velocity table and the starting state), timed
   separately, with the ratio (fwd + bwd) / fwd; fwd_bwd_keep_all is the same
   with a checkpoint (and the grid) kept at every substep;
-* batch (with --batch): 256 independent scenes of uneven size (16^3 .. 40^3
-  particle cubes, 5.85M particles, a 64^3 grid and a capsule each) advanced
-  together by one mpm_step(200) per step, as aggregate particle-substeps/s.
-  It is off by default so that the fused kernel's launches in a profile of
-  the default command all belong to the headline workload.
+* batch (unless --no-batch): 256 independent scenes of uneven size (16^3 ..
+  40^3 particle cubes, 5.85M particles, a 64^3 grid and a capsule each)
+  advanced together by one mpm_step(200) per step, as aggregate
+  particle-substeps/s. It runs after the headline timing and its kernel
+  timing, so the headline `roofline` covers c3 launches only; a profile of
+  the headline workload alone uses --no-batch.
 * solver_sweep (with --solver-sweep): the paper's solver comparison shape
   (Sec. III-D): a cube falling on a fixed 56^3 grid, N = 2^14 .. 2^22
   particles, one frame = 0.02 s: MLS-MPM and standard MPM take 10 substeps
@@ -81,15 +82,49 @@ def counted_traffic(scene_name):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(scene, n_sub):
-    """The FP64 oracle (single-threaded) on the full scene for n_sub substeps."""
-    from tests.parity import run_oracle
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def oracle_substeps_per_s(scene, n_sub):
+    """Wall time of the FP64 oracle's substep loop alone (scene setup and the
+    read-back excluded), single-threaded."""
+    import oracle as O
+    o = O.Oracle(scene.n_grid, scene.dt, gravity=scene.gravity, wall_band=scene.wall_band, nu=scene.nu,
+                 E_default=scene.E_default)
+    o.set_particles(scene.x, scene.v, scene.C, scene.F, scene.E, scene.mass, scene.vol0)
+    for k, t in enumerate(scene.tools):
+        o.set_tool(k, t.type, **t.kwargs())
     t0 = time.perf_counter()
-    run_oracle(scene, n_sub)
+    st = o.step(n_sub)
     dt = time.perf_counter() - t0
+    return dt, st
+
+
+def cpu_baseline(scene, n_sub):
+    """The FP64 oracle (single-threaded) on the full scene for n_sub
+    substeps, plus the whole c1 run (100 substeps of 8,000 particles)."""
+    from paper_2502_18437_amd import scenes
+    model, threads = host_cpu()
+    dt, _ = oracle_substeps_per_s(scene, n_sub)
+    c1 = scenes.make("c1")
+    dt1, _ = oracle_substeps_per_s(c1, c1.n_substeps)
     return {"value": scene.N * n_sub / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_sub} substeps of the full {scene.name} scene ({scene.N} particles, "
-                      f"{scene.n_grid}^3 grid), FP64, one host thread; {dt:.1f} s"}
+                      f"{scene.n_grid}^3 grid), FP64, one host thread, substep loop only (setup excluded); "
+                      f"{dt:.1f} s",
+            "host_cpu": model, "host_logical_cpus": threads,
+            "c1_full_run": {"substeps": c1.n_substeps, "particles": c1.N, "seconds": dt1,
+                            "particle_substeps_per_s": c1.N * c1.n_substeps / dt1}}
 
 
 def batch_throughput(steps, warmup=1):
@@ -253,7 +288,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd measurement")
-    ap.add_argument("--batch", action="store_true", help="also measure the 256-scene batch")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 256-scene batch (so that a profile of the command holds only the headline "
+                         "workload's fused-kernel launches)")
     ap.add_argument("--diff-steps", type=int, default=3)
     ap.add_argument("--solver-sweep", action="store_true",
                     help="also time the three solvers on the falling cube (paper's solver comparison shape)")
@@ -373,7 +410,7 @@ def main():
                            "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
-    if args.batch:
+    if not args.no_batch:
         out["batch"] = batch_throughput(args.diff_steps)
     if args.solver_sweep:
         out["solver_sweep"] = solver_sweep(sizes=sizes)
