@@ -60,6 +60,8 @@ extern "C" {
                                fixed-point range of the grid accumulator
                                (|m v| beyond about 1000 m_p m/s); that particle
                                is left out of the P2G of that substep */
+#define MPM_ETOOBIG (-8)    /* a size beyond a fixed maximum of an entry point
+                               that allocates nothing (nothing was computed) */
 
 /* Precedence when several device errors are pending:
  * MPM_ENONFINITE, then MPM_EDOMAIN, then MPM_ERANGE, then MPM_EINVERTED. */
@@ -242,6 +244,22 @@ const char* mpm_last_error(const mpm_handle* h);
 int mpm_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,
                     int32_t where);
 
+/* mpm_eval_stress without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, layout and result as mpm_eval_stress
+ * (bit for bit: the same kernel). Host inputs and outputs are staged
+ * through a fixed device array of MPM_NOALLOC_MAX_PARTICLES x 19 floats
+ * (about 5 MB), which the library holds on every GPU it runs on until the
+ * process ends; device inputs and outputs are used in place. Runs on the
+ * current device and the null stream; synchronous. Every call on one GPU
+ * shares that array: calls that overlap on one GPU (several host threads)
+ * race and must be serialised by the caller.
+ * Errors: MPM_EINVAL (bad argument), MPM_ETOOBIG (n above
+ * MPM_NOALLOC_MAX_PARTICLES; nothing is computed), MPM_EHIP. The message of
+ * a failure is given by mpm_last_error(NULL). */
+#define MPM_NOALLOC_MAX_PARTICLES 65536
+int mpm_eval_stress_noalloc(int64_t n, const float* F, const float* E, float nu, float* tau,
+                            int32_t where);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every launch while enabled. Kinds, in order: 0 sort (binning pipeline),

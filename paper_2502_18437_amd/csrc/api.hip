@@ -500,6 +500,7 @@ namespace {
 
 int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_handle** out) {
   g_create_error.clear();
+  noalloc_clear_error();
   if (!out) {
     g_create_error = "out is NULL";
     return MPM_EINVAL;
@@ -1549,7 +1550,10 @@ int mpm_get_info(mpm_handle* h, mpm_info* info) {
 }
 
 const char* mpm_last_error(const mpm_handle* h) {
-  if (!h) return g_create_error.c_str();
+  if (!h) {
+    const char* m = noalloc_last_error();
+    return m ? m : g_create_error.c_str();
+  }
   return h->err.c_str();
 }
 

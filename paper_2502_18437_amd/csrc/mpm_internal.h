@@ -236,6 +236,10 @@ void launch_sum_impulses(Buffers& b, const SimK& s, int scene, double* out, hipS
 // Stress evaluation (diagnostic entry point).
 void launch_eval_stress(int64_t n, const float* F, const float* E, float nu, float* tau,
                         hipStream_t st);
+// Message of the last failed mpm_eval_stress_noalloc call on this thread
+// (nullptr if none since the last clear), and its reset.
+const char* noalloc_last_error();
+void noalloc_clear_error();
 
 // Gather particles back into the caller's order (AoS outputs).
 void launch_unpermute(const Buffers& b, int64_t N, float* x, float* v, float* C, float* F,

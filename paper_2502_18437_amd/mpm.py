@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(HERE, "libmpm.so")
 
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EHIP, MPM_EDOMAIN, MPM_ENONFINITE, MPM_EINVERTED = 0, -1, -2, -3, -4, -5, -6
 MPM_ERANGE = -7
+MPM_ETOOBIG = -8
+MPM_NOALLOC_MAX_PARTICLES = 65536
 MPM_HOST, MPM_DEVICE = 0, 1
 MPM_ACCUM_F32, MPM_ACCUM_FIXED = 0, 1
 MPM_TOOL_NONE, MPM_TOOL_CAPSULE, MPM_TOOL_BOX, MPM_TOOL_PLANE = 0, 1, 2, 3
@@ -31,14 +33,15 @@ MPM_KERNEL_KINDS = 5
 KERNEL_NAMES = ("binning", "p2g", "g2p2g", "g2p", "grid")
 
 STATUS_NAMES = {0: "MPM_OK", -1: "MPM_EINVAL", -2: "MPM_ENOMEM", -3: "MPM_EHIP", -4: "MPM_EDOMAIN",
-                -5: "MPM_ENONFINITE", -6: "MPM_EINVERTED", -7: "MPM_ERANGE"}
+                -5: "MPM_ENONFINITE", -6: "MPM_EINVERTED", -7: "MPM_ERANGE", -8: "MPM_ETOOBIG"}
 
 EXPORTED = ("mpm_create", "mpm_destroy", "mpm_set_particles", "mpm_set_tool_sdf", "mpm_step",
             "mpm_read_state", "mpm_get_info", "mpm_last_error", "mpm_eval_stress", "mpm_profile",
             "mpm_profile_read", "mpm_read_tool_impulses", "mpm_set_tool_velocity_table", "mpm_rollout_forward",
             "mpm_rollout_backward", "mpm_create_batch", "mpm_set_batch_particles", "mpm_set_scene_tool",
             "mpm_set_scene_tool_velocity_table", "mpm_read_scene_tool_impulses", "mpm_get_launch_config",
-            "mpm_set_launch_config", "mpm_autotune", "mpm_set_solver", "mpm_get_solver")
+            "mpm_set_launch_config", "mpm_autotune", "mpm_set_solver", "mpm_get_solver",
+            "mpm_eval_stress_noalloc")
 
 
 class mpm_params(ctypes.Structure):
@@ -94,6 +97,7 @@ _lib.mpm_get_info.argtypes = [_h, ctypes.POINTER(mpm_info)]
 _lib.mpm_last_error.argtypes = [_h]
 _lib.mpm_last_error.restype = ctypes.c_char_p
 _lib.mpm_eval_stress.argtypes = [ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32]
+_lib.mpm_eval_stress_noalloc.argtypes = [ctypes.c_int64, _vp, _vp, ctypes.c_float, _vp, ctypes.c_int32]
 _lib.mpm_profile.argtypes = [_h, ctypes.c_int32]
 _lib.mpm_profile_read.argtypes = [_h, ctypes.POINTER(mpm_kernel_times)]
 _lib.mpm_read_tool_impulses.argtypes = [_h, ctypes.POINTER(ctypes.c_double)]
@@ -125,6 +129,7 @@ mpm_read_state = _lib.mpm_read_state
 mpm_get_info = _lib.mpm_get_info
 mpm_last_error = _lib.mpm_last_error
 mpm_eval_stress = _lib.mpm_eval_stress
+mpm_eval_stress_noalloc = _lib.mpm_eval_stress_noalloc
 mpm_profile = _lib.mpm_profile
 mpm_profile_read = _lib.mpm_profile_read
 mpm_read_tool_impulses = _lib.mpm_read_tool_impulses
