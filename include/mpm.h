@@ -125,7 +125,9 @@ typedef struct mpm_params {
   float nu;                /* Poisson ratio, 0 <= nu < 0.5 */
   float E_default;         /* Young's modulus used when no per-particle E */
   int32_t accum_mode;      /* MPM_ACCUM_F32 or MPM_ACCUM_FIXED */
-  int32_t tile;            /* 0 = default (8); grid block edge in nodes: 8 */
+  int32_t tile;            /* transfer work tile edge in cells: 8 (one 8^3 grid block) or 4
+                              (a quarter-edge sub-block, for small or sparse scenes); 0 = 8.
+                              mpm_set_launch_config and mpm_autotune can change it */
   int32_t resort_interval; /* substeps between particle re-binning; 0 = default */
   int64_t max_particles;   /* capacity reserved at create, >= 0 */
 } mpm_params;
@@ -167,7 +169,7 @@ typedef struct mpm_info {
   int64_t n_fallback;        /* particle-substeps that left their block's
                                 tile and took the global-memory path */
   int64_t n_range;           /* particle-substeps refused by the range check */
-  int32_t tile;
+  int32_t tile;             /* transfer work tile edge in use (4 or 8) */
   int32_t resort_interval;
   int32_t accum_mode;
   int32_t n_tools;
@@ -176,10 +178,12 @@ typedef struct mpm_info {
                                 differentiates the latest one */
 } mpm_info;
 
-/* Create a scene on the current HIP device. `hip_stream` is a hipStream_t
- * cast to uint64_t (e.g. torch.cuda.current_stream().cuda_stream); 0 makes
- * the library create and own a stream. Allocates the dense n_grid^3 grid
- * (two float4 arrays) and room for max_particles particles.
+/* Create a scene on the current HIP device (the paper's SimulationFactory
+ * building a Scene, Sec. V-A: the simulation domain, time step, gravity,
+ * boundary band and material defaults of Sec. III-A). `hip_stream` is a
+ * hipStream_t cast to uint64_t (e.g. torch.cuda.current_stream().cuda_stream);
+ * 0 makes the library create and own a stream. Allocates the dense n_grid^3
+ * grid (two float4 arrays) and room for max_particles particles.
  * Errors: MPM_EINVAL (NULL pointers, out-of-range field), MPM_ENOMEM,
  * MPM_EHIP. On error *out is NULL. */
 int mpm_create(const mpm_params* p, uint64_t hip_stream, mpm_handle** out);
@@ -202,8 +206,12 @@ int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v,
                       float mass, float vol0, int32_t where);
 
 /* Set, replace (or with type MPM_TOOL_NONE remove) tool `tool_id`
- * (0 <= tool_id < MPM_MAX_TOOLS). Tools are applied to each grid node in id
- * order, then the walls. Errors: MPM_EINVAL (bad id, type, size <= 0 for
+ * (0 <= tool_id < MPM_MAX_TOOLS): a rigid Shape of the scene (Sec. V-A)
+ * described by its signed distance function, with the contact law of
+ * Sec. IV-A (eq. v_correction) and the cutting and suturing geometries of
+ * Sec. IV-B and IV-C. Its pose advances kinematically with its velocity
+ * (Sec. V-C). Tools are applied to each grid node in id order, then the
+ * walls. Errors: MPM_EINVAL (bad id, type, size <= 0 for
  * the used fields, non-finite values, mu < 0, drag outside [0, 1]). */
 int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t);
 
@@ -212,8 +220,9 @@ int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t);
  * (n_substeps < 0), MPM_EHIP (launch failure). */
 int mpm_step(mpm_handle* h, int32_t n_substeps);
 
-/* Block until the stream drains (Scene::fetchResults) and write the state
- * in the caller's original particle order. NULL outputs are skipped.
+/* Block until the stream drains (Scene::fetchResults, Sec. V-A) and write
+ * the particle state of Algorithm 1 (x, v, C, F; Sec. III-B) in the caller's
+ * original particle order. NULL outputs are skipped.
  * Returns the pending device error, if any (the state is still written).
  * Errors: MPM_EINVAL (bad where), MPM_EHIP. */
 int mpm_read_state(mpm_handle* h, float* x, float* v, float* C, float* F, int32_t where);
@@ -300,17 +309,22 @@ typedef struct mpm_launch_config {
   int32_t graph_chunk;     /* runs of this many plain substeps (fused transfer + grid update) are
                               recorded once as a HIP graph and replayed; 0 = launch every kernel */
   int32_t rebin_mode;      /* MPM_REBIN_AUTO, MPM_REBIN_ADVANCE or MPM_REBIN_IN_PLACE */
+  int32_t tile;            /* transfer work tile edge in cells: 8 (512-thread workgroups, a
+                              10^3-node LDS tile) or 4 (128-thread workgroups, 6^3 nodes);
+                              0 keeps the current one. A change re-bins the particles */
 } mpm_launch_config;
 
 /* Read / replace the launch configuration (the defaults: resort_interval
- * from mpm_params or 32, two workgroups per compute unit, graph_chunk 8,
- * MPM_REBIN_AUTO). Errors: MPM_EINVAL (NULL, value out of range). */
+ * from mpm_params or 32, the tile of mpm_params, two 8-cell-tile or eight
+ * 4-cell-tile workgroups per compute unit, graph_chunk 8, MPM_REBIN_AUTO).
+ * Errors: MPM_EINVAL (NULL, value out of range). */
 int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out);
 int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
 
 /* Autotuner: times mpm_step(trial_substeps) on the current scene for each
- * candidate configuration (re-binning every 1, 2, 4, 8, 16, 32 or 64
- * substeps; 1 to 4 transfer workgroups per compute unit; graphs on or off),
+ * candidate configuration (work tiles of 8 or 4 cells; re-binning every 1,
+ * 2, 4, 8, 16, 32 or 64 substeps; 1 to 4 transfer workgroups per compute unit
+ * for 8-cell tiles, 4 to 16 for 4-cell ones; graphs on or off),
  * restoring the particles, their order, the device status and the clock
  * before every trial, and keeps the fastest (written to *chosen if not
  * NULL). For each workgroup count and graph setting the intervals are tried
@@ -321,7 +335,7 @@ int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c);
  * beats it by more than 5% (both timed once more at the end; the better of
  * each one's two timings counts), since short trials cannot resolve smaller
  * differences. The scene is left as it was, except that the next mpm_step
- * re-bins and the tool impulses read zero. Blocking; at most 120 calls of
+ * re-bins and the tool impulses read zero. Blocking; at most 232 calls of
  * mpm_step (a warm-up and a timed call per timing). A trial shorter than the
  * longer intervals cannot tell them apart.
  * Errors: MPM_EINVAL (no particles, trial_substeps < 1), MPM_ENOMEM (it

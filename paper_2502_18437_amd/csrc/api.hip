@@ -306,14 +306,37 @@ void drop_graphs(mpm_handle* h) {
       }
 }
 
+// Persistent transfer workgroups for a work tile edge: two 512-thread
+// workgroups per CU for 8-cell tiles (their 44 KB LDS tiles bound it), eight
+// 128-thread ones for 4-cell tiles (registers bound it at 16 waves per CU);
+// a multiple of 8 (one share per XCD).
+int default_transfer_wgs(const mpm_handle* h, int tile) {
+  const int per_cu = tile == 4 ? 8 : 2;
+  return (per_cu * h->cus + 7) / 8 * 8;
+}
+
+// Use work tiles of edge `tile` (4 or 8) from the next binning on: the tile
+// ranges of the previous sort are in the other indexing, so new orders are
+// built as for new particles, and recorded graphs are dropped.
+void set_tile(mpm_handle* h, int tile) {
+  if (tile == h->sim.tile) return;
+  h->sim.tile = tile;
+  h->sim.unit_shift = tile == 4 ? 3 : 0;
+  h->dirty = true;
+  h->fresh_order = true;
+  drop_graphs(h);
+}
+
 // Particles per transfer work item: about N / (4 x workgroups), so that
-// even a scene of a few dense blocks gives every persistent workgroup several
-// items, as a power of two in [kItemMin, kItemMax]. A change re-bins and
-// drops the recorded graphs.
+// even a scene of a few dense tiles gives every persistent workgroup several
+// items, as a power of two in [kItemMin, kItemMax] for 8-cell tiles and a
+// quarter of that for 4-cell tiles (whose workgroups are a quarter the
+// size). A change re-bins and drops the recorded graphs.
 void choose_item_size(mpm_handle* h) {
   const int64_t target = h->N / (4 * (int64_t)h->transfer_wgs);
-  unsigned item = kItemMin;
-  while (item < (unsigned)kItemMax && (int64_t)item * 2 <= target) item *= 2;
+  const unsigned lo = h->sim.tile == 4 ? kItemMin / 4 : kItemMin, hi = h->sim.tile == 4 ? kItemMax / 4 : kItemMax;
+  unsigned item = lo;
+  while (item < hi && (int64_t)item * 2 <= target) item *= 2;
   if (item != h->sim.item_particles) {
     h->sim.item_particles = item;
     h->dirty = true;
@@ -514,7 +537,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
       !(p->nu >= 0.0f && p->nu < 0.5f) || !(p->E_default >= 0.0f) || !std::isfinite(p->E_default) ||
       p->wall_band < 0 || p->wall_band > p->n_grid / 2 ||
       !(p->accum_mode == MPM_ACCUM_F32 || p->accum_mode == MPM_ACCUM_FIXED) ||
-      !(p->tile == 0 || p->tile == kTile) ||
+      !(p->tile == 0 || p->tile == 4 || p->tile == 8) ||
       p->resort_interval < 0 || p->max_particles < 0 || p->max_particles > 0x7fffffffLL ||
       !std::isfinite(p->gravity[0]) || !std::isfinite(p->gravity[1]) || !std::isfinite(p->gravity[2]) ||
       n_scenes < 1) {
@@ -535,7 +558,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
     return MPM_ENOMEM;
   }
   h->p = *p;
-  if (h->p.tile == 0) h->p.tile = kTile;
+  if (h->p.tile == 0) h->p.tile = 8;
   h->n_scenes = n_scenes;
   h->tools.assign((size_t)n_scenes * kMaxTools, HostTool());
   h->tool_tables.assign((size_t)n_scenes * kMaxTools, nullptr);
@@ -566,17 +589,17 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   int bits = 1;
   while ((1u << bits) < h->n_blocks + 1u) ++bits;
   h->key_bits = bits;
-  // Persistent transfer grid: two workgroups per CU (LDS bound), a multiple of 8.
-  int wgs = 2 * h->cus;
-  wgs = (wgs + 7) / 8 * 8;
-  h->transfer_wgs = wgs;
+  // Persistent transfer grid: two 8-cell-tile workgroups per CU (LDS bound)
+  // or eight 4-cell-tile ones (VGPR bound), a multiple of 8.
+  h->transfer_wgs = default_transfer_wgs(h, h->p.tile);
 
   const int64_t cap = p->max_particles > 0 ? p->max_particles : 1;
   Buffers& b = h->b;
   b.cap = cap;
   const int64_t n_tiles = (cap + 4095) / 4096;
   const int64_t hist_n = 256 * n_tiles;
-  const int64_t scan_part = (std::max<int64_t>(hist_n, h->n_blocks) + 2047) / 2048 + 1;
+  const int64_t n_units_max = (int64_t)h->n_blocks << kMaxUnitShift;  // 4-cell work tiles
+  const int64_t scan_part = (std::max<int64_t>(hist_n, n_units_max) + 2047) / 2048 + 1;
   const size_t grid_nodes = (size_t)h->n_blocks * kBlockNodes;
   bool ok = true;
   auto alloc = [&](void** ptr, size_t bytes) {
@@ -592,13 +615,13 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   }
   alloc((void**)&b.hist, sizeof(uint32_t) * hist_n);
   alloc((void**)&b.scan_tmp, sizeof(uint32_t) * scan_part);
-  alloc((void**)&b.blk_begin, sizeof(uint32_t) * h->n_blocks);
-  alloc((void**)&b.blk_end, sizeof(uint32_t) * h->n_blocks);
-  alloc((void**)&b.flags, sizeof(uint32_t) * h->n_blocks);
-  alloc((void**)&b.occ_list, sizeof(uint32_t) * h->n_blocks);
-  // at most one partial item per occupied block plus one per kItemRollout
-  // (<= kItemMin) particles
-  alloc((void**)&b.work, sizeof(uint2) * ((size_t)h->n_blocks + (size_t)(cap / kItemRollout) + 1));
+  alloc((void**)&b.blk_begin, sizeof(uint32_t) * n_units_max);
+  alloc((void**)&b.blk_end, sizeof(uint32_t) * n_units_max);
+  alloc((void**)&b.flags, sizeof(uint32_t) * n_units_max);
+  alloc((void**)&b.occ_list, sizeof(uint32_t) * n_units_max);
+  // at most one partial item per occupied work tile plus one per
+  // kItemMinAny (the smallest item of any tile edge or of the rollout) particles
+  alloc((void**)&b.work, sizeof(uint2) * ((size_t)n_units_max + (size_t)(cap / kItemMinAny) + 1));
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.node_cnt, sizeof(uint32_t) * h->n_blocks);
@@ -629,8 +652,8 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
                        (int64_t)(grid_nodes * mom_bytes / 4));
   hipLaunchKernelGGL(k_zero_f4, dim3(4096), dim3(256), 0, h->stream, b.vel, (int64_t)grid_nodes);
   // Block ranges of the previous sort, read by the binning keys: none yet.
-  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_begin, (int64_t)h->n_blocks);
-  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_end, (int64_t)h->n_blocks);
+  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_begin, n_units_max);
+  hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_end, n_units_max);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
   launch_set_clock(b, 0, 0, h->stream);
   // Scene constants.
@@ -643,6 +666,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   s.solver = SOLVER_MLS;
   s.pb_beta = 0.5f;
   s.item_particles = kItemMax;
+  set_tile(h, h->p.tile);
   launch_clear_impulses(b, s, h->stream);
   e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) e = hipGetLastError();
@@ -1045,9 +1069,10 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
       // Binning orders a block's particles by sub-cell class when the block
       // held few enough particles at the previous sort; new particles are
       // first sorted once to get those counts.
-      if (h->fresh_order) launch_binning(b, N, h->sim, h->key_bits, k == 0 || advance, h->stream);
+      const int bits = h->key_bits + h->sim.unit_shift;  // bits of a work tile id or the sentinel
+      if (h->fresh_order) launch_binning(b, N, h->sim, bits, k == 0 || advance, h->stream);
       h->fresh_order = false;
-      launch_binning(b, N, h->sim, h->key_bits, k == 0 || advance, h->stream);
+      launch_binning(b, N, h->sim, bits, k == 0 || advance, h->stream);
       h->dirty = false;
       h->since_sort = 0;
       h->resorts++;
@@ -1128,6 +1153,7 @@ int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out) {
   out->transfer_wgs = h->transfer_wgs;
   out->graph_chunk = h->graph_chunk;
   out->rebin_mode = h->rebin_mode;
+  out->tile = h->sim.tile;
   return MPM_OK;
 }
 
@@ -1135,8 +1161,9 @@ int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c) {
   if (!h) return MPM_EINVAL;
   if (!c || c->resort_interval < 1 || c->transfer_wgs < 8 || c->transfer_wgs % 8 != 0 || c->transfer_wgs > 65536 ||
       c->graph_chunk < 0 || c->graph_chunk > 256 || c->rebin_mode < MPM_REBIN_AUTO ||
-      c->rebin_mode > MPM_REBIN_IN_PLACE)
+      c->rebin_mode > MPM_REBIN_IN_PLACE || !(c->tile == 0 || c->tile == 4 || c->tile == 8))
     return fail(h, MPM_EINVAL, "mpm_set_launch_config: value out of range");
+  if (c->tile != 0) set_tile(h, c->tile);
   h->resort_interval = c->resort_interval;
   h->rebin_mode = c->rebin_mode;
   if (c->transfer_wgs != h->transfer_wgs || c->graph_chunk != h->graph_chunk) drop_graphs(h);
@@ -1175,7 +1202,7 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   const int cur0 = b.cur;
   const int64_t substep0 = h->substep, since0 = h->since_sort, resorts0 = h->resorts;
   const bool dirty0 = h->dirty, prof0 = h->prof;
-  const mpm_launch_config orig = {h->resort_interval, h->transfer_wgs, h->graph_chunk, h->rebin_mode};
+  const mpm_launch_config orig = {h->resort_interval, h->transfer_wgs, h->graph_chunk, h->rebin_mode, h->sim.tile};
   e = hipMemcpyAsync(save_part, b.part[cur0], part_bytes, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save_id, b.id[cur0], sizeof(uint32_t) * b.cap, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save_st, b.status, sizeof(Status), hipMemcpyDeviceToDevice, h->stream);
@@ -1194,13 +1221,14 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   if (e == hipSuccess) e = hipEventCreate(&ev0);
   if (e == hipSuccess) e = hipEventCreate(&ev1);
   h->prof = false;
-  // Candidates: re-binning interval, persistent workgroups per CU, graph
-  // replay on or off.
+  // Candidates: work tile edge, re-binning interval, persistent workgroups
+  // per CU, graph replay on or off.
   // Fast-moving scenes leave their tiles within a few substeps (the global
   // path then takes the scatter), so the short intervals are candidates too.
   const int resorts[] = {1, 2, 4, 8, 16, 32, 64};
   const int n_resorts = (int)(sizeof(resorts) / sizeof(resorts[0]));
-  const int per_cu[] = {1, 2, 3, 4};
+  const int per_cu[] = {1, 2, 3, 4};  // 8-cell tiles; four times as many 4-cell-tile workgroups
+  const int tiles[] = {8, 4};
   const int chunks[] = {0, kDefaultGraphChunk};
   mpm_launch_config best = orig;
   float best_ms = 0.0f;
@@ -1228,7 +1256,7 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   constexpr float kKeep = 0.05f;
   auto same = [](const mpm_launch_config& a, const mpm_launch_config& c) {
     return a.resort_interval == c.resort_interval && a.transfer_wgs == c.transfer_wgs &&
-           a.graph_chunk == c.graph_chunk && a.rebin_mode == c.rebin_mode;
+           a.graph_chunk == c.graph_chunk && a.rebin_mode == c.rebin_mode && a.tile == c.tile;
   };
   // warm-up (records graphs) and timed call of configuration c
   auto trial = [&](const mpm_launch_config& c, float* ms) -> bool {
@@ -1245,10 +1273,12 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
     best_ms = orig_ms;
     have = true;
   }
+  for (int ti = 0; ti < 2 && e == hipSuccess && rc == MPM_OK; ++ti)
   for (int wi = 0; wi < 4 && e == hipSuccess && rc == MPM_OK; ++wi)
     for (int ci = 0; ci < 2 && e == hipSuccess && rc == MPM_OK; ++ci)
       for (int ri = 0; ri < n_resorts && e == hipSuccess && rc == MPM_OK; ++ri) {
-        mpm_launch_config c = {resorts[ri], (per_cu[wi] * h->cus + 7) / 8 * 8, chunks[ci], MPM_REBIN_AUTO};
+        const int wg_per_cu = per_cu[wi] * (tiles[ti] == 4 ? 4 : 1);
+        mpm_launch_config c = {resorts[ri], (wg_per_cu * h->cus + 7) / 8 * 8, chunks[ci], MPM_REBIN_AUTO, tiles[ti]};
         rc = mpm_set_launch_config(h, &c);
         if (rc != MPM_OK) break;
         e = restore();
@@ -1538,7 +1568,7 @@ int mpm_get_info(mpm_handle* h, mpm_info* info) {
   info->n_nonfinite = (int64_t)st.n_nonfinite;
   info->n_fallback = (int64_t)st.n_fallback;
   info->n_range = (int64_t)st.n_range;
-  info->tile = kTile;
+  info->tile = h->sim.tile;
   info->resort_interval = h->resort_interval;
   info->accum_mode = h->p.accum_mode;
   int nt = 0;

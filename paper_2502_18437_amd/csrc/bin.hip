@@ -174,14 +174,19 @@ __global__ void k_keygen(const float* __restrict__ part, const uint32_t* __restr
       const uint32_t scene = s.n_scenes > 1 ? scene_of(scene_off, s.n_scenes, id[i]) : 0u;
       const uint32_t blk = scene * s.nb3 + (uint32_t)(((cell[2] >> kTileLog2) * s.nb + (cell[1] >> kTileLog2)) * s.nb +
                                                       (cell[0] >> kTileLog2));
-      const uint32_t prev = prev_end[blk] - prev_begin[blk];
-      const uint32_t z = (uint32_t)(cell[2] & (kTile - 1));
-      uint32_t sub = 0u;  // dense or new block: keep the order
+      // work tile: the block, or (4-cell tiles) its sub-block sx + 2 sy + 4 sz
+      uint32_t unit = blk;
+      if (s.unit_shift)
+        unit = (blk << 3) | (uint32_t)(((cell[0] >> 2) & 1) | (((cell[1] >> 2) & 1) << 1) | (((cell[2] >> 2) & 1) << 2));
+      const uint32_t prev = prev_end[unit] - prev_begin[unit];
+      const uint32_t z = (uint32_t)(cell[2] & (s.tile - 1));
+      const uint32_t dense = 8u * (uint32_t)(s.tile * s.tile * s.tile);
+      uint32_t sub = 0u;  // dense or new tile: keep the order
       if (prev > 0u && prev <= s.item_particles)
-        sub = (cls << 3) | z;  // one work item: class first, so a class spans the block's cells
-      else if (prev > 0u && prev <= kDenseBlock)
+        sub = (cls << 3) | z;  // one work item: class first, so a class spans the tile's cells
+      else if (prev > 0u && prev <= dense)
         sub = (z << 3) | cls;  // several items: z layers first, so an item covers a few layers
-      key = (blk << kClassBits) | sub;
+      key = (unit << kClassBits) | sub;
     } else if (!fin) {
       nf++;
     } else {
@@ -346,20 +351,27 @@ __global__ void k_flag_occupied(const uint32_t* __restrict__ begin, const uint32
     flags[b] = end[b] > begin[b] ? 1u : 0u;
 }
 
-// Blocks a tile of an occupied block touches, within the same scene.
+// Grid blocks that the LDS tile of an occupied work tile touches, within the
+// same scene: the tile of edge T at cell origin o spans nodes [o, o + T + 1]
+// per axis.
 __global__ void k_mark_dilated(const uint32_t* __restrict__ begin, const uint32_t* __restrict__ end,
-                               int nb, uint32_t nb3, uint32_t n_blocks, uint32_t* __restrict__ mark) {
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += gridDim.x * blockDim.x) {
-    if (!(end[b] > begin[b])) continue;
+                               int nb, uint32_t nb3, uint32_t n_units, int tile, int unit_shift,
+                               uint32_t* __restrict__ mark) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_units; u += gridDim.x * blockDim.x) {
+    if (!(end[u] > begin[u])) continue;
+    const uint32_t b = u >> unit_shift;
     const uint32_t scene = b / nb3, lb = b - scene * nb3;
-    const int bi = lb % nb, bj = (lb / nb) % nb, bk = lb / (nb * nb);
-    for (int dk = kTileLo; dk <= kTileHi; ++dk)
-      for (int dj = kTileLo; dj <= kTileHi; ++dj)
-        for (int di = kTileLo; di <= kTileHi; ++di) {
-          const int i = bi + di, j = bj + dj, k = bk + dk;
-          if (i < 0 || j < 0 || k < 0 || i >= nb || j >= nb || k >= nb) continue;
-          mark[scene * nb3 + (uint32_t)((k * nb + j) * nb + i)] = 1u;
-        }
+    int o[3] = {(int)(lb % nb) * kTile, (int)((lb / nb) % nb) * kTile, (int)(lb / (nb * nb)) * kTile};
+    if (unit_shift)
+      for (int a = 0; a < 3; ++a) o[a] += (int)((u >> a) & 1u) * tile;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = o[a] >> kTileLog2;
+      hi[a] = min((o[a] + tile + 1) >> kTileLog2, nb - 1);
+    }
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i) mark[scene * nb3 + (uint32_t)((k * nb + j) * nb + i)] = 1u;
   }
 }
 
@@ -431,11 +443,12 @@ static int radix_sort(Buffers& b, int64_t N, int key_bits, hipStream_t st) {
 
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool with_vc, hipStream_t st) {
   const uint32_t n_blocks = s.nb3 * (uint32_t)s.n_scenes;
-  const uint32_t sentinel = n_blocks << kClassBits;
-  // 1. keys: scene-major block ids, then sub-cell classes
+  const uint32_t n_units = n_blocks << s.unit_shift;  // work tiles
+  const uint32_t sentinel = n_units << kClassBits;
+  // 1. keys: scene-major work tile ids, then sub-cell classes
   hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur],
                      b.scene_off, b.cap, N, s, b.blk_begin, b.blk_end, b.keys[0], b.vals[0], sentinel, b.status);
-  // 2. stable LSD radix sort, 8 bits per pass
+  // 2. stable LSD radix sort, 8 bits per pass (key_bits: bits of a work tile id or the sentinel)
   const int src = radix_sort(b, N, key_bits + kClassBits, st);
   // 3. gather the particle state into key order
   const dim3 pg(grid_for(N, 256)), pb(256);
@@ -455,27 +468,29 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool wit
     hipLaunchKernelGGL((k_permute<false, false>), pg, pb, 0, st, ps, pd, b.id[b.cur], b.id[b.cur ^ 1], b.vals[src], kk,
                        sentinel, b.cap, N);
   b.cur ^= 1;
-  // 4. per-block ranges
-  fill_u32(b.blk_begin, n_blocks, 0u, st);
-  fill_u32(b.blk_end, n_blocks, 0u, st);
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_blocks, kClassBits,
+  // 4. per-tile ranges
+  fill_u32(b.blk_begin, n_units, 0u, st);
+  fill_u32(b.blk_end, n_units, 0u, st);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_units, kClassBits,
                      b.blk_begin, b.blk_end);
-  // 5. occupied list (ascending block id: spatially ordered, x fastest)
-  hipLaunchKernelGGL(k_flag_occupied, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,
-                     b.blk_end, n_blocks, b.flags);
-  exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_occ, st);
-  hipLaunchKernelGGL(k_compact, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     b.flags, n_blocks, 0, b.occ_list);
-  // 5b. transfer work items (ascending block id, then particle runs)
-  hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     n_blocks, s.item_particles, b.flags);
-  exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_work, st);
-  hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     b.flags, n_blocks, s.item_particles, kDenseBlock, b.work);
-  // 6. active list: occupied blocks dilated by one block
+  // 5. occupied list (ascending tile id: spatially ordered, x fastest)
+  hipLaunchKernelGGL(k_flag_occupied, dim3(grid_for(n_units, 256)), dim3(256), 0, st, b.blk_begin,
+                     b.blk_end, n_units, b.flags);
+  exclusive_scan(b.flags, b.flags, n_units, b.scan_tmp, &b.status->n_occ, st);
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(n_units, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     b.flags, n_units, 0, b.occ_list);
+  // 5b. transfer work items (ascending tile id, then particle runs); tiles
+  // above 8 particles per cell are dense
+  const uint32_t dense = 8u * (uint32_t)(s.tile * s.tile * s.tile);
+  hipLaunchKernelGGL(k_item_counts, dim3(grid_for(n_units, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     n_units, s.item_particles, b.flags);
+  exclusive_scan(b.flags, b.flags, n_units, b.scan_tmp, &b.status->n_work, st);
+  hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_units, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
+                     b.flags, n_units, s.item_particles, dense, b.work);
+  // 6. active list: the grid blocks the occupied tiles' LDS tiles touch
   fill_u32(b.mark, n_blocks, 0u, st);
-  hipLaunchKernelGGL(k_mark_dilated, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.blk_begin,
-                     b.blk_end, s.nb, s.nb3, n_blocks, b.mark);
+  hipLaunchKernelGGL(k_mark_dilated, dim3(grid_for(n_units, 256)), dim3(256), 0, st, b.blk_begin,
+                     b.blk_end, s.nb, s.nb3, n_units, s.tile, s.unit_shift, b.mark);
   hipLaunchKernelGGL(k_flag_marked, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, b.mark, n_blocks,
                      b.flags);
   exclusive_scan(b.flags, b.flags, n_blocks, b.scan_tmp, &b.status->n_act, st);

@@ -27,9 +27,9 @@
 // The two scatters (P2G forward, G2P reverse) walk the particles in a
 // spatial order (DiffOrder): each workgroup takes a run of one grid block's
 // particles, adds their contributions into an LDS tile of the block's
-// stencil nodes (the forward P2G in fixed point with integer LDS atomics,
-// the cotangent scatter with FP32 LDS atomics) and then adds the tile's
-// non-empty nodes into the dense grid. A particle that has left its block's
+// stencil nodes with integer LDS atomics (the forward P2G in the fixed-point
+// units of the main path, the cotangent scatter in int64 units chosen per
+// run) and then adds the tile's non-empty nodes into the dense grid. A particle that has left its block's
 // tile since the order was taken scatters straight into the dense grid.
 #include <hip/hip_runtime.h>
 

@@ -8,44 +8,67 @@
 namespace mpm {
 
 // Grid blocks are kTile^3 nodes, stored contiguously (x fastest inside a
-// block, blocks x fastest). A block's particles work on a tile of
-// (kTile + 2 + 2 * kSlack)^3 nodes in LDS: the 3-node stencils of the
-// block's cells plus kSlack cells of drift on each side since binning.
-// Particles that drift further take the global-memory path.
+// block, blocks x fastest); the grid update, the active and overflow lists
+// and the impulse sums work per block. The transfers work per work tile: a
+// cube of TileShape<T>::kEdge cells (T = 8: one block; T = 4: one of its
+// eight sub-blocks), whose particles share a tile of (T + 2)^3 nodes in LDS
+// (the 3-node stencils of its cells). Particles that drift out of their tile
+// since binning take the global-memory path.
 constexpr int kTile = 8;
 constexpr int kTileLog2 = 3;
-// Low bits of a binning key below the block id: the particle's sub-cell
+// Low bits of a binning key below the work tile id: the particle's sub-cell
 // class (a half of the base cell per axis, 3 bits) and the base cell's z
-// layer in the block (3 bits), in either order. Handles keep n_blocks below
-// 2^22, so a key stays below 2^28.
+// layer in the tile (3 bits), in either order. Handles keep n_blocks below
+// 2^22 (work tile ids below 2^25), so a key stays below 2^31.
 constexpr int kClassBits = 6;
-constexpr int kSlack = 0;
-constexpr int kSpan = kTile + 2 + 2 * kSlack;  // 10
+// The differentiable rollout's scatters work on 8-cell tiles: 10^3 nodes.
+constexpr int kSpan = kTile + 2;                   // 10
 constexpr int kSpanNodes = kSpan * kSpan * kSpan;  // 1000
-// Blocks a tile touches, relative to its own block: [kTileLo, kTileHi].
-constexpr int kTileLo = -((kSlack + kTile - 1) / kTile);
-constexpr int kTileHi = (kTile + 1 + kSlack) / kTile;
 constexpr int kBlockNodes = kTile * kTile * kTile;  // 512
+
+// Shape of a transfer work tile of edge T (4 or 8 cells): its LDS span, the
+// workgroup size of the transfer kernels, the shift from block ids to work
+// tile ids (a 4-cell tile is block * 8 + sub-block, sub-block = sx + 2 sy +
+// 4 sz), and the particle count above which a tile counts as dense (8 per
+// cell; see kDenseFlag).
+template <int T>
+struct TileShape {
+  static_assert(T == 4 || T == 8, "work tiles are 4 or 8 cells wide");
+  static constexpr int kEdge = T;
+  static constexpr int kLog2 = T == 8 ? 3 : 2;
+  static constexpr int kSpan = T + 2;
+  static constexpr int kSpanNodes = kSpan * kSpan * kSpan;
+  static constexpr int kWG = T == 8 ? 512 : 128;
+  static constexpr int kUnitShift = T == 8 ? 0 : 3;
+  static constexpr unsigned kDense = 8u * T * T * T;
+};
+// Sub-blocks per block for the finest work tile: the per-tile tables
+// (ranges, flags, work items) are sized for it.
+constexpr int kMaxUnitShift = 3;
 constexpr int kMaxTools = 8;
 constexpr int kImpulseRows = kMaxTools + 1;  // tools, then the walls
 constexpr int kGridSlots = 8192;             // largest grid-update launch
 constexpr int kFields = 25;  // x3 v3 C9 F9 E1, SoA
-// A transfer work item is one block's particles or, for a block holding more
-// than SimK::item_particles, a run of that many of them: dense blocks are
-// shared by several workgroups (each with its own LDS tile) instead of
-// serialising on one. The run length is a power of two in
-// [kItemMin, kItemMax] chosen from the particle and workgroup counts.
+// A transfer work item is one work tile's particles or, for a tile holding
+// more than SimK::item_particles, a run of that many of them: dense tiles
+// are shared by several workgroups (each with its own LDS tile) instead of
+// serialising on one. The run length is a power of two in [kItemMin / k,
+// kItemMax / k] (k = 1 for 8-cell tiles, 4 for 4-cell tiles, whose
+// workgroups are a quarter the size) chosen from the particle and workgroup
+// counts.
 constexpr int kItemMin = 512;
 constexpr int kItemMax = 2048;
-// Work items of a block holding more than kDenseBlock particles (8 per cell
-// on average) carry kDenseFlag in their block id: their particles are dealt
-// to the lanes of a wave 8 apart, so that one wave's LDS atomics do not pile
-// onto the same nodes.
-constexpr unsigned kDenseBlock = 8u * 512u;
+// Work items of a tile holding more than TileShape<T>::kDense particles (8
+// per cell on average) carry kDenseFlag in their tile id: their particles
+// are dealt to the lanes of a wave kWG / 64 apart, so that one wave's LDS
+// atomics do not pile onto the same nodes.
 constexpr unsigned kDenseFlag = 0x80000000u;
 // The differentiable rollout's scatters take runs of kItemRollout particles
 // (its scenes are small, so shorter runs keep every workgroup busy).
 constexpr int kItemRollout = 256;
+// The smallest work item of any kind (sizes the work list).
+constexpr int kItemMinAny = 128;
+static_assert(kItemMin / 4 >= kItemMinAny && kItemRollout >= kItemMinAny, "work list capacity");
 
 // Field offsets in the particle SoA (each field is `cap` floats).
 enum Field { FX = 0, FV = 3, FC = 6, FF = 15, FE = 24 };
@@ -117,6 +140,8 @@ struct SimK {
   int tool_slots;    // 1 + the highest tool slot in use in any scene (0: no tools)
   int push_out;      // some tool pushes particles out: the transfer kernels check positions
   unsigned item_particles;  // particles per transfer work item (at most)
+  int tile;          // transfer work tile edge in cells: 8 (a block) or 4 (a sub-block)
+  int unit_shift;    // work tile ids = block ids << unit_shift (3 for 4-cell tiles, else 0)
 };
 
 // Solvers of Sec. III: MLS-MPM (APIC transfers, fixed-corotated stress in the
@@ -136,7 +161,7 @@ struct Status {
   unsigned long long n_nonfinite;
   unsigned long long n_fallback;
   unsigned long long n_range;      // P2G contributions outside the fixed-point range
-  unsigned int n_occ;               // occupied blocks (this binning)
+  unsigned int n_occ;               // occupied work tiles (this binning)
   unsigned int n_work;              // transfer work items (this binning)
   unsigned int n_act;               // active blocks (this binning)
   unsigned int ovf_count[2];        // overflow blocks claimed, per parity
@@ -163,11 +188,11 @@ struct Buffers {
   uint32_t* vals[2] = {nullptr, nullptr};   // sort values ping-pong
   uint32_t* hist = nullptr;                 // radix histograms
   uint32_t* scan_tmp = nullptr;             // scan partials
-  uint32_t* blk_begin = nullptr;            // per block [begin, end)
+  uint32_t* blk_begin = nullptr;            // per work tile [begin, end) (n_blocks << kMaxUnitShift entries)
   uint32_t* blk_end = nullptr;
-  uint32_t* flags = nullptr;                // per block scratch for compaction
-  uint32_t* occ_list = nullptr;             // occupied blocks
-  uint2* work = nullptr;                    // transfer work items {block, first particle}
+  uint32_t* flags = nullptr;                // per work tile scratch for compaction
+  uint32_t* occ_list = nullptr;             // occupied work tiles
+  uint2* work = nullptr;                    // transfer work items {work tile, first particle}
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
   uint32_t* node_cnt = nullptr;             // per block: nodes with mass, last grid update

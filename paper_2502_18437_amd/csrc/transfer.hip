@@ -1,30 +1,34 @@
 // Particle <-> grid transfers of the MPM substep (CRESSim-MPM Sec. III-B,
-// Algorithm 1, and the solver variants of Sec. III-A and III-C), block-tiled
-// for CDNA4.
+// Algorithm 1, and the solver variants of Sec. III-A and III-C), tiled for
+// CDNA4.
 //
-// Particles are binned by the grid block (kTile^3 cells) of their base cell.
-// One workgroup owns one work item at a time (a block's particles, or a run of
-// s.item_particles of them when the block is dense): it stages the grid
-// velocities of the block's tile (kSpan^3 nodes: the block's stencils plus kSlack cells of
-// drift) in LDS, gathers (G2P) from LDS, scatters (P2G) into an LDS
-// accumulator tile with integer LDS atomics, then flushes the non-empty tile
-// nodes into the global accumulator (FP32 or integer atomics, one per value).
-// A particle whose stencil has drifted out of the tile since binning takes a
-// global-memory path with the same integer contributions and claims the
-// blocks it touches for the grid update (overflow list).
+// Particles are binned by the work tile of their base cell: a cube of T = 8
+// cells (one grid block) or T = 4 cells (one of its eight sub-blocks). The
+// kernels are templates on T; a 4-cell tile is worked by 128-thread
+// workgroups with a 6^3-node LDS tile, an 8-cell tile by 512-thread
+// workgroups with a 10^3-node tile. One workgroup owns one work item at a
+// time (a tile's particles, or a run of s.item_particles of them when the
+// tile is dense): it stages the grid velocities of the tile's (T + 2)^3 nodes
+// (the stencils of its cells) in LDS, gathers (G2P) from LDS, scatters (P2G)
+// into an LDS accumulator tile with integer LDS atomics, then flushes the
+// non-empty tile nodes into the global accumulator (FP32 or integer atomics,
+// one per value). A particle whose stencil has drifted out of the tile since
+// binning takes a global-memory path with the same integer contributions
+// and claims the grid blocks it touches for the grid update (overflow list).
 //
 // P2G accumulates integers because LDS float atomics are slow on gfx950 while
 // ds_add_u32 / ds_add_u64 run near LDS bandwidth; integer sums are also exact,
-// so the result does not depend on the order of the atomics. Weights are u32
-// in 2^-22 units: one work item (at most kItemMax particles, each adding at
-// most 0.75^3 to a node) cannot carry a node's sum past 2^32 - 1.
+// so the result does not depend on the order of the atomics (nor on the tile
+// edge). Weights are u32 in 2^-22 units: one work item (at most kItemMax
+// particles, each adding at most 0.75^3 to a node) cannot carry a node's sum
+// past 2^32 - 1.
 //
 // k_g2p2g fuses the G2P of substep k-1 with the P2G of substep k: v and C never
 // leave registers between the two, so a fused substep streams x, F, E in and
 // x, F out (100 B/particle). When a tool pushes particles out, an
-// instantiation with the push-out after the position update runs instead. A dense block's work items deal their particles
-// to a wave's lanes 8 apart (item_lane), so that one wave's atomics spread
-// over different cells.
+// instantiation with the push-out after the position update runs instead. A
+// dense tile's work items deal their particles to a wave's lanes kWG / 64
+// apart (item_lane), so that one wave's atomics spread over different cells.
 #include "mpm_device.h"
 #include "mpm_internal.h"
 #include "p2g_fixed.h"
@@ -32,7 +36,6 @@
 namespace mpm {
 
 constexpr int kXcds = 8;
-constexpr int kWG = 512;
 
 // Walk of a block list by a persistent grid whose size is a multiple of 8.
 // Workgroups are dealt round-robin to the 8 XCDs, so workgroup w runs on XCD
@@ -50,11 +53,13 @@ __device__ __forceinline__ void xcd_walk(unsigned n_items, unsigned* pos, unsign
 }
 
 // This thread's position in each run of kWG particles of a work item: its
-// own index, or for a dense block's items (kDenseFlag) lane l of wave w takes
-// position l * (kWG / 64) + w, so one wave's 64 particles lie 8 apart in the
-// block's order (different cells) instead of side by side.
-__device__ __forceinline__ unsigned item_lane(unsigned tagged_block) {
-  return (tagged_block & kDenseFlag) ? (threadIdx.x & 63u) * (kWG / 64) + (threadIdx.x >> 6) : threadIdx.x;
+// own index, or for a dense tile's items (kDenseFlag) lane l of wave w takes
+// position l * (kWG / 64) + w, so one wave's 64 particles lie kWG / 64 apart
+// in the tile's order (different cells) instead of side by side.
+template <int T>
+__device__ __forceinline__ unsigned item_lane(unsigned tagged_unit) {
+  constexpr unsigned kWG = TileShape<T>::kWG;
+  return (tagged_unit & kDenseFlag) ? (threadIdx.x & 63u) * (kWG / 64) + (threadIdx.x >> 6) : threadIdx.x;
 }
 
 struct Counters {
@@ -291,32 +296,42 @@ __device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const
 }
 
 // ------------------------------------------------------------------ per particle
+// The LDS tile of a work tile of edge T: (T + 2)^3 nodes.
+template <int T>
 struct Lds {
-  float4 v[kSpanNodes];                                     // staged grid velocity
-  uint32_t m[kSpanNodes];                                   // weight sums (2^-22 units)
-  long long p0[kSpanNodes], p1[kSpanNodes], p2[kSpanNodes];  // momentum (fixed point)
+  static constexpr int kNodes = TileShape<T>::kSpanNodes;
+  float4 v[kNodes];                             // staged grid velocity
+  uint32_t m[kNodes];                           // weight sums (2^-22 units)
+  long long p0[kNodes], p1[kNodes], p2[kNodes];  // momentum (fixed point)
 };
 
+template <int T>
 __device__ __forceinline__ int lds_index(int lx, int ly, int lz) {
-  return (lz * kSpan + ly) * kSpan + lx;
+  constexpr int S = TileShape<T>::kSpan;
+  return (lz * S + ly) * S + lx;
+}
+
+// Whether a stencil with base node `l` (tile coordinates) lies in the tile.
+template <int T>
+__device__ __forceinline__ bool in_tile(int l0, int l1, int l2) {
+  constexpr unsigned kMax = TileShape<T>::kSpan - 3;
+  return ((unsigned)l0 <= kMax) && ((unsigned)l1 <= kMax) && ((unsigned)l2 <= kMax);
 }
 
 // Commit one particle's scatter: into the LDS tile when its stencil lies in
 // the block's tile, else straight into the global accumulator.
-template <bool FIXED, class In>
-__device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int* to, Lds& L, ACC_PARAMS,
+template <bool FIXED, int T, class In>
+__device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int* to, Lds<T>& L, ACC_PARAMS,
                                            uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   const int l0 = P.base[0] - to[0], l1 = P.base[1] - to[1], l2 = P.base[2] - to[2];
-  const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
-                       ((unsigned)l2 <= (unsigned)(kSpan - 3));
-  if (!in_tile) {
+  if (!in_tile<T>(l0, l1, l2)) {
     ev |= kEvFbP2G;
     p2g_global<FIXED>(s, P, ACC_ARGS, mark, ovf, st, parity, to[3]);
     return;
   }
-  const int l = lds_index(l0, l1, l2);
+  const int l = lds_index<T>(l0, l1, l2);
   p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
-    const int idx = l + lds_index(ox, oy, oz);
+    const int idx = l + lds_index<T>(ox, oy, oz);
     atomicAdd(&L.m[idx], wq);
     atomicAdd((unsigned long long*)&L.p0[idx], (unsigned long long)p0);
     atomicAdd((unsigned long long*)&L.p1[idx], (unsigned long long)p1);
@@ -332,9 +347,9 @@ __device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int
 //            on the first pass of a step v also receives dt g.
 // The PB-MPM iterations after the first count no errors (the first pass of
 // the step has counted them).
-template <bool FIXED, int SOL, int PASS>
+template <bool FIXED, int SOL, int PASS, int T>
 __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, const float* v, const float* C,
-                                             const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
+                                             const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
                                              uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   constexpr bool kCount = !(SOL == SOLVER_PB && PASS == PB_ITER);
   P2GIn P;
@@ -404,9 +419,9 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
 // Neo-Hookean stress (gravity is added by the grid update). C is not
 // transferred; it holds the velocity gradient and is only checked for being
 // finite.
-template <bool FIXED>
+template <bool FIXED, int T>
 __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, const float* v, const float* C,
-                                                 const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
+                                                 const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
                                                  uint32_t* mark, uint32_t* ovf, Status* st, int parity,
                                                  unsigned& ev) {
   PICIn P;
@@ -457,9 +472,9 @@ __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, 
 // v' = sum N v_I and the velocity gradient L = sum v_I grad N^T in Cn.
 // Returns false if the stencil is outside the grid (the particle is then
 // left unchanged).
-template <int SOL>
+template <int SOL, int T>
 __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, const int* to,
-                                             const Lds& L, const float4* vel, float* vn, float* Cn,
+                                             const Lds<T>& L, const float4* vel, float* vn, float* Cn,
                                              unsigned& ev) {
   int base[3];
   float f[3];
@@ -467,67 +482,75 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
   float w[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) bspline_w(f[a], w[a]);
-  float S[3], T[9];
+  float S[3], Tm[9];
   const int l0 = base[0] - to[0], l1 = base[1] - to[1], l2 = base[2] - to[2];
-  const bool in_tile = ((unsigned)l0 <= (unsigned)(kSpan - 3)) && ((unsigned)l1 <= (unsigned)(kSpan - 3)) &&
-                       ((unsigned)l2 <= (unsigned)(kSpan - 3));
+  const bool in_tile_ = in_tile<T>(l0, l1, l2);
   if constexpr (SOL == SOLVER_PIC) {
     float dw[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) bspline_dw(f[a], dw[a]);
-    if (in_tile) {
-      const int l = lds_index(l0, l1, l2);
-      g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
+    if (in_tile_) {
+      const int l = lds_index<T>(l0, l1, l2);
+      g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) { return L.v[l + lds_index<T>(ox, oy, oz)]; }, S, Tm);
     } else {
       ev |= kEvFbG2P;
       const int node_base = to[3] * s.n3;
       g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) {
         return vel[node_base + grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb)];
-      }, S, T);
+      }, S, Tm);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       vn[a] = S[a];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) Cn[3 * a + b] = s.inv_dx * T[3 * a + b];
+      for (int b = 0; b < 3; ++b) Cn[3 * a + b] = s.inv_dx * Tm[3 * a + b];
     }
   } else {
-    // T[a][b] = sum N v_a o_b
-    if (in_tile) {
-      const int l = lds_index(l0, l1, l2);
-      g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index(ox, oy, oz)]; }, S, T);
+    // Tm[a][b] = sum N v_a o_b
+    if (in_tile_) {
+      const int l = lds_index<T>(l0, l1, l2);
+      g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index<T>(ox, oy, oz)]; }, S, Tm);
     } else {
       ev |= kEvFbG2P;
-      g2p_global(s, base, w, vel, S, T, to[3]);
+      g2p_global(s, base, w, vel, S, Tm, to[3]);
     }
     const float k = 4.0f * s.inv_dx;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       vn[a] = S[a];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) Cn[3 * a + b] = k * (T[3 * a + b] - S[a] * f[b]);
+      for (int b = 0; b < 3; ++b) Cn[3 * a + b] = k * (Tm[3 * a + b] - S[a] * f[b]);
     }
   }
   return true;
 }
 
 // ------------------------------------------------------------------ tile helpers
-// Tile origin of block b (node coordinates within its scene) in to[0..2] and
-// the block's scene in to[3].
-__device__ __forceinline__ void block_origin(const SimK& s, unsigned b, int* to) {
+// Tile origin of work tile u (node coordinates within its scene) in to[0..2]
+// and its scene in to[3]. For T = 4, u = block * 8 + (sx + 2 sy + 4 sz).
+template <int T>
+__device__ __forceinline__ void unit_origin(const SimK& s, unsigned u, int* to) {
+  constexpr int kShift = TileShape<T>::kUnitShift;
+  const unsigned b = u >> kShift;
   const unsigned scene = b / s.nb3;
   const unsigned lb = b - scene * s.nb3;
   const int bi = (int)(lb % (unsigned)s.nb);
   const int bj = (int)((lb / (unsigned)s.nb) % (unsigned)s.nb);
   const int bk = (int)(lb / ((unsigned)s.nb * (unsigned)s.nb));
-  to[0] = bi * kTile - kSlack;
-  to[1] = bj * kTile - kSlack;
-  to[2] = bk * kTile - kSlack;
+  to[0] = bi * kTile;
+  to[1] = bj * kTile;
+  to[2] = bk * kTile;
+  if constexpr (kShift != 0) {
+    to[0] += (int)(u & 1u) * T;
+    to[1] += (int)((u >> 1) & 1u) * T;
+    to[2] += (int)((u >> 2) & 1u) * T;
+  }
   to[3] = (int)scene;
 }
 
-__device__ __forceinline__ void tile_clear(Lds& L) {
-  for (int i = threadIdx.x; i < kSpanNodes; i += blockDim.x) {
+template <int T>
+__device__ __forceinline__ void tile_clear(Lds<T>& L) {
+  for (int i = threadIdx.x; i < Lds<T>::kNodes; i += blockDim.x) {
     L.m[i] = 0u;
     L.p0[i] = 0ll;
     L.p1[i] = 0ll;
@@ -535,10 +558,12 @@ __device__ __forceinline__ void tile_clear(Lds& L) {
   }
 }
 
+template <int T>
 __device__ __forceinline__ void tile_stage_velocity(const SimK& s, const int* to, const float4* vel,
-                                                    Lds& L) {
-  for (int i = threadIdx.x; i < kSpanNodes; i += blockDim.x) {
-    const int lx = i % kSpan, ly = (i / kSpan) % kSpan, lz = i / (kSpan * kSpan);
+                                                    Lds<T>& L) {
+  constexpr int S = TileShape<T>::kSpan;
+  for (int i = threadIdx.x; i < Lds<T>::kNodes; i += blockDim.x) {
+    const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
     const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
     float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if ((unsigned)gx < (unsigned)s.n && (unsigned)gy < (unsigned)s.n && (unsigned)gz < (unsigned)s.n)
@@ -548,13 +573,14 @@ __device__ __forceinline__ void tile_stage_velocity(const SimK& s, const int* to
 }
 
 // Non-empty tile nodes -> global accumulator.
-template <bool FIXED>
-__device__ __forceinline__ void tile_flush(const SimK& s, const int* to, const Lds& L, ACC_PARAMS) {
-  for (int i = threadIdx.x; i < kSpanNodes; i += blockDim.x) {
+template <bool FIXED, int T>
+__device__ __forceinline__ void tile_flush(const SimK& s, const int* to, const Lds<T>& L, ACC_PARAMS) {
+  constexpr int S = TileShape<T>::kSpan;
+  for (int i = threadIdx.x; i < Lds<T>::kNodes; i += blockDim.x) {
     const uint32_t wq = L.m[i];
     const long long p0 = L.p0[i], p1 = L.p1[i], p2 = L.p2[i];
     if ((wq | p0 | p1 | p2) == 0) continue;
-    const int lx = i % kSpan, ly = (i / kSpan) % kSpan, lz = i / (kSpan * kSpan);
+    const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
     const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
     // Only in-grid nodes can receive contributions (stencils are checked
     // against the grid); the test keeps the index in range regardless.
@@ -570,39 +596,39 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 
 // ------------------------------------------------------------------ kernels
 // Scatter of one particle by the solver's rule.
-template <bool FIXED, int SOL, int PASS>
+template <bool FIXED, int SOL, int PASS, int T>
 __device__ __forceinline__ void p2g_any(const SimK& s, const float* x, const float* v, const float* C,
-                                        const float* F, float E, const int* to, Lds& L, ACC_PARAMS,
+                                        const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
                                         uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   if constexpr (SOL == SOLVER_PIC)
-    p2g_particle_pic<FIXED>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+    p2g_particle_pic<FIXED, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
   else
-    p2g_particle<FIXED, SOL, PASS>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+    p2g_particle<FIXED, SOL, PASS, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
 }
 
 // P2G from the materialised particle state (first substep after binning; for
 // PB-MPM the first pass of a step).
-template <bool FIXED, int SOL>
-__global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, int64_t cap,
+template <bool FIXED, int SOL, int T>
+__global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint2* __restrict__ work, Status* st,
                                              ACC_PARAMS, uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
                                              int parity, SimK s) {
   uint32_t* ovf = parity ? ovf1 : ovf0;
-  __shared__ Lds L;
+  __shared__ Lds<T> L;
   Counters cnt;
   unsigned pos, end, stride;
   xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const uint2 item = work[pos];
     const unsigned b = item.x & ~kDenseFlag;
-    const unsigned q = item_lane(item.x);
+    const unsigned q = item_lane<T>(item.x);
     int to[4];
-    block_origin(s, b, to);
+    unit_origin<T>(s, b, to);
     tile_clear(L);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
-    for (unsigned p = item.y + q; p < pe; p += kWG) {
+    for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
       float x[3], v[3], C[9], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -616,11 +642,11 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
       }
       const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
       unsigned ev = 0u;
-      p2g_any<FIXED, SOL, PB_FIRST>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+      p2g_any<FIXED, SOL, PB_FIRST, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
       count_events(cnt, ev);
     }
     __syncthreads();
-    tile_flush<FIXED>(s, to, L, ACC_ARGS);
+    tile_flush<FIXED, T>(s, to, L, ACC_ARGS);
     __syncthreads();
   }
   flush_counters(st, cnt);
@@ -633,8 +659,8 @@ __global__ __launch_bounds__(kWG, 4) void k_p2g(const float* __restrict__ part, 
 // and F do not change and nothing is written back.
 // With PUSH, particles that the position update leaves inside a tool with
 // push-out on are moved to its surface (push_out) before the P2G.
-template <bool FIXED, int SOL, int PASS, bool PUSH>
-__global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int64_t cap,
+template <bool FIXED, int SOL, int PASS, bool PUSH, int T>
+__global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restrict__ part, int64_t cap,
                                                const uint32_t* __restrict__ blk_end,
                                                const uint2* __restrict__ work, Status* st,
                                                ACC_PARAMS, const float4* __restrict__ vel,
@@ -646,21 +672,21 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
   long long substep = 0;
   if constexpr (PUSH) substep = clk[parity].substep;
   uint32_t* ovf = parity ? ovf1 : ovf0;
-  __shared__ Lds L;
+  __shared__ Lds<T> L;
   Counters cnt;
   unsigned pos, end, stride;
   xcd_walk(st->n_work, &pos, &end, &stride);
   for (; pos < end; pos += stride) {
     const uint2 item = work[pos];
     const unsigned b = item.x & ~kDenseFlag;
-    const unsigned q = item_lane(item.x);
+    const unsigned q = item_lane<T>(item.x);
     int to[4];
-    block_origin(s, b, to);
+    unit_origin<T>(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     tile_clear(L);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
-    for (unsigned p = item.y + q; p < pe; p += kWG) {
+    for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
       float x[3], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = part[(FX + a) * cap + p];
@@ -668,7 +694,7 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
       unsigned ev = 0u;
-      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, ev)) continue;  // frozen (out of grid), no events
+      if (!g2p_particle<SOL, T>(s, x, to, L, vel, vn, Cn, ev)) continue;  // frozen (out of grid), no events
       if constexpr (kIntegrate) {
         float Fn[9];
 #pragma unroll
@@ -685,7 +711,7 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
 #pragma unroll
         for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
         const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
-        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+        p2g_any<FIXED, SOL, PASS, T>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
         // An update that moved the particle out of the grid (or left its
         // state not finite) is its last: the particle is left unchanged from
         // then on, so its v and C of this update are kept in memory with it.
@@ -696,12 +722,12 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
           for (int i = 0; i < 9; ++i) part[(FC + i) * cap + p] = Cn[i];
         }
       } else {
-        p2g_any<FIXED, SOL, PASS>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+        p2g_any<FIXED, SOL, PASS, T>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
       }
       count_events(cnt, ev);
     }
     __syncthreads();
-    tile_flush<FIXED>(s, to, L, ACC_ARGS);
+    tile_flush<FIXED, T>(s, to, L, ACC_ARGS);
     __syncthreads();
   }
   flush_counters(st, cnt);
@@ -709,13 +735,13 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p2g(float* __restrict__ part, int6
 
 // G2P that materialises the full state (x, v, C, F) in memory (the C slot
 // holds the velocity gradient for standard MPM).
-template <int SOL, bool PUSH>
-__global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_t cap,
+template <int SOL, bool PUSH, int T>
+__global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p(float* __restrict__ part, int64_t cap,
                                              const uint32_t* __restrict__ blk_end,
                                              const uint2* __restrict__ work, Status* st,
                                              const float4* __restrict__ vel, const Clock* __restrict__ clk,
                                              int parity, const ToolDesc* __restrict__ tools, SimK s) {
-  __shared__ Lds L;
+  __shared__ Lds<T> L;
   long long substep = 0;
   if constexpr (PUSH) substep = clk[parity].substep;
   Counters cnt;
@@ -724,13 +750,13 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
   for (; pos < end; pos += stride) {
     const uint2 item = work[pos];
     const unsigned b = item.x & ~kDenseFlag;
-    const unsigned q = item_lane(item.x);
+    const unsigned q = item_lane<T>(item.x);
     int to[4];
-    block_origin(s, b, to);
+    unit_origin<T>(s, b, to);
     tile_stage_velocity(s, to, vel, L);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
-    for (unsigned p = item.y + q; p < pe; p += kWG) {
+    for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
       float x[3], F[9];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = part[(FX + a) * cap + p];
@@ -738,7 +764,7 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
       unsigned ev = 0u;
-      if (!g2p_particle<SOL>(s, x, to, L, vel, vn, Cn, ev)) continue;  // no events
+      if (!g2p_particle<SOL, T>(s, x, to, L, vel, vn, Cn, ev)) continue;  // no events
       count_events(cnt, ev);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -764,90 +790,112 @@ __global__ __launch_bounds__(kWG, 4) void k_g2p(float* __restrict__ part, int64_
 }
 
 // ------------------------------------------------------------------ launchers
-template <bool FIXED, int SOL>
+template <bool FIXED, int SOL, int T>
 static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL((k_p2g<FIXED, SOL>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
+  hipLaunchKernelGGL((k_p2g<FIXED, SOL, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st, b.part[b.cur], b.cap,
                      b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
                      (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], parity, s);
 }
 
-template <bool FIXED, int SOL, int PASS, bool PUSH>
+template <bool FIXED, int SOL, int PASS, bool PUSH, int T>
 static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS, PUSH>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap,
-                     b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
-                     (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock,
-                     parity, (const ToolDesc*)b.tools, s);
+  hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS, PUSH, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st,
+                     b.part[b.cur], b.cap, b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0],
+                     (P*)b.acc_p[1], (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1],
+                     (const Clock*)b.clock, parity, (const ToolDesc*)b.tools, s);
 }
 
 // The integrating passes with or without push-out.
-template <bool FIXED, int SOL>
+template <bool FIXED, int SOL, int T>
 static void launch_g2p2g_p(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   if (s.push_out)
-    launch_g2p2g_t<FIXED, SOL, PB_FIRST, true>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, true, T>(b, s, grid_wgs, parity, st);
   else
-    launch_g2p2g_t<FIXED, SOL, PB_FIRST, false>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, false, T>(b, s, grid_wgs, parity, st);
 }
 
-template <bool FIXED>
+template <bool FIXED, int T>
 static void launch_p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   if (s.solver == SOLVER_PIC)
-    launch_p2g_t<FIXED, SOLVER_PIC>(b, s, grid_wgs, parity, st);
+    launch_p2g_t<FIXED, SOLVER_PIC, T>(b, s, grid_wgs, parity, st);
   else if (s.solver == SOLVER_PB)
-    launch_p2g_t<FIXED, SOLVER_PB>(b, s, grid_wgs, parity, st);
+    launch_p2g_t<FIXED, SOLVER_PB, T>(b, s, grid_wgs, parity, st);
   else
-    launch_p2g_t<FIXED, SOLVER_MLS>(b, s, grid_wgs, parity, st);
+    launch_p2g_t<FIXED, SOLVER_MLS, T>(b, s, grid_wgs, parity, st);
 }
 
-template <bool FIXED>
+template <bool FIXED, int T>
 static void launch_g2p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass) {
   if (s.solver == SOLVER_PIC)
-    launch_g2p2g_p<FIXED, SOLVER_PIC>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_p<FIXED, SOLVER_PIC, T>(b, s, grid_wgs, parity, st);
   else if (s.solver == SOLVER_PB && pass == PB_ITER)
-    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER, false>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER, false, T>(b, s, grid_wgs, parity, st);
   else if (s.solver == SOLVER_PB)
-    launch_g2p2g_p<FIXED, SOLVER_PB>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_p<FIXED, SOLVER_PB, T>(b, s, grid_wgs, parity, st);
   else
-    launch_g2p2g_p<FIXED, SOLVER_MLS>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_p<FIXED, SOLVER_MLS, T>(b, s, grid_wgs, parity, st);
 }
 
 void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   (void)N;
-  if (s.fixed)
-    launch_p2g_s<true>(b, s, grid_wgs, parity, st);
-  else
-    launch_p2g_s<false>(b, s, grid_wgs, parity, st);
+  if (s.tile == 4) {
+    if (s.fixed)
+      launch_p2g_s<true, 4>(b, s, grid_wgs, parity, st);
+    else
+      launch_p2g_s<false, 4>(b, s, grid_wgs, parity, st);
+  } else {
+    if (s.fixed)
+      launch_p2g_s<true, 8>(b, s, grid_wgs, parity, st);
+    else
+      launch_p2g_s<false, 8>(b, s, grid_wgs, parity, st);
+  }
 }
 
 void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass) {
   (void)N;
-  if (s.fixed)
-    launch_g2p2g_s<true>(b, s, grid_wgs, parity, st, pass);
-  else
-    launch_g2p2g_s<false>(b, s, grid_wgs, parity, st, pass);
+  if (s.tile == 4) {
+    if (s.fixed)
+      launch_g2p2g_s<true, 4>(b, s, grid_wgs, parity, st, pass);
+    else
+      launch_g2p2g_s<false, 4>(b, s, grid_wgs, parity, st, pass);
+  } else {
+    if (s.fixed)
+      launch_g2p2g_s<true, 8>(b, s, grid_wgs, parity, st, pass);
+    else
+      launch_g2p2g_s<false, 8>(b, s, grid_wgs, parity, st, pass);
+  }
 }
 
-template <int SOL>
+template <int SOL, int T>
 static void launch_g2p_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   const Clock* clk = (const Clock*)b.clock;
   const ToolDesc* tools = (const ToolDesc*)b.tools;
   if (s.push_out)
-    hipLaunchKernelGGL((k_g2p<SOL, true>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_end,
-                       b.work, b.status, b.vel, clk, parity, tools, s);
+    hipLaunchKernelGGL((k_g2p<SOL, true, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st, b.part[b.cur], b.cap,
+                       b.blk_end, b.work, b.status, b.vel, clk, parity, tools, s);
   else
-    hipLaunchKernelGGL((k_g2p<SOL, false>), dim3(grid_wgs), dim3(kWG), 0, st, b.part[b.cur], b.cap, b.blk_end,
-                       b.work, b.status, b.vel, clk, parity, tools, s);
+    hipLaunchKernelGGL((k_g2p<SOL, false, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st, b.part[b.cur], b.cap,
+                       b.blk_end, b.work, b.status, b.vel, clk, parity, tools, s);
+}
+
+template <int T>
+static void launch_g2p_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+  if (s.solver == SOLVER_PIC)
+    launch_g2p_t<SOLVER_PIC, T>(b, s, grid_wgs, parity, st);
+  else
+    launch_g2p_t<SOLVER_MLS, T>(b, s, grid_wgs, parity, st);
 }
 
 void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
   (void)N;
-  if (s.solver == SOLVER_PIC)
-    launch_g2p_t<SOLVER_PIC>(b, s, grid_wgs, parity, st);
+  if (s.tile == 4)
+    launch_g2p_s<4>(b, s, grid_wgs, parity, st);
   else
-    launch_g2p_t<SOLVER_MLS>(b, s, grid_wgs, parity, st);
+    launch_g2p_s<8>(b, s, grid_wgs, parity, st);
 }
 
 }  // namespace mpm
