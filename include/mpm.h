@@ -215,9 +215,12 @@ int mpm_set_particles(mpm_handle* h, int64_t n, const float* x, const float* v,
  * the used fields, non-finite values, mu < 0, drag outside [0, 1]). */
 int mpm_set_tool_sdf(mpm_handle* h, int32_t tool_id, const mpm_tool* t);
 
-/* Enqueue n_substeps substeps of Algorithm 1 and return without waiting
- * (Scene::advance). n_substeps = 0 is a no-op. Errors: MPM_EINVAL
- * (n_substeps < 0), MPM_EHIP (launch failure). */
+/* Enqueue n_substeps substeps of Algorithm 1 and return without waiting for
+ * them (Scene::advance, Sec. V-A). With adaptive re-binning on
+ * (mpm_launch_config.rebin_drift > 0, the default) the host stays at most 8
+ * substeps ahead of the device, so the call returns when the device is
+ * within 8 substeps of the end. n_substeps = 0 is a no-op. Errors:
+ * MPM_EINVAL (n_substeps < 0), MPM_EHIP (launch failure). */
 int mpm_step(mpm_handle* h, int32_t n_substeps);
 
 /* Block until the stream drains (Scene::fetchResults, Sec. V-A) and write
@@ -312,6 +315,11 @@ typedef struct mpm_launch_config {
   int32_t tile;            /* transfer work tile edge in cells: 8 (512-thread workgroups, a
                               10^3-node LDS tile) or 4 (128-thread workgroups, 6^3 nodes);
                               0 keeps the current one. A change re-bins the particles */
+  int32_t rebin_drift;     /* adaptive re-binning: re-bin before resort_interval ends once the
+                              particles outside their tiles (on the global-memory path) average
+                              more than this many per million per substep since the last
+                              re-binning (read without waiting, a few substeps late); 0 = off,
+                              default 5000 */
 } mpm_launch_config;
 
 /* Read / replace the launch configuration (the defaults: resort_interval

@@ -36,6 +36,22 @@ using namespace mpm;
 namespace {
 
 constexpr int kDefaultResort = 32;
+// Adaptive re-binning: re-bin before the interval ends once the particles on
+// the global path (outside their tiles) average more than this many per
+// million per substep since the last binning. Such a particle costs about 25
+// times one in its tile (108 global atomics instead of LDS ones), so at
+// 0.5% the fused kernel is already about 10% slower, while one in-place
+// re-binning costs about one and a half substeps.
+constexpr int kDefaultRebinDrift = 5000;
+// A drift-triggered re-binning waits at least this many substeps after the
+// previous one.
+constexpr int kMinDriftInterval = 2;
+// With adaptive re-binning on, mpm_step keeps at most this many substeps
+// enqueued ahead of the device (so that the fallback count it reads is
+// recent): before each launch it waits for the work enqueued kDriftLag
+// substeps earlier. The device then still has that many substeps queued.
+constexpr int kDriftLag = 8;
+constexpr int kDriftEvents = 32;
 constexpr int kDefaultGraphChunk = 8;
 
 struct HostTool {
@@ -136,6 +152,13 @@ struct mpm_handle {
   // grid update of the run (the kernels take the parity as an argument).
   int graph_chunk = kDefaultGraphChunk;
   int rebin_mode = MPM_REBIN_AUTO;
+  int rebin_drift = kDefaultRebinDrift;       // ppm of N per substep on the global path; 0: off
+  int64_t sort_substep = 0;                   // substep of the last binning
+  // progress marks of the enqueued work (adaptive re-binning): an event after
+  // each run of launches and the substep count it ends at, oldest first
+  hipEvent_t drift_ev[kDriftEvents] = {};
+  int64_t drift_sub[kDriftEvents] = {};
+  int drift_head = 0, drift_n = 0;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
@@ -351,6 +374,7 @@ void free_buffers(Buffers& b) {
                   b.status, b.scene_off, b.tools, b.clock};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (b.drift_host) (void)hipHostFree(b.drift_host);
   b = Buffers();
 }
 
@@ -374,6 +398,7 @@ __global__ void k_reset_status(Status* st) {
   st->n_act = 0u;
   st->ovf_count[0] = 0u;
   st->ovf_count[1] = 0u;
+  st->fb_at_sort = 0ull;
 }
 
 __global__ void k_zero_u32(uint32_t* p, int64_t n) {
@@ -629,6 +654,9 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   alloc((void**)&b.scene_off, sizeof(uint32_t) * ((size_t)n_scenes + 1));
   alloc((void**)&b.tools, sizeof(ToolDesc) * (size_t)n_scenes * kMaxTools);
   alloc((void**)&b.clock, 2 * sizeof(Clock));
+  if (ok && hipHostMalloc((void**)&b.drift_host, 4 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+    ok = false;
+  if (ok) std::memset(b.drift_host, 0, 4 * sizeof(unsigned long long));
   alloc((void**)&h->imp_sum, sizeof(double) * kImpulseRows * 3);
   alloc((void**)&h->scratch_u64, sizeof(unsigned long long));
   const size_t mom_bytes = p->accum_mode == MPM_ACCUM_FIXED ? sizeof(long long) : sizeof(float);
@@ -714,6 +742,8 @@ int mpm_destroy(mpm_handle* h) {
     (void)hipEventDestroy(pe.b);
   }
   for (auto e : h->prof_pool) (void)hipEventDestroy(e);
+  for (auto e : h->drift_ev)
+    if (e) (void)hipEventDestroy(e);
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   free_buffers(h->b);
@@ -991,6 +1021,54 @@ bool rebin_in_place(const mpm_handle* h) {
   return h->sim.solver != SOLVER_PB && h->resort_interval >= 4;
 }
 
+// Adaptive re-binning keeps the host at most kDriftLag substeps ahead of the
+// device: wait for the progress marks that end kDriftLag or more substeps
+// before the current count (the device still has that many queued).
+hipError_t drift_throttle(mpm_handle* h) {
+  while (h->drift_n > 0 && h->drift_sub[h->drift_head] <= h->substep - kDriftLag) {
+    const hipError_t e = hipEventSynchronize(h->drift_ev[h->drift_head]);
+    if (e != hipSuccess) return e;
+    h->drift_head = (h->drift_head + 1) % kDriftEvents;
+    h->drift_n--;
+  }
+  return hipSuccess;
+}
+
+// A progress mark after a run of launches that ends at substep h->substep.
+hipError_t drift_mark(mpm_handle* h) {
+  if (h->drift_n == kDriftEvents) {  // ring full: retire the oldest
+    const hipError_t e = hipEventSynchronize(h->drift_ev[h->drift_head]);
+    if (e != hipSuccess) return e;
+    h->drift_head = (h->drift_head + 1) % kDriftEvents;
+    h->drift_n--;
+  }
+  const int slot = (h->drift_head + h->drift_n) % kDriftEvents;
+  if (!h->drift_ev[slot]) {
+    const hipError_t e = hipEventCreateWithFlags(&h->drift_ev[slot], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  const hipError_t e = hipEventRecord(h->drift_ev[slot], h->stream);
+  if (e != hipSuccess) return e;
+  h->drift_sub[slot] = h->substep;
+  h->drift_n++;
+  return hipSuccess;
+}
+
+// Whether the particles on the global path since the last binning call for
+// a re-binning before the interval ends: the grid update mirrors the
+// device's fallback count into pinned host memory after every substep, and
+// this reads the latest mirror without waiting on the stream (it lags the
+// enqueued work by however far the device is behind).
+bool drift_rebin(const mpm_handle* h) {
+  if (h->rebin_drift <= 0 || h->dirty || h->since_sort < kMinDriftInterval) return false;
+  const volatile unsigned long long* m = h->b.drift_host;
+  const int64_t sub = (int64_t)__atomic_load_n(&m[0], __ATOMIC_ACQUIRE);
+  const unsigned long long fb = m[1], fb0 = m[2];
+  if (sub <= h->sort_substep || sub > h->substep || fb < fb0) return false;  // none since the binning
+  const double per_substep = (double)(fb - fb0) / (double)(sub - h->sort_substep);
+  return per_substep * 1e6 > (double)h->rebin_drift * (double)h->N;
+}
+
 // Grid update `it` of `passes` in a substep, of parity `parity`: PB-MPM
 // leaves gravity out (it is added to the particles) and keeps the impulses of
 // the last pass only; the clock's substep advances after the last pass.
@@ -1050,8 +1128,10 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
   launch_set_clock(b, (long long)h->substep, (int)(h->updates & 1), h->stream);
   const int passes = transfer_passes(h);
   const bool in_place = rebin_in_place(h);
+  const bool adaptive = h->rebin_drift > 0;
   for (int k = 0; k < n_substeps;) {
-    const bool rebin = h->dirty || h->since_sort >= h->resort_interval;
+    if (adaptive) HIP_OR_RETURN(h, drift_throttle(h));
+    const bool rebin = h->dirty || h->since_sort >= h->resort_interval || drift_rebin(h);
     // Within a call the particle memory holds x and F as the next G2P reads
     // them (v and C live in registers between G2P and P2G). A re-binning in
     // place sorts by those positions, so every G2P stencil of the next fused
@@ -1075,6 +1155,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
       launch_binning(b, N, h->sim, bits, k == 0 || advance, h->stream);
       h->dirty = false;
       h->since_sort = 0;
+      h->sort_substep = h->substep;
       h->resorts++;
     }
     if (k == 0 || advance) {
@@ -1094,6 +1175,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
         h->substep += h->graph_chunk;
         h->updates += (int64_t)h->graph_chunk * passes;
         h->since_sort += h->graph_chunk;
+        if (adaptive) HIP_OR_RETURN(h, drift_mark(h));
         continue;
       }
       ProfScope ps(h, 2);
@@ -1112,6 +1194,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     h->substep++;
     h->since_sort++;
     ++k;
+    if (adaptive) HIP_OR_RETURN(h, drift_mark(h));
   }
   {
     ProfScope ps(h, 3);
@@ -1154,6 +1237,7 @@ int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out) {
   out->graph_chunk = h->graph_chunk;
   out->rebin_mode = h->rebin_mode;
   out->tile = h->sim.tile;
+  out->rebin_drift = h->rebin_drift;
   return MPM_OK;
 }
 
@@ -1161,8 +1245,10 @@ int mpm_set_launch_config(mpm_handle* h, const mpm_launch_config* c) {
   if (!h) return MPM_EINVAL;
   if (!c || c->resort_interval < 1 || c->transfer_wgs < 8 || c->transfer_wgs % 8 != 0 || c->transfer_wgs > 65536 ||
       c->graph_chunk < 0 || c->graph_chunk > 256 || c->rebin_mode < MPM_REBIN_AUTO ||
-      c->rebin_mode > MPM_REBIN_IN_PLACE || !(c->tile == 0 || c->tile == 4 || c->tile == 8))
+      c->rebin_mode > MPM_REBIN_IN_PLACE || !(c->tile == 0 || c->tile == 4 || c->tile == 8) ||
+      c->rebin_drift < 0 || c->rebin_drift > 1000000)
     return fail(h, MPM_EINVAL, "mpm_set_launch_config: value out of range");
+  h->rebin_drift = c->rebin_drift;
   if (c->tile != 0) set_tile(h, c->tile);
   h->resort_interval = c->resort_interval;
   h->rebin_mode = c->rebin_mode;
@@ -1202,7 +1288,8 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   const int cur0 = b.cur;
   const int64_t substep0 = h->substep, since0 = h->since_sort, resorts0 = h->resorts;
   const bool dirty0 = h->dirty, prof0 = h->prof;
-  const mpm_launch_config orig = {h->resort_interval, h->transfer_wgs, h->graph_chunk, h->rebin_mode, h->sim.tile};
+  const mpm_launch_config orig = {h->resort_interval, h->transfer_wgs, h->graph_chunk, h->rebin_mode, h->sim.tile,
+                                   h->rebin_drift};
   e = hipMemcpyAsync(save_part, b.part[cur0], part_bytes, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save_id, b.id[cur0], sizeof(uint32_t) * b.cap, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(save_st, b.status, sizeof(Status), hipMemcpyDeviceToDevice, h->stream);
@@ -1256,7 +1343,8 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   constexpr float kKeep = 0.05f;
   auto same = [](const mpm_launch_config& a, const mpm_launch_config& c) {
     return a.resort_interval == c.resort_interval && a.transfer_wgs == c.transfer_wgs &&
-           a.graph_chunk == c.graph_chunk && a.rebin_mode == c.rebin_mode && a.tile == c.tile;
+           a.graph_chunk == c.graph_chunk && a.rebin_mode == c.rebin_mode && a.tile == c.tile &&
+           a.rebin_drift == c.rebin_drift;
   };
   // warm-up (records graphs) and timed call of configuration c
   auto trial = [&](const mpm_launch_config& c, float* ms) -> bool {
@@ -1278,7 +1366,8 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
     for (int ci = 0; ci < 2 && e == hipSuccess && rc == MPM_OK; ++ci)
       for (int ri = 0; ri < n_resorts && e == hipSuccess && rc == MPM_OK; ++ri) {
         const int wg_per_cu = per_cu[wi] * (tiles[ti] == 4 ? 4 : 1);
-        mpm_launch_config c = {resorts[ri], (wg_per_cu * h->cus + 7) / 8 * 8, chunks[ci], MPM_REBIN_AUTO, tiles[ti]};
+        mpm_launch_config c = {resorts[ri], (wg_per_cu * h->cus + 7) / 8 * 8, chunks[ci], MPM_REBIN_AUTO, tiles[ti],
+                               h->rebin_drift};
         rc = mpm_set_launch_config(h, &c);
         if (rc != MPM_OK) break;
         e = restore();
@@ -1324,6 +1413,9 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
   hipError_t e2 = restore();
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  // the trials' fallback counts and progress marks must not count later
+  if (e == hipSuccess) std::memset(h->b.drift_host, 0, 4 * sizeof(unsigned long long));
+  h->drift_n = 0;
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   release();

@@ -414,6 +414,7 @@ __global__ void k_compact(const uint32_t* __restrict__ mark_or_range_b,
 __global__ void k_reset_epoch(Status* st) {
   st->ovf_count[0] = 0u;
   st->ovf_count[1] = 0u;
+  st->fb_at_sort = st->n_fallback;
 }
 
 static unsigned grid_for(int64_t n, int wg) {

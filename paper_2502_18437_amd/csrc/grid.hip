@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
                                                   uint32_t* mark, uint32_t* __restrict__ node_cnt,
                                                   float* __restrict__ imp_blocks, const ToolDesc* __restrict__ tools,
                                                   Status* st, Clock* clk, int parity, int dsub, int record,
-                                                  SimK s) {
+                                                  unsigned long long* drift_host, SimK s) {
   const long long substep = clk[parity].substep;
   const uint32_t* __restrict__ ovf_list = parity ? ovf1 : ovf0;
   // Momentum given to the material by each tool and by the walls on the nodes
@@ -200,6 +200,15 @@ __global__ __launch_bounds__(kGridWG) void k_grid(void* __restrict__ acc_m, void
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->ovf_count[parity ^ 1] = 0u;
     clk[parity ^ 1].substep = substep + dsub;
+    // After a substep's last pass, the fallback count so far (the fused
+    // kernel before this one has added its own) for the host to read
+    // without waiting; the substep word goes last.
+    if (dsub && drift_host) {
+      __hip_atomic_store(&drift_host[1], st->n_fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&drift_host[2], st->fb_at_sort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&drift_host[0], (unsigned long long)(substep + dsub), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -217,7 +226,8 @@ void launch_grid(Buffers& b, const SimK& s, int max_act, int parity, hipStream_t
   if (!gravity) k.g[0] = k.g[1] = k.g[2] = 0.0f;
   hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
                      b.acc_p[2], b.vel, b.act_list, b.ovf_list[0], b.ovf_list[1], b.mark, b.node_cnt, b.imp_blocks,
-                     (const ToolDesc*)b.tools, b.status, b.clock, parity & 1, last ? 1 : 0, record ? 1 : 0, k);
+                     (const ToolDesc*)b.tools, b.status, b.clock, parity & 1, last ? 1 : 0, record ? 1 : 0,
+                     b.drift_host, k);
 }
 
 }  // namespace mpm

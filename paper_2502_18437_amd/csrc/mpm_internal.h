@@ -165,6 +165,7 @@ struct Status {
   unsigned int n_work;              // transfer work items (this binning)
   unsigned int n_act;               // active blocks (this binning)
   unsigned int ovf_count[2];        // overflow blocks claimed, per parity
+  unsigned long long fb_at_sort;    // n_fallback when the last binning ended
 };
 
 // Substep clock on the device, one entry per parity of the grid update
@@ -205,6 +206,11 @@ struct Buffers {
   float4* vel = nullptr;                    // grid velocity
   Status* status = nullptr;
   Clock* clock = nullptr;                   // two entries, by parity
+  // Pinned host words the grid update writes after a substep's last pass:
+  // {substep, n_fallback, fb_at_sort}, so that the host can see how many
+  // particles take the global path since the last binning without waiting
+  // on the stream (adaptive re-binning).
+  unsigned long long* drift_host = nullptr;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -232,6 +238,8 @@ void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, 
 // impulse sums.
 void launch_grid(Buffers& b, const SimK& s, int max_act, int parity, hipStream_t st, bool gravity = true,
                  bool record = true, bool last = true);
+// The grid update after a substep's last pass also mirrors {substep,
+// n_fallback, fb_at_sort} into Buffers::drift_host.
 // Set the clock entry of `parity` to `substep`.
 void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st);
 

@@ -68,7 +68,8 @@ class mpm_info(ctypes.Structure):
 
 class mpm_launch_config(ctypes.Structure):
     _fields_ = [("resort_interval", ctypes.c_int32), ("transfer_wgs", ctypes.c_int32),
-                ("graph_chunk", ctypes.c_int32), ("rebin_mode", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("graph_chunk", ctypes.c_int32), ("rebin_mode", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("rebin_drift", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -369,12 +370,13 @@ class Simulation:
         return c.as_dict()
 
     def set_launch_config(self, resort_interval=None, transfer_wgs=None, graph_chunk=None, rebin_mode=None,
-                          tile=None):
+                          tile=None, rebin_drift=None):
         """Replace the given fields of the launch configuration (MPM_REBIN_*
-        for rebin_mode; tile 4 or 8 cells); the others keep their values."""
+        for rebin_mode; tile 4 or 8 cells; rebin_drift in particles per
+        million per substep, 0 = off); the others keep their values."""
         cur = self.launch_config()
         given = {"resort_interval": resort_interval, "transfer_wgs": transfer_wgs, "graph_chunk": graph_chunk,
-                 "rebin_mode": rebin_mode, "tile": tile}
+                 "rebin_mode": rebin_mode, "tile": tile, "rebin_drift": rebin_drift}
         c = mpm_launch_config(**{k: int(v if v is not None else cur[k]) for k, v in given.items()})
         self._check(_lib.mpm_set_launch_config(self.h, ctypes.byref(c)))
 
@@ -418,8 +420,9 @@ def eval_stress(F, E, nu):
 def simulation_from_scene(scene, **kw):
     """Create a Simulation holding a scenes.Scene (particles and tools).
     Keywords are Simulation parameters (tile among them) or
-    launch-configuration fields (transfer_wgs, graph_chunk, rebin_mode)."""
-    launch = {k: kw.pop(k) for k in ("transfer_wgs", "graph_chunk", "rebin_mode") if k in kw}
+    launch-configuration fields (transfer_wgs, graph_chunk, rebin_mode,
+    rebin_drift)."""
+    launch = {k: kw.pop(k) for k in ("transfer_wgs", "graph_chunk", "rebin_mode", "rebin_drift") if k in kw}
     params = dict(n_grid=scene.n_grid, dt=scene.dt, gravity=scene.gravity, wall_band=scene.wall_band,
                   nu=scene.nu, E_default=scene.E_default, max_particles=max(1, scene.N))
     params.update(kw)

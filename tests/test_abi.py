@@ -50,7 +50,7 @@ int main(void) {
   printf("mpm_info SIZEOF %zu\n", sizeof(mpm_info));
   F(mpm_info, n_particles) F(mpm_info, n_fallback) F(mpm_info, n_range) F(mpm_info, tile) F(mpm_info, n_tools) F(mpm_info, rollouts)
   printf("mpm_launch_config SIZEOF %zu\n", sizeof(mpm_launch_config));
-  F(mpm_launch_config, resort_interval) F(mpm_launch_config, transfer_wgs) F(mpm_launch_config, graph_chunk) F(mpm_launch_config, rebin_mode) F(mpm_launch_config, tile)
+  F(mpm_launch_config, resort_interval) F(mpm_launch_config, transfer_wgs) F(mpm_launch_config, graph_chunk) F(mpm_launch_config, rebin_mode) F(mpm_launch_config, tile) F(mpm_launch_config, rebin_drift)
   printf("mpm_kernel_times SIZEOF %zu\n", sizeof(mpm_kernel_times));
   F(mpm_kernel_times, total_ms) F(mpm_kernel_times, launches)
   return 0;

@@ -58,7 +58,7 @@ def check_cores(s, g, k, cores, label):
 def test_c3_full_size_sampled():
     s = scenes.scene_c3()
     k = 10
-    g, info = run_full_gpu(s, k, resort_interval=4)
+    g, info = run_full_gpu(s, k, resort_interval=4, rebin_drift=0)
     assert info["resorts"] == 3
     top = 3 * s.dx + 0.2
     cores = [
@@ -96,9 +96,9 @@ def golden(name):
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_full_size_100_substeps_default_launch(name):
     """The whole scene for the 100-substep parity window in the library's
-    default launch configuration (re-binning every 32 substeps, the
-    re-binning mode chosen automatically, runs of substeps replayed as HIP
-    graphs), against the FP64 oracle's run of the same full scene on a
+    default launch configuration (re-binning every 32 substeps or earlier
+    when particles drift out of their tiles, the re-binning mode chosen
+    automatically, runs of substeps replayed as HIP graphs), against the FP64 oracle's run of the same full scene on a
     sample of particles (uniform, plus particles along each tool's path),
     with the tool impulses of the 100 substeps."""
     from paper_2502_18437_amd import mpm
@@ -107,6 +107,7 @@ def test_full_size_100_substeps_default_launch(name):
     sim = mpm.simulation_from_scene(s)
     cfg = sim.launch_config()
     assert cfg["resort_interval"] == 32 and cfg["rebin_mode"] == mpm.MPM_REBIN_AUTO and cfg["graph_chunk"] > 0
+    assert cfg["rebin_drift"] > 0 and cfg["tile"] == 8
     sim.step(k)
     r, st = sim.read_state()
     info = sim.info()
