@@ -338,18 +338,6 @@ int default_transfer_wgs(const mpm_handle* h, int tile) {
   return (per_cu * h->cus + 7) / 8 * 8;
 }
 
-// Use work tiles of edge `tile` (4 or 8) from the next binning on: the tile
-// ranges of the previous sort are in the other indexing, so new orders are
-// built as for new particles, and recorded graphs are dropped.
-void set_tile(mpm_handle* h, int tile) {
-  if (tile == h->sim.tile) return;
-  h->sim.tile = tile;
-  h->sim.unit_shift = tile == 4 ? 3 : 0;
-  h->dirty = true;
-  h->fresh_order = true;
-  drop_graphs(h);
-}
-
 // Particles per transfer work item: about N / (4 x workgroups), so that
 // even a scene of a few dense tiles gives every persistent workgroup several
 // items, as a power of two in [kItemMin, kItemMax] for 8-cell tiles and a
@@ -365,6 +353,19 @@ void choose_item_size(mpm_handle* h) {
     h->dirty = true;
     drop_graphs(h);
   }
+}
+
+// Use work tiles of edge `tile` (4 or 8) from the next binning on: the tile
+// ranges of the previous sort are in the other indexing, so new orders are
+// built as for new particles, and recorded graphs are dropped.
+void set_tile(mpm_handle* h, int tile) {
+  if (tile == h->sim.tile) return;
+  h->sim.tile = tile;
+  h->sim.unit_shift = tile == 4 ? 3 : 0;
+  h->dirty = true;
+  h->fresh_order = true;
+  drop_graphs(h);
+  choose_item_size(h);  // item sizes are bounded per tile edge
 }
 
 void free_buffers(Buffers& b) {

@@ -29,6 +29,7 @@
 // instantiation with the push-out after the position update runs instead. A
 // dense tile's work items deal their particles to a wave's lanes kWG / 64
 // apart (item_lane), so that one wave's atomics spread over different cells.
+
 #include "mpm_device.h"
 #include "mpm_internal.h"
 #include "p2g_fixed.h"
@@ -193,18 +194,25 @@ __device__ __forceinline__ void p2g_global(const SimK& s, const In& P, ACC_PARAM
     const int g = node_base + grid_index(P.base[0] + ox, P.base[1] + oy, P.base[2] + oz, s.nb);
     acc_add<FIXED>(s, ACC_ARGS, g, wq, p0, p1, p2);
   });
+  // The stencil spans one or two blocks per axis. All their marks are loaded
+  // before any is tested, so that the loads overlap instead of each waiting
+  // on the previous test.
   const int b0[3] = {P.base[0] >> kTileLog2, P.base[1] >> kTileLog2, P.base[2] >> kTileLog2};
   const int b1[3] = {(P.base[0] + 2) >> kTileLog2, (P.base[1] + 2) >> kTileLog2, (P.base[2] + 2) >> kTileLog2};
-  for (int bz = b0[2]; bz <= b1[2]; ++bz)
-    for (int by = b0[1]; by <= b1[1]; ++by)
-      for (int bx = b0[0]; bx <= b1[0]; ++bx) {
-        const unsigned b = (unsigned)scene * s.nb3 + (unsigned)((bz * s.nb + by) * s.nb + bx);
-        if (__hip_atomic_load(&mark[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) continue;
-        if (atomicCAS(&mark[b], 0u, 2u) == 0u) {
-          const unsigned slot = atomicAdd(&st->ovf_count[parity], 1u);
-          ovf[slot] = b;
-        }
-      }
+  unsigned blk[8], seen[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int bx = b0[0] + (k & 1), by = b0[1] + ((k >> 1) & 1), bz = b0[2] + (k >> 2);
+    const bool spans = bx <= b1[0] && by <= b1[1] && bz <= b1[2];
+    blk[k] = (unsigned)scene * s.nb3 + (unsigned)((bz * s.nb + by) * s.nb + bx);
+    seen[k] = spans ? __hip_atomic_load(&mark[blk[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 1u;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (seen[k] == 0u && atomicCAS(&mark[blk[k]], 0u, 2u) == 0u) {
+      const unsigned slot = atomicAdd(&st->ovf_count[parity], 1u);
+      ovf[slot] = blk[k];
+    }
 }
 
 // G2P sums of one particle, S = sum N v_I and T[a][b] = sum N v_I[a] o_b, with
@@ -296,14 +304,66 @@ __device__ __forceinline__ void g2p_global(const SimK& s, const int* base, const
 }
 
 // ------------------------------------------------------------------ per particle
-// The LDS tile of a work tile of edge T: (T + 2)^3 nodes.
+// The LDS tile of a work tile of edge T: (T + 2)^3 nodes, the span of the
+// stencils whose base cell lies in the tile. Scatters also have a shell one
+// node thick around the span: a particle whose base cell has moved at most
+// one cell out of the tile since the binning (base -1 .. T per axis) still
+// scatters into LDS instead of global memory. Such particles come in waves
+// (a layer of a lattice crossing a block boundary), and their global
+// atomics pile up on the same nodes.
 template <int T>
 struct Lds {
   static constexpr int kNodes = TileShape<T>::kSpanNodes;
+  static constexpr int kSpan = TileShape<T>::kSpan;
+  static constexpr int kOuter = kSpan + 2;
+  static constexpr int kShell = kOuter * kOuter * kOuter - kNodes;
   float4 v[kNodes];                             // staged grid velocity
   uint32_t m[kNodes];                           // weight sums (2^-22 units)
   long long p0[kNodes], p1[kNodes], p2[kNodes];  // momentum (fixed point)
+  uint32_t sm[kShell];                          // the shell's sums
+  long long sp0[kShell], sp1[kShell], sp2[kShell];
+  // A scatter into the shell copies item_tag (set per work item) into
+  // shell_mark, so the flush can tell whether this item used the shell.
+  uint32_t item_tag, shell_mark;
 };
+
+// Shell node index of tile node (x, y, z), each in [-1, kSpan], at least
+// one of them outside [0, kSpan): the two z faces (kOuter^2 nodes each),
+// then the two y faces without the z faces (kSpan x kOuter), then the two x
+// faces (kSpan^2).
+template <int T>
+__device__ __forceinline__ int shell_index(int x, int y, int z) {
+  constexpr int S = Lds<T>::kSpan, A = Lds<T>::kOuter;
+  if (z < 0) return (y + 1) * A + (x + 1);
+  if (z >= S) return A * A + (y + 1) * A + (x + 1);
+  if (y < 0) return 2 * A * A + z * A + (x + 1);
+  if (y >= S) return 2 * A * A + S * A + z * A + (x + 1);
+  if (x < 0) return 2 * A * A + 2 * S * A + z * S + y;
+  return 2 * A * A + 2 * S * A + S * S + z * S + y;
+}
+
+// Tile node (x, y, z) of shell node j (the inverse of shell_index).
+template <int T>
+__device__ __forceinline__ void shell_node(int j, int* x, int* y, int* z) {
+  constexpr int S = Lds<T>::kSpan, A = Lds<T>::kOuter;
+  if (j < 2 * A * A) {
+    *z = j < A * A ? -1 : S;
+    j %= A * A;
+    *y = j / A - 1;
+    *x = j % A - 1;
+  } else if ((j -= 2 * A * A) < 2 * S * A) {
+    *y = j < S * A ? -1 : S;
+    j %= S * A;
+    *z = j / A;
+    *x = j % A - 1;
+  } else {
+    j -= 2 * S * A;
+    *x = j < S * S ? -1 : S;
+    j %= S * S;
+    *z = j / S;
+    *y = j % S;
+  }
+}
 
 template <int T>
 __device__ __forceinline__ int lds_index(int lx, int ly, int lz) {
@@ -320,13 +380,45 @@ __device__ __forceinline__ bool in_tile(int l0, int l1, int l2) {
 
 // Commit one particle's scatter: into the LDS tile when its stencil lies in
 // the block's tile, else straight into the global accumulator.
-template <bool FIXED, int T, class In>
+template <bool FIXED, int T, bool SHELL, class In>
 __device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int* to, Lds<T>& L, ACC_PARAMS,
                                            uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   const int l0 = P.base[0] - to[0], l1 = P.base[1] - to[1], l2 = P.base[2] - to[2];
   if (!in_tile<T>(l0, l1, l2)) {
-    ev |= kEvFbP2G;
-    p2g_global<FIXED>(s, P, ACC_ARGS, mark, ovf, st, parity, to[3]);
+    constexpr unsigned kMarginMax = T + 1;  // base -1 .. T, shifted by one
+    if (!SHELL || (unsigned)(l0 + 1) > kMarginMax || (unsigned)(l1 + 1) > kMarginMax ||
+        (unsigned)(l2 + 1) > kMarginMax) {
+      ev |= kEvFbP2G;
+      p2g_global<FIXED>(s, P, ACC_ARGS, mark, ovf, st, parity, to[3]);
+      return;
+    }
+    // One cell out: the nodes in the span go to the tile, the others to the
+    // shell. (The PB-MPM and push-out variants leave this to the global path:
+    // the shell's code does not fit their registers at 4 waves per SIMD.)
+    constexpr int S = TileShape<T>::kSpan;
+    L.shell_mark = L.item_tag;
+    p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
+      const int x = l0 + ox, y = l1 + oy, z = l2 + oz;
+      uint32_t* m;
+      unsigned long long *a0, *a1, *a2;
+      if ((unsigned)x < (unsigned)S && (unsigned)y < (unsigned)S && (unsigned)z < (unsigned)S) {
+        const int idx = lds_index<T>(x, y, z);
+        m = &L.m[idx];
+        a0 = (unsigned long long*)&L.p0[idx];
+        a1 = (unsigned long long*)&L.p1[idx];
+        a2 = (unsigned long long*)&L.p2[idx];
+      } else {
+        const int j = shell_index<T>(x, y, z);
+        m = &L.sm[j];
+        a0 = (unsigned long long*)&L.sp0[j];
+        a1 = (unsigned long long*)&L.sp1[j];
+        a2 = (unsigned long long*)&L.sp2[j];
+      }
+      atomicAdd(m, wq);
+      atomicAdd(a0, (unsigned long long)p0);
+      atomicAdd(a1, (unsigned long long)p1);
+      atomicAdd(a2, (unsigned long long)p2);
+    });
     return;
   }
   const int l = lds_index<T>(l0, l1, l2);
@@ -347,7 +439,7 @@ __device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int
 //            on the first pass of a step v also receives dt g.
 // The PB-MPM iterations after the first count no errors (the first pass of
 // the step has counted them).
-template <bool FIXED, int SOL, int PASS, int T>
+template <bool FIXED, int SOL, int PASS, int T, bool SHELL>
 __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, const float* v, const float* C,
                                              const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
                                              uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
@@ -411,7 +503,7 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
 #pragma unroll
     for (int b = 0; b < 3; ++b) P.Adx[3 * a + b] = (double)(Af[3 * a + b] * s.dx) * s.fx_p;
   }
-  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+  p2g_commit<FIXED, T, SHELL>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
 }
 
 // P2G of one particle for standard MPM (Sec. III-A): mass N m and momentum
@@ -419,7 +511,7 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
 // Neo-Hookean stress (gravity is added by the grid update). C is not
 // transferred; it holds the velocity gradient and is only checked for being
 // finite.
-template <bool FIXED, int T>
+template <bool FIXED, int T, bool SHELL>
 __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, const float* v, const float* C,
                                                  const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
                                                  uint32_t* mark, uint32_t* ovf, Status* st, int parity,
@@ -464,7 +556,7 @@ __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, 
     return;
   }
   P.fx_p = s.fx_p;
-  p2g_commit<FIXED>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+  p2g_commit<FIXED, T, SHELL>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
 }
 
 // G2P of one particle (Algorithm 1, third loop). APIC (MLS-MPM, PB-MPM):
@@ -474,7 +566,7 @@ __device__ __forceinline__ void p2g_particle_pic(const SimK& s, const float* x, 
 // left unchanged).
 template <int SOL, int T>
 __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, const int* to,
-                                             const Lds<T>& L, const float4* vel, float* vn, float* Cn,
+                                             const float4* Lv, const float4* vel, float* vn, float* Cn,
                                              unsigned& ev) {
   int base[3];
   float f[3];
@@ -491,7 +583,7 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
     for (int a = 0; a < 3; ++a) bspline_dw(f[a], dw[a]);
     if (in_tile_) {
       const int l = lds_index<T>(l0, l1, l2);
-      g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) { return L.v[l + lds_index<T>(ox, oy, oz)]; }, S, Tm);
+      g2p_sums_pic(w, dw, [&](int ox, int oy, int oz) { return Lv[l + lds_index<T>(ox, oy, oz)]; }, S, Tm);
     } else {
       ev |= kEvFbG2P;
       const int node_base = to[3] * s.n3;
@@ -509,7 +601,7 @@ __device__ __forceinline__ bool g2p_particle(const SimK& s, const float* x, cons
     // Tm[a][b] = sum N v_a o_b
     if (in_tile_) {
       const int l = lds_index<T>(l0, l1, l2);
-      g2p_sums(w, [&](int ox, int oy, int oz) { return L.v[l + lds_index<T>(ox, oy, oz)]; }, S, Tm);
+      g2p_sums(w, [&](int ox, int oy, int oz) { return Lv[l + lds_index<T>(ox, oy, oz)]; }, S, Tm);
     } else {
       ev |= kEvFbG2P;
       g2p_global(s, base, w, vel, S, Tm, to[3]);
@@ -548,19 +640,62 @@ __device__ __forceinline__ void unit_origin(const SimK& s, unsigned u, int* to) 
   to[3] = (int)scene;
 }
 
+// Clears the span and the shell, and starts work item `tag` (nonzero, new
+// for each item of a workgroup); a barrier must follow.
 template <int T>
-__device__ __forceinline__ void tile_clear(Lds<T>& L) {
+__device__ __forceinline__ void tile_clear(Lds<T>& L, uint32_t tag) {
   for (int i = threadIdx.x; i < Lds<T>::kNodes; i += blockDim.x) {
     L.m[i] = 0u;
     L.p0[i] = 0ll;
     L.p1[i] = 0ll;
     L.p2[i] = 0ll;
   }
+  for (int j = threadIdx.x; j < Lds<T>::kShell; j += blockDim.x) {
+    L.sm[j] = 0u;
+    L.sp0[j] = 0ll;
+    L.sp1[j] = 0ll;
+    L.sp2[j] = 0ll;
+  }
+  if (threadIdx.x == 0) {
+    L.item_tag = tag;
+    L.shell_mark = 0u;
+  }
+}
+
+// The shell's non-empty nodes -> global accumulator, if work item `tag`
+// scattered into it, clearing them on the way. A shell node one cell below
+// the tile can lie in a block that the binning did not activate: it is
+// claimed for the grid update as the global path does.
+template <bool FIXED, int T>
+__device__ __forceinline__ void shell_flush_clear(const SimK& s, const int* to, Lds<T>& L, ACC_PARAMS, uint32_t tag,
+                                                  uint32_t* mark, uint32_t* ovf, Status* st, int parity) {
+  if (L.shell_mark != tag) return;  // the same in every thread: no scatter of this item reached the shell
+  for (int j = threadIdx.x; j < Lds<T>::kShell; j += blockDim.x) {
+    const uint32_t wq = L.sm[j];
+    const long long p0 = L.sp0[j], p1 = L.sp1[j], p2 = L.sp2[j];
+    if ((wq | p0 | p1 | p2) == 0) continue;
+    L.sm[j] = 0u;
+    L.sp0[j] = 0ll;
+    L.sp1[j] = 0ll;
+    L.sp2[j] = 0ll;
+    int x, y, z;
+    shell_node<T>(j, &x, &y, &z);
+    const int gx = to[0] + x, gy = to[1] + y, gz = to[2] + z;
+    if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
+    acc_add<FIXED>(s, ACC_ARGS, to[3] * s.n3 + grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2);
+    const unsigned b = (unsigned)to[3] * s.nb3 +
+                       (unsigned)((((gz >> kTileLog2) * s.nb) + (gy >> kTileLog2)) * s.nb + (gx >> kTileLog2));
+    if (__hip_atomic_load(&mark[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+        atomicCAS(&mark[b], 0u, 2u) == 0u) {
+      const unsigned slot = atomicAdd(&st->ovf_count[parity], 1u);
+      ovf[slot] = b;
+    }
+  }
 }
 
 template <int T>
 __device__ __forceinline__ void tile_stage_velocity(const SimK& s, const int* to, const float4* vel,
-                                                    Lds<T>& L) {
+                                                    float4* Lv) {
   constexpr int S = TileShape<T>::kSpan;
   for (int i = threadIdx.x; i < Lds<T>::kNodes; i += blockDim.x) {
     const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
@@ -568,7 +703,37 @@ __device__ __forceinline__ void tile_stage_velocity(const SimK& s, const int* to
     float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if ((unsigned)gx < (unsigned)s.n && (unsigned)gy < (unsigned)s.n && (unsigned)gz < (unsigned)s.n)
       val = vel[to[3] * s.n3 + grid_index(gx, gy, gz, s.nb)];
-    L.v[i] = val;
+    Lv[i] = val;
+  }
+}
+
+// Hides a value from the optimiser, so that index arithmetic that only
+// depends on the thread is recomputed where it is used instead of being
+// hoisted out of the work-item loop and held in registers across it.
+__device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
+
+// Non-empty tile nodes -> global accumulator, clearing the tile for the next
+// work item on the way (each thread clears the nodes it flushed).
+template <bool FIXED, int T>
+__device__ __forceinline__ void tile_flush_clear(const SimK& s, const int* to, Lds<T>& L, ACC_PARAMS) {
+  constexpr int S = TileShape<T>::kSpan;
+  constexpr int kSlots = (Lds<T>::kNodes + TileShape<T>::kWG - 1) / TileShape<T>::kWG;
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    int i = threadIdx.x + k * TileShape<T>::kWG;
+    if (i >= Lds<T>::kNodes) break;
+    opaque(i);
+    const uint32_t wq = L.m[i];
+    const long long p0 = L.p0[i], p1 = L.p1[i], p2 = L.p2[i];
+    L.m[i] = 0u;
+    L.p0[i] = 0ll;
+    L.p1[i] = 0ll;
+    L.p2[i] = 0ll;
+    if ((wq | p0 | p1 | p2) == 0) continue;
+    const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
+    const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
+    if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
+    acc_add<FIXED>(s, ACC_ARGS, to[3] * s.n3 + grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2);
   }
 }
 
@@ -595,15 +760,16 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 }
 
 // ------------------------------------------------------------------ kernels
-// Scatter of one particle by the solver's rule.
-template <bool FIXED, int SOL, int PASS, int T>
+// Scatter of one particle by the solver's rule (SHELL: one-cell-out
+// particles scatter into the tile's shell).
+template <bool FIXED, int SOL, int PASS, int T, bool SHELL = true>
 __device__ __forceinline__ void p2g_any(const SimK& s, const float* x, const float* v, const float* C,
                                         const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
                                         uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
   if constexpr (SOL == SOLVER_PIC)
-    p2g_particle_pic<FIXED, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+    p2g_particle_pic<FIXED, T, SHELL>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
   else
-    p2g_particle<FIXED, SOL, PASS, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+    p2g_particle<FIXED, SOL, PASS, T, SHELL>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
 }
 
 // P2G from the materialised particle state (first substep after binning; for
@@ -625,7 +791,7 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __res
     const unsigned q = item_lane<T>(item.x);
     int to[4];
     unit_origin<T>(s, b, to);
-    tile_clear(L);
+    tile_clear(L, pos + 1u);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
     for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
@@ -647,6 +813,7 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __res
     }
     __syncthreads();
     tile_flush<FIXED, T>(s, to, L, ACC_ARGS);
+    shell_flush_clear<FIXED, T>(s, to, L, ACC_ARGS, pos + 1u, mark, ovf, st, parity);
     __syncthreads();
   }
   flush_counters(st, cnt);
@@ -669,22 +836,35 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
                                                const ToolDesc* __restrict__ tools, SimK s) {
   constexpr bool kIntegrate = !(SOL == SOLVER_PB && PASS == PB_ITER);
   static_assert(!PUSH || kIntegrate, "push-out follows a position update");
+  constexpr bool kShell = SOL != SOLVER_PB && !PUSH;
   long long substep = 0;
   if constexpr (PUSH) substep = clk[parity].substep;
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds<T> L;
+  __shared__ float4 Vb[Lds<T>::kNodes];  // second velocity buffer
   Counters cnt;
   unsigned pos, end, stride;
   xcd_walk(st->n_work, &pos, &end, &stride);
-  for (; pos < end; pos += stride) {
-    const uint2 item = work[pos];
+  uint2 item = make_uint2(0u, 0u);
+  bool flip = false;  // which of the two velocity buffers holds this item's tile
+  if (pos < end) {
+    item = work[pos];
+    int to[4];
+    unit_origin<T>(s, item.x & ~kDenseFlag, to);
+    tile_stage_velocity<T>(s, to, vel, L.v);
+    tile_clear(L, pos + 1u);
+    __syncthreads();
+  }
+  // Each pass: the particles of one work item, after which each thread
+  // stages its share of the next item's velocities into the other buffer
+  // (nothing reads it during this item); then, after one barrier, the flush
+  // of the tile and its shell, which also clears them.
+  while (pos < end) {
+    const float4* Lv = flip ? Vb : L.v;
     const unsigned b = item.x & ~kDenseFlag;
     const unsigned q = item_lane<T>(item.x);
     int to[4];
     unit_origin<T>(s, b, to);
-    tile_stage_velocity(s, to, vel, L);
-    tile_clear(L);
-    __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
     for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
       float x[3], F[9];
@@ -694,7 +874,7 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
       unsigned ev = 0u;
-      if (!g2p_particle<SOL, T>(s, x, to, L, vel, vn, Cn, ev)) continue;  // frozen (out of grid), no events
+      if (!g2p_particle<SOL, T>(s, x, to, Lv, vel, vn, Cn, ev)) continue;  // frozen (out of grid), no events
       if constexpr (kIntegrate) {
         float Fn[9];
 #pragma unroll
@@ -711,7 +891,7 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
 #pragma unroll
         for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
         const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
-        p2g_any<FIXED, SOL, PASS, T>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+        p2g_any<FIXED, SOL, PASS, T, kShell>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
         // An update that moved the particle out of the grid (or left its
         // state not finite) is its last: the particle is left unchanged from
         // then on, so its v and C of this update are kept in memory with it.
@@ -722,13 +902,27 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
           for (int i = 0; i < 9; ++i) part[(FC + i) * cap + p] = Cn[i];
         }
       } else {
-        p2g_any<FIXED, SOL, PASS, T>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+        p2g_any<FIXED, SOL, PASS, T, kShell>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
       }
       count_events(cnt, ev);
     }
-    __syncthreads();
-    tile_flush<FIXED, T>(s, to, L, ACC_ARGS);
-    __syncthreads();
+    const unsigned npos = pos + stride;
+    const bool more = npos < end;  // the same for the whole workgroup
+    uint2 nitem = item;
+    if (more) {
+      nitem = work[npos];
+      int nto[4];
+      unit_origin<T>(s, nitem.x & ~kDenseFlag, nto);
+      tile_stage_velocity<T>(s, nto, vel, flip ? L.v : Vb);
+    }
+    __syncthreads();  // every P2G atomic into this tile is done; the next velocities are staged
+    tile_flush_clear<FIXED, T>(s, to, L, ACC_ARGS);
+    shell_flush_clear<FIXED, T>(s, to, L, ACC_ARGS, pos + 1u, mark, ovf, st, parity);
+    if (threadIdx.x == 0) L.item_tag = npos + 1u;  // nothing reads it before the next barrier
+    pos = npos;
+    item = nitem;
+    flip = !flip;
+    if (more) __syncthreads();  // the tile is cleared
   }
   flush_counters(st, cnt);
 }
@@ -753,7 +947,7 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p(float* __restrict_
     const unsigned q = item_lane<T>(item.x);
     int to[4];
     unit_origin<T>(s, b, to);
-    tile_stage_velocity(s, to, vel, L);
+    tile_stage_velocity<T>(s, to, vel, L.v);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
     for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
@@ -764,7 +958,7 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p(float* __restrict_
       for (int i = 0; i < 9; ++i) F[i] = part[(FF + i) * cap + p];
       float vn[3], Cn[9];
       unsigned ev = 0u;
-      if (!g2p_particle<SOL, T>(s, x, to, L, vel, vn, Cn, ev)) continue;  // no events
+      if (!g2p_particle<SOL, T>(s, x, to, L.v, vel, vn, Cn, ev)) continue;  // no events
       count_events(cnt, ev);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
