@@ -14,6 +14,9 @@ Also reported on the same JSON line:
   HIP events on the library's stream during the timed steps; `traffic` is
   the kernel's HBM bytes per launch from hardware counters
   (profiles/k_g2p2g_<scene>_counters.md), null once its sources changed;
+  `atomics` is its TCC atomic requests per launch (from
+  profiles/k_g2p2g_<scene>_atomics.md) over the same live launch time,
+  against the measured request rate of coalesced FP32 atomics;
 * substep_roofline: the whole substep against the HBM byte model
   N x 100 B + N_act x 72 B;
 * cpu_baseline: the FP64 oracle timed on the host for a bounded sample of
@@ -58,28 +61,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def counted_traffic(scene_name):
-    """HBM bytes per launch of the fused kernel from the committed counter
-    summary, or None when there is none for this workload or the kernel's
-    sources changed since the counters were taken."""
+def profile_fields(name, keys):
+    """Machine-readable fields of a committed counter summary under
+    profiles/, or None when it is missing or the kernel's sources changed
+    since the counters were taken (the summary records their SHA-256)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_g2p2g_{scene_name}_counters.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
+    want = set(keys) | {"kernel_source_sha256", "kernel_sources"}
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256",
-                                                     "kernel_sources"):
+        if ":" in line and line.split(":", 1)[0] in want:
             k, v = line.split(":", 1)
             fields[k] = v.strip()
-    if len(fields) != 3:
+    if set(fields) != want:
         return None
     h = hashlib.sha256()
     for f in fields["kernel_sources"].split():
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != fields["kernel_source_sha256"]:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return {k: float(fields[k]) for k in keys}
+
+
+def counted_traffic(scene_name):
+    """HBM bytes per launch of the fused kernel (FETCH_SIZE + WRITE_SIZE,
+    calibrated by a copy of known size), or None."""
+    f = profile_fields(f"k_g2p2g_{scene_name}_counters.md", ["traffic_bytes_per_launch"])
+    return None if f is None else f["traffic_bytes_per_launch"]
+
+
+def counted_atomics(scene_name, avg_s):
+    """Global atomic requests of the fused kernel (TCC_ATOMIC per launch)
+    over its live launch time, against the measured request rate of
+    coalesced FP32 atomics, or None."""
+    f = profile_fields(f"k_g2p2g_{scene_name}_atomics.md",
+                       ["atomic_requests_per_launch", "atomic_request_peak_per_s"])
+    if f is None:
+        return None
+    rate = f["atomic_requests_per_launch"] / avg_s
+    return {"requests_per_launch": f["atomic_requests_per_launch"], "achieved_per_s": rate,
+            "peak_per_s": f["atomic_request_peak_per_s"], "frac": rate / f["atomic_request_peak_per_s"],
+            "unit": "TCC atomic requests/s"}
 
 
 def host_cpu():
@@ -407,7 +431,8 @@ def main():
         achieved = bytes_launch / avg_s / 1e9
         out["roofline"] = {"kernel": "k_g2p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(s.name),
-                           "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n}
+                           "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n,
+                           "atomics": counted_atomics(s.name, avg_s)}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}
     if not args.no_batch:
