@@ -35,7 +35,12 @@ using namespace mpm;
 
 namespace {
 
-constexpr int kDefaultResort = 32;
+// Re-binning interval when mpm_params gives none. Adaptive re-binning (below)
+// re-bins earlier where particles drift out of their tiles, and particles
+// one cell out still scatter into their tile's shell, so the interval is a
+// backstop: on c3, 128 against 32 saves more in binning (about 7 us per
+// substep) than the extra particles on the global path cost (about 4).
+constexpr int kDefaultResort = 128;
 // Adaptive re-binning: re-bin before the interval ends once the particles on
 // the global path (outside their tiles) average more than this many per
 // million per substep since the last binning. Such a particle costs about 25
@@ -160,6 +165,10 @@ struct mpm_handle {
   int64_t drift_sub[kDriftEvents] = {};
   int drift_head = 0, drift_n = 0;
   hipStream_t cap_stream = nullptr;
+  // The rollout backward recomputes the next segment on rec_stream while
+  // the adjoint of the current one runs on `stream`.
+  hipStream_t rec_stream = nullptr;
+  std::vector<hipEvent_t> seg_ev;  // two events per segment: recomputed, differentiated
   hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
@@ -747,6 +756,8 @@ int mpm_destroy(mpm_handle* h) {
     if (e) (void)hipEventDestroy(e);
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->rec_stream) (void)hipStreamDestroy(h->rec_stream);
+  for (auto e : h->seg_ev) (void)hipEventDestroy(e);
   free_buffers(h->b);
   free_diff(h->d);
   for (double* t : h->tool_tables)
@@ -1511,9 +1522,18 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
   const int T = d.T, K = d.K;
   const int64_t SF = (int64_t)kStateFloats * N;
   const int64_t nn = (int64_t)h->p.n_grid * h->p.n_grid * h->p.n_grid;
+  const int nseg = d.grids_kept ? 0 : (T + K - 1) / K;
   if (!d.grids_kept) {
-    ALLOC_OR_RETURN(h, ensure(&d.seg, &d.seg_slots, (int64_t)K, sizeof(float) * SF));
-    ALLOC_OR_RETURN(h, ensure(&d.grids, &d.grid_slots, (int64_t)K, sizeof(float4) * 2 * nn));
+    // two sets of segment states and grids: the segment being differentiated
+    // and the one being recomputed
+    ALLOC_OR_RETURN(h, ensure(&d.seg, &d.seg_slots, 2 * (int64_t)K, sizeof(float) * SF));
+    ALLOC_OR_RETURN(h, ensure(&d.grids, &d.grid_slots, 2 * (int64_t)K, sizeof(float4) * 2 * nn));
+    if (!h->rec_stream) HIP_OR_RETURN(h, hipStreamCreateWithFlags(&h->rec_stream, hipStreamNonBlocking));
+    while ((int)h->seg_ev.size() < 2 * nseg + 1) {
+      hipEvent_t e;
+      HIP_OR_RETURN(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      h->seg_ev.push_back(e);
+    }
   }
   // per substep: kToolRedCopies partial sums, then (after them, for all
   // substeps) the totals
@@ -1550,31 +1570,46 @@ int mpm_rollout_backward(mpm_handle* h, const float* xb, const float* vb, const 
                           j + 1 < T ? &next : nullptr, h->stream);
     }
   } else {
+    // Segments from the last: each is recomputed from its checkpoint (the
+    // states and grids of its substeps kept in slot set a & 1), then
+    // differentiated. The recomputation of segment a - 1 runs on rec_stream
+    // while segment a is differentiated on the main stream: they share no
+    // buffer (the forward substep uses the P2G accumulator and the skip
+    // flags, the adjoint the cotangent grids), and a slot set is refilled
+    // only after the adjoint of the segment that used it is done.
     const DState none = {nullptr, nullptr, nullptr, nullptr};
-    const int nseg = (T + K - 1) / K;
+    hipEvent_t start = h->seg_ev[2 * nseg];
+    HIP_OR_RETURN(h, hipEventRecord(start, h->stream));  // seeds, fills and the forward pass are enqueued
+    HIP_OR_RETURN(h, hipStreamWaitEvent(h->rec_stream, start, 0));
     for (int a = nseg - 1; a >= 0; --a) {
       const int s0 = a * K;
       const int n_in = (T - s0) < K ? (T - s0) : K;
+      const int64_t set = (int64_t)(a & 1) * K;
       auto st = [&](int i) -> DState {
-        return i == 0 ? dstate(d.ckpt + (int64_t)a * SF, N) : dstate(d.seg + (int64_t)i * SF, N);
+        return i == 0 ? dstate(d.ckpt + (int64_t)a * SF, N) : dstate(d.seg + (set + i) * SF, N);
       };
+      hipEvent_t recomputed = h->seg_ev[2 * a], differentiated = h->seg_ev[2 * a + 1];
+      if (a + 2 < nseg) HIP_OR_RETURN(h, hipStreamWaitEvent(h->rec_stream, h->seg_ev[2 * (a + 2) + 1], 0));
       // Recompute the segment from its checkpoint, keeping states and grids.
       // (A segment lies inside one order period.)
-      order_for(s0);
+      const DiffOrder seg_ord = order_slot(h, s0 / R);
       for (int i = 0; i < n_in; ++i) {
-        float4* vel = grid_of(i);
+        float4* vel = grid_of((int)set + i);
         launch_diff_substep(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + s0 + i), N, st(i), d.E,
-                            i + 1 < n_in ? st(i + 1) : none, false, h->b.status, ord, h->stream);
+                            i + 1 < n_in ? st(i + 1) : none, false, h->b.status, seg_ord, h->rec_stream);
       }
+      HIP_OR_RETURN(h, hipEventRecord(recomputed, h->rec_stream));
+      HIP_OR_RETURN(h, hipStreamWaitEvent(h->stream, recomputed, 0));
       for (int i = n_in - 1; i >= 0; --i) {
         const int j = s0 + i;
-        float4* vel = grid_of(i);
+        float4* vel = grid_of((int)set + i);
         // the state after substep j: the next segment's checkpoint at the end
         const DState next = i + 1 < n_in ? st(i + 1) : dstate(d.ckpt + (int64_t)(a + 1) * SF, N);
         launch_adjoint_head(d.g, vel, vel + nn, h->sim, tools_at(h, d.start + j), N, st(i), d.E, adj, theta_bar,
-                            d.tool_red + (int64_t)j * red_row * kToolRedCopies, ord, j + 1 < T ? &next : nullptr,
-                            h->stream);
+                            d.tool_red + (int64_t)j * red_row * kToolRedCopies, seg_ord,
+                            j + 1 < T ? &next : nullptr, h->stream);
       }
+      HIP_OR_RETURN(h, hipEventRecord(differentiated, h->stream));
     }
   }
   if (T > 0) launch_adjoint_tail(d.g, h->sim, N, dstate(d.ckpt, N), d.E, adj, theta_bar, h->stream);

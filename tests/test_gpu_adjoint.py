@@ -256,7 +256,8 @@ def test_c5_full_size_gradient_matches_oracle():
     assert T == 200 and s.vel_tables[0].shape == (T, 3)
     seeds = seeds_for(s, 4)
     state, g = gpu_rollout(s, T, 20, seeds)
-    assert state["status"] == 0
+    bad = np.flatnonzero(~np.isfinite(state["x"]).all(1))
+    assert state["status"] == 0, (state["status"], bad.size, bad[:8].tolist())
     o, r = oracle_gradient(s, T, seeds)
     assert_parity(state, r, s.x, T, "c5 forward")
     compare_grads(g, o, "c5")
