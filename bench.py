@@ -322,6 +322,8 @@ def main():
                     help="comma-separated particle counts for --solver-sweep (default: 2^14 .. 2^22)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the solver sweep (for profiling its kernels) and print its JSON")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="run only the c5 fwd+bwd leg (checkpoints every 20) and print its JSON (for profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 256-scene batch (for profiling its kernels) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -345,6 +347,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batch": batch_throughput(args.diff_steps)}), flush=True)
+        return
+    if args.fwd_bwd_only:
+        print(json.dumps({"fwd_bwd": fwd_bwd(args.diff_steps, checkpoint_every=20)}), flush=True)
         return
     s = scenes.make(args.scene)
     n_sub = args.substeps or s.n_substeps

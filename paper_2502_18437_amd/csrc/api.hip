@@ -409,6 +409,7 @@ __global__ void k_reset_status(Status* st) {
   st->ovf_count[0] = 0u;
   st->ovf_count[1] = 0u;
   st->fb_at_sort = 0ull;
+  for (int i = 0; i < kXcds; ++i) st->claim[i] = st->claim_done[i] = 0u;
 }
 
 __global__ void k_zero_u32(uint32_t* p, int64_t n) {

@@ -155,6 +155,10 @@ enum Solver { SOLVER_MLS = 0, SOLVER_PIC = 1, SOLVER_PB = 2 };
 enum PBPass { PB_FIRST = 0, PB_ITER = 1 };
 
 // Device status word (one per handle).
+// XCDs of the chip. Workgroups of a launch are dealt round-robin to them, so
+// workgroup w runs on XCD w % kXcds, each with its own L2.
+constexpr int kXcds = 8;
+
 struct Status {
   unsigned long long n_inverted;
   unsigned long long n_domain;
@@ -166,6 +170,11 @@ struct Status {
   unsigned int n_act;               // active blocks (this binning)
   unsigned int ovf_count[2];        // overflow blocks claimed, per parity
   unsigned long long fb_at_sort;    // n_fallback when the last binning ended
+  // Work items claimed beyond the first one per workgroup, and workgroups
+  // done, per XCD, in the persistent transfer kernels. Zero between launches:
+  // the last workgroup of an XCD to finish puts both back to zero.
+  unsigned int claim[kXcds];
+  unsigned int claim_done[kXcds];
 };
 
 // Substep clock on the device, one entry per parity of the grid update

@@ -36,22 +36,37 @@
 
 namespace mpm {
 
-constexpr int kXcds = 8;
-
-// Walk of a block list by a persistent grid whose size is a multiple of 8.
-// Workgroups are dealt round-robin to the 8 XCDs, so workgroup w runs on XCD
-// w % 8; each XCD takes one contiguous eighth of the spatially ordered list,
-// so blocks that share halo nodes share an L2.
-__device__ __forceinline__ void xcd_walk(unsigned n_items, unsigned* pos, unsigned* end,
-                                         unsigned* stride) {
-  const unsigned per = gridDim.x / kXcds;
-  const unsigned xcd = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
-  const unsigned chunk = (n_items + kXcds - 1) / kXcds;
-  const unsigned s = xcd * chunk;
-  *pos = s + slot;
-  *end = min(s + chunk, n_items);
-  *stride = per;
-}
+// Work distribution of the persistent transfer kernels (a grid size that is
+// a multiple of kXcds). XCD x owns the x-th contiguous eighth of the
+// spatially ordered work list, so tiles that share halo nodes share an L2.
+// Workgroup w starts at item w / kXcds of its XCD's range; after that, the
+// XCD's workgroups claim the range's next unclaimed item from a counter, so
+// a workgroup that drew items of sparse tiles (tens of particles against up
+// to a few thousand in a dense one) takes more of them. Thread 0 claims and
+// hands the item to its workgroup through LDS; every workgroup calls finish
+// once, after its last claim.
+struct WorkWalk {
+  unsigned begin, end, xcd, per;
+  __device__ __forceinline__ explicit WorkWalk(unsigned n_items) {
+    per = gridDim.x / kXcds;
+    xcd = blockIdx.x % kXcds;
+    const unsigned chunk = (n_items + kXcds - 1) / kXcds;
+    begin = min(xcd * chunk, n_items);
+    end = min(begin + chunk, n_items);
+  }
+  __device__ __forceinline__ unsigned first() const { return begin + blockIdx.x / kXcds; }
+  __device__ __forceinline__ unsigned claim(Status* st) const {
+    return begin + per + atomicAdd(&st->claim[xcd], 1u);
+  }
+  // The last workgroup of the XCD to finish puts the counters back to zero
+  // for the next launch (all claims of the others are done by then).
+  __device__ __forceinline__ void finish(Status* st) const {
+    if (atomicAdd(&st->claim_done[xcd], 1u) == per - 1u) {
+      atomicExch(&st->claim[xcd], 0u);
+      atomicExch(&st->claim_done[xcd], 0u);
+    }
+  }
+};
 
 // This thread's position in each run of kWG particles of a work item: its
 // own index, or for a dense tile's items (kDenseFlag) lane l of wave w takes
@@ -325,6 +340,7 @@ struct Lds {
   // A scatter into the shell copies item_tag (set per work item) into
   // shell_mark, so the flush can tell whether this item used the shell.
   uint32_t item_tag, shell_mark;
+  uint32_t claimed[2];  // work items claimed by thread 0 (WorkWalk)
 };
 
 // Shell node index of tile node (x, y, z), each in [-1, kSpan], at least
@@ -783,14 +799,16 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __res
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds<T> L;
   Counters cnt;
-  unsigned pos, end, stride;
-  xcd_walk(st->n_work, &pos, &end, &stride);
-  for (; pos < end; pos += stride) {
+  const WorkWalk walk(st->n_work);
+  unsigned pos = walk.first();
+  while (pos < walk.end) {
     const uint2 item = work[pos];
     const unsigned b = item.x & ~kDenseFlag;
     const unsigned q = item_lane<T>(item.x);
     int to[4];
     unit_origin<T>(s, b, to);
+    unsigned next = 0u;
+    if (threadIdx.x == 0) next = walk.claim(st);
     tile_clear(L, pos + 1u);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
@@ -811,11 +829,15 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __res
       p2g_any<FIXED, SOL, PB_FIRST, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
       count_events(cnt, ev);
     }
+    if (threadIdx.x == 0) L.claimed[1] = next;
     __syncthreads();
+    next = L.claimed[1];
     tile_flush<FIXED, T>(s, to, L, ACC_ARGS);
     shell_flush_clear<FIXED, T>(s, to, L, ACC_ARGS, pos + 1u, mark, ovf, st, parity);
     __syncthreads();
+    pos = next;
   }
+  if (threadIdx.x == 0) walk.finish(st);
   flush_counters(st, cnt);
 }
 
@@ -843,23 +865,25 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
   __shared__ Lds<T> L;
   __shared__ float4 Vb[Lds<T>::kNodes];  // second velocity buffer
   Counters cnt;
-  unsigned pos, end, stride;
-  xcd_walk(st->n_work, &pos, &end, &stride);
+  const WorkWalk walk(st->n_work);
+  unsigned pos = walk.first(), npos = walk.end;
   uint2 item = make_uint2(0u, 0u);
   bool flip = false;  // which of the two velocity buffers holds this item's tile
-  if (pos < end) {
+  if (pos < walk.end) {
+    if (threadIdx.x == 0) L.claimed[0] = walk.claim(st);
     item = work[pos];
     int to[4];
     unit_origin<T>(s, item.x & ~kDenseFlag, to);
     tile_stage_velocity<T>(s, to, vel, L.v);
     tile_clear(L, pos + 1u);
     __syncthreads();
+    npos = L.claimed[0];
   }
   // Each pass: the particles of one work item, after which each thread
   // stages its share of the next item's velocities into the other buffer
   // (nothing reads it during this item); then, after one barrier, the flush
   // of the tile and its shell, which also clears them.
-  while (pos < end) {
+  while (pos < walk.end) {
     const float4* Lv = flip ? Vb : L.v;
     const unsigned b = item.x & ~kDenseFlag;
     const unsigned q = item_lane<T>(item.x);
@@ -906,24 +930,29 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
       }
       count_events(cnt, ev);
     }
-    const unsigned npos = pos + stride;
-    const bool more = npos < end;  // the same for the whole workgroup
+    const bool more = npos < walk.end;  // the same for the whole workgroup
     uint2 nitem = item;
+    unsigned claim = 0u;
     if (more) {
+      if (threadIdx.x == 0) claim = walk.claim(st);  // the item after the next one
       nitem = work[npos];
       int nto[4];
       unit_origin<T>(s, nitem.x & ~kDenseFlag, nto);
       tile_stage_velocity<T>(s, nto, vel, flip ? L.v : Vb);
+      if (threadIdx.x == 0) L.claimed[1] = claim;
     }
     __syncthreads();  // every P2G atomic into this tile is done; the next velocities are staged
+    const unsigned nnpos = more ? L.claimed[1] : walk.end;
     tile_flush_clear<FIXED, T>(s, to, L, ACC_ARGS);
     shell_flush_clear<FIXED, T>(s, to, L, ACC_ARGS, pos + 1u, mark, ovf, st, parity);
     if (threadIdx.x == 0) L.item_tag = npos + 1u;  // nothing reads it before the next barrier
     pos = npos;
+    npos = nnpos;
     item = nitem;
     flip = !flip;
-    if (more) __syncthreads();  // the tile is cleared
+    if (more) __syncthreads();  // the tile is cleared; L.claimed[1] is read
   }
+  if (threadIdx.x == 0) walk.finish(st);
   flush_counters(st, cnt);
 }
 
@@ -939,14 +968,16 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p(float* __restrict_
   long long substep = 0;
   if constexpr (PUSH) substep = clk[parity].substep;
   Counters cnt;
-  unsigned pos, end, stride;
-  xcd_walk(st->n_work, &pos, &end, &stride);
-  for (; pos < end; pos += stride) {
+  const WorkWalk walk(st->n_work);
+  unsigned pos = walk.first();
+  while (pos < walk.end) {
     const uint2 item = work[pos];
     const unsigned b = item.x & ~kDenseFlag;
     const unsigned q = item_lane<T>(item.x);
     int to[4];
     unit_origin<T>(s, b, to);
+    unsigned next = 0u;
+    if (threadIdx.x == 0) next = walk.claim(st);
     tile_stage_velocity<T>(s, to, vel, L.v);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
@@ -978,8 +1009,11 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p(float* __restrict_
 #pragma unroll
       for (int i = 0; i < 9; ++i) part[(FC + i) * cap + p] = Cn[i];
     }
+    if (threadIdx.x == 0) L.claimed[1] = next;
     __syncthreads();
+    pos = L.claimed[1];
   }
+  if (threadIdx.x == 0) walk.finish(st);
   flush_counters(st, cnt);
 }
 
