@@ -72,12 +72,19 @@ extern "C" {
 #define MPM_MAX_TOOLS 8
 
 /* Grid accumulation mode of the P2G scatter. Each particle's contributions
- * are rounded to fixed point (weights in units of 2^-22, momentum in units
- * of 2^-40 of the particle mass times 1 m/s) and summed exactly per block in
- * LDS; the modes differ in the global sum over blocks. */
-#define MPM_ACCUM_F32 0   /* block sums added with FP32 atomics: fastest; the
-                             summation order of the FP32 adds varies */
-#define MPM_ACCUM_FIXED 1 /* block sums added with integer atomics: results
+ * are rounded to fixed point (weights in units of 2^-22) and summed exactly
+ * per block in LDS; the modes differ in the momentum units and in the global
+ * sum over blocks. */
+#define MPM_ACCUM_F32 0   /* momentum in 32-bit fields at a power-of-two unit
+                             chosen per work item from the bound of its
+                             particles' contributions (MLS-MPM; the other
+                             solvers and push-out use the units of
+                             MPM_ACCUM_FIXED), block sums added with FP32
+                             atomics: fastest; the summation order of the
+                             FP32 adds varies */
+#define MPM_ACCUM_FIXED 1 /* momentum in 64-bit fields in units of 2^-40 of
+                             the particle mass times 1 m/s, block sums added
+                             with integer atomics: results
                              are bit-identical run to run, for any particle
                              order and re-binning schedule. A node's 32-bit
                              weight sum holds up to 1024 (about 1000 particles

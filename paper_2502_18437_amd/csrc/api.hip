@@ -381,7 +381,7 @@ void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
                   b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.work, b.act_list, b.mark,
                   b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.imp_blocks, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
-                  b.status, b.scene_off, b.tools, b.clock};
+                  b.status, b.scene_off, b.tools, b.clock, b.pbound[0], b.pbound[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b.drift_host) (void)hipHostFree(b.drift_host);
@@ -648,6 +648,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
     alloc((void**)&b.keys[i], sizeof(uint32_t) * cap);
     alloc((void**)&b.vals[i], sizeof(uint32_t) * cap);
     alloc((void**)&b.ovf_list[i], sizeof(uint32_t) * h->n_blocks);
+    alloc((void**)&b.pbound[i], sizeof(unsigned long long) * n_units_max);
   }
   alloc((void**)&b.hist, sizeof(uint32_t) * hist_n);
   alloc((void**)&b.scan_tmp, sizeof(uint32_t) * scan_part);
@@ -693,6 +694,8 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   // Block ranges of the previous sort, read by the binning keys: none yet.
   hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_begin, n_units_max);
   hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, b.blk_end, n_units_max);
+  for (int i = 0; i < 2; ++i)  // no bound recorded yet (substep stamp 0, value 0)
+    hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, (uint32_t*)b.pbound[i], 2 * n_units_max);
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(1), 0, h->stream, b.status);
   launch_set_clock(b, 0, 0, h->stream);
   // Scene constants.
@@ -1311,6 +1314,12 @@ int mpm_autotune(mpm_handle* h, int32_t trial_substeps, mpm_launch_config* chose
     hipError_t r = hipMemcpyAsync(b.part[cur0], save_part, part_bytes, hipMemcpyDeviceToDevice, h->stream);
     if (r == hipSuccess) r = hipMemcpyAsync(b.id[cur0], save_id, sizeof(uint32_t) * b.cap, hipMemcpyDeviceToDevice, h->stream);
     if (r == hipSuccess) r = hipMemcpyAsync(b.status, save_st, sizeof(Status), hipMemcpyDeviceToDevice, h->stream);
+    // The tile bounds carry substep stamps that the trials ran past.
+    for (int i = 0; i < 2 && r == hipSuccess; ++i) {
+      hipLaunchKernelGGL(k_zero_u32, dim3(256), dim3(256), 0, h->stream, (uint32_t*)b.pbound[i],
+                         (int64_t)(2 * ((int64_t)h->n_blocks << kMaxUnitShift)));
+      r = hipGetLastError();
+    }
     h->substep = substep0;
     h->since_sort = since0;
     h->resorts = resorts0;

@@ -205,6 +205,11 @@ struct Buffers {
   uint2* work = nullptr;                    // transfer work items {work tile, first particle}
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
+  // Per work tile, one per grid-update parity: the largest P2G contribution
+  // bound of the tile's particles in the substep of that parity, as
+  // (substep << 32) | FP32 bits, merged with atomicMax (FP32 accumulation,
+  // MLS-MPM only; sets the scale of the packed LDS sums of the next substep).
+  unsigned long long* pbound[2] = {nullptr, nullptr};
   uint32_t* node_cnt = nullptr;             // per block: nodes with mass, last grid update
   float* imp_blocks = nullptr;              // per grid block: impulse sums (kImpulseRows x 3)
   uint32_t* scene_off = nullptr;            // n_scenes + 1 particle offsets (original order)

@@ -21,7 +21,10 @@
 // so the result does not depend on the order of the atomics (nor on the tile
 // edge). Weights are u32 in 2^-22 units: one work item (at most kItemMax
 // particles, each adding at most 0.75^3 to a node) cannot carry a node's sum
-// past 2^32 - 1.
+// past 2^32 - 1. Momentum is int64 in fixed units, except in the FP32 mode of
+// MLS-MPM, whose tile packs each node into two 64-bit words of 32-bit fields
+// at a unit chosen per work item (the packed P2G below): 2 LDS atomics per
+// node instead of 4.
 //
 // k_g2p2g fuses the G2P of substep k-1 with the P2G of substep k: v and C never
 // leave registers between the two, so a fused substep streams x, F, E in and
@@ -201,19 +204,15 @@ __device__ __forceinline__ void acc_add(const SimK& s, typename AccT<FIXED>::M* 
 
 // P2G of one particle straight into the global accumulator; claims every
 // block its stencil touches that the current binning did not activate.
-template <bool FIXED, class In>
-__device__ __forceinline__ void p2g_global(const SimK& s, const In& P, ACC_PARAMS, uint32_t* mark,
-                                        uint32_t* ovf, Status* st, int parity, int scene) {
-  const int node_base = scene * s.n3;
-  p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
-    const int g = node_base + grid_index(P.base[0] + ox, P.base[1] + oy, P.base[2] + oz, s.nb);
-    acc_add<FIXED>(s, ACC_ARGS, g, wq, p0, p1, p2);
-  });
+// Claims every block that the stencil with base node `base` touches and the
+// current binning did not activate, for the grid update (overflow list).
+__device__ __forceinline__ void claim_stencil_blocks(const SimK& s, const int* base, uint32_t* mark, uint32_t* ovf,
+                                                     Status* st, int parity, int scene) {
   // The stencil spans one or two blocks per axis. All their marks are loaded
   // before any is tested, so that the loads overlap instead of each waiting
   // on the previous test.
-  const int b0[3] = {P.base[0] >> kTileLog2, P.base[1] >> kTileLog2, P.base[2] >> kTileLog2};
-  const int b1[3] = {(P.base[0] + 2) >> kTileLog2, (P.base[1] + 2) >> kTileLog2, (P.base[2] + 2) >> kTileLog2};
+  const int b0[3] = {base[0] >> kTileLog2, base[1] >> kTileLog2, base[2] >> kTileLog2};
+  const int b1[3] = {(base[0] + 2) >> kTileLog2, (base[1] + 2) >> kTileLog2, (base[2] + 2) >> kTileLog2};
   unsigned blk[8], seen[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -228,6 +227,17 @@ __device__ __forceinline__ void p2g_global(const SimK& s, const In& P, ACC_PARAM
       const unsigned slot = atomicAdd(&st->ovf_count[parity], 1u);
       ovf[slot] = blk[k];
     }
+}
+
+template <bool FIXED, class In>
+__device__ __forceinline__ void p2g_global(const SimK& s, const In& P, ACC_PARAMS, uint32_t* mark,
+                                        uint32_t* ovf, Status* st, int parity, int scene) {
+  const int node_base = scene * s.n3;
+  p2g_emit(P, [&](int ox, int oy, int oz, uint32_t wq, long long p0, long long p1, long long p2) {
+    const int g = node_base + grid_index(P.base[0] + ox, P.base[1] + oy, P.base[2] + oz, s.nb);
+    acc_add<FIXED>(s, ACC_ARGS, g, wq, p0, p1, p2);
+  });
+  claim_stencil_blocks(s, P.base, mark, ovf, st, parity, scene);
 }
 
 // G2P sums of one particle, S = sum N v_I and T[a][b] = sum N v_I[a] o_b, with
@@ -341,6 +351,10 @@ struct Lds {
   // shell_mark, so the flush can tell whether this item used the shell.
   uint32_t item_tag, shell_mark;
   uint32_t claimed[2];  // work items claimed by thread 0 (WorkWalk)
+  // Per velocity buffer, per wave: the largest |velocity component| of the
+  // nodes the wave staged (the packed scatter's capacity).
+  float vw[2][TileShape<T>::kWG / 64];
+  unsigned long long pbe[2];  // per velocity buffer: its item's tile bound entry (Buffers::pbound)
 };
 
 // Shell node index of tile node (x, y, z), each in [-1, kSpan], at least
@@ -455,10 +469,12 @@ __device__ __forceinline__ void p2g_commit(const SimK& s, const In& P, const int
 //            on the first pass of a step v also receives dt g.
 // The PB-MPM iterations after the first count no errors (the first pass of
 // the step has counted them).
+// `bmax` takes the largest contribution bound of the particles scattered.
 template <bool FIXED, int SOL, int PASS, int T, bool SHELL>
 __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, const float* v, const float* C,
                                              const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
-                                             uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
+                                             uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev,
+                                             float& bmax) {
   constexpr bool kCount = !(SOL == SOLVER_PB && PASS == PB_ITER);
   P2GIn P;
   float f[3];
@@ -512,6 +528,7 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
     ev |= kEvRng;
     return;
   }
+  bmax = fmaxf(bmax, bound);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float qa = s.mass * vp[a] - (Af[3 * a] * f[0] + Af[3 * a + 1] * f[1] + Af[3 * a + 2] * f[2]) * s.dx;
@@ -520,6 +537,244 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
     for (int b = 0; b < 3; ++b) P.Adx[3 * a + b] = (double)(Af[3 * a + b] * s.dx) * s.fx_p;
   }
   p2g_commit<FIXED, T, SHELL>(s, P, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+}
+
+// ------------------------------------------------------------------ packed P2G
+// FP32 accumulation, MLS-MPM: the LDS tile holds each node as two 64-bit
+// words, (p1, p0) and (p2, weight), every field a 32-bit integer, so that a
+// node takes 2 LDS atomics instead of 4. The momentum fields count units of
+// 2^e kg m/s, with e chosen per work item (item_scale) so that no node sum of
+// the item can leave 32 bits. The scale comes from the largest contribution
+// bound of the tile's particles in the previous substep (Buffers::pbound),
+// times 1.25; a particle whose own bound exceeds that capacity scatters into
+// the global accumulator instead, so no sum can wrap whatever the previous
+// substep said. A contribution is rounded to an integer by one FP32 fma with
+// 1.5 * 2^23. Two such biased words, less the doubled bias in one 64-bit
+// subtraction, give hi 2^32 + lo with lo signed; 64-bit sums of such words
+// decode into the exact sums of both fields while each stays within 32 bits.
+// The weight field is unsigned and needs no bias.
+constexpr float kMagicF = 12582912.0f;  // 1.5 * 2^23
+constexpr uint32_t kMagicFBits = 0x4B400000u;
+constexpr unsigned long long kMagicPair = ((unsigned long long)kMagicFBits << 32) | kMagicFBits;
+
+// Per work item: the largest particle bound (kg m/s) its LDS sums take
+// (cap < 0: none, every particle takes the global path), and 2^-e. Both are
+// the same in every lane and are kept in scalar registers.
+struct ItemScale {
+  float cap, in;
+  // 2^e, from the exponent bits of 2^-e
+  __device__ __forceinline__ float out() const { return __int_as_float((254 << 23) - __float_as_int(in)); }
+};
+
+// Scale of a work item of n particles from its tile's bound entry (valid if
+// stamped with substep `prev`) and vmax, the largest velocity component of
+// the tile's staged nodes: the item takes particles whose bound is at most
+// 1.25 times the larger of the recorded bound and m vmax. The recorded bound
+// follows the stress; m vmax bounds |m v| of every particle that gathers from
+// the tile, and covers the first substeps from rest, where the bounds grow
+// by large factors from one substep to the next. A node sum of the item has at most n terms,
+// each at most 0.421875 (the largest weight) times that capacity, so X below
+// bounds every |sum|; with X 2^-e < 2^31 / (1 + 2^-10) every sum decodes from
+// its 32 bits with room for the FP32 rounding of the terms (and, n counted as
+// at least 512, every term stays under the 2^22 range of the rounding fma).
+__device__ __forceinline__ ItemScale item_scale(unsigned long long entry, unsigned prev, unsigned n, float mvmax) {
+  float cap = -1.0f;
+  int e = 0;
+  {
+    const float recorded = (unsigned)(entry >> 32) == prev ? __uint_as_float((uint32_t)entry) : 0.0f;
+    const float c = 1.25f * fmaxf(recorded, mvmax);
+    if (c > 0.0f && c < 1e30f) {
+      cap = c;
+      const float X = (float)max(n, 512u) * 0.421875f * c * (1.0f + 0x1p-10f);
+      e = max(ilogbf(X) - 30, -100);
+    }
+  }
+  ItemScale sc;
+  sc.cap = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cap)));
+  sc.in = __int_as_float(__builtin_amdgcn_readfirstlane((127 - e) << 23));
+  return sc;
+}
+
+// Merge the largest bound of a wave's particles into the tile's entry for
+// this substep (all lanes of the wave call it).
+__device__ __forceinline__ void record_bound(unsigned long long* pb, unsigned unit, unsigned stamp, float bmax) {
+  float m = bmax;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63u) == 0u && m > 0.0f)
+    atomicMax(pb + unit, ((unsigned long long)stamp << 32) | __float_as_uint(m));
+}
+
+// Per-particle inputs of the packed scatter: the affine momentum field
+// q + A o dx in units of 2^e as FP32 (q = m v - A f dx).
+struct P2GPk {
+  float w[3][3];
+  float q[3];
+  float Adx[9];
+};
+
+__device__ __forceinline__ float affine_step_f(float base, float slope, int o) {
+  return o == 0 ? base : (o == 1 ? base + slope : fmaf(slope, 2.0f, base));
+}
+
+// The 27 contributions of one particle as FP32 (weight N and the affine
+// field q + A o dx at the node, not yet times N), handed to `sink`.
+template <class Sink>
+__device__ __forceinline__ void p2g_emit_f32(const P2GPk& P, Sink&& sink) {
+#pragma unroll 1
+  for (int ox = 0; ox < 3; ++ox) {
+    const float wx = ox == 0 ? P.w[0][0] : (ox == 1 ? P.w[0][1] : P.w[0][2]);
+    float qx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) qx[a] = fmaf(P.Adx[3 * a], (float)ox, P.q[a]);
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy) {
+      float qy[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) qy[a] = affine_step_f(qx[a], P.Adx[3 * a + 1], oy);
+      const float wxy = wx * P.w[1][oy];
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz)
+        sink(ox, oy, oz, wxy * P.w[2][oz], affine_step_f(qy[0], P.Adx[2], oz), affine_step_f(qy[1], P.Adx[5], oz),
+             affine_step_f(qy[2], P.Adx[8], oz));
+    }
+  }
+}
+
+// The 27 packed contributions of one particle (q, A dx in units of 2^e),
+// handed to `sink`.
+template <class Sink>
+__device__ __forceinline__ void p2g_emit_pk(const P2GPk& P, Sink&& sink) {
+  p2g_emit_f32(P, [&](int ox, int oy, int oz, float N, float c0, float c1, float c2) {
+    const uint32_t wq = (uint32_t)fmaf(N, kWeightUnits, 0.5f);
+    const uint32_t b0 = __float_as_uint(fmaf(N, c0, kMagicF));
+    const uint32_t b1 = __float_as_uint(fmaf(N, c1, kMagicF));
+    const uint32_t b2 = __float_as_uint(fmaf(N, c2, kMagicF));
+    const unsigned long long w01 = (((unsigned long long)b1 << 32) | b0) - kMagicPair;
+    const unsigned long long w2m = ((unsigned long long)(b2 - kMagicFBits) << 32) | wq;
+    sink(ox, oy, oz, w01, w2m);
+  });
+}
+
+// The sums of a packed node: weight units and momentum in units of 2^e.
+__device__ __forceinline__ void unpack_node(unsigned long long w01, unsigned long long w2m, uint32_t& wq, int& p0,
+                                            int& p1, int& p2) {
+  p0 = (int)(uint32_t)w01;
+  p1 = (int)(uint32_t)((w01 - (unsigned long long)(long long)p0) >> 32);
+  wq = (uint32_t)w2m;
+  p2 = (int)(uint32_t)(w2m >> 32);
+}
+
+__device__ __forceinline__ void acc_add_pk(const SimK& s, float* am, float* ap0, float* ap1, float* ap2, int g,
+                                           uint32_t wq, int p0, int p1, int p2, float out) {
+  unsafeAtomicAdd(am + g, (float)wq * s.m_unit);
+  unsafeAtomicAdd(ap0 + g, (float)p0 * out);
+  unsafeAtomicAdd(ap1 + g, (float)p1 * out);
+  unsafeAtomicAdd(ap2 + g, (float)p2 * out);
+}
+
+// MLS-MPM P2G of one particle into the packed tile (the arithmetic of
+// p2g_particle up to the contribution bound); particles outside the tile and
+// its shell, or beyond the item's capacity, add their FP32 contributions
+// straight into the FP32 accumulator. Uses L.p0 / L.p1 (L.sp0 / L.sp1 for
+// the shell) as the two packed words of a node.
+template <bool FIXED, int T>
+__device__ __forceinline__ void p2g_particle_pk(const SimK& s, const float* x, const float* v, const float* C,
+                                                const float* F, float E, const int* to, Lds<T>& L,
+                                                const ItemScale& sc, ACC_PARAMS, uint32_t* mark, uint32_t* ovf,
+                                                Status* st, int parity, unsigned& ev, float& bmax) {
+  static_assert(!FIXED, "the packed tile feeds the FP32 accumulator");
+  int base[3];
+  float f[3];
+  if (!particle_stencil(s, x, base, f)) {
+    if (isfinite(x[0] + x[1] + x[2]))
+      ev |= kEvDom;
+    else
+      ev |= kEvNf;
+    return;
+  }
+  float tau[9];
+  bool inv;
+  kirchhoff(F, s.c_mu * E, s.c_la * E, tau, &inv);
+  float Af[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Af[i] = s.mass * C[i] - s.p2g_stress * tau[i];
+  float chk = v[0] + v[1] + v[2];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) chk += Af[i];
+  if (!isfinite(chk)) {
+    ev |= kEvNf;
+    return;
+  }
+  if (inv) ev |= kEvInv;
+  float bound = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float row = fabsf(Af[3 * a]) + fabsf(Af[3 * a + 1]) + fabsf(Af[3 * a + 2]);
+    bound = fmaxf(bound, fabsf(s.mass * v[a]) + 1.5f * s.dx * row);
+  }
+  if (!(bound < s.p_limit)) {
+    ev |= kEvRng;
+    return;
+  }
+  bmax = fmaxf(bmax, bound);
+  const int l0 = base[0] - to[0], l1 = base[1] - to[1], l2 = base[2] - to[2];
+  constexpr unsigned kMarginMax = T + 1;  // base -1 .. T, shifted by one
+  const bool in = in_tile<T>(l0, l1, l2);
+  const bool shell = !in && (unsigned)(l0 + 1) <= kMarginMax && (unsigned)(l1 + 1) <= kMarginMax &&
+                     (unsigned)(l2 + 1) <= kMarginMax;
+  const bool lds = (in || shell) && bound <= sc.cap;
+  const float scale = lds ? sc.in : 1.0f;
+  P2GPk P;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    bspline_w(f[a], P.w[a]);
+    const float qa = s.mass * v[a] - (Af[3 * a] * f[0] + Af[3 * a + 1] * f[1] + Af[3 * a + 2] * f[2]) * s.dx;
+    P.q[a] = qa * scale;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) P.Adx[3 * a + b] = (Af[3 * a + b] * s.dx) * scale;
+  }
+  if (!lds) {
+    // FP32 contributions straight into the FP32 accumulator.
+    if (!(in || shell)) ev |= kEvFbP2G;
+    const int node_base = to[3] * s.n3;
+    p2g_emit_f32(P, [&](int ox, int oy, int oz, float N, float c0, float c1, float c2) {
+      const int g = node_base + grid_index(base[0] + ox, base[1] + oy, base[2] + oz, s.nb);
+      unsafeAtomicAdd(am + g, N * s.mass);
+      unsafeAtomicAdd(ap0 + g, N * c0);
+      unsafeAtomicAdd(ap1 + g, N * c1);
+      unsafeAtomicAdd(ap2 + g, N * c2);
+    });
+    claim_stencil_blocks(s, base, mark, ovf, st, parity, to[3]);
+    return;
+  }
+  if (shell) {
+    // One cell out: the nodes in the span go to the tile, the others to the shell.
+    constexpr int S = TileShape<T>::kSpan;
+    L.shell_mark = L.item_tag;
+    p2g_emit_pk(P, [&](int ox, int oy, int oz, unsigned long long w01, unsigned long long w2m) {
+      const int x = l0 + ox, y = l1 + oy, z = l2 + oz;
+      unsigned long long *a0, *a1;
+      if ((unsigned)x < (unsigned)S && (unsigned)y < (unsigned)S && (unsigned)z < (unsigned)S) {
+        const int idx = lds_index<T>(x, y, z);
+        a0 = (unsigned long long*)&L.p0[idx];
+        a1 = (unsigned long long*)&L.p1[idx];
+      } else {
+        const int j = shell_index<T>(x, y, z);
+        a0 = (unsigned long long*)&L.sp0[j];
+        a1 = (unsigned long long*)&L.sp1[j];
+      }
+      atomicAdd(a0, w01);
+      atomicAdd(a1, w2m);
+    });
+    return;
+  }
+  const int l = lds_index<T>(l0, l1, l2);
+  p2g_emit_pk(P, [&](int ox, int oy, int oz, unsigned long long w01, unsigned long long w2m) {
+    const int idx = l + lds_index<T>(ox, oy, oz);
+    atomicAdd((unsigned long long*)&L.p0[idx], w01);
+    atomicAdd((unsigned long long*)&L.p1[idx], w2m);
+  });
 }
 
 // P2G of one particle for standard MPM (Sec. III-A): mass N m and momentum
@@ -728,6 +983,29 @@ __device__ __forceinline__ void tile_stage_velocity(const SimK& s, const int* to
 // hoisted out of the work-item loop and held in registers across it.
 __device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
 
+// tile_stage_velocity that also leaves, per wave, the largest |velocity
+// component| of the staged nodes in vw (one slot per wave).
+template <int T>
+__device__ __forceinline__ void tile_stage_velocity_max(const SimK& s, const int* to, const float4* vel, float4* Lv,
+                                                        float* vw) {
+  constexpr int S = TileShape<T>::kSpan;
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < Lds<T>::kNodes; i += blockDim.x) {
+    const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
+    const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
+    float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if ((unsigned)gx < (unsigned)s.n && (unsigned)gy < (unsigned)s.n && (unsigned)gz < (unsigned)s.n)
+      val = vel[to[3] * s.n3 + grid_index(gx, gy, gz, s.nb)];
+    Lv[i] = val;
+    m = fmaxf(m, fmaxf(fabsf(val.x), fmaxf(fabsf(val.y), fabsf(val.z))));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  int w = (int)(threadIdx.x >> 6);
+  opaque(w);  // recomputed here rather than held across the work-item loop
+  if ((threadIdx.x & 63u) == 0u) vw[w] = m;
+}
+
 // Non-empty tile nodes -> global accumulator, clearing the tile for the next
 // work item on the way (each thread clears the nodes it flushed).
 template <bool FIXED, int T>
@@ -770,6 +1048,61 @@ __device__ __forceinline__ void tile_flush(const SimK& s, const int* to, const L
   }
 }
 
+// The packed tile's non-empty nodes -> FP32 accumulator (momentum sums
+// times `out` = 2^e), clearing them on the way.
+template <int T>
+__device__ __forceinline__ void tile_flush_clear_pk(const SimK& s, const int* to, Lds<T>& L, float* am, float* ap0,
+                                                    float* ap1, float* ap2, float out) {
+  constexpr int S = TileShape<T>::kSpan;
+  constexpr int kSlots = (Lds<T>::kNodes + TileShape<T>::kWG - 1) / TileShape<T>::kWG;
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    int i = threadIdx.x + k * TileShape<T>::kWG;
+    if (i >= Lds<T>::kNodes) break;
+    opaque(i);
+    const unsigned long long w01 = (unsigned long long)L.p0[i], w2m = (unsigned long long)L.p1[i];
+    L.p0[i] = 0ll;
+    L.p1[i] = 0ll;
+    if ((w01 | w2m) == 0ull) continue;
+    const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
+    const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
+    if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
+    uint32_t wq;
+    int p0, p1, p2;
+    unpack_node(w01, w2m, wq, p0, p1, p2);
+    acc_add_pk(s, am, ap0, ap1, ap2, to[3] * s.n3 + grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2, out);
+  }
+}
+
+// The packed shell, as shell_flush_clear.
+template <int T>
+__device__ __forceinline__ void shell_flush_clear_pk(const SimK& s, const int* to, Lds<T>& L, float* am, float* ap0,
+                                                     float* ap1, float* ap2, float out, uint32_t tag, uint32_t* mark,
+                                                     uint32_t* ovf, Status* st, int parity) {
+  if (L.shell_mark != tag) return;  // the same in every thread
+  for (int j = threadIdx.x; j < Lds<T>::kShell; j += blockDim.x) {
+    const unsigned long long w01 = (unsigned long long)L.sp0[j], w2m = (unsigned long long)L.sp1[j];
+    if ((w01 | w2m) == 0ull) continue;
+    L.sp0[j] = 0ll;
+    L.sp1[j] = 0ll;
+    int x, y, z;
+    shell_node<T>(j, &x, &y, &z);
+    const int gx = to[0] + x, gy = to[1] + y, gz = to[2] + z;
+    if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
+    uint32_t wq;
+    int p0, p1, p2;
+    unpack_node(w01, w2m, wq, p0, p1, p2);
+    acc_add_pk(s, am, ap0, ap1, ap2, to[3] * s.n3 + grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2, out);
+    const unsigned b = (unsigned)to[3] * s.nb3 +
+                       (unsigned)((((gz >> kTileLog2) * s.nb) + (gy >> kTileLog2)) * s.nb + (gx >> kTileLog2));
+    if (__hip_atomic_load(&mark[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+        atomicCAS(&mark[b], 0u, 2u) == 0u) {
+      const unsigned slot = atomicAdd(&st->ovf_count[parity], 1u);
+      ovf[slot] = b;
+    }
+  }
+}
+
 __device__ __forceinline__ float particle_E(const SimK& s, const float* __restrict__ part, int64_t cap,
                                             unsigned p) {
   return s.has_E ? part[FE * cap + p] : s.E_default;
@@ -781,11 +1114,12 @@ __device__ __forceinline__ float particle_E(const SimK& s, const float* __restri
 template <bool FIXED, int SOL, int PASS, int T, bool SHELL = true>
 __device__ __forceinline__ void p2g_any(const SimK& s, const float* x, const float* v, const float* C,
                                         const float* F, float E, const int* to, Lds<T>& L, ACC_PARAMS,
-                                        uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev) {
+                                        uint32_t* mark, uint32_t* ovf, Status* st, int parity, unsigned& ev,
+                                        float& bmax) {
   if constexpr (SOL == SOLVER_PIC)
     p2g_particle_pic<FIXED, T, SHELL>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
   else
-    p2g_particle<FIXED, SOL, PASS, T, SHELL>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+    p2g_particle<FIXED, SOL, PASS, T, SHELL>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev, bmax);
 }
 
 // P2G from the materialised particle state (first substep after binning; for
@@ -795,10 +1129,15 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __res
                                              const uint32_t* __restrict__ blk_end,
                                              const uint2* __restrict__ work, Status* st,
                                              ACC_PARAMS, uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
+                                             const Clock* __restrict__ clk, unsigned long long* pb_wr,
                                              int parity, SimK s) {
+  // The bounds of this substep set the scale of the next (packed) one.
+  constexpr bool kTrack = !FIXED && SOL == SOLVER_MLS;
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds<T> L;
   Counters cnt;
+  unsigned stamp = 0u;
+  if constexpr (kTrack) stamp = (unsigned)clk[parity].substep;
   const WorkWalk walk(st->n_work);
   unsigned pos = walk.first();
   while (pos < walk.end) {
@@ -812,6 +1151,7 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __res
     tile_clear(L, pos + 1u);
     __syncthreads();
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
+    float bmax = 0.0f;
     for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
       float x[3], v[3], C[9], F[9];
 #pragma unroll
@@ -826,9 +1166,10 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_p2g(const float* __res
       }
       const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
       unsigned ev = 0u;
-      p2g_any<FIXED, SOL, PB_FIRST, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+      p2g_any<FIXED, SOL, PB_FIRST, T>(s, x, v, C, F, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev, bmax);
       count_events(cnt, ev);
     }
+    if constexpr (kTrack) record_bound(pb_wr, b, stamp, bmax);
     if (threadIdx.x == 0) L.claimed[1] = next;
     __syncthreads();
     next = L.claimed[1];
@@ -854,13 +1195,18 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
                                                const uint2* __restrict__ work, Status* st,
                                                ACC_PARAMS, const float4* __restrict__ vel,
                                                uint32_t* mark, uint32_t* ovf0, uint32_t* ovf1,
-                                               const Clock* __restrict__ clk, int parity,
+                                               const Clock* __restrict__ clk,
+                                               const unsigned long long* __restrict__ pb_rd,
+                                               unsigned long long* pb_wr, int parity,
                                                const ToolDesc* __restrict__ tools, SimK s) {
   constexpr bool kIntegrate = !(SOL == SOLVER_PB && PASS == PB_ITER);
   static_assert(!PUSH || kIntegrate, "push-out follows a position update");
   constexpr bool kShell = SOL != SOLVER_PB && !PUSH;
+  // FP32 MLS-MPM scatters into the packed tile (the push-out variant keeps
+  // the int64 tile: the packed path does not fit its registers).
+  constexpr bool kPack = !FIXED && SOL == SOLVER_MLS && !PUSH;
   long long substep = 0;
-  if constexpr (PUSH) substep = clk[parity].substep;
+  if constexpr (PUSH || kPack) substep = clk[parity].substep;
   uint32_t* ovf = parity ? ovf1 : ovf0;
   __shared__ Lds<T> L;
   __shared__ float4 Vb[Lds<T>::kNodes];  // second velocity buffer
@@ -872,9 +1218,14 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
   if (pos < walk.end) {
     if (threadIdx.x == 0) L.claimed[0] = walk.claim(st);
     item = work[pos];
+    if constexpr (kPack)
+      if (threadIdx.x == 0) L.pbe[0] = pb_rd[item.x & ~kDenseFlag];
     int to[4];
     unit_origin<T>(s, item.x & ~kDenseFlag, to);
-    tile_stage_velocity<T>(s, to, vel, L.v);
+    if constexpr (kPack)
+      tile_stage_velocity_max<T>(s, to, vel, L.v, L.vw[0]);
+    else
+      tile_stage_velocity<T>(s, to, vel, L.v);
     tile_clear(L, pos + 1u);
     __syncthreads();
     npos = L.claimed[0];
@@ -890,6 +1241,14 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
     int to[4];
     unit_origin<T>(s, b, to);
     const unsigned pe = min(item.y + s.item_particles, blk_end[b]);
+    ItemScale sc{-1.0f, 1.0f};
+    if constexpr (kPack) {
+      float vmax = 0.0f;
+#pragma unroll
+      for (int w = 0; w < TileShape<T>::kWG / 64; ++w) vmax = fmaxf(vmax, L.vw[flip ? 1 : 0][w]);
+      sc = item_scale(L.pbe[flip ? 1 : 0], (unsigned)(substep - 1), pe - item.y, s.mass * vmax);
+    }
+    float bmax = 0.0f;
     for (unsigned p = item.y + q; p < pe; p += TileShape<T>::kWG) {
       float x[3], F[9];
 #pragma unroll
@@ -915,7 +1274,11 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
 #pragma unroll
         for (int i = 0; i < 9; ++i) part[(FF + i) * cap + p] = Fn[i];
         const float E = SOL == SOLVER_PB ? 0.0f : particle_E(s, part, cap, p);
-        p2g_any<FIXED, SOL, PASS, T, kShell>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+        if constexpr (kPack)
+          p2g_particle_pk<FIXED, T>(s, x, vn, Cn, Fn, E, to, L, sc, ACC_ARGS, mark, ovf, st, parity, ev, bmax);
+        else
+          p2g_any<FIXED, SOL, PASS, T, kShell>(s, x, vn, Cn, Fn, E, to, L, ACC_ARGS, mark, ovf, st, parity, ev,
+                                               bmax);
         // An update that moved the particle out of the grid (or left its
         // state not finite) is its last: the particle is left unchanged from
         // then on, so its v and C of this update are kept in memory with it.
@@ -926,25 +1289,37 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
           for (int i = 0; i < 9; ++i) part[(FC + i) * cap + p] = Cn[i];
         }
       } else {
-        p2g_any<FIXED, SOL, PASS, T, kShell>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev);
+        p2g_any<FIXED, SOL, PASS, T, kShell>(s, x, vn, Cn, F, 0.0f, to, L, ACC_ARGS, mark, ovf, st, parity, ev,
+                                             bmax);
       }
       count_events(cnt, ev);
     }
+    if constexpr (kPack) record_bound(pb_wr, b, (unsigned)substep, bmax);
     const bool more = npos < walk.end;  // the same for the whole workgroup
     uint2 nitem = item;
     unsigned claim = 0u;
     if (more) {
       if (threadIdx.x == 0) claim = walk.claim(st);  // the item after the next one
       nitem = work[npos];
+      if constexpr (kPack)
+        if (threadIdx.x == 0) L.pbe[flip ? 0 : 1] = pb_rd[nitem.x & ~kDenseFlag];
       int nto[4];
       unit_origin<T>(s, nitem.x & ~kDenseFlag, nto);
-      tile_stage_velocity<T>(s, nto, vel, flip ? L.v : Vb);
+      if constexpr (kPack)
+        tile_stage_velocity_max<T>(s, nto, vel, flip ? L.v : Vb, L.vw[flip ? 0 : 1]);
+      else
+        tile_stage_velocity<T>(s, nto, vel, flip ? L.v : Vb);
       if (threadIdx.x == 0) L.claimed[1] = claim;
     }
     __syncthreads();  // every P2G atomic into this tile is done; the next velocities are staged
     const unsigned nnpos = more ? L.claimed[1] : walk.end;
-    tile_flush_clear<FIXED, T>(s, to, L, ACC_ARGS);
-    shell_flush_clear<FIXED, T>(s, to, L, ACC_ARGS, pos + 1u, mark, ovf, st, parity);
+    if constexpr (kPack) {
+      tile_flush_clear_pk<T>(s, to, L, am, ap0, ap1, ap2, sc.out());
+      shell_flush_clear_pk<T>(s, to, L, am, ap0, ap1, ap2, sc.out(), pos + 1u, mark, ovf, st, parity);
+    } else {
+      tile_flush_clear<FIXED, T>(s, to, L, ACC_ARGS);
+      shell_flush_clear<FIXED, T>(s, to, L, ACC_ARGS, pos + 1u, mark, ovf, st, parity);
+    }
     if (threadIdx.x == 0) L.item_tag = npos + 1u;  // nothing reads it before the next barrier
     pos = npos;
     npos = nnpos;
@@ -1024,7 +1399,8 @@ static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hi
   using P = typename AccT<FIXED>::P;
   hipLaunchKernelGGL((k_p2g<FIXED, SOL, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st, b.part[b.cur], b.cap,
                      b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
-                     (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], parity, s);
+                     (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock,
+                     b.pbound[parity & 1], parity, s);
 }
 
 template <bool FIXED, int SOL, int PASS, bool PUSH, int T>
@@ -1034,7 +1410,8 @@ static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, 
   hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS, PUSH, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st,
                      b.part[b.cur], b.cap, b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0],
                      (P*)b.acc_p[1], (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1],
-                     (const Clock*)b.clock, parity, (const ToolDesc*)b.tools, s);
+                     (const Clock*)b.clock, (const unsigned long long*)b.pbound[(parity & 1) ^ 1],
+                     b.pbound[parity & 1], parity, (const ToolDesc*)b.tools, s);
 }
 
 // The integrating passes with or without push-out.
