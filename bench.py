@@ -11,7 +11,11 @@ substep, all in the HIP library). `value` = particles x substeps / second.
 Also reported on the same JSON line:
 * roofline: the dominant kernel (the fused G2P2G) against the HBM peak,
   from its algorithmic bytes per launch and its mean duration measured with
-  HIP events on the library's stream during the timed steps; `traffic` is
+  HIP events on the library's stream during the timed steps (the events
+  ride on the kernels' dispatches, on every PROFILE_EVERY-th substep, a
+  uniform sample over the run that keeps the events' own cost, a few us per
+  event, off the other substeps; every substep launches its kernels one by
+  one meanwhile); `traffic` is
   the kernel's HBM bytes per launch from hardware counters
   (profiles/k_g2p2g_<scene>_counters.md), null once its sources changed;
   `atomics` is its TCC atomic requests per launch (from
@@ -51,6 +55,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle-substeps/s (P2G+grid+G2P) fwd & fwd+bwd; % HBM roofline at 4M particles"
+# Per-kernel events on every PROFILE_EVERY-th substep of the timed steps.
+PROFILE_EVERY = 4
 HBM_PEAK_GBS = 8000.0
 B_PARTICLE = 100.0      # x, F, E read + x, F written per particle-substep (fused path)
 B_NODE_SUBSTEP = 72.0   # P2G result write+read, reset, velocity write+read per active node
@@ -373,7 +379,7 @@ def main():
     torch.cuda.synchronize()
 
     if not args.no_profile:
-        sim.profile(True)
+        sim.profile(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -437,6 +443,7 @@ def main():
         out["roofline"] = {"kernel": "k_g2p2g", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(s.name),
                            "bytes_per_launch": bytes_launch, "avg_us": avg_s * 1e6, "launches": n,
+                           "timed_every": PROFILE_EVERY,
                            "atomics": counted_atomics(s.name, avg_s)}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": 1e3 * v[0] / v[1] if v[1] else None} for k, v in prof.items()}

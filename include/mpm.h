@@ -280,16 +280,24 @@ int mpm_eval_stress(int64_t n, const float* F, const float* E, float nu, float* 
 int mpm_eval_stress_noalloc(int64_t n, const float* F, const float* E, float nu, float* tau,
                             int32_t where);
 
-/* Per-kernel timing with HIP events recorded on the handle's stream around
- * every launch while enabled. Kinds, in order: 0 sort (binning pipeline),
- * 1 p2g, 2 g2p2g (fused), 3 g2p, 4 grid update. */
+/* Per-kernel timing with HIP events on the handle's stream while enabled:
+ * the transfer and grid kernels record theirs as part of their dispatch
+ * (hipExtLaunchKernel), the binning pipeline between marker events. Kinds,
+ * in order: 0 sort (binning pipeline), 1 p2g, 2 g2p2g (fused), 3 g2p, 4 grid
+ * update. While timing, every substep launches its kernels one by one (no
+ * graph replay). */
 #define MPM_KERNEL_KINDS 5
 typedef struct mpm_kernel_times {
   double total_ms[MPM_KERNEL_KINDS];
   int64_t launches[MPM_KERNEL_KINDS];
 } mpm_kernel_times;
 
-/* Enable (1) or disable (0) event timing; enabling clears the totals. */
+/* Enable (enable >= 1) or disable (0) event timing; enabling clears the
+ * totals. enable = k > 1 times the transfer and grid kernels of every k-th
+ * substep only (substep index divisible by k), a uniform sample that keeps
+ * the events' own cost (a few microseconds per event on the stream) off the
+ * other substeps; binning is timed at every re-binning. EINVAL for
+ * enable < 0. */
 int mpm_profile(mpm_handle* h, int32_t enable);
 /* Synchronise and return the totals accumulated since timing was enabled. */
 int mpm_profile_read(mpm_handle* h, mpm_kernel_times* out);

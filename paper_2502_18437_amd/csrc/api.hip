@@ -145,6 +145,8 @@ struct mpm_handle {
   int transfer_wgs = 512;
   std::string err;
   bool prof = false;
+  int prof_every = 1;   // time the transfer and grid kernels of every prof_every-th substep
+  bool prof_now = false;  // this substep's kernels are timed
   std::vector<ProfEvent> prof_pending;
   std::vector<hipEvent_t> prof_pool;
   double prof_ms[MPM_KERNEL_KINDS] = {0, 0, 0, 0, 0};
@@ -313,6 +315,26 @@ struct ProfScope {
         h->prof_pool.push_back(a);
       }
     }
+  }
+};
+
+// The events of one timed kernel launch, recorded by the launch itself
+// (KernelEvents; none when not timing), queued for prof_collect.
+struct KernelTimer {
+  mpm_handle* h;
+  int kind;
+  KernelEvents ev;
+  KernelTimer(mpm_handle* hh, int k) : h(hh), kind(k) {
+    if (!h->prof_now) return;
+    ev.start = prof_event(h);
+    ev.stop = ev.start ? prof_event(h) : nullptr;
+    if (!ev.stop) {
+      if (ev.start) h->prof_pool.push_back(ev.start);
+      ev = KernelEvents();
+    }
+  }
+  ~KernelTimer() {
+    if (ev.start) h->prof_pending.push_back({kind, ev.start, ev.stop});
   }
 };
 
@@ -1088,9 +1110,9 @@ bool drift_rebin(const mpm_handle* h) {
 // Grid update `it` of `passes` in a substep, of parity `parity`: PB-MPM
 // leaves gravity out (it is added to the particles) and keeps the impulses of
 // the last pass only; the clock's substep advances after the last pass.
-void launch_grid_pass(mpm_handle* h, int it, int passes, int parity, hipStream_t st) {
+void launch_grid_pass(mpm_handle* h, int it, int passes, int parity, hipStream_t st, KernelEvents ev = {}) {
   const bool last = it == passes - 1;
-  launch_grid(h->b, h->sim, (int)h->n_blocks, parity, st, h->sim.solver != SOLVER_PB, last, last);
+  launch_grid(h->b, h->sim, (int)h->n_blocks, parity, st, h->sim.solver != SOLVER_PB, last, last, ev);
 }
 
 // Record `chunk` plain substeps (fused transfer + grid update) as a graph
@@ -1156,9 +1178,10 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     // substep the memory holds the full state (v, C included).
     const bool advance = rebin && k > 0 && !in_place;
     const int parity = (int)(h->updates & 1);
+    h->prof_now = h->prof && h->substep % h->prof_every == 0;
     if (advance) {
-      ProfScope ps(h, 3);
-      launch_g2p(b, N, h->sim, wgs, parity, h->stream);
+      KernelTimer kt(h, 3);
+      launch_g2p(b, N, h->sim, wgs, parity, h->stream, kt.ev);
     }
     if (rebin) {
       ProfScope ps(h, 0);
@@ -1175,8 +1198,8 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
       h->resorts++;
     }
     if (k == 0 || advance) {
-      ProfScope ps(h, 1);
-      launch_p2g(b, N, h->sim, wgs, parity, h->stream);
+      KernelTimer kt(h, 1);
+      launch_p2g(b, N, h->sim, wgs, parity, h->stream, kt.ev);
     } else {
       // Plain substeps until the next re-binning or the end of the call:
       // whole chunks replay the recorded graph (not while timing kernels).
@@ -1194,17 +1217,17 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
         if (adaptive) HIP_OR_RETURN(h, drift_mark(h));
         continue;
       }
-      ProfScope ps(h, 2);
-      launch_g2p2g(b, N, h->sim, wgs, parity, h->stream, PB_FIRST);
+      KernelTimer kt(h, 2);
+      launch_g2p2g(b, N, h->sim, wgs, parity, h->stream, PB_FIRST, kt.ev);
     }
     for (int it = 0; it < passes; ++it) {
       const int pit = (parity + it) & 1;
       if (it > 0) {
-        ProfScope ps(h, 2);
-        launch_g2p2g(b, N, h->sim, wgs, pit, h->stream, PB_ITER);
+        KernelTimer kt(h, 2);
+        launch_g2p2g(b, N, h->sim, wgs, pit, h->stream, PB_ITER, kt.ev);
       }
-      ProfScope ps(h, 4);
-      launch_grid_pass(h, it, passes, pit, h->stream);
+      KernelTimer kt(h, 4);
+      launch_grid_pass(h, it, passes, pit, h->stream, kt.ev);
     }
     h->updates += passes;
     h->substep++;
@@ -1213,9 +1236,11 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     if (adaptive) HIP_OR_RETURN(h, drift_mark(h));
   }
   {
-    ProfScope ps(h, 3);
-    launch_g2p(b, N, h->sim, wgs, (int)(h->updates & 1), h->stream);
+    h->prof_now = h->prof;  // the closing G2P, once per call
+    KernelTimer kt(h, 3);
+    launch_g2p(b, N, h->sim, wgs, (int)(h->updates & 1), h->stream, kt.ev);
   }
+  h->prof_now = false;
   HIP_OR_RETURN(h, hipGetLastError());
   return MPM_OK;
 }
@@ -1777,6 +1802,7 @@ int mpm_read_tool_impulses(mpm_handle* h, double* out) { return mpm_read_scene_t
 
 int mpm_profile(mpm_handle* h, int32_t enable) {
   if (!h) return MPM_EINVAL;
+  if (enable < 0) return fail(h, MPM_EINVAL, "mpm_profile: enable < 0");
   if (enable) {
     HIP_OR_RETURN(h, select_device(h));
     int rc = sync(h);
@@ -1788,6 +1814,7 @@ int mpm_profile(mpm_handle* h, int32_t enable) {
     }
   }
   h->prof = enable != 0;
+  h->prof_every = enable > 1 ? enable : 1;
   return MPM_OK;
 }
 

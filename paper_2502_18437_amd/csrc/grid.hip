@@ -219,12 +219,12 @@ void launch_set_clock(Buffers& b, long long substep, int parity, hipStream_t st)
 }
 
 void launch_grid(Buffers& b, const SimK& s, int max_act, int parity, hipStream_t st, bool gravity, bool record,
-                 bool last) {
+                 bool last, KernelEvents ev) {
   int wgs = max_act < kGridSlots ? max_act : kGridSlots;
   if (wgs < 1) wgs = 1;
   SimK k = s;
   if (!gravity) k.g[0] = k.g[1] = k.g[2] = 0.0f;
-  hipLaunchKernelGGL(k_grid, dim3(wgs), dim3(kGridWG), 0, st, b.acc_m, b.acc_p[0], b.acc_p[1],
+  launch_kernel(k_grid, dim3(wgs), dim3(kGridWG), st, ev, b.acc_m, b.acc_p[0], b.acc_p[1],
                      b.acc_p[2], b.vel, b.act_list, b.ovf_list[0], b.ovf_list[1], b.mark, b.node_cnt, b.imp_blocks,
                      (const ToolDesc*)b.tools, b.status, b.clock, parity & 1, last ? 1 : 0, record ? 1 : 0,
                      b.drift_host, k);

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace mpm {
@@ -235,14 +236,31 @@ struct Buffers {
 // held in memory).
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool with_vc, hipStream_t st);
 
+// Optional HIP events that a launcher records around its one kernel as part
+// of the kernel's dispatch (hipExtLaunchKernel), for per-kernel timing
+// without marker packets of their own; both null: a plain launch.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
+template <class F, class... Args>
+inline void launch_kernel(F kernel, dim3 grid, dim3 block, hipStream_t st, KernelEvents ev, Args... args) {
+  if (ev.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev.start, ev.stop, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
 // Transfers before the grid update of parity `parity` (its overflow list
 // takes drifted particles; push-out reads its clock entry). The solver is
 // s.solver; `pass` selects the PB-MPM pass (PBPass) and is ignored by the
 // other solvers.
-void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st);
+void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st,
+                KernelEvents ev = {});
 void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st,
-                  int pass = PB_FIRST);
-void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st);
+                  int pass = PB_FIRST, KernelEvents ev = {});
+void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st,
+                KernelEvents ev = {});
 
 // Grid update of parity `parity` over active blocks and that parity's
 // overflow blocks, with each scene's tools at their pose of the clock
@@ -251,7 +269,7 @@ void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, 
 // velocities; `record` adds the tools' and walls' momentum changes to the
 // impulse sums.
 void launch_grid(Buffers& b, const SimK& s, int max_act, int parity, hipStream_t st, bool gravity = true,
-                 bool record = true, bool last = true);
+                 bool record = true, bool last = true, KernelEvents ev = {});
 // The grid update after a substep's last pass also mirrors {substep,
 // n_fallback, fb_at_sort} into Buffers::drift_host.
 // Set the clock entry of `parity` to `substep`.

@@ -1394,20 +1394,20 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p(float* __restrict_
 
 // ------------------------------------------------------------------ launchers
 template <bool FIXED, int SOL, int T>
-static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+static void launch_p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL((k_p2g<FIXED, SOL, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st, b.part[b.cur], b.cap,
+  launch_kernel(k_p2g<FIXED, SOL, T>, dim3(grid_wgs), dim3(TileShape<T>::kWG), st, ev, (const float*)b.part[b.cur], b.cap,
                      b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0], (P*)b.acc_p[1],
                      (P*)b.acc_p[2], b.mark, b.ovf_list[0], b.ovf_list[1], (const Clock*)b.clock,
                      b.pbound[parity & 1], parity, s);
 }
 
 template <bool FIXED, int SOL, int PASS, bool PUSH, int T>
-static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   using M = typename AccT<FIXED>::M;
   using P = typename AccT<FIXED>::P;
-  hipLaunchKernelGGL((k_g2p2g<FIXED, SOL, PASS, PUSH, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st,
+  launch_kernel(k_g2p2g<FIXED, SOL, PASS, PUSH, T>, dim3(grid_wgs), dim3(TileShape<T>::kWG), st, ev,
                      b.part[b.cur], b.cap, b.blk_end, b.work, b.status, (M*)b.acc_m, (P*)b.acc_p[0],
                      (P*)b.acc_p[1], (P*)b.acc_p[2], b.vel, b.mark, b.ovf_list[0], b.ovf_list[1],
                      (const Clock*)b.clock, (const unsigned long long*)b.pbound[(parity & 1) ^ 1],
@@ -1416,91 +1416,91 @@ static void launch_g2p2g_t(Buffers& b, const SimK& s, int grid_wgs, int parity, 
 
 // The integrating passes with or without push-out.
 template <bool FIXED, int SOL, int T>
-static void launch_g2p2g_p(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+static void launch_g2p2g_p(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   if (s.push_out)
-    launch_g2p2g_t<FIXED, SOL, PB_FIRST, true, T>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, true, T>(b, s, grid_wgs, parity, st, ev);
   else
-    launch_g2p2g_t<FIXED, SOL, PB_FIRST, false, T>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_t<FIXED, SOL, PB_FIRST, false, T>(b, s, grid_wgs, parity, st, ev);
 }
 
 template <bool FIXED, int T>
-static void launch_p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+static void launch_p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   if (s.solver == SOLVER_PIC)
-    launch_p2g_t<FIXED, SOLVER_PIC, T>(b, s, grid_wgs, parity, st);
+    launch_p2g_t<FIXED, SOLVER_PIC, T>(b, s, grid_wgs, parity, st, ev);
   else if (s.solver == SOLVER_PB)
-    launch_p2g_t<FIXED, SOLVER_PB, T>(b, s, grid_wgs, parity, st);
+    launch_p2g_t<FIXED, SOLVER_PB, T>(b, s, grid_wgs, parity, st, ev);
   else
-    launch_p2g_t<FIXED, SOLVER_MLS, T>(b, s, grid_wgs, parity, st);
+    launch_p2g_t<FIXED, SOLVER_MLS, T>(b, s, grid_wgs, parity, st, ev);
 }
 
 template <bool FIXED, int T>
-static void launch_g2p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass) {
+static void launch_g2p2g_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass, KernelEvents ev) {
   if (s.solver == SOLVER_PIC)
-    launch_g2p2g_p<FIXED, SOLVER_PIC, T>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_p<FIXED, SOLVER_PIC, T>(b, s, grid_wgs, parity, st, ev);
   else if (s.solver == SOLVER_PB && pass == PB_ITER)
-    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER, false, T>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_t<FIXED, SOLVER_PB, PB_ITER, false, T>(b, s, grid_wgs, parity, st, ev);
   else if (s.solver == SOLVER_PB)
-    launch_g2p2g_p<FIXED, SOLVER_PB, T>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_p<FIXED, SOLVER_PB, T>(b, s, grid_wgs, parity, st, ev);
   else
-    launch_g2p2g_p<FIXED, SOLVER_MLS, T>(b, s, grid_wgs, parity, st);
+    launch_g2p2g_p<FIXED, SOLVER_MLS, T>(b, s, grid_wgs, parity, st, ev);
 }
 
-void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+void launch_p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   (void)N;
   if (s.tile == 4) {
     if (s.fixed)
-      launch_p2g_s<true, 4>(b, s, grid_wgs, parity, st);
+      launch_p2g_s<true, 4>(b, s, grid_wgs, parity, st, ev);
     else
-      launch_p2g_s<false, 4>(b, s, grid_wgs, parity, st);
+      launch_p2g_s<false, 4>(b, s, grid_wgs, parity, st, ev);
   } else {
     if (s.fixed)
-      launch_p2g_s<true, 8>(b, s, grid_wgs, parity, st);
+      launch_p2g_s<true, 8>(b, s, grid_wgs, parity, st, ev);
     else
-      launch_p2g_s<false, 8>(b, s, grid_wgs, parity, st);
+      launch_p2g_s<false, 8>(b, s, grid_wgs, parity, st, ev);
   }
 }
 
-void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass) {
+void launch_g2p2g(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st, int pass, KernelEvents ev) {
   (void)N;
   if (s.tile == 4) {
     if (s.fixed)
-      launch_g2p2g_s<true, 4>(b, s, grid_wgs, parity, st, pass);
+      launch_g2p2g_s<true, 4>(b, s, grid_wgs, parity, st, pass, ev);
     else
-      launch_g2p2g_s<false, 4>(b, s, grid_wgs, parity, st, pass);
+      launch_g2p2g_s<false, 4>(b, s, grid_wgs, parity, st, pass, ev);
   } else {
     if (s.fixed)
-      launch_g2p2g_s<true, 8>(b, s, grid_wgs, parity, st, pass);
+      launch_g2p2g_s<true, 8>(b, s, grid_wgs, parity, st, pass, ev);
     else
-      launch_g2p2g_s<false, 8>(b, s, grid_wgs, parity, st, pass);
+      launch_g2p2g_s<false, 8>(b, s, grid_wgs, parity, st, pass, ev);
   }
 }
 
 template <int SOL, int T>
-static void launch_g2p_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+static void launch_g2p_t(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   const Clock* clk = (const Clock*)b.clock;
   const ToolDesc* tools = (const ToolDesc*)b.tools;
   if (s.push_out)
-    hipLaunchKernelGGL((k_g2p<SOL, true, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st, b.part[b.cur], b.cap,
+    launch_kernel(k_g2p<SOL, true, T>, dim3(grid_wgs), dim3(TileShape<T>::kWG), st, ev, b.part[b.cur], b.cap,
                        b.blk_end, b.work, b.status, b.vel, clk, parity, tools, s);
   else
-    hipLaunchKernelGGL((k_g2p<SOL, false, T>), dim3(grid_wgs), dim3(TileShape<T>::kWG), 0, st, b.part[b.cur], b.cap,
+    launch_kernel(k_g2p<SOL, false, T>, dim3(grid_wgs), dim3(TileShape<T>::kWG), st, ev, b.part[b.cur], b.cap,
                        b.blk_end, b.work, b.status, b.vel, clk, parity, tools, s);
 }
 
 template <int T>
-static void launch_g2p_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+static void launch_g2p_s(Buffers& b, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   if (s.solver == SOLVER_PIC)
-    launch_g2p_t<SOLVER_PIC, T>(b, s, grid_wgs, parity, st);
+    launch_g2p_t<SOLVER_PIC, T>(b, s, grid_wgs, parity, st, ev);
   else
-    launch_g2p_t<SOLVER_MLS, T>(b, s, grid_wgs, parity, st);
+    launch_g2p_t<SOLVER_MLS, T>(b, s, grid_wgs, parity, st, ev);
 }
 
-void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st) {
+void launch_g2p(Buffers& b, int64_t N, const SimK& s, int grid_wgs, int parity, hipStream_t st, KernelEvents ev) {
   (void)N;
   if (s.tile == 4)
-    launch_g2p_s<4>(b, s, grid_wgs, parity, st);
+    launch_g2p_s<4>(b, s, grid_wgs, parity, st, ev);
   else
-    launch_g2p_s<8>(b, s, grid_wgs, parity, st);
+    launch_g2p_s<8>(b, s, grid_wgs, parity, st, ev);
 }
 
 }  // namespace mpm

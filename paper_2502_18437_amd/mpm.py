@@ -388,8 +388,10 @@ class Simulation:
         self._check(_lib.mpm_autotune(self.h, int(trial_substeps), ctypes.byref(c)))
         return c.as_dict()
 
-    def profile(self, enable=True):
-        self._check(_lib.mpm_profile(self.h, int(bool(enable))))
+    def profile(self, enable=True, every=1):
+        """Per-kernel event timing on (the transfer and grid kernels of every
+        `every`-th substep) or off."""
+        self._check(_lib.mpm_profile(self.h, max(1, int(every)) if enable else 0))
 
     def profile_read(self):
         t = mpm_kernel_times()
