@@ -338,7 +338,7 @@ typedef struct mpm_launch_config {
 } mpm_launch_config;
 
 /* Read / replace the launch configuration (the defaults: resort_interval
- * from mpm_params or 128, the tile of mpm_params, two 8-cell-tile or eight
+ * from mpm_params or 256, the tile of mpm_params, two 8-cell-tile or eight
  * 4-cell-tile workgroups per compute unit, graph_chunk 8, MPM_REBIN_AUTO).
  * Errors: MPM_EINVAL (NULL, value out of range). */
 int mpm_get_launch_config(const mpm_handle* h, mpm_launch_config* out);

@@ -38,9 +38,11 @@ namespace {
 // Re-binning interval when mpm_params gives none. Adaptive re-binning (below)
 // re-bins earlier where particles drift out of their tiles, and particles
 // one cell out still scatter into their tile's shell, so the interval is a
-// backstop: on c3, 128 against 32 saves more in binning (about 7 us per
-// substep) than the extra particles on the global path cost (about 4).
-constexpr int kDefaultResort = 128;
+// backstop: on c3 (500 substeps), 256 substeps measured 259.2 us per
+// substep against 262.3 at 128 and 260.6 at 512, and 128 against 32 had
+// saved more in binning (about 7 us per substep) than the extra particles
+// on the global path cost (about 4).
+constexpr int kDefaultResort = 256;
 // Adaptive re-binning: re-bin before the interval ends once the particles on
 // the global path (outside their tiles) average more than this many per
 // million per substep since the last binning. Such a particle costs about 25

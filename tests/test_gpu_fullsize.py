@@ -96,7 +96,7 @@ def golden(name):
 @pytest.mark.parametrize("name,resort", [("c2", 0), ("c3", 0), ("c3", 32)])
 def test_full_size_100_substeps_default_launch(name, resort):
     """The whole scene for the 100-substep parity window in the library's
-    default launch configuration (re-binning every 128 substeps or earlier
+    default launch configuration (re-binning every 256 substeps or earlier
     when particles drift out of their tiles, the re-binning mode chosen
     automatically, runs of substeps replayed as HIP graphs), and for c3 also
     re-binning every 32 substeps (in-place re-binnings inside the window),
@@ -108,7 +108,7 @@ def test_full_size_100_substeps_default_launch(name, resort):
     k = int(z["n_substeps"])
     sim = mpm.simulation_from_scene(s)
     cfg = sim.launch_config()
-    assert cfg["resort_interval"] == 128 and cfg["rebin_mode"] == mpm.MPM_REBIN_AUTO and cfg["graph_chunk"] > 0
+    assert cfg["resort_interval"] == 256 and cfg["rebin_mode"] == mpm.MPM_REBIN_AUTO and cfg["graph_chunk"] > 0
     assert cfg["rebin_drift"] > 0 and cfg["tile"] == 8
     if resort:
         sim.set_launch_config(resort_interval=resort)

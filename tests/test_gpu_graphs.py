@@ -113,9 +113,9 @@ def test_autotune_keeps_the_scene():
     before, _ = sim.read_state()
     chosen = sim.autotune(trial_substeps=8)
     print(f"[autotune c3s] {chosen}", flush=True)
-    # a candidate interval, or the configuration in use (the default 128),
+    # a candidate interval, or the configuration in use (the default 256),
     # which is kept unless a candidate beats it by more than 5%
-    assert chosen["resort_interval"] in (1, 2, 4, 8, 16, 32, 64, 128)
+    assert chosen["resort_interval"] in (1, 2, 4, 8, 16, 32, 64, 128, 256)
     assert chosen["transfer_wgs"] % 8 == 0 and chosen["graph_chunk"] in (0, 8)
     assert chosen["rebin_mode"] in (mpm.MPM_REBIN_AUTO, mpm.MPM_REBIN_ADVANCE, mpm.MPM_REBIN_IN_PLACE)
     assert sim.launch_config() == chosen
