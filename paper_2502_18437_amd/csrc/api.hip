@@ -59,6 +59,10 @@ constexpr int kMinDriftInterval = 2;
 // substeps earlier. The device then still has that many substeps queued.
 constexpr int kDriftLag = 8;
 constexpr int kDriftEvents = 32;
+// Substeps launched one by one leave a progress mark every kDriftMarkEvery
+// substeps (an event recorded on the stream costs a few microseconds of GPU
+// time), so the host runs at most kDriftLag + kDriftMarkEvery - 1 ahead.
+constexpr int kDriftMarkEvery = 4;
 constexpr int kDefaultGraphChunk = 8;
 
 struct HostTool {
@@ -1235,7 +1239,7 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     h->substep++;
     h->since_sort++;
     ++k;
-    if (adaptive) HIP_OR_RETURN(h, drift_mark(h));
+    if (adaptive && (h->substep % kDriftMarkEvery == 0 || k == n_substeps)) HIP_OR_RETURN(h, drift_mark(h));
   }
   {
     h->prof_now = h->prof;  // the closing G2P, once per call

@@ -913,13 +913,15 @@ __device__ __forceinline__ void unit_origin(const SimK& s, unsigned u, int* to) 
 
 // Clears the span and the shell, and starts work item `tag` (nonzero, new
 // for each item of a workgroup); a barrier must follow.
-template <int T>
+// (KEEP_P2: the packed tile uses p0 and p1 only and keeps its slot table in
+// p2.)
+template <int T, bool KEEP_P2 = false>
 __device__ __forceinline__ void tile_clear(Lds<T>& L, uint32_t tag) {
   for (int i = threadIdx.x; i < Lds<T>::kNodes; i += blockDim.x) {
     L.m[i] = 0u;
     L.p0[i] = 0ll;
     L.p1[i] = 0ll;
-    L.p2[i] = 0ll;
+    if constexpr (!KEEP_P2) L.p2[i] = 0ll;
   }
   for (int j = threadIdx.x; j < Lds<T>::kShell; j += blockDim.x) {
     L.sm[j] = 0u;
@@ -1006,6 +1008,50 @@ __device__ __forceinline__ void tile_stage_velocity_max(const SimK& s, const int
   if ((threadIdx.x & 63u) == 0u) vw[w] = m;
 }
 
+// Slot table of a block-aligned (8-cell) tile, in the packed kernel's free
+// weight-sum array: per tile node, its offset from the tile's first node in
+// the block-major grid layout (low 32 bits) and its tile coordinates (4 bits
+// each from bit 32). A thread fills and reads only the slots it stages and
+// flushes (node i of thread threadIdx.x + k * blockDim.x), so no barrier
+// orders them.
+__device__ __forceinline__ void fill_slot_table(const SimK& s, long long* tab) {
+  constexpr int S = TileShape<8>::kSpan;
+  for (int i = threadIdx.x; i < Lds<8>::kNodes; i += blockDim.x) {
+    const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
+    const unsigned blk = (unsigned)((((lz >> 3) * s.nb + (ly >> 3)) * s.nb) + (lx >> 3));
+    const unsigned off = (blk << (3 * kTileLog2)) + (unsigned)((((lz & 7) << 3) + (ly & 7)) << 3) + (unsigned)(lx & 7);
+    tab[i] = (long long)((unsigned long long)off | ((unsigned long long)(lx | (ly << 4) | (lz << 8)) << 32));
+  }
+}
+
+// Grid index of the node in slot entry e of the tile at `to`, or -1 outside
+// the grid (tile coordinates at or beyond lim = n - to per axis).
+__device__ __forceinline__ int slot_node(long long e, int base, int limx, int limy, int limz) {
+  const unsigned c = (unsigned)((unsigned long long)e >> 32);
+  const bool in = (int)(c & 15u) < limx && (int)((c >> 4) & 15u) < limy && (int)(c >> 8) < limz;
+  return in ? base + (int)(unsigned)e : -1;
+}
+
+// tile_stage_velocity_max through the slot table (8-cell tiles).
+__device__ __forceinline__ void tile_stage_velocity_tab(const SimK& s, const int* to, const float4* vel, float4* Lv,
+                                                        float* vw, const long long* tab) {
+  const int base = to[3] * s.n3 + grid_index(to[0], to[1], to[2], s.nb);
+  const int limx = s.n - to[0], limy = s.n - to[1], limz = s.n - to[2];
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < Lds<8>::kNodes; i += blockDim.x) {
+    const int g = slot_node(tab[i], base, limx, limy, limz);
+    float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (g >= 0) val = vel[g];
+    Lv[i] = val;
+    m = fmaxf(m, fmaxf(fabsf(val.x), fmaxf(fabsf(val.y), fabsf(val.z))));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  int w = (int)(threadIdx.x >> 6);
+  opaque(w);
+  if ((threadIdx.x & 63u) == 0u) vw[w] = m;
+}
+
 // Non-empty tile nodes -> global accumulator, clearing the tile for the next
 // work item on the way (each thread clears the nodes it flushed).
 template <bool FIXED, int T>
@@ -1064,13 +1110,22 @@ __device__ __forceinline__ void tile_flush_clear_pk(const SimK& s, const int* to
     L.p0[i] = 0ll;
     L.p1[i] = 0ll;
     if ((w01 | w2m) == 0ull) continue;
-    const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
-    const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
-    if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
+    int g;
+    if constexpr (T == 8) {
+      // the slot table in the free p2 array (fill_slot_table)
+      g = slot_node(L.p2[i], to[3] * s.n3 + grid_index(to[0], to[1], to[2], s.nb), s.n - to[0], s.n - to[1],
+                    s.n - to[2]);
+      if (g < 0) continue;
+    } else {
+      const int lx = i % S, ly = (i / S) % S, lz = i / (S * S);
+      const int gx = to[0] + lx, gy = to[1] + ly, gz = to[2] + lz;
+      if ((unsigned)gx >= (unsigned)s.n || (unsigned)gy >= (unsigned)s.n || (unsigned)gz >= (unsigned)s.n) continue;
+      g = to[3] * s.n3 + grid_index(gx, gy, gz, s.nb);
+    }
     uint32_t wq;
     int p0, p1, p2;
     unpack_node(w01, w2m, wq, p0, p1, p2);
-    acc_add_pk(s, am, ap0, ap1, ap2, to[3] * s.n3 + grid_index(gx, gy, gz, s.nb), wq, p0, p1, p2, out);
+    acc_add_pk(s, am, ap0, ap1, ap2, g, wq, p0, p1, p2, out);
   }
 }
 
@@ -1215,6 +1270,10 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
   unsigned pos = walk.first(), npos = walk.end;
   uint2 item = make_uint2(0u, 0u);
   bool flip = false;  // which of the two velocity buffers holds this item's tile
+  // The packed tile leaves the p2 array free: 8-cell tiles keep their slot
+  // table there (staging and flush address the grid through it).
+  constexpr bool kTable = kPack && T == 8;
+  if constexpr (kTable) fill_slot_table(s, L.p2);
   if (pos < walk.end) {
     if (threadIdx.x == 0) L.claimed[0] = walk.claim(st);
     item = work[pos];
@@ -1222,11 +1281,13 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
       if (threadIdx.x == 0) L.pbe[0] = pb_rd[item.x & ~kDenseFlag];
     int to[4];
     unit_origin<T>(s, item.x & ~kDenseFlag, to);
-    if constexpr (kPack)
+    if constexpr (kTable)
+      tile_stage_velocity_tab(s, to, vel, L.v, L.vw[0], L.p2);
+    else if constexpr (kPack)
       tile_stage_velocity_max<T>(s, to, vel, L.v, L.vw[0]);
     else
       tile_stage_velocity<T>(s, to, vel, L.v);
-    tile_clear(L, pos + 1u);
+    tile_clear<T, kTable>(L, pos + 1u);
     __syncthreads();
     npos = L.claimed[0];
   }
@@ -1305,7 +1366,9 @@ __global__ __launch_bounds__(TileShape<T>::kWG, 4) void k_g2p2g(float* __restric
         if (threadIdx.x == 0) L.pbe[flip ? 0 : 1] = pb_rd[nitem.x & ~kDenseFlag];
       int nto[4];
       unit_origin<T>(s, nitem.x & ~kDenseFlag, nto);
-      if constexpr (kPack)
+      if constexpr (kTable)
+        tile_stage_velocity_tab(s, nto, vel, flip ? L.v : Vb, L.vw[flip ? 0 : 1], L.p2);
+      else if constexpr (kPack)
         tile_stage_velocity_max<T>(s, nto, vel, flip ? L.v : Vb, L.vw[flip ? 0 : 1]);
       else
         tile_stage_velocity<T>(s, nto, vel, flip ? L.v : Vb);
