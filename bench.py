@@ -56,7 +56,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-substeps/s (P2G+grid+G2P) fwd & fwd+bwd; % HBM roofline at 4M particles"
 # Per-kernel events on every PROFILE_EVERY-th substep of the timed steps.
-PROFILE_EVERY = 4
+PROFILE_EVERY = 8
 HBM_PEAK_GBS = 8000.0
 B_PARTICLE = 100.0      # x, F, E read + x, F written per particle-substep (fused path)
 B_NODE_SUBSTEP = 72.0   # P2G result write+read, reset, velocity write+read per active node
