@@ -343,8 +343,12 @@ struct Lds {
   static constexpr int kOuter = kSpan + 2;
   static constexpr int kShell = kOuter * kOuter * kOuter - kNodes;
   float4 v[kNodes];                             // staged grid velocity
-  uint32_t m[kNodes];                           // weight sums (2^-22 units)
-  long long p0[kNodes], p1[kNodes], p2[kNodes];  // momentum (fixed point)
+  // Weight sums (2^-22 units) and momentum (fixed point). The packed tile of
+  // the FP32 MLS-MPM kernel holds a node in p0 and p1 (and its shell in sp0
+  // and sp1) and keeps the 8-cell tiles' slot table in p2; m, sm and sp2 are
+  // then unused.
+  uint32_t m[kNodes];
+  long long p0[kNodes], p1[kNodes], p2[kNodes];
   uint32_t sm[kShell];                          // the shell's sums
   long long sp0[kShell], sp1[kShell], sp2[kShell];
   // A scatter into the shell copies item_tag (set per work item) into
