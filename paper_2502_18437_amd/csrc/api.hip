@@ -1192,10 +1192,10 @@ int mpm_step(mpm_handle* h, int32_t n_substeps) {
     if (rebin) {
       ProfScope ps(h, 0);
       // Binning orders a block's particles by sub-cell class when the block
-      // held few enough particles at the previous sort; new particles are
-      // first sorted once to get those counts.
+      // held few enough particles at the previous sort; for new particles a
+      // sort of their keys alone gives those counts first.
       const int bits = h->key_bits + h->sim.unit_shift;  // bits of a work tile id or the sentinel
-      if (h->fresh_order) launch_binning(b, N, h->sim, bits, k == 0 || advance, h->stream);
+      if (h->fresh_order) launch_tile_counts(b, N, h->sim, bits, h->stream);
       h->fresh_order = false;
       launch_binning(b, N, h->sim, bits, k == 0 || advance, h->stream);
       h->dirty = false;

@@ -442,6 +442,23 @@ static int radix_sort(Buffers& b, int64_t N, int key_bits, hipStream_t st) {
   return src;
 }
 
+// Tile counts of particles in memory order, for the binning of new
+// particles: the keys and their sort as in launch_binning, then the tile
+// ranges of the sorted keys in blk_begin / blk_end; the particles stay where
+// they are and no list is built. The binning that follows reads the counts.
+void launch_tile_counts(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st) {
+  const uint32_t n_blocks = s.nb3 * (uint32_t)s.n_scenes;
+  const uint32_t n_units = n_blocks << s.unit_shift;
+  const uint32_t sentinel = n_units << kClassBits;
+  hipLaunchKernelGGL(k_keygen, dim3(grid_for(N, 256)), dim3(256), 0, st, b.part[b.cur], b.id[b.cur],
+                     b.scene_off, b.cap, N, s, b.blk_begin, b.blk_end, b.keys[0], b.vals[0], sentinel, b.status);
+  const int src = radix_sort(b, N, key_bits + kClassBits, st);
+  fill_u32(b.blk_begin, n_units, 0u, st);
+  fill_u32(b.blk_end, n_units, 0u, st);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(N, 256)), dim3(256), 0, st, b.keys[src], N, n_units, kClassBits,
+                     b.blk_begin, b.blk_end);
+}
+
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool with_vc, hipStream_t st) {
   const uint32_t n_blocks = s.nb3 * (uint32_t)s.n_scenes;
   const uint32_t n_units = n_blocks << s.unit_shift;  // work tiles

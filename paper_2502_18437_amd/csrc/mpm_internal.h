@@ -235,6 +235,9 @@ struct Buffers {
 // also permute v and C (false between fused substeps, where only x, F, E are
 // held in memory).
 void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool with_vc, hipStream_t st);
+// The tile counts that launch_binning's ordering rule reads, for particles
+// without a previous sort (blk_begin / blk_end; nothing else changes).
+void launch_tile_counts(Buffers& b, int64_t N, const SimK& s, int key_bits, hipStream_t st);
 
 // Optional HIP events that a launcher records around its one kernel as part
 // of the kernel's dispatch (hipExtLaunchKernel), for per-kernel timing
