@@ -407,7 +407,7 @@ void set_tile(mpm_handle* h, int tile) {
 
 void free_buffers(Buffers& b) {
   void* ptrs[] = {b.part[0], b.part[1], b.id[0], b.id[1], b.keys[0], b.keys[1], b.vals[0], b.vals[1],
-                  b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.work, b.act_list, b.mark,
+                  b.hist, b.scan_tmp, b.blk_begin, b.blk_end, b.flags, b.occ_list, b.work, b.work_tmp, b.act_list, b.mark,
                   b.ovf_list[0], b.ovf_list[1], b.node_cnt, b.imp_blocks, b.acc_m, b.acc_p[0], b.acc_p[1], b.acc_p[2], b.vel,
                   b.status, b.scene_off, b.tools, b.clock, b.pbound[0], b.pbound[1]};
   for (void* p : ptrs)
@@ -687,6 +687,7 @@ int create_impl(const mpm_params* p, int32_t n_scenes, uint64_t hip_stream, mpm_
   // at most one partial item per occupied work tile plus one per
   // kItemMinAny (the smallest item of any tile edge or of the rollout) particles
   alloc((void**)&b.work, sizeof(uint2) * ((size_t)n_units_max + (size_t)(cap / kItemMinAny) + 1));
+  alloc((void**)&b.work_tmp, sizeof(uint2) * ((size_t)n_units_max + (size_t)(cap / kItemMinAny) + 1));
   alloc((void**)&b.act_list, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.mark, sizeof(uint32_t) * h->n_blocks);
   alloc((void**)&b.node_cnt, sizeof(uint32_t) * h->n_blocks);

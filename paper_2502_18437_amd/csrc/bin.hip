@@ -401,6 +401,61 @@ __global__ void k_emit_items(const uint32_t* __restrict__ begin, const uint32_t*
   }
 }
 
+// Work items of each XCD's range (the contiguous eighth of the list that
+// the transfer kernels' walk gives an XCD) from `src` to `dst` in decreasing
+// size, in buckets of item_particles / 64 particles and in list (spatial)
+// order within a bucket: the workgroups of an XCD take its first items and
+// then claim the rest in order, so the items claimed last, at the end of a
+// launch, are the small ones (longest first). One workgroup per range; tiles
+// of the range in order, each item ranked among the tile's items of its
+// bucket before it, keep the order within a bucket.
+constexpr int kOrderWG = 256;
+constexpr int kSizeBuckets = 64;
+__global__ __launch_bounds__(kOrderWG) void k_order_items(const uint2* __restrict__ src, uint2* __restrict__ dst,
+                                                          const uint32_t* __restrict__ blk_end, const Status* st,
+                                                          uint32_t item, int bucket_shift) {
+  __shared__ uint32_t cnt[kSizeBuckets], start[kSizeBuckets];
+  __shared__ uint8_t tb[kOrderWG];
+  const uint32_t n = st->n_work, chunk = (n + kXcds - 1) / kXcds;
+  const uint32_t lo = min(blockIdx.x * chunk, n), hi = min(lo + chunk, n);
+  auto bucket = [&](uint2 it) -> uint32_t {
+    const uint32_t c = min(item, blk_end[it.x & ~kDenseFlag] - it.y);
+    return (kSizeBuckets - 1) - min((uint32_t)(kSizeBuckets - 1), c >> bucket_shift);
+  };
+  if (threadIdx.x < kSizeBuckets) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += kOrderWG) atomicAdd(&cnt[bucket(src[i])], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = lo;
+    for (int k = 0; k < kSizeBuckets; ++k) {
+      start[k] = s;
+      s += cnt[k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t t0 = lo; t0 < hi; t0 += kOrderWG) {
+    const uint32_t i = t0 + threadIdx.x;
+    const bool has = i < hi;
+    const uint2 it = has ? src[i] : make_uint2(0u, 0u);
+    const uint32_t bk = has ? bucket(it) : (uint32_t)kSizeBuckets;
+    tb[threadIdx.x] = (uint8_t)bk;
+    __syncthreads();
+    if (has) {
+      uint32_t rank = 0u;
+      for (uint32_t j = 0; j < threadIdx.x; ++j) rank += tb[j] == bk;
+      dst[start[bk] + rank] = it;
+    }
+    __syncthreads();
+    if (threadIdx.x < kSizeBuckets) {
+      uint32_t c = 0u;
+      for (int j = 0; j < kOrderWG; ++j) c += tb[j] == threadIdx.x;
+      start[threadIdx.x] += c;
+    }
+    __syncthreads();
+  }
+}
+
 // list[pos[b]] = b for flagged blocks; flags and pos may not alias.
 __global__ void k_compact(const uint32_t* __restrict__ mark_or_range_b,
                           const uint32_t* __restrict__ range_e, const uint32_t* __restrict__ pos,
@@ -504,7 +559,12 @@ void launch_binning(Buffers& b, int64_t N, const SimK& s, int key_bits, bool wit
                      n_units, s.item_particles, b.flags);
   exclusive_scan(b.flags, b.flags, n_units, b.scan_tmp, &b.status->n_work, st);
   hipLaunchKernelGGL(k_emit_items, dim3(grid_for(n_units, 256)), dim3(256), 0, st, b.blk_begin, b.blk_end,
-                     b.flags, n_units, s.item_particles, dense, b.work);
+                     b.flags, n_units, s.item_particles, dense, b.work_tmp);
+  // 5c. largest items first within each XCD's range
+  int bucket_shift = 0;
+  while (((uint32_t)kSizeBuckets << (bucket_shift + 1)) <= (uint32_t)s.item_particles) ++bucket_shift;
+  hipLaunchKernelGGL(k_order_items, dim3(kXcds), dim3(kOrderWG), 0, st, (const uint2*)b.work_tmp, b.work,
+                     (const uint32_t*)b.blk_end, (const Status*)b.status, (uint32_t)s.item_particles, bucket_shift);
   // 6. active list: the grid blocks the occupied tiles' LDS tiles touch
   fill_u32(b.mark, n_blocks, 0u, st);
   hipLaunchKernelGGL(k_mark_dilated, dim3(grid_for(n_units, 256)), dim3(256), 0, st, b.blk_begin,

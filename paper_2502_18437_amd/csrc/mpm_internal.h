@@ -204,6 +204,7 @@ struct Buffers {
   uint32_t* flags = nullptr;                // per work tile scratch for compaction
   uint32_t* occ_list = nullptr;             // occupied work tiles
   uint2* work = nullptr;                    // transfer work items {work tile, first particle}
+  uint2* work_tmp = nullptr;                // the items as emitted, before ordering by size
   uint32_t* act_list = nullptr;             // active (dilated) blocks
   uint32_t* mark = nullptr;                 // per block: 0 idle, 1 active, 2 overflow
   // Per work tile, one per grid-update parity: the largest P2G contribution
