@@ -548,12 +548,12 @@ __device__ __forceinline__ void p2g_particle(const SimK& s, const float* x, cons
 // words, (p1, p0) and (p2, weight), every field a 32-bit integer, so that a
 // node takes 2 LDS atomics instead of 4. The momentum fields count units of
 // 2^e kg m/s, with e chosen per work item (item_scale) so that no node sum of
-// the item can leave 32 bits. The scale comes from the largest contribution
-// bound of the tile's particles in the previous substep (Buffers::pbound),
-// times 1.25; a particle whose own bound exceeds that capacity scatters into
-// the global accumulator instead, so no sum can wrap whatever the previous
-// substep said. A contribution is rounded to an integer by one FP32 fma with
-// 1.5 * 2^23. Two such biased words, less the doubled bias in one 64-bit
+// the item can leave 32 bits. The scale comes from a capacity: 1.25 times the
+// larger of the tile's largest contribution bound in the previous substep
+// (Buffers::pbound) and the particle mass times the largest staged grid
+// velocity. A particle whose own bound exceeds the capacity scatters into the
+// global accumulator instead, so no sum can wrap whatever the estimate said.
+// A contribution is rounded to an integer by one FP32 fma with 1.5 * 2^23. Two such biased words, less the doubled bias in one 64-bit
 // subtraction, give hi 2^32 + lo with lo signed; 64-bit sums of such words
 // decode into the exact sums of both fields while each stays within 32 bits.
 // The weight field is unsigned and needs no bias.
@@ -575,9 +575,10 @@ struct ItemScale {
 // the tile's staged nodes: the item takes particles whose bound is at most
 // 1.25 times the larger of the recorded bound and m vmax. The recorded bound
 // follows the stress; m vmax bounds |m v| of every particle that gathers from
-// the tile, and covers the first substeps from rest, where the bounds grow
-// by large factors from one substep to the next. A node sum of the item has at most n terms,
-// each at most 0.421875 (the largest weight) times that capacity, so X below
+// the tile, and covers the first substeps from rest, where the bounds grow by
+// large factors from one substep to the next. A node sum of the item has at
+// most n terms, each at most 0.421875 (the largest weight) times that
+// capacity, so X below
 // bounds every |sum|; with X 2^-e < 2^31 / (1 + 2^-10) every sum decodes from
 // its 32 bits with room for the FP32 rounding of the terms (and, n counted as
 // at least 512, every term stays under the 2^22 range of the rounding fma).
